@@ -1,0 +1,147 @@
+"""CPU oracle for checkerboard Metropolis sweeps of the 2D Ising model.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package imports this
+package; only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may.  It shares no code with the GPU library.
+
+Contents:
+  - ``liboracle.so`` (from ``ising_oracle.c``): Philox4x32-10, thresholds,
+    random/cold initial states, plain int8 sweeps, observables, threaded
+    batches over replicas.  This module is its ctypes front-end.
+  - ``philox``: a second, pure-Python Philox4x32-10.
+  - ``exact``: exact results (enumeration, transfer matrix, Kaufman torus
+    partition function, Onsager energy and T_c, Yang magnetisation).
+  - ``stats``: autocorrelation time, binned errors, chi-square helpers.
+  - ``nn_ref``: float64 numpy reference of the block-proposal network.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+INIT_RANDOM, INIT_UP, INIT_DOWN = 0, 1, 2
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("J", ctypes.c_double),
+                ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("init", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liboracle.so, building it with gcc first if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from oracle import build as _build
+            _build.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_thresholds.argtypes = [ctypes.c_double, ctypes.c_double, u32p, u32p,
+                                        ctypes.POINTER(ctypes.c_int32)]
+        L.oracle_init.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p]
+        L.oracle_observables.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_observables.restype = None
+        L.oracle_sweeps.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+        L.oracle_run_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int32]
+        _lib = L
+    return _lib
+
+
+def desc(Lx, Ly, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM):
+    return Desc(int(Lx), int(Ly), float(J), float(beta), int(seed), int(replica), int(init))
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xffffffff for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def thresholds(J, beta):
+    """(thr4, thr8, always) for the Metropolis rule; raises ValueError if invalid."""
+    a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int32()
+    st = lib().oracle_thresholds(float(J), float(beta), ctypes.byref(a), ctypes.byref(b),
+                                 ctypes.byref(c))
+    if st != 0:
+        raise ValueError("invalid J/beta")
+    return int(a.value), int(b.value), int(c.value)
+
+
+def init_state(d):
+    """Initial state of one replica as an (Ly, Lx) int8 array of +-1."""
+    s = np.empty((d.Ly, d.Lx), dtype=np.int8)
+    st = lib().oracle_init(ctypes.byref(d), s.ctypes.data)
+    if st != 0:
+        raise ValueError("invalid descriptor")
+    return s
+
+
+def observables(s):
+    """(B, M) of an (Ly, Lx) +-1 array: bond sum (E = -J B) and magnetisation."""
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    B, M = ctypes.c_int64(), ctypes.c_int64()
+    lib().oracle_observables(s.shape[1], s.shape[0], s.ctypes.data, ctypes.byref(B),
+                             ctypes.byref(M))
+    return int(B.value), int(M.value)
+
+
+def sweeps(d, s, n, t0=0, record_every=0):
+    """Run n sweeps in place on s (int8, C-contiguous); returns (bond, mag) traces."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape == (d.Ly, d.Lx)
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros(max(n_rec, 1), dtype=np.int64)
+    mag = np.zeros(max(n_rec, 1), dtype=np.int64)
+    st = lib().oracle_sweeps(ctypes.byref(d), s.ctypes.data, int(t0), int(n), int(record_every),
+                             bond.ctypes.data if n_rec else None,
+                             mag.ctypes.data if n_rec else None)
+    if st != 0:
+        raise ValueError("invalid arguments")
+    return bond[:n_rec], mag[:n_rec]
+
+
+def run_batch(descs, states, n, t0=None, record_every=0, threads=None):
+    """Sweep many replicas in place on host threads.
+
+    ``states`` is a list of (Ly, Lx) int8 arrays; returns (bond, mag) traces of
+    shape (n_replicas, n // record_every).
+    """
+    nrep = len(descs)
+    arr = (Desc * nrep)(*descs)
+    ptrs = (ctypes.c_void_p * nrep)()
+    for r, s in enumerate(states):
+        assert s.dtype == np.int8 and s.flags.c_contiguous
+        assert s.shape == (descs[r].Ly, descs[r].Lx)
+        ptrs[r] = s.ctypes.data
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
+    mag = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
+    t0a = None
+    if t0 is not None:
+        t0a = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.uint64), (nrep,)))
+    if threads is None:
+        threads = os.cpu_count() or 1
+    st = lib().oracle_run_batch(nrep, arr, ptrs, t0a.ctypes.data if t0a is not None else None,
+                                int(n), int(record_every),
+                                bond.ctypes.data if n_rec else None,
+                                mag.ctypes.data if n_rec else None, int(threads))
+    if st != 0:
+        raise ValueError("invalid arguments")
+    return bond[:, :n_rec], mag[:, :n_rec]

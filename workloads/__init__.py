@@ -1,0 +1,124 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle runs.
+
+This module holds inputs only: lattice shapes, couplings, temperatures, seeds,
+replica ids, initial-state modes and seeded +-1 arrays.  It contains none of
+the method's arithmetic (no random-number stream of the sweep, no
+acceptance thresholds, no update rule), so that both the GPU library and the
+CPU oracle can be driven from it without sharing any of the method's code.
+
+The paper publishes no dataset; its workloads are random-start lattices of
+1024^2 to 4096^2 spins over T/J from 0.385 to 4.145 (validation, section 3.1),
+2048^2 to 16384^2 single lattices (flip-rate runs, section 3.2) and up to 754
+simultaneous simulations of about 200 M spins in total (section 3.2, Table 1).
+The configurations below are synthetic stand-ins of those shapes.
+"""
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+INIT_RANDOM, INIT_UP, INIT_DOWN = 0, 1, 2
+BASE_SEED = 16990
+T_CRITICAL_PRINTED = 2.269185  # critical temperature as printed in section 3.1
+
+
+@dataclass
+class Replica:
+    Lx: int
+    Ly: int
+    T: float
+    seed: int
+    replica: int
+    init: int = INIT_RANDOM
+    J: float = 1.0
+
+    @property
+    def beta(self) -> float:
+        return 1.0 / self.T
+
+    @property
+    def spins(self) -> int:
+        return self.Lx * self.Ly
+
+
+@dataclass
+class Workload:
+    name: str
+    replicas: List[Replica]
+    sweeps: int
+    record_every: int
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def spins(self) -> int:
+        return sum(r.spins for r in self.replicas)
+
+    @property
+    def flip_attempts(self) -> int:
+        return self.spins * self.sweeps
+
+
+def single_64() -> Workload:
+    """One 64x64 lattice at T = 2.269185, random start, 1000 sweeps, (B, M) every sweep."""
+    return Workload("single-64x64-Tc", [Replica(64, 64, T_CRITICAL_PRINTED, BASE_SEED, 0)],
+                    sweeps=1000, record_every=1)
+
+
+def batch_256x1024() -> Workload:
+    """256 replicas of 1024x1024, T_r = 1.5 + 2 r / 255, seed 16990 + r, random start."""
+    reps = [Replica(1024, 1024, 1.5 + 2.0 * r / 255.0, BASE_SEED + r, r) for r in range(256)]
+    return Workload("256x1024^2-T1.5..3.5", reps, sweeps=10000, record_every=100)
+
+
+def uneven_512(n: int = 512) -> Workload:
+    """Uneven batch: side 2^k, k uniform on {7..13}; T uniform on [2.0, 2.6).
+
+    Both drawn from numpy's PCG64 seeded with 16990, sides first then temperatures.
+    """
+    rng = np.random.Generator(np.random.PCG64(BASE_SEED))
+    ks = rng.integers(7, 14, size=n)
+    Ts = rng.uniform(2.0, 2.6, size=n)
+    reps = [Replica(1 << int(k), 1 << int(k), float(T), BASE_SEED + r, r)
+            for r, (k, T) in enumerate(zip(ks, Ts))]
+    return Workload("uneven-512-L128..8192", reps, sweeps=2000, record_every=100)
+
+
+def paper_scale() -> Workload:
+    """754 replicas of Lx=512 x Ly=528 at T = linspace(1.8, 3.0, 754), plus one
+    Lx=16384 x Ly=12288 lattice at T = 2.269185; all cold (+1) starts; 1000 sweeps."""
+    Ts = np.linspace(1.8, 3.0, 754)
+    reps = [Replica(512, 528, float(T), BASE_SEED + r, r, INIT_UP) for r, T in enumerate(Ts)]
+    reps.append(Replica(16384, 12288, T_CRITICAL_PRINTED, BASE_SEED, 754, INIT_UP))
+    return Workload("paper-scale-754x512x528+16384x12288", reps, sweeps=1000, record_every=100)
+
+
+def learned_64x256() -> Workload:
+    """64 replicas of 256x256 at T = linspace(2.20, 2.35, 64) for the block-proposal path."""
+    Ts = np.linspace(2.20, 2.35, 64)
+    reps = [Replica(256, 256, float(T), BASE_SEED + r, r) for r, T in enumerate(Ts)]
+    return Workload("learned-64x256^2-T2.20..2.35", reps, sweeps=1000, record_every=1)
+
+
+ALL = {
+    "single_64": single_64,
+    "batch_256x1024": batch_256x1024,
+    "uneven_512": uneven_512,
+    "paper_scale": paper_scale,
+    "learned_64x256": learned_64x256,
+}
+
+
+def random_pm1(shape, seed: int) -> np.ndarray:
+    """Seeded +-1 int8 array (numpy PCG64), for set-spins / checkpoint tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (1 - 2 * rng.integers(0, 2, size=shape)).astype(np.int8)
+
+
+def small_shapes(seed: int, count: int, max_wx: int = 4, max_ly: int = 40):
+    """Seeded list of (Lx, Ly) with Lx a multiple of 64 and Ly even, for parity sweeps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        out.append((64 * int(rng.integers(1, max_wx + 1)), 2 * int(rng.integers(1, max_ly // 2 + 1))))
+    return out

@@ -1,0 +1,188 @@
+/*
+ * ising.h — C ABI of the MI355X checkerboard Metropolis library (libising.so).
+ *
+ * The library runs red/black Metropolis sweeps of the periodic 2D
+ * nearest-neighbour Ising model, H = -J sum_<ij> s_i s_j with s = +-1 and
+ * J > 0 (paper section 1), for a batch of independent replicas, each with its
+ * own size, coupling, temperature, seed and replica id.  A sweep updates every
+ * red site ((x+y) even) and then every blue site, each proposal accepted by the
+ * Metropolis rule ran() < exp(-beta dE) (section 1; section 2 and the
+ * checkerboard multi-spin algorithm of the Supplementary Information, S.1).
+ *
+ * Conventions shared by every call:
+ *  - Plain C; every function returns an int status: ISING_OK (0) or a
+ *    negative ISING_E_* code.  ising_last_error() gives detail for the
+ *    calling thread.
+ *  - All device memory belongs to the caller.  ising_state_bytes() says how
+ *    many bytes of device memory a batch needs; the caller allocates them
+ *    (any allocator) and keeps them alive, unmoved, until
+ *    ising_batch_destroy().  The library allocates no device memory; it owns
+ *    only host-side metadata.
+ *  - "stream" arguments are hipStream_t values passed as void* (NULL = the
+ *    null stream).  Calls documented as asynchronous only enqueue work on that
+ *    stream; device faults surface at the next blocking call.
+ *  - A handle must not be used from two host threads at once.
+ *  - Spin encoding inside the library: 1 bit per spin, bit 1 <=> s = +1.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the
+ *    replica's 64-bit seed; the uniform of site (x, y) in sweep t is word
+ *    (h & 3) of Philox(ctr = {h >> 2, t, replica, colour}), h = (y*Lx + x) >> 1,
+ *    colour = (x + y) & 1.  Results therefore do not depend on word width,
+ *    launch shape or how replicas are batched.
+ *  - Acceptance: dE <= 0 always; dE = 4J iff r < floor(exp(-4 beta J) 2^32);
+ *    dE = 8J iff r < floor(exp(-8 beta J) 2^32) (thresholds clamped to
+ *    2^32 - 1; beta*J == 0 accepts everything).
+ *  - Observables: bond sum B = sum_{x,y} s(x,y) (s(x+1,y) + s(x,y+1)), every
+ *    bond once, so E = -J B; magnetisation M = sum s (|M| is the observable of
+ *    paper section 3.1).
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ISING_OK = 0,
+    ISING_E_INVALID = -1,     /* an argument is out of range or inconsistent */
+    ISING_E_UNSUPPORTED = -2, /* valid physics, but a shape this library does not run */
+    ISING_E_NOMEM = -3,       /* host allocation failed or a caller buffer is too small */
+    ISING_E_HIP = -4,         /* a HIP runtime call failed; detail in ising_last_error() */
+    ISING_E_STATE = -5        /* the call is not valid in the handle's current state */
+};
+
+enum { ISING_INIT_RANDOM = 0, ISING_INIT_UP = 1, ISING_INIT_DOWN = 2 };
+
+/*
+ * One replica (one simulation; the paper runs one per PE column, section 2).
+ *  Lx, Ly   columns and rows; Lx must be a positive multiple of 64 and Ly even
+ *           and >= 2 (ISING_E_UNSUPPORTED otherwise); Lx*Ly < 2^32.
+ *  J        coupling, finite and > 0 (ISING_E_INVALID otherwise).
+ *  beta     inverse temperature 1/T (k_B = 1), >= 0; +infinity means T = 0.
+ *  seed     64-bit Philox key of this replica.
+ *  replica  32-bit replica id (third Philox counter word); replicas that share
+ *           a seed must differ here to draw independent numbers.
+ *  init     ISING_INIT_RANDOM: s = +1 iff word (g & 3) of
+ *           Philox(ctr = {g >> 2, 0, replica, 2}) >= 2^31 with g = y*Lx + x
+ *           (the paper starts from a completely random configuration,
+ *           section 3.1); ISING_INIT_UP / ISING_INIT_DOWN: all +1 / all -1.
+ */
+typedef struct {
+    int32_t Lx, Ly;
+    double J, beta;
+    uint64_t seed;
+    uint32_t replica;
+    int32_t init;
+} ising_desc;
+
+typedef struct ising_batch ising_batch;
+
+/* Static text for a status code. */
+const char *ising_strerror(int code);
+
+/* Detail of the last failure on the calling thread ("" if none); valid until
+ * the next library call on this thread. */
+const char *ising_last_error(void);
+
+/*
+ * Bytes of device memory needed for a batch of n replicas described by d[0..n).
+ * Pure host computation (no device call).  Errors: ISING_E_INVALID (n <= 0,
+ * NULL pointers, bad J/beta/init), ISING_E_UNSUPPORTED (bad shape).
+ */
+int ising_state_bytes(int32_t n, const ising_desc *d, size_t *bytes);
+
+/*
+ * Create a batch in the caller's device buffer dev_buf (bytes >= the value
+ * from ising_state_bytes, 256-byte aligned) and enqueue initialisation of
+ * every replica on stream.  Sweep counters start at 0.  Asynchronous.
+ * On success *out holds the handle.  Errors: as ising_state_bytes, plus
+ * ISING_E_NOMEM (buffer too small or host allocation failure), ISING_E_HIP.
+ */
+int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t bytes,
+                       void *stream, ising_batch **out);
+
+/*
+ * Run n_sweeps full sweeps (red then blue, Supplementary algorithm S2) of
+ * every replica.  Asynchronous on stream.  Replica r's sweep counter t_r
+ * advances by n_sweeps and must stay below 2^32 (ISING_E_INVALID otherwise).
+ * Running a then b sweeps gives exactly the state of running a + b.
+ *
+ * If record_every > 0 and both trace pointers are non-NULL, after the sweep
+ * with run-local index i (0-based) such that (i + 1) % record_every == 0 the
+ * replica's (B, M) are written to dev_bond_trace[r * n_rec + j] and
+ * dev_mag_trace[r * n_rec + j], j = (i + 1) / record_every - 1,
+ * n_rec = n_sweeps / record_every.  Both traces are device arrays of at least
+ * n * n_rec int64 values owned by the caller; every slot is written.
+ * record_every == 0 or NULL traces record nothing.
+ */
+int ising_batch_run(ising_batch *b, uint64_t n_sweeps, uint32_t record_every,
+                    int64_t *dev_bond_trace, int64_t *dev_mag_trace, void *stream);
+
+/*
+ * Current (B, M) of every replica into host arrays of n int64 each.
+ * Blocking: enqueues a popcount reduction on stream and waits for it.
+ */
+int ising_batch_observables(ising_batch *b, int64_t *host_bond, int64_t *host_mag,
+                            void *stream);
+
+/*
+ * Copy replica r's spins to / from a host int8 array of Lx*Ly values +-1 in
+ * row-major order (index y*Lx + x).  Blocking on stream.  set_spins rejects
+ * values other than +-1 with ISING_E_INVALID and leaves the state unchanged.
+ */
+int ising_batch_get_spins(ising_batch *b, int32_t r, int8_t *host_pm1, void *stream);
+int ising_batch_set_spins(ising_batch *b, int32_t r, const int8_t *host_pm1, void *stream);
+
+/* Read / set replica r's sweep counter (for checkpoint and resume). */
+int ising_batch_get_sweep(ising_batch *b, int32_t r, uint64_t *t, void *stream);
+int ising_batch_set_sweep(ising_batch *b, int32_t r, uint64_t t, void *stream);
+
+/* Change replica r's inverse temperature; thresholds are recomputed. */
+int ising_batch_set_beta(ising_batch *b, int32_t r, double beta, void *stream);
+
+/*
+ * Execution schedule (what the autotuner chooses; every schedule gives
+ * bit-identical results).
+ *  word_bits        32 or 64: bits per machine word a thread updates
+ *                   (64 needs Lx % 128 == 0; such replicas fall back to 32).
+ *  resident_max_bytes  replicas whose two colour planes fit in this many
+ *                   bytes of LDS run whole sweeps inside one workgroup;
+ *                   0 disables that mode, larger than the device's LDS per
+ *                   workgroup is clamped.
+ *  resident_threads workgroup size of the LDS-resident mode (64..1024, a
+ *                   multiple of 64).
+ *  stream_threads   workgroup size of the streaming mode (64..1024).
+ *  stream_words     words per streaming workgroup (a multiple of stream_threads).
+ *  sweeps_per_launch  sweeps per graph launch / resident launch (>= 1).
+ *  use_graph        1: capture sweeps_per_launch sweeps into a hipGraph and
+ *                   replay it; 0: launch kernels directly.
+ */
+typedef struct {
+    int32_t word_bits;
+    int32_t resident_max_bytes;
+    int32_t resident_threads;
+    int32_t stream_threads;
+    int32_t stream_words;
+    int32_t sweeps_per_launch;
+    int32_t use_graph;
+} ising_schedule;
+
+int ising_batch_get_schedule(ising_batch *b, ising_schedule *s);
+/* Validates s (ISING_E_INVALID) and installs it; cached graphs are dropped. */
+int ising_batch_set_schedule(ising_batch *b, const ising_schedule *s);
+
+/* Number of replicas in each execution mode under the current schedule. */
+int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed);
+
+/* Free host metadata and cached graphs.  Waits for no device work; the caller
+ * must not free dev_buf while work on it is still queued. */
+int ising_batch_destroy(ising_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

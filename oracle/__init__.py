@@ -63,6 +63,15 @@ def lib():
     return _lib
 
 
+def default_threads():
+    """Host threads for batched oracle runs: the CPUs this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def desc(Lx, Ly, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM):
     return Desc(int(Lx), int(Ly), float(J), float(beta), int(seed), int(replica), int(init))
 
@@ -137,7 +146,7 @@ def run_batch(descs, states, n, t0=None, record_every=0, threads=None):
     if t0 is not None:
         t0a = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.uint64), (nrep,)))
     if threads is None:
-        threads = os.cpu_count() or 1
+        threads = default_threads()
     st = lib().oracle_run_batch(nrep, arr, ptrs, t0a.ctypes.data if t0a is not None else None,
                                 int(n), int(record_every),
                                 bond.ctypes.data if n_rec else None,

@@ -1,0 +1,270 @@
+"""Python binding of libising.so, the MI355X checkerboard Metropolis library.
+
+Argument marshalling only: every step of a sweep runs in the library's HIP
+kernels.  The functions keep the C ABI's names (see include/ising.h);
+``Batch`` is a convenience owner of the device buffer (a torch uint8 tensor)
+that calls them.  Importing works without a GPU; calls that touch the device
+need one.  There is no fallback: if the library is missing, every call raises.
+"""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libising.so")
+
+ISING_OK = 0
+ISING_E_INVALID = -1
+ISING_E_UNSUPPORTED = -2
+ISING_E_NOMEM = -3
+ISING_E_HIP = -4
+ISING_E_STATE = -5
+ISING_INIT_RANDOM, ISING_INIT_UP, ISING_INIT_DOWN = 0, 1, 2
+
+EXPORTED = [
+    "ising_strerror", "ising_last_error", "ising_state_bytes", "ising_batch_create",
+    "ising_batch_run", "ising_batch_observables", "ising_batch_get_spins",
+    "ising_batch_set_spins", "ising_batch_get_sweep", "ising_batch_set_sweep",
+    "ising_batch_set_beta", "ising_batch_get_schedule", "ising_batch_set_schedule",
+    "ising_batch_mode_counts", "ising_batch_destroy",
+]
+
+
+class ising_desc(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("J", ctypes.c_double),
+                ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("init", ctypes.c_int32)]
+
+
+class ising_schedule(ctypes.Structure):
+    _fields_ = [("word_bits", ctypes.c_int32), ("resident_max_bytes", ctypes.c_int32),
+                ("resident_threads", ctypes.c_int32), ("stream_threads", ctypes.c_int32),
+                ("stream_words", ctypes.c_int32), ("sweeps_per_launch", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code, func, detail):
+        self.code = code
+        super().__init__(f"{func} failed ({code}: {detail})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libising.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2404_16990_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+        P = ctypes.POINTER
+        L.ising_strerror.argtypes = [ctypes.c_int]
+        L.ising_strerror.restype = ctypes.c_char_p
+        L.ising_last_error.argtypes = []
+        L.ising_last_error.restype = ctypes.c_char_p
+        L.ising_state_bytes.argtypes = [i32, P(ising_desc), P(ctypes.c_size_t)]
+        L.ising_batch_create.argtypes = [i32, P(ising_desc), vp, ctypes.c_size_t, vp, P(vp)]
+        L.ising_batch_run.argtypes = [vp, u64, u32, vp, vp, vp]
+        L.ising_batch_observables.argtypes = [vp, vp, vp, vp]
+        L.ising_batch_get_spins.argtypes = [vp, i32, vp, vp]
+        L.ising_batch_set_spins.argtypes = [vp, i32, vp, vp]
+        L.ising_batch_get_sweep.argtypes = [vp, i32, P(u64), vp]
+        L.ising_batch_set_sweep.argtypes = [vp, i32, u64, vp]
+        L.ising_batch_set_beta.argtypes = [vp, i32, ctypes.c_double, vp]
+        L.ising_batch_get_schedule.argtypes = [vp, P(ising_schedule)]
+        L.ising_batch_set_schedule.argtypes = [vp, P(ising_schedule)]
+        L.ising_batch_mode_counts.argtypes = [vp, P(i32), P(i32)]
+        L.ising_batch_destroy.argtypes = [vp]
+        for name in EXPORTED[2:]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, func):
+    if code != ISING_OK:
+        detail = lib().ising_last_error().decode() or lib().ising_strerror(code).decode()
+        raise IsingError(code, func, detail)
+
+
+def _descs(descs):
+    arr = (ising_desc * len(descs))()
+    for i, d in enumerate(descs):
+        if isinstance(d, ising_desc):
+            arr[i] = d
+        else:
+            arr[i] = ising_desc(int(d["Lx"]), int(d["Ly"]), float(d.get("J", 1.0)), float(d["beta"]),
+                                int(d["seed"]), int(d["replica"]), int(d.get("init", 0)))
+    return arr
+
+
+# ---- same names as the C ABI ------------------------------------------------
+
+def ising_strerror(code):
+    return lib().ising_strerror(int(code)).decode()
+
+
+def ising_last_error():
+    return lib().ising_last_error().decode()
+
+
+def ising_state_bytes(descs):
+    arr = _descs(descs)
+    n = ctypes.c_size_t()
+    _check(lib().ising_state_bytes(len(arr), arr, ctypes.byref(n)), "ising_state_bytes")
+    return int(n.value)
+
+
+def ising_batch_create(descs, dev_buf, nbytes, stream=None):
+    arr = _descs(descs)
+    h = ctypes.c_void_p()
+    _check(lib().ising_batch_create(len(arr), arr, dev_buf, nbytes, stream, ctypes.byref(h)),
+           "ising_batch_create")
+    return h
+
+
+def ising_batch_run(h, n_sweeps, record_every=0, dev_bond=None, dev_mag=None, stream=None):
+    _check(lib().ising_batch_run(h, int(n_sweeps), int(record_every), dev_bond, dev_mag, stream),
+           "ising_batch_run")
+
+
+def ising_batch_observables(h, host_bond, host_mag, stream=None):
+    _check(lib().ising_batch_observables(h, host_bond, host_mag, stream), "ising_batch_observables")
+
+
+def ising_batch_get_spins(h, r, host_pm1, stream=None):
+    _check(lib().ising_batch_get_spins(h, int(r), host_pm1, stream), "ising_batch_get_spins")
+
+
+def ising_batch_set_spins(h, r, host_pm1, stream=None):
+    _check(lib().ising_batch_set_spins(h, int(r), host_pm1, stream), "ising_batch_set_spins")
+
+
+def ising_batch_get_sweep(h, r, stream=None):
+    t = ctypes.c_uint64()
+    _check(lib().ising_batch_get_sweep(h, int(r), ctypes.byref(t), stream), "ising_batch_get_sweep")
+    return int(t.value)
+
+
+def ising_batch_set_sweep(h, r, t, stream=None):
+    _check(lib().ising_batch_set_sweep(h, int(r), int(t), stream), "ising_batch_set_sweep")
+
+
+def ising_batch_set_beta(h, r, beta, stream=None):
+    _check(lib().ising_batch_set_beta(h, int(r), float(beta), stream), "ising_batch_set_beta")
+
+
+def ising_batch_get_schedule(h):
+    s = ising_schedule()
+    _check(lib().ising_batch_get_schedule(h, ctypes.byref(s)), "ising_batch_get_schedule")
+    return s
+
+
+def ising_batch_set_schedule(h, sched):
+    if isinstance(sched, dict):
+        s = ising_schedule(**{k: int(v) for k, v in sched.items()})
+    else:
+        s = sched
+    _check(lib().ising_batch_set_schedule(h, ctypes.byref(s)), "ising_batch_set_schedule")
+
+
+def ising_batch_mode_counts(h):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ising_batch_mode_counts(h, ctypes.byref(a), ctypes.byref(b)), "ising_batch_mode_counts")
+    return int(a.value), int(b.value)
+
+
+def ising_batch_destroy(h):
+    _check(lib().ising_batch_destroy(h), "ising_batch_destroy")
+
+
+# ---- convenience owner -------------------------------------------------------
+
+class Batch:
+    """A batch of replicas in a torch-owned device buffer on the current device."""
+
+    def __init__(self, descs, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.descs = list(descs)
+        self.n = len(self.descs)
+        self.nbytes = ising_state_bytes(self.descs)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buf.device)
+        self.h = ising_batch_create(self.descs, self.buf.data_ptr(), self.nbytes, self._s())
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def _spins(self, r):
+        d = self.descs[r]
+        return (d["Ly"], d["Lx"]) if isinstance(d, dict) else (d.Ly, d.Lx)
+
+    def run(self, n_sweeps, record_every=0):
+        """Enqueue n_sweeps sweeps; returns device (bond, mag) traces or None."""
+        torch = self.torch
+        n_rec = n_sweeps // record_every if record_every else 0
+        if n_rec:
+            bond = torch.empty((self.n, n_rec), dtype=torch.int64, device=self.buf.device)
+            mag = torch.empty((self.n, n_rec), dtype=torch.int64, device=self.buf.device)
+            ising_batch_run(self.h, n_sweeps, record_every, bond.data_ptr(), mag.data_ptr(), self._s())
+            return bond, mag
+        ising_batch_run(self.h, n_sweeps, 0, None, None, self._s())
+        return None
+
+    def observables(self):
+        import numpy as np
+        b = np.zeros(self.n, dtype=np.int64)
+        m = np.zeros(self.n, dtype=np.int64)
+        ising_batch_observables(self.h, b.ctypes.data, m.ctypes.data, self._s())
+        return b, m
+
+    def get_spins(self, r):
+        import numpy as np
+        out = np.empty(self._spins(r), dtype=np.int8)
+        ising_batch_get_spins(self.h, r, out.ctypes.data, self._s())
+        return out
+
+    def set_spins(self, r, s):
+        import numpy as np
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        assert s.shape == self._spins(r)
+        ising_batch_set_spins(self.h, r, s.ctypes.data, self._s())
+
+    def get_sweep(self, r):
+        return ising_batch_get_sweep(self.h, r, self._s())
+
+    def set_sweep(self, r, t):
+        ising_batch_set_sweep(self.h, r, t, self._s())
+
+    def set_beta(self, r, beta):
+        ising_batch_set_beta(self.h, r, beta, self._s())
+
+    @property
+    def schedule(self):
+        return ising_batch_get_schedule(self.h).as_dict()
+
+    def set_schedule(self, **kw):
+        s = self.schedule
+        s.update(kw)
+        ising_batch_set_schedule(self.h, s)
+
+    def mode_counts(self):
+        return ising_batch_mode_counts(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ising_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

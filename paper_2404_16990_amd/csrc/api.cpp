@@ -1,0 +1,664 @@
+// Host runtime and C ABI of libising.so: argument validation, acceptance
+// thresholds, device descriptors, execution schedule, hipGraph capture of
+// sweep chunks, and the set/get calls.  Every device computation is a kernel
+// in kernels.hip; this file only marshals and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ising.h"
+#include "device.hpp"
+#include "launch.hpp"
+
+using namespace ising;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define ISING_HIP(expr)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(ISING_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr int32_t kMaxReplicas = 65535;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Metropolis acceptance thresholds (paper section 1: accept iff ran() <
+// exp(-beta dE)).  With K = beta*J rounded once, P(accept | dE = 4kJ) =
+// thr_k / 2^32 where thr_k = floor(exp(-4kK) 2^32), clamped to 2^32 - 1.
+uint32_t prob_threshold(double p)
+{
+    const double scaled = std::ldexp(p, 32);
+    if (scaled >= 4294967295.0)
+        return 0xffffffffu;
+    return static_cast<uint32_t>(std::floor(scaled));
+}
+
+void set_thresholds(RepDev &r, double J, double beta)
+{
+    const double K = beta * J;
+    r.always = K == 0.0 ? 1u : 0u;
+    r.thr4 = prob_threshold(std::exp(-4.0 * K));
+    r.thr8 = prob_threshold(std::exp(-8.0 * K));
+}
+
+int check_physics(double J, double beta)
+{
+    if (!(J > 0.0) || std::isinf(J))
+        return fail(ISING_E_INVALID, "J must be finite and > 0");
+    if (std::isnan(beta) || beta < 0.0)
+        return fail(ISING_E_INVALID, "beta must be >= 0 (or +inf)");
+    return ISING_OK;
+}
+
+int check_desc(const ising_desc &d, int32_t i)
+{
+    const std::string at = " (replica index " + std::to_string(i) + ")";
+    int st = check_physics(d.J, d.beta);
+    if (st != ISING_OK)
+        return fail(st, g_last_error + at);
+    if (d.init != ISING_INIT_RANDOM && d.init != ISING_INIT_UP && d.init != ISING_INIT_DOWN)
+        return fail(ISING_E_INVALID, "unknown init mode" + at);
+    if (d.Lx <= 0 || d.Lx % 64 != 0)
+        return fail(ISING_E_UNSUPPORTED, "Lx must be a positive multiple of 64" + at);
+    if (d.Ly < 2 || d.Ly % 2 != 0)
+        return fail(ISING_E_UNSUPPORTED, "Ly must be even and >= 2" + at);
+    if ((uint64_t)d.Lx * (uint64_t)d.Ly >= (1ull << 32))
+        return fail(ISING_E_UNSUPPORTED, "Lx*Ly must be below 2^32" + at);
+    return ISING_OK;
+}
+
+struct Layout {
+    size_t reps = 0, lists = 0, obs = 0, modes = 0;
+    std::vector<size_t> planes;
+    size_t total = 0;
+};
+
+// Device buffer: [descriptors | schedule lists | observable scratch | init modes | planes...]
+int make_layout(int32_t n, const ising_desc *d, Layout *L)
+{
+    if (n <= 0 || !d)
+        return fail(ISING_E_INVALID, "need n > 0 replicas and a descriptor array");
+    if (n > kMaxReplicas)
+        return fail(ISING_E_UNSUPPORTED, "at most 65535 replicas per batch");
+    for (int32_t i = 0; i < n; ++i) {
+        int st = check_desc(d[i], i);
+        if (st != ISING_OK)
+            return st;
+    }
+    size_t off = 0;
+    L->reps = off;
+    off += align256((size_t)n * sizeof(RepDev));
+    L->lists = off;
+    off += align256((size_t)(6 * (size_t)n + 2) * sizeof(uint32_t));
+    L->obs = off;
+    off += align256((size_t)2 * n * sizeof(int64_t));
+    L->modes = off;
+    off += align256((size_t)n * sizeof(int32_t));
+    L->planes.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        L->planes[i] = off;
+        off += align256((size_t)2 * d[i].Ly * (d[i].Lx / 64) * sizeof(uint32_t));
+    }
+    L->total = off;
+    return ISING_OK;
+}
+
+struct GraphKey {
+    uint32_t sweeps;
+    int64_t *bond, *mag;
+    uint32_t every, n_rec;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(sweeps, bond, mag, every, n_rec) < std::tie(o.sweeps, o.bond, o.mag, o.every, o.n_rec);
+    }
+};
+
+}  // namespace
+
+struct ising_batch {
+    int32_t n = 0;
+    std::vector<ising_desc> desc;
+    std::vector<RepDev> rep;  // host mirror; t advanced when work is enqueued
+    char *buf = nullptr;
+    size_t bytes = 0;
+    Layout layout;
+    RepDev *d_rep = nullptr;
+    uint32_t *d_lists = nullptr;
+    int64_t *d_obs = nullptr;
+    int device = 0;
+    int lds_max = 0;        // LDS per workgroup the device allows (bytes)
+    ising_schedule sched{};
+    // derived schedule
+    ResidentList res[2]{};  // [0] 32-bit words, [1] 64-bit words
+    StreamList str[2]{};
+    uint32_t max_words = 0;
+    hipStream_t aux = nullptr, cap = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+void drop_graphs(ising_batch *b)
+{
+    for (auto &kv : b->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+int validate_schedule(const ising_schedule &s)
+{
+    auto pow2_threads = [](int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; };
+    if (s.word_bits != 32 && s.word_bits != 64)
+        return fail(ISING_E_INVALID, "word_bits must be 32 or 64");
+    if (s.resident_max_bytes < 0)
+        return fail(ISING_E_INVALID, "resident_max_bytes must be >= 0");
+    if (!pow2_threads(s.resident_threads) || !pow2_threads(s.stream_threads))
+        return fail(ISING_E_INVALID, "thread counts must be 64, 128, 256, 512 or 1024");
+    if (s.stream_words <= 0 || s.stream_words % s.stream_threads != 0)
+        return fail(ISING_E_INVALID, "stream_words must be a positive multiple of stream_threads");
+    if (s.sweeps_per_launch < 1)
+        return fail(ISING_E_INVALID, "sweeps_per_launch must be >= 1");
+    if (s.use_graph != 0 && s.use_graph != 1)
+        return fail(ISING_E_INVALID, "use_graph must be 0 or 1");
+    return ISING_OK;
+}
+
+// Split replicas into resident / streaming and 32 / 64-bit lists; upload the
+// lists and the streaming workgroup prefixes.  Blocking.
+int apply_schedule(ising_batch *b, hipStream_t st)
+{
+    const ising_schedule &s = b->sched;
+    const int n = b->n;
+    // the dynamic-LDS limit was raised for the largest static footprint (1024 threads)
+    int lds_cap = b->lds_max - (int)resident_static_lds(1024);
+    if (s.resident_max_bytes < lds_cap)
+        lds_cap = s.resident_max_bytes;
+    std::vector<uint32_t> rl[2], sl[2], pf[2];
+    uint32_t lds_need[2] = {0, 0};
+    for (int r = 0; r < n; ++r) {
+        const RepDev &d = b->rep[r];
+        const int wide = (s.word_bits == 64 && d.W % 2 == 0) ? 1 : 0;
+        const uint64_t plane_bytes = (uint64_t)2 * d.Ly * d.W * 4;
+        if (plane_bytes <= (uint64_t)(lds_cap > 0 ? lds_cap : 0)) {
+            rl[wide].push_back((uint32_t)r);
+            if (plane_bytes > lds_need[wide])
+                lds_need[wide] = (uint32_t)plane_bytes;
+        } else {
+            sl[wide].push_back((uint32_t)r);
+        }
+    }
+    const uint32_t wpw = (uint32_t)s.stream_words;
+    for (int k = 0; k < 2; ++k) {
+        pf[k].push_back(0);
+        for (uint32_t r : sl[k]) {
+            const RepDev &d = b->rep[r];
+            const uint32_t words = d.Ly * (d.W / (k ? 2u : 1u));
+            pf[k].push_back(pf[k].back() + (words + wpw - 1) / wpw);
+        }
+    }
+    // device list area: res32[n] res64[n] str32[n] str64[n] pf32[n+1] pf64[n+1]
+    std::vector<uint32_t> area(6 * (size_t)n + 2, 0);
+    uint32_t *a_res[2] = {&area[0], &area[n]};
+    uint32_t *a_str[2] = {&area[2 * (size_t)n], &area[3 * (size_t)n]};
+    uint32_t *a_pf[2] = {&area[4 * (size_t)n], &area[5 * (size_t)n + 1]};
+    for (int k = 0; k < 2; ++k) {
+        std::copy(rl[k].begin(), rl[k].end(), a_res[k]);
+        std::copy(sl[k].begin(), sl[k].end(), a_str[k]);
+        std::copy(pf[k].begin(), pf[k].end(), a_pf[k]);
+    }
+    ISING_HIP(hipMemcpyAsync(b->d_lists, area.data(), area.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    ISING_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < 2; ++k) {
+        b->res[k].reps = b->d_rep;
+        b->res[k].list = b->d_lists + (a_res[k] - area.data());
+        b->res[k].n = (uint32_t)rl[k].size();
+        b->res[k].lds_bytes = lds_need[k];
+        b->str[k].reps = b->d_rep;
+        b->str[k].list = b->d_lists + (a_str[k] - area.data());
+        b->str[k].prefix = b->d_lists + (a_pf[k] - area.data());
+        b->str[k].n = (uint32_t)sl[k].size();
+        b->str[k].n_wg = pf[k].back();
+        b->str[k].words_per_wg = wpw;
+    }
+    drop_graphs(b);
+    return ISING_OK;
+}
+
+// One chunk of `sweeps` sweeps: resident replicas run all of them in one
+// launch (on the auxiliary stream when streaming work runs beside it);
+// streaming replicas get one launch per colour per sweep; then t += sweeps.
+int enqueue_chunk(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipStream_t st)
+{
+    const ising_schedule &s = b->sched;
+    const bool have_res = b->res[0].n + b->res[1].n > 0;
+    const bool have_str = b->str[0].n + b->str[1].n > 0;
+    const bool fork = have_res && have_str;
+    hipStream_t rs = st;
+    if (fork) {
+        ISING_HIP(hipEventRecord(b->ev_fork, st));
+        ISING_HIP(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+        rs = b->aux;
+    }
+    for (int k = 0; k < 2; ++k)
+        ISING_HIP(launch_sweep_resident(b->res[k], k ? 64 : 32, s.resident_threads, sweeps, rec, rs));
+    if (fork)
+        ISING_HIP(hipEventRecord(b->ev_join, b->aux));
+    for (uint32_t i = 0; i < sweeps && have_str; ++i)
+        for (uint32_t c = 0; c < 2; ++c)
+            for (int k = 0; k < 2; ++k)
+                ISING_HIP(launch_sweep_stream(b->str[k], k ? 64 : 32, s.stream_threads, c, i, rec, st));
+    if (fork)
+        ISING_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
+    ISING_HIP(launch_advance(b->d_rep, (uint32_t)b->n, sweeps, st));
+    return ISING_OK;
+}
+
+int get_graph(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipGraphExec_t *out)
+{
+    GraphKey key{sweeps, rec.bond, rec.mag, rec.every, rec.n_rec};
+    auto it = b->graphs.find(key);
+    if (it != b->graphs.end()) {
+        *out = it->second;
+        return ISING_OK;
+    }
+    if (b->graphs.size() >= 16)
+        drop_graphs(b);
+    ISING_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int st = enqueue_chunk(b, sweeps, rec, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != ISING_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return fail(ISING_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return fail(ISING_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    b->graphs[key] = ex;
+    *out = ex;
+    return ISING_OK;
+}
+
+int check_handle(ising_batch *b)
+{
+    if (!b)
+        return fail(ISING_E_INVALID, "null batch handle");
+    return ISING_OK;
+}
+
+int check_replica(ising_batch *b, int32_t r)
+{
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (r < 0 || r >= b->n)
+        return fail(ISING_E_INVALID, "replica index out of range");
+    return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ising_strerror(int code)
+{
+    switch (code) {
+    case ISING_OK: return "success";
+    case ISING_E_INVALID: return "invalid argument";
+    case ISING_E_UNSUPPORTED: return "unsupported lattice shape or batch size";
+    case ISING_E_NOMEM: return "out of memory or buffer too small";
+    case ISING_E_HIP: return "HIP runtime error";
+    case ISING_E_STATE: return "invalid handle state";
+    default: return "unknown status";
+    }
+}
+
+const char *ising_last_error(void) { return g_last_error.c_str(); }
+
+int ising_state_bytes(int32_t n, const ising_desc *d, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes)
+        return fail(ISING_E_INVALID, "bytes must not be NULL");
+    Layout L;
+    int st = make_layout(n, d, &L);
+    if (st != ISING_OK)
+        return st;
+    *bytes = L.total;
+    return ISING_OK;
+}
+
+int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t bytes, void *stream,
+                       ising_batch **out)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(ISING_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    Layout L;
+    int st = make_layout(n, d, &L);
+    if (st != ISING_OK)
+        return st;
+    if (!dev_buf)
+        return fail(ISING_E_INVALID, "dev_buf must not be NULL");
+    if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0)
+        return fail(ISING_E_INVALID, "dev_buf must be 256-byte aligned");
+    if (bytes < L.total)
+        return fail(ISING_E_NOMEM, "dev_buf is smaller than ising_state_bytes()");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+
+    ising_batch *b = new (std::nothrow) ising_batch();
+    if (!b)
+        return fail(ISING_E_NOMEM, "host allocation failed");
+    b->n = n;
+    b->desc.assign(d, d + n);
+    b->buf = static_cast<char *>(dev_buf);
+    b->bytes = bytes;
+    b->layout = L;
+    b->d_rep = reinterpret_cast<RepDev *>(b->buf + L.reps);
+    b->d_lists = reinterpret_cast<uint32_t *>(b->buf + L.lists);
+    b->d_obs = reinterpret_cast<int64_t *>(b->buf + L.obs);
+    b->rep.resize(n);
+    std::vector<int32_t> modes(n);
+    for (int32_t i = 0; i < n; ++i) {
+        RepDev &r = b->rep[i];
+        std::memset(&r, 0, sizeof(r));
+        r.plane0 = reinterpret_cast<uint32_t *>(b->buf + L.planes[i]);
+        r.Lx = (uint32_t)d[i].Lx;
+        r.Ly = (uint32_t)d[i].Ly;
+        r.W = (uint32_t)d[i].Lx / 64u;
+        r.seed_lo = (uint32_t)(d[i].seed & 0xffffffffu);
+        r.seed_hi = (uint32_t)(d[i].seed >> 32);
+        r.replica = d[i].replica;
+        set_thresholds(r, d[i].J, d[i].beta);
+        r.t = 0;
+        r.t0 = 0;
+        r.N = (uint64_t)d[i].Lx * (uint64_t)d[i].Ly;
+        modes[i] = d[i].init;
+        b->max_words = std::max(b->max_words, r.Ly * r.W);
+    }
+    auto cleanup = [&](int code) {
+        ising_batch_destroy(b);
+        return code;
+    };
+    hipError_t e;
+#define CREATE_HIP(expr)                                                                        \
+    do {                                                                                        \
+        e = (expr);                                                                             \
+        if (e != hipSuccess)                                                                    \
+            return cleanup(fail(ISING_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e))); \
+    } while (0)
+    CREATE_HIP(hipGetDevice(&b->device));
+    CREATE_HIP(hipDeviceGetAttribute(&b->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device));
+    CREATE_HIP(prepare_resident_kernels(b->lds_max - (int)resident_static_lds(1024)));
+    CREATE_HIP(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking));
+    CREATE_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    CREATE_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    CREATE_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    CREATE_HIP(hipMemcpyAsync(b->d_rep, b->rep.data(), (size_t)n * sizeof(RepDev), hipMemcpyHostToDevice, hs));
+    int32_t *d_modes = reinterpret_cast<int32_t *>(b->buf + L.modes);
+    CREATE_HIP(hipMemcpyAsync(d_modes, modes.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, hs));
+    CREATE_HIP(launch_init(b->d_rep, d_modes, (uint32_t)n, b->max_words, hs));
+    CREATE_HIP(hipStreamSynchronize(hs));
+#undef CREATE_HIP
+    b->sched.word_bits = 32;
+    b->sched.resident_max_bytes = b->lds_max;
+    b->sched.resident_threads = 256;
+    b->sched.stream_threads = 256;
+    b->sched.stream_words = 1024;
+    b->sched.sweeps_per_launch = 50;
+    b->sched.use_graph = 1;
+    st = apply_schedule(b, hs);
+    if (st != ISING_OK)
+        return cleanup(st);
+    *out = b;
+    return ISING_OK;
+}
+
+int ising_batch_run(ising_batch *b, uint64_t n_sweeps, uint32_t record_every, int64_t *dev_bond_trace,
+                    int64_t *dev_mag_trace, void *stream)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (n_sweeps == 0)
+        return ISING_OK;
+    for (int32_t r = 0; r < b->n; ++r)
+        if ((uint64_t)b->rep[r].t + n_sweeps > 0xffffffffull)
+            return fail(ISING_E_INVALID, "sweep counter would reach 2^32");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    RecArgs rec{nullptr, nullptr, 0u, 0u};
+    if (record_every > 0 && dev_bond_trace && dev_mag_trace && n_sweeps / record_every > 0) {
+        rec.bond = dev_bond_trace;
+        rec.mag = dev_mag_trace;
+        rec.every = record_every;
+        rec.n_rec = (uint32_t)(n_sweeps / record_every);
+        const uint64_t slots = (uint64_t)b->n * rec.n_rec;
+        ISING_HIP(launch_fill_i64(rec.bond, slots, 0, hs));
+        ISING_HIP(launch_fill_i64(rec.mag, slots, 0, hs));
+    }
+    ISING_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, hs));
+    const uint64_t S = (uint64_t)b->sched.sweeps_per_launch;
+    const uint64_t full = n_sweeps / S, rem = n_sweeps % S;
+    if (full > 0) {
+        if (b->sched.use_graph) {
+            hipGraphExec_t ex = nullptr;
+            st = get_graph(b, (uint32_t)S, rec, &ex);
+            if (st != ISING_OK)
+                return st;
+            for (uint64_t i = 0; i < full; ++i)
+                ISING_HIP(hipGraphLaunch(ex, hs));
+        } else {
+            for (uint64_t i = 0; i < full; ++i) {
+                st = enqueue_chunk(b, (uint32_t)S, rec, hs);
+                if (st != ISING_OK)
+                    return st;
+            }
+        }
+    }
+    if (rem > 0) {
+        st = enqueue_chunk(b, (uint32_t)rem, rec, hs);
+        if (st != ISING_OK)
+            return st;
+    }
+    for (int32_t r = 0; r < b->n; ++r)
+        b->rep[r].t += (uint32_t)n_sweeps;
+    return ISING_OK;
+}
+
+int ising_batch_observables(ising_batch *b, int64_t *host_bond, int64_t *host_mag, void *stream)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (!host_bond || !host_mag)
+        return fail(ISING_E_INVALID, "output arrays must not be NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ISING_HIP(launch_fill_i64(b->d_obs, 2 * (uint64_t)b->n, 0, hs));
+    ISING_HIP(launch_observables(b->d_rep, (uint32_t)b->n, b->max_words, b->d_obs, b->d_obs + b->n, hs));
+    ISING_HIP(hipMemcpyAsync(host_bond, b->d_obs, (size_t)b->n * sizeof(int64_t), hipMemcpyDeviceToHost, hs));
+    ISING_HIP(hipMemcpyAsync(host_mag, b->d_obs + b->n, (size_t)b->n * sizeof(int64_t), hipMemcpyDeviceToHost, hs));
+    ISING_HIP(hipStreamSynchronize(hs));
+    return ISING_OK;
+}
+
+int ising_batch_get_spins(ising_batch *b, int32_t r, int8_t *host_pm1, void *stream)
+{
+    g_last_error.clear();
+    int st = check_replica(b, r);
+    if (st != ISING_OK)
+        return st;
+    if (!host_pm1)
+        return fail(ISING_E_INVALID, "host_pm1 must not be NULL");
+    const RepDev &d = b->rep[r];
+    std::vector<uint32_t> planes((size_t)2 * d.Ly * d.W);
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ISING_HIP(hipMemcpyAsync(planes.data(), d.plane0, planes.size() * 4, hipMemcpyDeviceToHost, hs));
+    ISING_HIP(hipStreamSynchronize(hs));
+    for (uint32_t y = 0; y < d.Ly; ++y)
+        for (uint32_t x = 0; x < d.Lx; ++x) {
+            const uint32_t c = (x + y) & 1u, k = x >> 1;
+            const uint32_t word = planes[(size_t)c * d.Ly * d.W + (size_t)y * d.W + (k >> 5)];
+            host_pm1[(size_t)y * d.Lx + x] = ((word >> (k & 31)) & 1u) ? 1 : -1;
+        }
+    return ISING_OK;
+}
+
+int ising_batch_set_spins(ising_batch *b, int32_t r, const int8_t *host_pm1, void *stream)
+{
+    g_last_error.clear();
+    int st = check_replica(b, r);
+    if (st != ISING_OK)
+        return st;
+    if (!host_pm1)
+        return fail(ISING_E_INVALID, "host_pm1 must not be NULL");
+    const RepDev &d = b->rep[r];
+    std::vector<uint32_t> planes((size_t)2 * d.Ly * d.W, 0u);
+    for (uint32_t y = 0; y < d.Ly; ++y)
+        for (uint32_t x = 0; x < d.Lx; ++x) {
+            const int8_t v = host_pm1[(size_t)y * d.Lx + x];
+            if (v != 1 && v != -1)
+                return fail(ISING_E_INVALID, "spins must be +1 or -1");
+            if (v == 1) {
+                const uint32_t c = (x + y) & 1u, k = x >> 1;
+                planes[(size_t)c * d.Ly * d.W + (size_t)y * d.W + (k >> 5)] |= 1u << (k & 31);
+            }
+        }
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ISING_HIP(hipMemcpyAsync(d.plane0, planes.data(), planes.size() * 4, hipMemcpyHostToDevice, hs));
+    ISING_HIP(hipStreamSynchronize(hs));
+    return ISING_OK;
+}
+
+int ising_batch_get_sweep(ising_batch *b, int32_t r, uint64_t *t, void *stream)
+{
+    (void)stream;
+    g_last_error.clear();
+    int st = check_replica(b, r);
+    if (st != ISING_OK)
+        return st;
+    if (!t)
+        return fail(ISING_E_INVALID, "t must not be NULL");
+    *t = b->rep[r].t;
+    return ISING_OK;
+}
+
+int ising_batch_set_sweep(ising_batch *b, int32_t r, uint64_t t, void *stream)
+{
+    g_last_error.clear();
+    int st = check_replica(b, r);
+    if (st != ISING_OK)
+        return st;
+    if (t > 0xffffffffull)
+        return fail(ISING_E_INVALID, "sweep counter must be below 2^32");
+    b->rep[r].t = (uint32_t)t;
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    ISING_HIP(hipMemcpyAsync(&b->d_rep[r].t, &b->rep[r].t, sizeof(uint32_t), hipMemcpyHostToDevice, hs));
+    ISING_HIP(hipStreamSynchronize(hs));
+    return ISING_OK;
+}
+
+int ising_batch_set_beta(ising_batch *b, int32_t r, double beta, void *stream)
+{
+    g_last_error.clear();
+    int st = check_replica(b, r);
+    if (st != ISING_OK)
+        return st;
+    st = check_physics(b->desc[r].J, beta);
+    if (st != ISING_OK)
+        return st;
+    b->desc[r].beta = beta;
+    set_thresholds(b->rep[r], b->desc[r].J, beta);
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    // always, thr4, thr8 are contiguous in the descriptor
+    ISING_HIP(hipMemcpyAsync(&b->d_rep[r].always, &b->rep[r].always, 3 * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, hs));
+    ISING_HIP(hipStreamSynchronize(hs));
+    return ISING_OK;
+}
+
+int ising_batch_get_schedule(ising_batch *b, ising_schedule *s)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (!s)
+        return fail(ISING_E_INVALID, "s must not be NULL");
+    *s = b->sched;
+    return ISING_OK;
+}
+
+int ising_batch_set_schedule(ising_batch *b, const ising_schedule *s)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (!s)
+        return fail(ISING_E_INVALID, "s must not be NULL");
+    st = validate_schedule(*s);
+    if (st != ISING_OK)
+        return st;
+    // the schedule lists live in device memory that queued work may still read
+    ISING_HIP(hipDeviceSynchronize());
+    b->sched = *s;
+    return apply_schedule(b, nullptr);
+}
+
+int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (n_resident)
+        *n_resident = (int32_t)(b->res[0].n + b->res[1].n);
+    if (n_streamed)
+        *n_streamed = (int32_t)(b->str[0].n + b->str[1].n);
+    return ISING_OK;
+}
+
+int ising_batch_destroy(ising_batch *b)
+{
+    if (!b)
+        return ISING_OK;
+    drop_graphs(b);
+    if (b->ev_fork)
+        (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join)
+        (void)hipEventDestroy(b->ev_join);
+    if (b->aux)
+        (void)hipStreamDestroy(b->aux);
+    if (b->cap)
+        (void)hipStreamDestroy(b->cap);
+    delete b;
+    return ISING_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// Device-side building blocks shared by the sweep, init and observable kernels.
+//
+// Layout of one replica in device memory (1 bit per spin, bit 1 <=> s = +1):
+//   plane c (c = colour 0 red, 1 blue) holds Ly rows of W = Lx/64 uint32 words;
+//   bit b of word w in row y is the site with compact index k = 32 w + b of
+//   that colour in that row, i.e. column x = 2 k + ((c + y) & 1).
+//   Plane 1 follows plane 0 directly.  A 64-bit word w' is the pair of 32-bit
+//   words (2w', 2w'+1), little-endian, so 32- and 64-bit access see the same
+//   bytes.
+// This replaces the paper's eight int16 arrays with domain folding (section 2,
+// Eq. 1 and Fig. 3), which exist to keep periodic neighbours on adjacent
+// processing elements; global memory and LDS need no such adjacency.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ising {
+
+// Per-replica device descriptor (64 bytes), written by the host at create and
+// by set_* calls; t and t0 are advanced on the device by the run kernels.
+struct RepDev {
+    uint32_t *plane0;   // colour-0 plane; colour-1 plane = plane0 + Ly * W
+    uint32_t Lx, Ly, W; // W = 32-bit words per colour row = Lx / 64
+    uint32_t seed_lo, seed_hi, replica;
+    uint32_t always;    // 1 when beta*J == 0: every proposal is accepted
+    uint32_t thr4, thr8;  // acceptance thresholds for dE = 4J and 8J
+    uint32_t t;         // sweeps completed
+    uint32_t t0;        // value of t when the current run started
+    uint32_t pad;
+    uint64_t N;         // Lx * Ly
+};
+static_assert(sizeof(RepDev) == 64, "descriptor must stay 64 bytes");
+
+// Where fused observables of recorded sweeps go.
+struct RecArgs {
+    int64_t *bond;   // [n_replicas * n_rec] or null
+    int64_t *mag;
+    uint32_t every;  // 0 = no recording
+    uint32_t n_rec;
+};
+
+template <typename Word> struct WordTraits;
+template <> struct WordTraits<uint32_t> { static constexpr int BITS = 32; static constexpr int PER32 = 1; };
+template <> struct WordTraits<uint64_t> { static constexpr int BITS = 64; static constexpr int PER32 = 2; };
+
+// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------------
+// Each round: two 32x32->64-bit products (v_mad_u64_u32), the high halves
+// XORed with the other two counter words and the round key in one 3-input
+// bitwise op (v_bitop3_b32 with truth table 0x96 = a ^ b ^ c).  Key words are
+// wave-uniform and stay in scalar registers.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Everything the update of one colour of one sweep of one replica needs
+// besides the spins (all wave-uniform).
+struct SweepKey {
+    uint32_t k0, k1, t, replica, colour, thr4, thr8, always;
+};
+
+__device__ __forceinline__ SweepKey make_key(const RepDev &d, uint32_t t, uint32_t colour)
+{
+    SweepKey k;
+    k.k0 = d.seed_lo;
+    k.k1 = d.seed_hi;
+    k.t = t;
+    k.replica = d.replica;
+    k.colour = colour;
+    k.thr4 = d.thr4;
+    k.thr8 = d.thr8;
+    k.always = d.always;
+    return k;
+}
+
+// Neighbour classification and Metropolis acceptance for one word of
+// same-colour spins (the multi-spin idea of the paper's Algorithm 2,
+// flipQuarter, restated for 1-bit words):
+//   a_k = s ^ n_k marks spins anti-aligned with neighbour k;
+//   two half adders give per-bit partial sums (s1, c1), (s2, c2);
+//   >= 2 anti-aligned neighbours  <=> dE <= 0   -> flip unconditionally;
+//   exactly one                   <=> dE = 4J   -> flip iff r < thr4;
+//   none                          <=> dE = 8J   -> flip iff r < thr8.
+// q0 = Philox counter word of the word's first four sites (sites 4j..4j+3 of
+// the word use call j).  Returns the mask of spins to flip.
+template <typename Word>
+__device__ __forceinline__ Word flip_mask(Word s, Word up, Word dn, Word same, Word side,
+                                          uint32_t q0, const SweepKey &K)
+{
+    constexpr int BITS = WordTraits<Word>::BITS;
+    if (K.always)
+        return ~Word(0);
+    const Word a1 = s ^ up, a2 = s ^ dn, a3 = s ^ same, a4 = s ^ side;
+    const Word s1 = a1 ^ a2, c1 = a1 & a2;
+    const Word s2 = a3 ^ a4, c2 = a3 & a4;
+    const Word ge2 = c1 | c2 | (s1 & s2);
+    const Word eq1 = (s1 ^ s2) & ~(c1 | c2);
+    Word acc = 0;
+#pragma unroll
+    for (int q = 0; q < BITS / 4; ++q) {
+        uint32_t r[4];
+        philox4x32_10(q0 + q, K.t, K.replica, K.colour, K.k0, K.k1, r);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = 4 * q + j;
+            const uint32_t thr = ((eq1 >> b) & 1) ? K.thr4 : K.thr8;
+            acc |= Word(r[j] < thr) << b;
+        }
+    }
+    return ge2 | acc;
+}
+
+// Horizontal neighbour word of the other colour (the paper's Algorithm 1,
+// getBitAbove / getBitBelow, as a funnel shift).  For a target word in a row
+// whose colour-c sites sit at odd columns (p = 1) the second horizontal
+// neighbour of bit k is bit k + 1 of the other plane; for p = 0 it is bit k - 1.
+template <typename Word>
+__device__ __forceinline__ Word side_word(Word same, Word next, Word prev, uint32_t p)
+{
+    constexpr int BITS = WordTraits<Word>::BITS;
+    return p ? (Word)((same >> 1) | (next << (BITS - 1)))
+             : (Word)((same << 1) | (prev >> (BITS - 1)));
+}
+
+// Number of anti-aligned bonds touching the (already updated) word s.
+template <typename Word>
+__device__ __forceinline__ uint32_t anti_bonds(Word s, Word up, Word dn, Word same, Word side)
+{
+    return (uint32_t)(__popcll((uint64_t)(s ^ up)) + __popcll((uint64_t)(s ^ dn)) +
+                      __popcll((uint64_t)(s ^ same)) + __popcll((uint64_t)(s ^ side)));
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+}  // namespace ising

@@ -1,0 +1,451 @@
+// HIP kernels for gfx950: initial state, checkerboard sweeps (streaming and
+// LDS-resident), observables, and small bookkeeping kernels.
+//
+// The sweep follows the checkerboard algorithm (paper section 2 and the
+// Supplementary checkerboard multi-spin algorithm): every colour-0 site, then
+// every colour-1 site reading the updated colour 0.  One thread updates one
+// 32- or 64-bit word of same-colour spins; neighbour words come from the other
+// colour's plane (up, down, same position, and a funnel-shifted horizontal
+// word), so a colour phase reads only the other plane and its own word.
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace ising {
+
+// ---------------------------------------------------------------------------
+// initial state: one thread per 32-bit word of one plane
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init(const RepDev *__restrict__ reps,
+                                              const int32_t *__restrict__ modes)
+{
+    const uint32_t r = blockIdx.y;
+    const RepDev d = reps[r];
+    const int32_t mode = modes[r];
+    const uint32_t words = 2u * d.Ly * d.W;  // both planes
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) {
+        uint32_t v;
+        if (mode == 1) {
+            v = 0xffffffffu;
+        } else if (mode == 2) {
+            v = 0u;
+        } else {
+            const uint32_t c = i >= d.Ly * d.W ? 1u : 0u;
+            const uint32_t j = i - c * d.Ly * d.W;
+            const uint32_t y = j / d.W, w = j - y * d.W;
+            const uint32_t p = (c + y) & 1u;
+            // site b of this word: x = 64 w + 2 b + p, g = y Lx + x; the
+            // Philox call g >> 2 = (y Lx + 64 w) / 4 + b / 2 serves bits 2m, 2m+1
+            const uint32_t qbase = (y * d.Lx + 64u * w) >> 2;
+            v = 0;
+#pragma unroll 4
+            for (uint32_t m = 0; m < 16; ++m) {
+                uint32_t o[4];
+                philox4x32_10(qbase + m, 0u, d.replica, 2u, d.seed_lo, d.seed_hi, o);
+                v |= (uint32_t)(o[p] >= 0x80000000u) << (2 * m);
+                v |= (uint32_t)(o[p + 2] >= 0x80000000u) << (2 * m + 1);
+            }
+        }
+        d.plane0[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// streaming sweep: one colour of one sweep for a list of replicas; each
+// workgroup takes a contiguous run of words_per_wg words of one replica
+// ---------------------------------------------------------------------------
+template <typename Word, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_sweep_stream(const RepDev *__restrict__ reps,
+                                                          const uint32_t *__restrict__ list,
+                                                          const uint32_t *__restrict__ prefix,
+                                                          uint32_t nlist, uint32_t words_per_wg,
+                                                          uint32_t colour, uint32_t sweep_off,
+                                                          RecArgs rec)
+{
+    constexpr int PER32 = WordTraits<Word>::PER32;
+    // workgroup -> list entry: largest e with prefix[e] <= blockIdx.x
+    uint32_t lo = 0, hi = nlist;
+    const uint32_t bid = blockIdx.x;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= bid)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint32_t tile = bid - prefix[lo];
+    const uint32_t r = list[lo];
+    const RepDev d = reps[r];
+    const uint32_t Wn = d.W / PER32;
+    const uint32_t Ly = d.Ly;
+    const uint32_t total = Ly * Wn;
+    const uint32_t t = d.t + sweep_off;
+    const Word *__restrict__ src = reinterpret_cast<const Word *>(d.plane0 + (colour ^ 1u) * Ly * d.W);
+    Word *__restrict__ dst = reinterpret_cast<Word *>(d.plane0 + colour * Ly * d.W);
+    const SweepKey K = make_key(d, t, colour);
+
+    // recording decision (uniform): after the blue phase of run-local sweep i
+    const uint32_t i_run = t - d.t0;
+    const bool record = colour == 1u && rec.every != 0u && ((i_run + 1u) % rec.every) == 0u &&
+                        ((i_run + 1u) / rec.every - 1u) < rec.n_rec;
+
+    const uint32_t begin = tile * words_per_wg;
+    const uint32_t end = min(begin + words_per_wg, total);
+    uint32_t idx = begin + threadIdx.x;
+    uint32_t y = idx / Wn, w = idx - y * Wn;
+    const uint32_t dy = THREADS / Wn, dw = THREADS - dy * Wn;
+    uint32_t anti = 0, pop = 0;
+    for (; idx < end; idx += THREADS) {
+        const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
+        const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
+        const uint32_t p = (colour + y) & 1u;
+        const Word same = src[y * Wn + w];
+        const Word up = src[yu * Wn + w];
+        const Word dn = src[yd * Wn + w];
+        const uint32_t wn = p ? (w + 1 == Wn ? 0 : w + 1) : (w == 0 ? Wn - 1 : w - 1);
+        const Word nb = src[y * Wn + wn];
+        const Word side = side_word<Word>(same, nb, nb, p);
+        const Word s = dst[idx];
+        // compact index of the word's first site: y Lx/2 + BITS w; quad = that / 4
+        const uint32_t q0 = y * (d.Lx >> 3) + w * (WordTraits<Word>::BITS / 4);
+        const Word f = flip_mask<Word>(s, up, dn, same, side, q0, K);
+        const Word ns = s ^ f;
+        dst[idx] = ns;
+        if (record) {
+            anti += anti_bonds<Word>(ns, up, dn, same, side);
+            pop += (uint32_t)(__popcll((uint64_t)ns) + __popcll((uint64_t)same));
+        }
+        w += dw;
+        y += dy;
+        if (w >= Wn) {
+            w -= Wn;
+            ++y;
+        }
+    }
+    if (record) {
+        __shared__ int64_t red[2][THREADS / 64];
+        const int64_t a = wave_sum((int64_t)anti);
+        const int64_t m = wave_sum((int64_t)pop);
+        const int wid = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[0][wid] = a;
+            red[1][wid] = m;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t A = 0, Mp = 0;
+#pragma unroll
+            for (int k = 0; k < THREADS / 64; ++k) {
+                A += red[0][k];
+                Mp += red[1][k];
+            }
+            // B = 2N - 2 anti, M = 2 pop - N; the first tile adds the constants
+            int64_t db = -2 * A, dm = 2 * Mp;
+            if (tile == 0) {
+                db += 2 * (int64_t)d.N;
+                dm -= (int64_t)d.N;
+            }
+            const uint32_t slot = (i_run + 1u) / rec.every - 1u;
+            atomicAdd(reinterpret_cast<unsigned long long *>(&rec.bond[(uint64_t)r * rec.n_rec + slot]),
+                      (unsigned long long)db);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&rec.mag[(uint64_t)r * rec.n_rec + slot]),
+                      (unsigned long long)dm);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident sweeps: one workgroup owns one replica for n_sweeps sweeps
+// ---------------------------------------------------------------------------
+template <typename Word, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_sweep_resident(const RepDev *__restrict__ reps,
+                                                            const uint32_t *__restrict__ list,
+                                                            uint32_t n_sweeps, RecArgs rec)
+{
+    constexpr int PER32 = WordTraits<Word>::PER32;
+    extern __shared__ uint4 lds4[];
+    const uint32_t r = list[blockIdx.x];
+    const RepDev d = reps[r];
+    const uint32_t Ly = d.Ly;
+    const uint32_t words32 = Ly * d.W;  // per plane
+    const uint32_t Wn = d.W / PER32;
+    const uint32_t total = Ly * Wn;
+    // both planes: 2 Ly W words; Ly even => a multiple of 4 words (16 bytes)
+    const uint32_t n4 = (2u * words32) >> 2;
+    const uint4 *__restrict__ g4 = reinterpret_cast<const uint4 *>(d.plane0);
+    for (uint32_t i = threadIdx.x; i < n4; i += THREADS)
+        lds4[i] = g4[i];
+    __syncthreads();
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+
+    const uint32_t dy = THREADS / Wn, dw = THREADS - dy * Wn;
+    const uint32_t y_start = threadIdx.x / Wn, w_start = threadIdx.x - y_start * Wn;
+    __shared__ int64_t red[2][THREADS / 64];
+
+    for (uint32_t s_i = 0; s_i < n_sweeps; ++s_i) {
+        const uint32_t t = d.t + s_i;
+        const uint32_t i_run = t - d.t0;
+        const bool record = rec.every != 0u && ((i_run + 1u) % rec.every) == 0u &&
+                            ((i_run + 1u) / rec.every - 1u) < rec.n_rec;
+#pragma unroll 1
+        for (uint32_t colour = 0; colour < 2; ++colour) {
+            const Word *src = reinterpret_cast<const Word *>(lds + (colour ^ 1u) * words32);
+            Word *dst = reinterpret_cast<Word *>(lds + colour * words32);
+            const SweepKey K = make_key(d, t, colour);
+            const bool rec_here = record && colour == 1u;
+            uint32_t anti = 0, pop = 0;
+            uint32_t y = y_start, w = w_start;
+            for (uint32_t idx = threadIdx.x; idx < total; idx += THREADS) {
+                const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
+                const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
+                const uint32_t p = (colour + y) & 1u;
+                const Word same = src[y * Wn + w];
+                const Word up = src[yu * Wn + w];
+                const Word dn = src[yd * Wn + w];
+                const uint32_t wn = p ? (w + 1 == Wn ? 0 : w + 1) : (w == 0 ? Wn - 1 : w - 1);
+                const Word nb = src[y * Wn + wn];
+                const Word side = side_word<Word>(same, nb, nb, p);
+                const Word s = dst[idx];
+                const uint32_t q0 = y * (d.Lx >> 3) + w * (WordTraits<Word>::BITS / 4);
+                const Word ns = s ^ flip_mask<Word>(s, up, dn, same, side, q0, K);
+                dst[idx] = ns;
+                if (rec_here) {
+                    anti += anti_bonds<Word>(ns, up, dn, same, side);
+                    pop += (uint32_t)(__popcll((uint64_t)ns) + __popcll((uint64_t)same));
+                }
+                w += dw;
+                y += dy;
+                if (w >= Wn) {
+                    w -= Wn;
+                    ++y;
+                }
+            }
+            if (rec_here) {
+                const int64_t a = wave_sum((int64_t)anti);
+                const int64_t m = wave_sum((int64_t)pop);
+                if ((threadIdx.x & 63) == 0) {
+                    red[0][threadIdx.x >> 6] = a;
+                    red[1][threadIdx.x >> 6] = m;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int64_t A = 0, Mp = 0;
+                    for (int k = 0; k < THREADS / 64; ++k) {
+                        A += red[0][k];
+                        Mp += red[1][k];
+                    }
+                    const uint32_t slot = (i_run + 1u) / rec.every - 1u;
+                    rec.bond[(uint64_t)r * rec.n_rec + slot] = 2 * (int64_t)d.N - 2 * A;
+                    rec.mag[(uint64_t)r * rec.n_rec + slot] = 2 * Mp - (int64_t)d.N;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    uint4 *__restrict__ o4 = reinterpret_cast<uint4 *>(d.plane0);
+    for (uint32_t i = threadIdx.x; i < n4; i += THREADS)
+        o4[i] = lds4[i];
+}
+
+// ---------------------------------------------------------------------------
+// observables of the current state: grid (x: tiles, y: replica)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_observables(const RepDev *__restrict__ reps,
+                                                     int64_t *__restrict__ bond,
+                                                     int64_t *__restrict__ mag)
+{
+    const uint32_t r = blockIdx.y;
+    const RepDev d = reps[r];
+    const uint32_t W = d.W, Ly = d.Ly;
+    const uint32_t *src = d.plane0;              // colour 0
+    const uint32_t *tgt = d.plane0 + Ly * W;     // colour 1
+    uint32_t anti = 0, pop = 0;
+    for (uint32_t idx = blockIdx.x * 256 + threadIdx.x; idx < Ly * W; idx += gridDim.x * 256) {
+        const uint32_t y = idx / W, w = idx - y * W;
+        const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
+        const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
+        const uint32_t p = (1u + y) & 1u;
+        const uint32_t same = src[y * W + w];
+        const uint32_t wn = p ? (w + 1 == W ? 0 : w + 1) : (w == 0 ? W - 1 : w - 1);
+        const uint32_t side = side_word<uint32_t>(same, src[y * W + wn], src[y * W + wn], p);
+        const uint32_t s = tgt[idx];
+        anti += anti_bonds<uint32_t>(s, src[yu * W + w], src[yd * W + w], same, side);
+        pop += (uint32_t)(__popc(s) + __popc(same));
+    }
+    __shared__ int64_t red[2][4];
+    const int64_t a = wave_sum((int64_t)anti), m = wave_sum((int64_t)pop);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a;
+        red[1][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t A = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        int64_t Mp = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        int64_t db = -2 * A, dm = 2 * Mp;
+        if (blockIdx.x == 0) {
+            db += 2 * (int64_t)d.N;
+            dm -= (int64_t)d.N;
+        }
+        atomicAdd(reinterpret_cast<unsigned long long *>(&bond[r]), (unsigned long long)db);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&mag[r]), (unsigned long long)dm);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bookkeeping (graph-safe: plain kernels, no memset nodes)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i64(int64_t *__restrict__ p, uint64_t n, int64_t v)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_begin_run(RepDev *__restrict__ reps, uint32_t n)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n)
+        reps[r].t0 = reps[r].t;
+}
+
+__global__ void k_advance(RepDev *__restrict__ reps, uint32_t n, uint32_t delta)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n)
+        reps[r].t += delta;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_init(const RepDev *reps, const int32_t *modes, uint32_t n, uint32_t max_words,
+                       hipStream_t st)
+{
+    const uint32_t blocks = std::min<uint32_t>((2u * max_words + 255u) / 256u, 4096u);
+    hipLaunchKernelGGL(k_init, dim3(blocks, n), dim3(256), 0, st, reps, modes);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words, int64_t *bond,
+                              int64_t *mag, hipStream_t st)
+{
+    const uint32_t blocks = std::min<uint32_t>((max_words + 255u) / 256u, 2048u);
+    hipLaunchKernelGGL(k_observables, dim3(blocks, n), dim3(256), 0, st, reps, bond, mag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st)
+{
+    if (n == 0)
+        return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_i64, dim3((uint32_t)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_begin_run, dim3((n + 255) / 256), dim3(256), 0, st, reps, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(RepDev *reps, uint32_t n, uint32_t delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, reps, n, delta);
+    return hipGetLastError();
+}
+
+template <typename Word, int T>
+static hipError_t stream_t(const StreamList &L, uint32_t colour, uint32_t sweep_off, const RecArgs &rec,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sweep_stream<Word, T>), dim3(L.n_wg), dim3(T), 0, st, L.reps, L.list,
+                       L.prefix, L.n, L.words_per_wg, colour, sweep_off, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_stream(const StreamList &L, int word_bits, int threads, uint32_t colour,
+                               uint32_t sweep_off, const RecArgs &rec, hipStream_t st)
+{
+    if (L.n == 0)
+        return hipSuccess;
+    if (word_bits == 64) {
+        switch (threads) {
+        case 64: return stream_t<uint64_t, 64>(L, colour, sweep_off, rec, st);
+        case 128: return stream_t<uint64_t, 128>(L, colour, sweep_off, rec, st);
+        case 256: return stream_t<uint64_t, 256>(L, colour, sweep_off, rec, st);
+        case 512: return stream_t<uint64_t, 512>(L, colour, sweep_off, rec, st);
+        case 1024: return stream_t<uint64_t, 1024>(L, colour, sweep_off, rec, st);
+        }
+    } else {
+        switch (threads) {
+        case 64: return stream_t<uint32_t, 64>(L, colour, sweep_off, rec, st);
+        case 128: return stream_t<uint32_t, 128>(L, colour, sweep_off, rec, st);
+        case 256: return stream_t<uint32_t, 256>(L, colour, sweep_off, rec, st);
+        case 512: return stream_t<uint32_t, 512>(L, colour, sweep_off, rec, st);
+        case 1024: return stream_t<uint32_t, 1024>(L, colour, sweep_off, rec, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Word, int T>
+static hipError_t resident_t(const ResidentList &L, uint32_t n_sweeps, const RecArgs &rec, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sweep_resident<Word, T>), dim3(L.n), dim3(T), L.lds_bytes, st, L.reps, L.list,
+                       n_sweeps, rec);
+    return hipGetLastError();
+}
+
+template <typename Word, int T>
+static hipError_t raise_lds(int bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_resident<Word, T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t prepare_resident_kernels(int max_dynamic_lds)
+{
+    hipError_t e = hipSuccess;
+#define ISING_RAISE(W, T)                                  \
+    if (e == hipSuccess)                                   \
+        e = raise_lds<W, T>(max_dynamic_lds);
+    ISING_RAISE(uint32_t, 64) ISING_RAISE(uint32_t, 128) ISING_RAISE(uint32_t, 256)
+    ISING_RAISE(uint32_t, 512) ISING_RAISE(uint32_t, 1024) ISING_RAISE(uint64_t, 64)
+    ISING_RAISE(uint64_t, 128) ISING_RAISE(uint64_t, 256) ISING_RAISE(uint64_t, 512)
+    ISING_RAISE(uint64_t, 1024)
+#undef ISING_RAISE
+    return e;
+}
+
+uint32_t resident_static_lds(int threads)
+{
+    return 2u * (uint32_t)(threads / 64) * (uint32_t)sizeof(int64_t);
+}
+
+hipError_t launch_sweep_resident(const ResidentList &L, int word_bits, int threads, uint32_t n_sweeps,
+                                 const RecArgs &rec, hipStream_t st)
+{
+    if (L.n == 0)
+        return hipSuccess;
+    if (word_bits == 64) {
+        switch (threads) {
+        case 64: return resident_t<uint64_t, 64>(L, n_sweeps, rec, st);
+        case 128: return resident_t<uint64_t, 128>(L, n_sweeps, rec, st);
+        case 256: return resident_t<uint64_t, 256>(L, n_sweeps, rec, st);
+        case 512: return resident_t<uint64_t, 512>(L, n_sweeps, rec, st);
+        case 1024: return resident_t<uint64_t, 1024>(L, n_sweeps, rec, st);
+        }
+    } else {
+        switch (threads) {
+        case 64: return resident_t<uint32_t, 64>(L, n_sweeps, rec, st);
+        case 128: return resident_t<uint32_t, 128>(L, n_sweeps, rec, st);
+        case 256: return resident_t<uint32_t, 256>(L, n_sweeps, rec, st);
+        case 512: return resident_t<uint32_t, 512>(L, n_sweeps, rec, st);
+        case 1024: return resident_t<uint32_t, 1024>(L, n_sweeps, rec, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ising

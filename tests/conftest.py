@@ -34,3 +34,16 @@ def pytest_collection_modifyitems(config, items):
 def oracle_lib():
     import oracle
     return oracle.lib()
+
+
+@pytest.fixture(autouse=True)
+def _progress_log(request):
+    """With ISING_PROGRESS_LOG set, append each test id (flushed) before it runs,
+    so a run that dies on the GPU still names the case it was in."""
+    path = os.environ.get("ISING_PROGRESS_LOG")
+    if path:
+        import time
+        with open(path, "a") as f:
+            f.write(f"{time.strftime('%H:%M:%S')} START {request.node.nodeid}\n")
+            f.flush()
+    yield

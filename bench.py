@@ -18,17 +18,46 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published figures used for the roofline (see the design notes)
-CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
-# lane-cycles of the minimal instruction sequence for one flip attempt: a
-# quarter of a Philox4x32-10 call (5 full 32x32->64 products at quarter rate
-# = 20, 5 three-input XORs = 5) plus one threshold compare
-LANE_CYCLES_PER_FLIP = 26.0
+# MI355X published figures: 256 CUs at 2.4 GHz; the fp32 vector peak of
+# 157.3 TFLOP/s is 128 FMA lanes per CU per clock, i.e. 128 full-rate 32-bit
+# VALU lane-operations per CU per clock.
+CUS, LANE_OPS_PER_CU_CLK, CLOCK_HZ = 256, 128, 2.4e9
+# Full-rate VALU slots of the minimal instruction sequence for one flip
+# attempt: a quarter of one Philox4x32-10 call (20 v_mad_u64_u32 at 1.86 slots
+# each, measured, + 20 v_bitop3_b32 at 1 slot) plus one threshold compare and
+# one bit insert.
+SLOTS_PER_FLIP = (20 * 1.86 + 20 * 1.0) / 4 + 2.0
 HBM_BYTES_PER_S = 8.0e12
 
 
 def alu_peak_flips():
-    return CUS * LANES_PER_CU * CLOCK_HZ / LANE_CYCLES_PER_FLIP
+    return CUS * LANE_OPS_PER_CU_CLK * CLOCK_HZ / SLOTS_PER_FLIP
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_2404_16990_amd/csrc/kernels.hip", "paper_2404_16990_amd/csrc/device.hpp",
+                "paper_2404_16990_amd/csrc/launch.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload_name):
+    """HBM bytes per launch from the committed counter summary, or None when the
+    summary is for another kernel/workload or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_sweep_resident_batch256x1024.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None, None
+    if d.get("kernel_source_sha256") != kernel_source_digest():
+        return None, None
+    if not d["kernel"].startswith(kernel) or not d["workload"].startswith(workload_name):
+        return None, None
+    return d["traffic_bytes_per_launch"], d["algorithmic_bytes_per_launch"]
 
 
 def host_threads():
@@ -64,6 +93,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="JSON dict overriding the execution schedule")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-sweeps", type=int, default=20)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -82,8 +113,13 @@ def main():
     descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
              for r in work.replicas]
     batch = P.Batch(descs, stream=stream)
+    tuned = None
     if args.schedule:
         batch.set_schedule(**json.loads(args.schedule))
+    elif not args.no_autotune:
+        t0 = time.perf_counter()
+        _, n_tried = batch.autotune(trial_sweeps=args.tune_sweeps)
+        tuned = {"candidates": n_tried, "seconds": time.perf_counter() - t0}
     sched = batch.schedule
     n_res, n_str = batch.mode_counts()
     spw = args.sweeps_per_step
@@ -111,18 +147,33 @@ def main():
     flips = work.spins * spw * args.steps
     value = flips / total_s
 
-    # dominant kernel: each step is spw / sweeps_per_launch graph launches of the
-    # sweep kernel (plus a one-thread-per-replica counter kernel)
-    launches_per_step = max(1, spw // sched["sweeps_per_launch"])
-    launch_s = (total_s / args.steps) / launches_per_step
-    flips_per_launch = work.spins * min(spw, sched["sweeps_per_launch"])
+    # dominant kernel: all-resident batches launch one k_sweep_resident per
+    # sweeps_per_launch sweeps; all-streaming batches one k_sweep_stream per
+    # colour per sweep.  Launches on the stream are back to back, so the mean
+    # launch duration is the timed region over the number of launches (it
+    # includes the one-thread-per-replica counter kernel after each chunk).
+    S = sched["sweeps_per_launch"]
+    if n_str == 0:
+        kernel, launches, sweeps_per_launch = "k_sweep_resident", args.steps * -(-spw // S), min(spw, S)
+    elif n_res == 0:
+        kernel, launches, sweeps_per_launch = "k_sweep_stream", args.steps * spw * 2, 0.5
+    else:
+        kernel, launches, sweeps_per_launch = "k_sweep_resident+k_sweep_stream (concurrent)", \
+            args.steps * -(-spw // S), min(spw, S)
+    launch_s = total_s / launches
+    flips_per_launch = work.spins * sweeps_per_launch
     achieved = flips_per_launch / launch_s
     peak = alu_peak_flips()
-    kernel = "k_sweep_resident" if n_str == 0 else ("k_sweep_stream" if n_res == 0 else "mixed")
+    traffic, algo_bytes = (None, None)
+    if kernel == "k_sweep_resident" and S == 50 and sched["resident_threads"] == 1024 \
+            and sched["word_bits"] == 64:
+        traffic, algo_bytes = measured_traffic(kernel, work.name)
     roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e9, "peak": peak / 1e9,
-                "unit": "Gflip/s", "frac": achieved / peak, "traffic": None,
-                "per_unit": f"{LANE_CYCLES_PER_FLIP:g} VALU lane-cycles per flip attempt",
-                "launch_ms": launch_s * 1e3}
+                "unit": "Gflip/s", "frac": achieved / peak, "traffic": traffic,
+                "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt",
+                "launch_ms": launch_s * 1e3, "launches": launches,
+                "hbm_bytes_per_launch_algorithmic": algo_bytes,
+                "hbm_frac_of_8TBps": (traffic / launch_s / HBM_BYTES_PER_S) if traffic else None}
     # sanity: the last trace is finite and physical
     b_last = traces[-1][0][:, -1].cpu()
     assert int(b_last.abs().max()) <= 2 * max(r.spins for r in work.replicas)
@@ -143,7 +194,7 @@ def main():
         "config": {"workload": work.name, "replicas": len(work.replicas), "spins": work.spins,
                    "sweeps_per_step": spw, "record_every": rec_every, "schedule": sched,
                    "resident_replicas": n_res, "streamed_replicas": n_str,
-                   "wall_s": wall},
+                   "autotune": tuned, "wall_s": wall},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -96,8 +96,9 @@ int ising_state_bytes(int32_t n, const ising_desc *d, size_t *bytes);
 
 /*
  * Create a batch in the caller's device buffer dev_buf (bytes >= the value
- * from ising_state_bytes, 256-byte aligned) and enqueue initialisation of
- * every replica on stream.  Sweep counters start at 0.  Asynchronous.
+ * from ising_state_bytes, 256-byte aligned) and initialise every replica on
+ * stream.  Sweep counters start at 0.  Blocking: returns once the
+ * descriptors are uploaded and the initial states written.
  * On success *out holds the handle.  Errors: as ising_state_bytes, plus
  * ISING_E_NOMEM (buffer too small or host allocation failure), ISING_E_HIP.
  */
@@ -136,11 +137,15 @@ int ising_batch_observables(ising_batch *b, int64_t *host_bond, int64_t *host_ma
 int ising_batch_get_spins(ising_batch *b, int32_t r, int8_t *host_pm1, void *stream);
 int ising_batch_set_spins(ising_batch *b, int32_t r, const int8_t *host_pm1, void *stream);
 
-/* Read / set replica r's sweep counter (for checkpoint and resume). */
+/* Read / set replica r's sweep counter (for checkpoint and resume).  The
+ * counter read is the value after all work enqueued so far; set_sweep blocks
+ * until the new value is on the device. */
 int ising_batch_get_sweep(ising_batch *b, int32_t r, uint64_t *t, void *stream);
 int ising_batch_set_sweep(ising_batch *b, int32_t r, uint64_t t, void *stream);
 
-/* Change replica r's inverse temperature; thresholds are recomputed. */
+/* Change replica r's inverse temperature (same validity rules as in
+ * ising_desc); thresholds are recomputed.  Blocking; applies to sweeps
+ * enqueued afterwards. */
 int ising_batch_set_beta(ising_batch *b, int32_t r, double beta, void *stream);
 
 /*
@@ -173,6 +178,26 @@ typedef struct {
 int ising_batch_get_schedule(ising_batch *b, ising_schedule *s);
 /* Validates s (ISING_E_INVALID) and installs it; cached graphs are dropped. */
 int ising_batch_set_schedule(ising_batch *b, const ising_schedule *s);
+
+/*
+ * Choose the execution schedule by measurement (the project's autotuner) and
+ * install it.  Blocking.  The batch's planes are saved to host memory; each
+ * candidate schedule then runs trial_sweeps sweeps (>= 1) from that same saved
+ * state, timed with HIP events after one untimed warm-up pass, and its final
+ * planes must equal the first candidate's bit for bit (ISING_E_STATE
+ * otherwise: that would be a kernel bug, and the detail names the candidate).
+ * Candidates are searched one schedule field at a time (word width, resident
+ * threshold and workgroup size, streaming workgroup shape, sweeps per launch).
+ * Afterwards the saved planes and sweep counters are restored, so tuning
+ * leaves the simulation unchanged.  If the environment variable
+ * ISING_AUTOTUNE_CACHE names a file, a schedule stored there for the same
+ * device and the same multiset of lattice shapes is installed without
+ * measuring, and new results are appended to it.  *chosen (optional) receives
+ * the installed schedule; *n_tried (optional) the number of candidates timed
+ * (0 on a cache hit).
+ */
+int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *chosen,
+                         int32_t *n_tried, void *stream);
 
 /* Number of replicas in each execution mode under the current schedule. */
 int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed);

@@ -25,7 +25,7 @@ EXPORTED = [
     "ising_batch_run", "ising_batch_observables", "ising_batch_get_spins",
     "ising_batch_set_spins", "ising_batch_get_sweep", "ising_batch_set_sweep",
     "ising_batch_set_beta", "ising_batch_get_schedule", "ising_batch_set_schedule",
-    "ising_batch_mode_counts", "ising_batch_destroy",
+    "ising_batch_mode_counts", "ising_batch_autotune", "ising_batch_destroy",
 ]
 
 
@@ -80,6 +80,7 @@ def lib():
         L.ising_batch_get_schedule.argtypes = [vp, P(ising_schedule)]
         L.ising_batch_set_schedule.argtypes = [vp, P(ising_schedule)]
         L.ising_batch_mode_counts.argtypes = [vp, P(i32), P(i32)]
+        L.ising_batch_autotune.argtypes = [vp, i32, P(ising_schedule), P(i32), vp]
         L.ising_batch_destroy.argtypes = [vp]
         for name in EXPORTED[2:]:
             getattr(L, name).restype = ctypes.c_int
@@ -180,6 +181,15 @@ def ising_batch_mode_counts(h):
     return int(a.value), int(b.value)
 
 
+def ising_batch_autotune(h, trial_sweeps, stream=None):
+    """Returns (installed schedule, number of candidates timed; 0 on a cache hit)."""
+    s = ising_schedule()
+    n = ctypes.c_int32()
+    _check(lib().ising_batch_autotune(h, int(trial_sweeps), ctypes.byref(s), ctypes.byref(n), stream),
+           "ising_batch_autotune")
+    return s, int(n.value)
+
+
 def ising_batch_destroy(h):
     _check(lib().ising_batch_destroy(h), "ising_batch_destroy")
 
@@ -257,6 +267,10 @@ class Batch:
 
     def mode_counts(self):
         return ising_batch_mode_counts(self.h)
+
+    def autotune(self, trial_sweeps=10):
+        s, n = ising_batch_autotune(self.h, trial_sweeps, self._s())
+        return s.as_dict(), n
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -12,15 +12,16 @@ CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 OUT = os.path.join(OUT_DIR, "libising.so")
 SOURCES = ["kernels.hip", "api.cpp"]
+PROBE_OUT = os.path.join(OUT_DIR, "libising_probe.so")
+PROBE_SOURCES = ["probe.hip"]
 # Packed FP32 instructions stay disabled in every HIP build of this project.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
+def _compile(sources, out, verbose):
     cmd = ["hipcc", *HIP_FLAGS, "-shared", "-I", os.path.join(ROOT, "include"),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", OUT + ".tmp"]
+           *[os.path.join(CSRC, s) for s in sources], "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -30,8 +31,15 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + err)
     if err.strip() and verbose:
         print(err, file=sys.stderr)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libising.so (the sweep library) and libising_probe.so (micro-benchmarks)."""
+    os.makedirs(OUT_DIR, exist_ok=True)
+    _compile(PROBE_SOURCES, PROBE_OUT, verbose)
+    return _compile(SOURCES, OUT, verbose)
 
 
 if __name__ == "__main__":

@@ -4,8 +4,11 @@
 // in kernels.hip; this file only marshals and enqueues.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -424,9 +427,9 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
     CREATE_HIP(launch_init(b->d_rep, d_modes, (uint32_t)n, b->max_words, hs));
     CREATE_HIP(hipStreamSynchronize(hs));
 #undef CREATE_HIP
-    b->sched.word_bits = 32;
+    b->sched.word_bits = 64;
     b->sched.resident_max_bytes = b->lds_max;
-    b->sched.resident_threads = 256;
+    b->sched.resident_threads = 1024;
     b->sched.stream_threads = 256;
     b->sched.stream_words = 1024;
     b->sched.sweeps_per_launch = 50;
@@ -629,6 +632,233 @@ int ising_batch_set_schedule(ising_batch *b, const ising_schedule *s)
     ISING_HIP(hipDeviceSynchronize());
     b->sched = *s;
     return apply_schedule(b, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---- autotuner ---------------------------------------------------------------
+
+int save_planes(ising_batch *b, std::vector<char> &host, hipStream_t st)
+{
+    const size_t off = b->layout.planes[0];
+    host.resize(b->layout.total - off);
+    ISING_HIP(hipMemcpyAsync(host.data(), b->buf + off, host.size(), hipMemcpyDeviceToHost, st));
+    ISING_HIP(hipStreamSynchronize(st));
+    return ISING_OK;
+}
+
+int restore_state(ising_batch *b, const std::vector<char> &host, const std::vector<uint32_t> &t, hipStream_t st)
+{
+    const size_t off = b->layout.planes[0];
+    for (int32_t r = 0; r < b->n; ++r)
+        b->rep[r].t = t[r];
+    ISING_HIP(hipMemcpyAsync(b->buf + off, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    ISING_HIP(hipMemcpyAsync(b->d_rep, b->rep.data(), (size_t)b->n * sizeof(RepDev), hipMemcpyHostToDevice, st));
+    ISING_HIP(hipStreamSynchronize(st));
+    return ISING_OK;
+}
+
+std::string tune_key(ising_batch *b)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess)
+        arch = prop.gcnArchName;
+    std::vector<std::pair<int32_t, int32_t>> shapes;
+    for (const auto &d : b->desc)
+        shapes.emplace_back(d.Lx, d.Ly);
+    std::sort(shapes.begin(), shapes.end());
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the sorted shapes
+    for (const auto &p : shapes)
+        for (int32_t v : {p.first, p.second})
+            for (int k = 0; k < 4; ++k) {
+                h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+                h *= 1099511628211ull;
+            }
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "%s|n=%d|shapes=%016llx", arch.c_str(), b->n, (unsigned long long)h);
+    std::string key = buf;
+    for (char &c : key)
+        if (c == ' ')
+            c = '_';
+    return key;
+}
+
+bool cache_lookup(const std::string &key, ising_schedule *s)
+{
+    const char *path = std::getenv("ISING_AUTOTUNE_CACHE");
+    if (!path || !*path)
+        return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    char k[256];
+    ising_schedule c{};
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d", k, &c.word_bits, &c.resident_max_bytes,
+                       &c.resident_threads, &c.stream_threads, &c.stream_words, &c.sweeps_per_launch,
+                       &c.use_graph) == 8) {
+        if (key == k && validate_schedule(c) == ISING_OK) {
+            *s = c;  // the last entry for a key wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    g_last_error.clear();
+    return found;
+}
+
+void cache_store(const std::string &key, const ising_schedule &c)
+{
+    const char *path = std::getenv("ISING_AUTOTUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), c.word_bits, c.resident_max_bytes,
+                 c.resident_threads, c.stream_threads, c.stream_words, c.sweeps_per_launch, c.use_graph);
+    std::fclose(f);
+}
+
+std::string describe(const ising_schedule &c)
+{
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "{word_bits=%d resident_max_bytes=%d resident_threads=%d stream_threads=%d "
+                  "stream_words=%d sweeps_per_launch=%d use_graph=%d}", c.word_bits, c.resident_max_bytes,
+                  c.resident_threads, c.stream_threads, c.stream_words, c.sweeps_per_launch, c.use_graph);
+    return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *chosen, int32_t *n_tried,
+                         void *stream)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (trial_sweeps < 1)
+        return fail(ISING_E_INVALID, "trial_sweeps must be >= 1");
+    for (int32_t r = 0; r < b->n; ++r)
+        if ((uint64_t)b->rep[r].t + (uint64_t)trial_sweeps > 0xffffffffull)
+            return fail(ISING_E_INVALID, "sweep counter too close to 2^32 for tuning runs");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (n_tried)
+        *n_tried = 0;
+    const std::string key = tune_key(b);
+    ising_schedule cached{};
+    if (cache_lookup(key, &cached)) {
+        ISING_HIP(hipStreamSynchronize(hs));
+        b->sched = cached;
+        st = apply_schedule(b, hs);
+        if (st == ISING_OK && chosen)
+            *chosen = b->sched;
+        return st;
+    }
+    ISING_HIP(hipStreamSynchronize(hs));
+    std::vector<char> saved, ref, got;
+    std::vector<uint32_t> t0(b->n);
+    for (int32_t r = 0; r < b->n; ++r)
+        t0[r] = b->rep[r].t;
+    st = save_planes(b, saved, hs);
+    if (st != ISING_OK)
+        return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ISING_HIP(hipEventCreate(&e0));
+    ISING_HIP(hipEventCreate(&e1));
+    const ising_schedule start = b->sched;
+    int tried = 0;
+    // time one candidate: warm-up pass, restore, timed pass, compare planes
+    auto trial = [&](const ising_schedule &c, float *ms) -> int {
+        b->sched = c;
+        int s2 = apply_schedule(b, hs);
+        if (s2 != ISING_OK)
+            return s2;
+        s2 = ising_batch_run(b, (uint64_t)trial_sweeps, 0, nullptr, nullptr, hs);
+        if (s2 != ISING_OK)
+            return s2;
+        s2 = restore_state(b, saved, t0, hs);
+        if (s2 != ISING_OK)
+            return s2;
+        ISING_HIP(hipEventRecord(e0, hs));
+        s2 = ising_batch_run(b, (uint64_t)trial_sweeps, 0, nullptr, nullptr, hs);
+        if (s2 != ISING_OK)
+            return s2;
+        ISING_HIP(hipEventRecord(e1, hs));
+        ISING_HIP(hipEventSynchronize(e1));
+        ISING_HIP(hipEventElapsedTime(ms, e0, e1));
+        s2 = save_planes(b, ref.empty() ? ref : got, hs);
+        if (s2 != ISING_OK)
+            return s2;
+        if (!got.empty() && got != ref)
+            return fail(ISING_E_STATE, "autotune: schedule " + describe(c) +
+                                           " gave planes different from schedule " + describe(start));
+        ++tried;
+        return restore_state(b, saved, t0, hs);
+    };
+    float best_ms = 0.0f;
+    ising_schedule best = start;
+    st = trial(best, &best_ms);
+    const int lds = b->lds_max;
+    std::vector<std::vector<ising_schedule>> dims;
+    auto vary = [&](auto setter, std::initializer_list<int> values) {
+        std::vector<ising_schedule> v;
+        for (int x : values) {
+            ising_schedule c = best;
+            setter(c, x);
+            v.push_back(c);
+        }
+        return v;
+    };
+    const int n_dims = 6;
+    for (int dim = 0; dim < n_dims && st == ISING_OK; ++dim) {
+        std::vector<ising_schedule> cands;
+        switch (dim) {
+        case 0: cands = vary([](ising_schedule &c, int x) { c.word_bits = x; }, {32, 64}); break;
+        case 1: cands = vary([](ising_schedule &c, int x) { c.resident_max_bytes = x; }, {0, lds / 4, lds}); break;
+        case 2: cands = vary([](ising_schedule &c, int x) { c.resident_threads = x; }, {256, 512, 1024}); break;
+        case 3: cands = vary([](ising_schedule &c, int x) { c.stream_threads = x; c.stream_words = x; }, {256, 512, 1024}); break;
+        case 4: cands = vary([](ising_schedule &c, int x) { c.stream_words = c.stream_threads * x; }, {1, 2, 4, 8}); break;
+        case 5: cands = vary([](ising_schedule &c, int x) { c.sweeps_per_launch = x; }, {10, 25, 50, 100}); break;
+        }
+        for (const auto &c : cands) {
+            if (std::memcmp(&c, &best, sizeof c) == 0)
+                continue;
+            float ms = 0.0f;
+            st = trial(c, &ms);
+            if (st != ISING_OK)
+                break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ISING_OK) {
+        const std::string why = g_last_error;
+        b->sched = start;
+        (void)apply_schedule(b, hs);
+        (void)restore_state(b, saved, t0, hs);
+        return fail(st, why);
+    }
+    b->sched = best;
+    st = apply_schedule(b, hs);
+    if (st != ISING_OK)
+        return st;
+    cache_store(key, best);
+    if (chosen)
+        *chosen = best;
+    if (n_tried)
+        *n_tried = tried;
+    return ISING_OK;
 }
 
 int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed)

@@ -96,7 +96,7 @@ __device__ __forceinline__ SweepKey make_key(const RepDev &d, uint32_t t, uint32
     return k;
 }
 
-// Neighbour classification and Metropolis acceptance for one word of
+// Neighbour classification and Metropolis acceptance for one 32-bit word of
 // same-colour spins (the multi-spin idea of the paper's Algorithm 2,
 // flipQuarter, restated for 1-bit words):
 //   a_k = s ^ n_k marks spins anti-aligned with neighbour k;
@@ -105,29 +105,25 @@ __device__ __forceinline__ SweepKey make_key(const RepDev &d, uint32_t t, uint32
 //   exactly one                   <=> dE = 4J   -> flip iff r < thr4;
 //   none                          <=> dE = 8J   -> flip iff r < thr8.
 // q0 = Philox counter word of the word's first four sites (sites 4j..4j+3 of
-// the word use call j).  Returns the mask of spins to flip.
-template <typename Word>
-__device__ __forceinline__ Word flip_mask(Word s, Word up, Word dn, Word same, Word side,
-                                          uint32_t q0, const SweepKey &K)
+// the word use call q0 + j).  Returns the mask of spins to flip.
+__device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_t dn, uint32_t same,
+                                                uint32_t side, uint32_t q0, const SweepKey &K)
 {
-    constexpr int BITS = WordTraits<Word>::BITS;
-    if (K.always)
-        return ~Word(0);
-    const Word a1 = s ^ up, a2 = s ^ dn, a3 = s ^ same, a4 = s ^ side;
-    const Word s1 = a1 ^ a2, c1 = a1 & a2;
-    const Word s2 = a3 ^ a4, c2 = a3 & a4;
-    const Word ge2 = c1 | c2 | (s1 & s2);
-    const Word eq1 = (s1 ^ s2) & ~(c1 | c2);
-    Word acc = 0;
+    const uint32_t a1 = s ^ up, a2 = s ^ dn, a3 = s ^ same, a4 = s ^ side;
+    const uint32_t s1 = a1 ^ a2, c1 = a1 & a2;
+    const uint32_t s2 = a3 ^ a4, c2 = a3 & a4;
+    const uint32_t ge2 = c1 | c2 | (s1 & s2);
+    const uint32_t eq1 = (s1 ^ s2) & ~(c1 | c2);
+    uint32_t acc = 0;
 #pragma unroll
-    for (int q = 0; q < BITS / 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
         uint32_t r[4];
         philox4x32_10(q0 + q, K.t, K.replica, K.colour, K.k0, K.k1, r);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int b = 4 * q + j;
-            const uint32_t thr = ((eq1 >> b) & 1) ? K.thr4 : K.thr8;
-            acc |= Word(r[j] < thr) << b;
+            const uint32_t thr = ((eq1 >> b) & 1u) ? K.thr4 : K.thr8;
+            acc |= (uint32_t)(r[j] < thr) << b;
         }
     }
     return ge2 | acc;
@@ -136,13 +132,34 @@ __device__ __forceinline__ Word flip_mask(Word s, Word up, Word dn, Word same, W
 // Horizontal neighbour word of the other colour (the paper's Algorithm 1,
 // getBitAbove / getBitBelow, as a funnel shift).  For a target word in a row
 // whose colour-c sites sit at odd columns (p = 1) the second horizontal
-// neighbour of bit k is bit k + 1 of the other plane; for p = 0 it is bit k - 1.
+// neighbour of bit k is bit k + 1 of the other plane, taken from the next word
+// nb at the top; for p = 0 it is bit k - 1, taken from the previous word nb.
 template <typename Word>
-__device__ __forceinline__ Word side_word(Word same, Word next, Word prev, uint32_t p)
+__device__ __forceinline__ Word side_word(Word same, Word nb, uint32_t p)
 {
     constexpr int BITS = WordTraits<Word>::BITS;
-    return p ? (Word)((same >> 1) | (next << (BITS - 1)))
-             : (Word)((same << 1) | (prev >> (BITS - 1)));
+    const Word from_next = (same >> 1) | (nb << (BITS - 1));
+    const Word from_prev = (same << 1) | (nb >> (BITS - 1));
+    return p ? from_next : from_prev;
+}
+
+// Update of one Word (32 or 64 spins) given its neighbour words; a 64-bit
+// word is two independent 32-bit halves (sites 0..31 and 32..63).
+template <typename Word>
+__device__ __forceinline__ Word update_word(Word s, Word up, Word dn, Word same, Word side, uint32_t q0,
+                                            const SweepKey &K)
+{
+    if (K.always)
+        return ~s;
+    if constexpr (WordTraits<Word>::BITS == 32) {
+        return s ^ flip_mask32(s, up, dn, same, side, q0, K);
+    } else {
+        const uint32_t lo = flip_mask32((uint32_t)s, (uint32_t)up, (uint32_t)dn, (uint32_t)same,
+                                        (uint32_t)side, q0, K);
+        const uint32_t hi = flip_mask32((uint32_t)(s >> 32), (uint32_t)(up >> 32), (uint32_t)(dn >> 32),
+                                        (uint32_t)(same >> 32), (uint32_t)(side >> 32), q0 + 8, K);
+        return s ^ (((uint64_t)hi << 32) | lo);
+    }
 }
 
 // Number of anti-aligned bonds touching the (already updated) word s.
@@ -151,6 +168,27 @@ __device__ __forceinline__ uint32_t anti_bonds(Word s, Word up, Word dn, Word sa
 {
     return (uint32_t)(__popcll((uint64_t)(s ^ up)) + __popcll((uint64_t)(s ^ dn)) +
                       __popcll((uint64_t)(s ^ same)) + __popcll((uint64_t)(s ^ side)));
+}
+
+// Indices of the neighbour words of word (y, w) in a plane of Ly rows x Wn
+// words, periodic in both directions, without branches.
+struct NeighIdx {
+    uint32_t same, up, dn, nb, p;
+};
+
+__device__ __forceinline__ NeighIdx neigh_idx(uint32_t y, uint32_t w, uint32_t Ly, uint32_t Wn, uint32_t colour)
+{
+    NeighIdx n;
+    const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
+    const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
+    const uint32_t wp = w + 1 == Wn ? 0 : w + 1;
+    const uint32_t wm = w == 0 ? Wn - 1 : w - 1;
+    n.p = (colour + y) & 1u;
+    n.same = y * Wn + w;
+    n.up = yu * Wn + w;
+    n.dn = yd * Wn + w;
+    n.nb = y * Wn + (n.p ? wp : wm);
+    return n;
 }
 
 __device__ __forceinline__ int64_t wave_sum(int64_t v)

@@ -95,20 +95,16 @@ __global__ __launch_bounds__(THREADS) void k_sweep_stream(const RepDev *__restri
     const uint32_t dy = THREADS / Wn, dw = THREADS - dy * Wn;
     uint32_t anti = 0, pop = 0;
     for (; idx < end; idx += THREADS) {
-        const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
-        const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
-        const uint32_t p = (colour + y) & 1u;
-        const Word same = src[y * Wn + w];
-        const Word up = src[yu * Wn + w];
-        const Word dn = src[yd * Wn + w];
-        const uint32_t wn = p ? (w + 1 == Wn ? 0 : w + 1) : (w == 0 ? Wn - 1 : w - 1);
-        const Word nb = src[y * Wn + wn];
-        const Word side = side_word<Word>(same, nb, nb, p);
+        const NeighIdx n = neigh_idx(y, w, Ly, Wn, colour);
+        const Word same = src[n.same];
+        const Word up = src[n.up];
+        const Word dn = src[n.dn];
+        const Word nb = src[n.nb];
         const Word s = dst[idx];
+        const Word side = side_word<Word>(same, nb, n.p);
         // compact index of the word's first site: y Lx/2 + BITS w; quad = that / 4
         const uint32_t q0 = y * (d.Lx >> 3) + w * (WordTraits<Word>::BITS / 4);
-        const Word f = flip_mask<Word>(s, up, dn, same, side, q0, K);
-        const Word ns = s ^ f;
+        const Word ns = update_word<Word>(s, up, dn, same, side, q0, K);
         dst[idx] = ns;
         if (record) {
             anti += anti_bonds<Word>(ns, up, dn, same, side);
@@ -195,18 +191,15 @@ __global__ __launch_bounds__(THREADS) void k_sweep_resident(const RepDev *__rest
             uint32_t anti = 0, pop = 0;
             uint32_t y = y_start, w = w_start;
             for (uint32_t idx = threadIdx.x; idx < total; idx += THREADS) {
-                const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
-                const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
-                const uint32_t p = (colour + y) & 1u;
-                const Word same = src[y * Wn + w];
-                const Word up = src[yu * Wn + w];
-                const Word dn = src[yd * Wn + w];
-                const uint32_t wn = p ? (w + 1 == Wn ? 0 : w + 1) : (w == 0 ? Wn - 1 : w - 1);
-                const Word nb = src[y * Wn + wn];
-                const Word side = side_word<Word>(same, nb, nb, p);
+                const NeighIdx n = neigh_idx(y, w, Ly, Wn, colour);
+                const Word same = src[n.same];
+                const Word up = src[n.up];
+                const Word dn = src[n.dn];
+                const Word nb = src[n.nb];
                 const Word s = dst[idx];
+                const Word side = side_word<Word>(same, nb, n.p);
                 const uint32_t q0 = y * (d.Lx >> 3) + w * (WordTraits<Word>::BITS / 4);
-                const Word ns = s ^ flip_mask<Word>(s, up, dn, same, side, q0, K);
+                const Word ns = update_word<Word>(s, up, dn, same, side, q0, K);
                 dst[idx] = ns;
                 if (rec_here) {
                     anti += anti_bonds<Word>(ns, up, dn, same, side);
@@ -261,14 +254,11 @@ __global__ __launch_bounds__(256) void k_observables(const RepDev *__restrict__ 
     uint32_t anti = 0, pop = 0;
     for (uint32_t idx = blockIdx.x * 256 + threadIdx.x; idx < Ly * W; idx += gridDim.x * 256) {
         const uint32_t y = idx / W, w = idx - y * W;
-        const uint32_t yu = y == 0 ? Ly - 1 : y - 1;
-        const uint32_t yd = y + 1 == Ly ? 0 : y + 1;
-        const uint32_t p = (1u + y) & 1u;
-        const uint32_t same = src[y * W + w];
-        const uint32_t wn = p ? (w + 1 == W ? 0 : w + 1) : (w == 0 ? W - 1 : w - 1);
-        const uint32_t side = side_word<uint32_t>(same, src[y * W + wn], src[y * W + wn], p);
+        const NeighIdx n = neigh_idx(y, w, Ly, W, 1u);
+        const uint32_t same = src[n.same];
+        const uint32_t side = side_word<uint32_t>(same, src[n.nb], n.p);
         const uint32_t s = tgt[idx];
-        anti += anti_bonds<uint32_t>(s, src[yu * W + w], src[yd * W + w], same, side);
+        anti += anti_bonds<uint32_t>(s, src[n.up], src[n.dn], same, side);
         pop += (uint32_t)(__popc(s) + __popc(same));
     }
     __shared__ int64_t red[2][4];

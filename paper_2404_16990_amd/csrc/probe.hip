@@ -1,0 +1,243 @@
+// Micro-benchmarks that measure the issue cost of the instructions the sweep
+// is built from, and a plain copy kernel of known size used to calibrate HBM
+// traffic counters.  Built into libising_probe.so (not part of the sweep
+// library); the roofline of the sweep kernel is derived from these costs.
+//
+// Each probe thread runs 8 independent dependency chains of one instruction
+// so that issue rate, not latency, bounds it.  Only ALU instructions appear in
+// the inline assembly; the chains' results are stored with ordinary stores.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kChains = 8;
+
+enum Which { MAD_U64_U32 = 0, MUL_HI_U32 = 1, MUL_LO_U32 = 2, BITOP3 = 3, XOR = 4, ADD = 5, PHILOX = 6 };
+
+template <int W>
+__global__ __launch_bounds__(256) void k_alu(uint32_t *out, uint32_t seed, int iters)
+{
+    uint32_t a[kChains], b[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+        a[c] = seed ^ (threadIdx.x * 0x9E3779B9u + c);
+        b[c] = seed + blockIdx.x * 77u + c;
+    }
+    const uint32_t m = 0xD2511F53u ^ seed;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) {
+            if constexpr (W == MAD_U64_U32) {
+                uint64_t acc = ((uint64_t)b[c] << 32) | a[c];
+                asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(acc) : "v"(a[c]), "v"(m) : "vcc");
+                a[c] = (uint32_t)acc;
+                b[c] = (uint32_t)(acc >> 32);
+            } else if constexpr (W == MUL_HI_U32) {
+                asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a[c]) : "v"(m));
+            } else if constexpr (W == MUL_LO_U32) {
+                asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[c]) : "v"(m));
+            } else if constexpr (W == BITOP3) {
+                asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a[c]) : "v"(b[c]), "v"(m));
+            } else if constexpr (W == XOR) {
+                asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[c]) : "v"(b[c]));
+            } else if constexpr (W == ADD) {
+                asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[c]) : "v"(b[c]));
+            }
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+        r ^= a[c] ^ b[c];
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+// Philox4x32-10 throughput: calls per second (each thread: 4 independent calls per iteration)
+__global__ __launch_bounds__(256) void k_philox(uint32_t *out, uint32_t seed, int iters)
+{
+    uint32_t acc = 0;
+    const uint32_t base = blockIdx.x * 256u + threadIdx.x;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t x0 = base * 4u + c, x1 = (uint32_t)i, x2 = 7u, x3 = 0u;
+            uint32_t k0 = seed, k1 = seed * 3u;
+#pragma unroll
+            for (int rnd = 0; rnd < 10; ++rnd) {
+                const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+                const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+                const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x1, k0, 0x96);
+                const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x3, k1, 0x96);
+                x1 = (uint32_t)p1;
+                x3 = (uint32_t)p0;
+                x0 = n0;
+                x2 = n2;
+                k0 += 0x9E3779B9u;
+                k1 += 0xBB67AE85u;
+            }
+            acc += x0 ^ x1 ^ x2 ^ x3;
+        }
+    }
+    out[base] = acc;
+}
+
+// Shader-clock and real-time stamps around a chain of v_xor_b32 (lane 0 of each
+// wave records both), to measure the shader clock and the per-SIMD issue rate.
+__global__ __launch_bounds__(256) void k_clock(uint64_t *stamps, uint32_t *out, int iters)
+{
+    uint32_t a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+        a[c] = threadIdx.x * 3u + c;
+    const uint32_t b = blockIdx.x ^ 0x5bd1e995u;
+    const uint64_t c0 = clock64();
+    const uint64_t w0 = wall_clock64();
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c)
+            asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[c]) : "v"(b));
+    }
+    const uint64_t c1 = clock64();
+    const uint64_t w1 = wall_clock64();
+    uint32_t r = 0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+        r ^= a[c];
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+    if ((threadIdx.x & 63) == 0) {
+        const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+        stamps[4 * wave + 0] = c1 - c0;
+        stamps[4 * wave + 1] = w1 - w0;
+        stamps[4 * wave + 2] = c0;
+        stamps[4 * wave + 3] = w0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16)
+{
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+template <int W>
+hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_alu<W>, dim3(blocks), dim3(256), 0, st, out, 12345u, iters);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+/*
+ * Time one probe on the null stream.  which: 0 v_mad_u64_u32, 1 v_mul_hi_u32,
+ * 2 v_mul_lo_u32, 3 v_bitop3_b32, 4 v_xor_b32, 5 v_add_u32, 6 full Philox4x32-10.
+ * out: device buffer of blocks*256 uint32.  Returns 0 and the elapsed
+ * milliseconds of the timed launch (after one warm-up launch), <0 on error.
+ * Operations counted: blocks*256*iters*8 instructions (which 0..5) or
+ * blocks*256*iters*4 Philox calls (which 6).
+ */
+int ising_probe_alu(int which, void *out, int blocks, int iters, float *ms)
+{
+    if (!out || blocks <= 0 || iters <= 0 || !ms)
+        return -1;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return -4;
+    uint32_t *o = static_cast<uint32_t *>(out);
+    hipError_t err = hipSuccess;
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+        if (rep == 1)
+            err = hipEventRecord(e0, nullptr);
+        if (err != hipSuccess)
+            break;
+        switch (which) {
+        case MAD_U64_U32: err = run_alu<MAD_U64_U32>(o, blocks, iters, nullptr); break;
+        case MUL_HI_U32: err = run_alu<MUL_HI_U32>(o, blocks, iters, nullptr); break;
+        case MUL_LO_U32: err = run_alu<MUL_LO_U32>(o, blocks, iters, nullptr); break;
+        case BITOP3: err = run_alu<BITOP3>(o, blocks, iters, nullptr); break;
+        case XOR: err = run_alu<XOR>(o, blocks, iters, nullptr); break;
+        case ADD: err = run_alu<ADD>(o, blocks, iters, nullptr); break;
+        case PHILOX:
+            hipLaunchKernelGGL(k_philox, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters);
+            err = hipGetLastError();
+            break;
+        default: err = hipErrorInvalidValue;
+        }
+    }
+    if (err == hipSuccess)
+        err = hipEventRecord(e1, nullptr);
+    if (err == hipSuccess)
+        err = hipEventSynchronize(e1);
+    if (err == hipSuccess)
+        err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err == hipSuccess ? 0 : -4;
+}
+
+/*
+ * Clock probe: blocks*4 waves each run iters*8 dependent-free v_xor_b32; for
+ * every wave, stamps[4w..4w+3] = {shader cycles, wall ticks, start cycle,
+ * start wall tick} (wall ticks from the constant-rate real-time counter).
+ * stamps: device buffer of blocks*4*4 uint64; out: blocks*256 uint32.
+ * *ms: event-timed duration of the launch; *wall_khz: the real-time
+ * counter's rate reported by the runtime.
+ */
+int ising_probe_clock(void *stamps, void *out, int blocks, int iters, float *ms, int *wall_khz)
+{
+    if (!stamps || !out || blocks <= 0 || iters <= 0 || !ms || !wall_khz)
+        return -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return -4;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return -4;
+    hipError_t err = hipEventRecord(e0, nullptr);
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(k_clock, dim3(blocks), dim3(256), 0, nullptr, static_cast<uint64_t *>(stamps),
+                           static_cast<uint32_t *>(out), iters);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess)
+        err = hipEventRecord(e1, nullptr);
+    if (err == hipSuccess)
+        err = hipEventSynchronize(e1);
+    if (err == hipSuccess)
+        err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err == hipSuccess ? 0 : -4;
+}
+
+/* Copy bytes (a multiple of 16) from src to dst `reps` times; elapsed ms of all reps. */
+int ising_probe_copy(void *dst, const void *src, size_t bytes, int reps, float *ms)
+{
+    if (!dst || !src || bytes % 16 != 0 || reps <= 0 || !ms)
+        return -1;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return -4;
+    const size_t n16 = bytes / 16;
+    hipError_t err = hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, nullptr, static_cast<uint4 *>(dst),
+                           static_cast<const uint4 *>(src), n16);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess)
+        err = hipEventRecord(e1, nullptr);
+    if (err == hipSuccess)
+        err = hipEventSynchronize(e1);
+    if (err == hipSuccess)
+        err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err == hipSuccess ? 0 : -4;
+}
+
+}  // extern "C"

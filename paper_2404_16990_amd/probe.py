@@ -1,0 +1,116 @@
+"""Measured issue costs of the sweep's instructions and HBM copy bandwidth.
+
+Runs the probes in libising_probe.so (built beside libising.so).  The ALU
+ceiling of the sweep is 256 CUs x 64 lanes x clock divided by the lane-cycles
+one flip attempt needs; the lane-cycle cost of each instruction is measured
+here relative to a full-rate 32-bit XOR.  Usage: ``python -m paper_2404_16990_amd.probe``.
+"""
+import ctypes
+import json
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libising_probe.so")
+NAMES = ["v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_bitop3_b32", "v_xor_b32", "v_add_u32",
+         "philox4x32_10"]
+CUS, LANES = 256, 64
+
+
+def _lib():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} missing: run python -m paper_2404_16990_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    L.ising_probe_alu.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_float)]
+    L.ising_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_float)]
+    return L
+
+
+def measure(blocks=256 * 16, iters=4096):
+    import torch
+    L = _lib()
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    res = {}
+    for which, name in enumerate(NAMES):
+        ms = ctypes.c_float()
+        st = L.ising_probe_alu(which, out.data_ptr(), blocks, iters, ctypes.byref(ms))
+        if st != 0:
+            raise RuntimeError(f"probe {name} failed ({st})")
+        per_thread = iters * (4 if name == "philox4x32_10" else 8)
+        res[name] = blocks * 256 * per_thread / (ms.value * 1e-3)
+    xor = res["v_xor_b32"]
+    lane_clock = xor / (CUS * LANES)  # full-rate ops per lane per second = effective clock
+    costs = {k: xor / v for k, v in res.items() if k != "philox4x32_10"}
+    return {"ops_per_s": res, "lane_cycles": costs, "effective_clock_hz": lane_clock,
+            "philox_calls_per_s": res["philox4x32_10"],
+            "philox_lane_cycles_per_call": xor / res["philox4x32_10"]}
+
+
+def clock(blocks_per_cu=(1, 2, 4, 8), iters=20000):
+    """Shader clock and per-CU issue rate of full-rate VALU ops.
+
+    Every wave runs iters*8 independent v_xor_b32 between two shader-clock
+    stamps and two real-time stamps.  Cycles per instruction per wave at a
+    given occupancy give the issue rate: lane-ops per CU per cycle =
+    64 * (waves per CU) / (cycles per instruction).  The shader clock is
+    cycles over real time, with the real-time rate both as reported by the
+    runtime and as calibrated against the launch's event time.
+    """
+    import numpy as np
+    import torch
+    L = _lib()
+    L.ising_probe_clock.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int)]
+    res = {}
+    for bpc in blocks_per_cu:
+        blocks = CUS * bpc
+        stamps = torch.zeros(blocks * 4 * 4, dtype=torch.int64, device="cuda")
+        out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+        ms, khz = ctypes.c_float(), ctypes.c_int()
+        if L.ising_probe_clock(stamps.data_ptr(), out.data_ptr(), blocks, iters, ctypes.byref(ms),
+                               ctypes.byref(khz)) != 0:
+            raise RuntimeError("clock probe failed")
+        st = stamps.view(-1, 4).cpu().numpy().astype(np.float64)
+        cyc, wall, w0 = st[:, 0], st[:, 1], st[:, 3]
+        span_ticks = (w0 + wall).max() - w0.min()
+        calibrated_hz = span_ticks / (ms.value * 1e-3)  # real-time ticks per second (upper bound on span)
+        cpi = np.median(cyc) / (iters * 8)
+        waves_per_cu = 4 * bpc
+        xor_rate = blocks * 256 * iters * 8 / (ms.value * 1e-3)
+        res[f"{waves_per_cu}_waves_per_cu"] = {
+            "event_ms": ms.value, "wall_clock_khz_reported": khz.value,
+            "wall_ticks_per_s_calibrated": float(calibrated_hz),
+            "shader_clock_hz_reported_rate": float(np.median(cyc / (wall / (khz.value * 1e3)))),
+            "shader_clock_hz_calibrated_rate": float(np.median(cyc / (wall / calibrated_hz))),
+            "cycles_per_instr_per_wave": float(cpi),
+            "lane_ops_per_cu_per_cycle": 64.0 * waves_per_cu / cpi,
+            "xor_lane_ops_per_s": xor_rate}
+    return res
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    import torch
+    L = _lib()
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ms = ctypes.c_float()
+    st = L.ising_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, 1, ctypes.byref(ms))
+    st |= L.ising_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, reps, ctypes.byref(ms))
+    if st != 0:
+        raise RuntimeError("copy probe failed")
+    return 2 * nbytes * reps / (ms.value * 1e-3)
+
+
+if __name__ == "__main__":
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "copy":
+        # calibration run for hardware traffic counters: each k_copy dispatch
+        # reads and writes exactly 256 MiB
+        bw = copy_bandwidth(nbytes=256 << 20, reps=3)
+        print(json.dumps({"copy_dispatch_bytes_each_way": 256 << 20, "copy_bytes_per_s": bw}))
+    else:
+        r = measure()
+        r["clock"] = clock()
+        r["copy_bytes_per_s"] = copy_bandwidth()
+        print(json.dumps(r, indent=1))

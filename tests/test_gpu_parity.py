@@ -261,3 +261,72 @@ def test_batch_256x1024_all_replicas_20_sweeps():
     states, ob, om = oracle_run(w.replicas, 20, 10)
     assert np.array_equal(gb, ob) and np.array_equal(gm, om)
     assert_states(b, w.replicas, states, which=range(0, 256, 17))
+
+
+# ---- autotuner: state untouched, self-checked candidates, cache ---------------------
+
+def test_autotune_leaves_state_and_keeps_parity(tmp_path, monkeypatch):
+    monkeypatch.setenv("ISING_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    reps = _random_reps(21, 6) + [workloads.Replica(1024, 64, 2.3, 9, 99)]
+    b = gpu_batch(reps)
+    gpu_run(b, 3)
+    before = [b.get_spins(i) for i in range(len(reps))]
+    sched, n_tried = b.autotune(trial_sweeps=4)
+    assert n_tried >= 6
+    assert [b.get_sweep(i) for i in range(len(reps))] == [3] * len(reps)
+    for i, s in enumerate(before):
+        assert np.array_equal(b.get_spins(i), s)
+    assert b.schedule == sched
+    gb, gm = gpu_run(b, 9, 3)
+    states, ob, om = oracle_run(reps, 12, 1)
+    assert np.array_equal(gb, ob[:, 5::3]) and np.array_equal(gm, om[:, 5::3])
+    assert_states(b, reps, states)
+    # same shapes again: served from the cache file without timing
+    b2 = gpu_batch(reps)
+    sched2, n2 = b2.autotune(trial_sweeps=4)
+    assert n2 == 0 and sched2 == sched
+
+
+# ---- full-size uneven and paper-scale batches, sampled replicas -----------------------
+
+def _sample_by_size(reps, per_size=1):
+    seen = {}
+    for i, r in enumerate(reps):
+        seen.setdefault((r.Lx, r.Ly), [])
+        if len(seen[(r.Lx, r.Ly)]) < per_size:
+            seen[(r.Lx, r.Ly)].append(i)
+    return sorted(i for v in seen.values() for i in v)
+
+
+def test_uneven_512_sampled():
+    w = workloads.uneven_512()
+    b = gpu_batch(w.replicas)
+    n_res, n_str = b.mode_counts()
+    assert n_res > 0 and n_str > 0  # both execution modes run side by side
+    gb, gm = gpu_run(b, 4, 2)
+    idx = _sample_by_size(w.replicas)
+    sub = [w.replicas[i] for i in idx]
+    states, ob, om = oracle_run(sub, 4, 2)
+    assert np.array_equal(gb[idx], ob) and np.array_equal(gm[idx], om)
+    for k, i in enumerate(idx):
+        assert np.array_equal(b.get_spins(i), states[k]), (i, w.replicas[i].Lx)
+
+
+def test_paper_scale_sampled():
+    w = workloads.paper_scale()
+    b = gpu_batch(w.replicas)
+    gb, gm = gpu_run(b, 2, 1)
+    big = len(w.replicas) - 1
+    small = list(range(0, big, 63))
+    idx = small + [big]
+    sub = [w.replicas[i] for i in idx]
+    states, ob, om = oracle_run(sub, 2, 1)
+    assert np.array_equal(gb[idx], ob) and np.array_equal(gm[idx], om)
+    assert np.array_equal(b.get_spins(big), states[-1])
+    # 18 more sweeps: the small replicas against the oracle continued from its states
+    gb, gm = gpu_run(b, 18, 18)
+    ssub = sub[:-1]
+    sb, sm = oracle.run_batch([odesc(r) for r in ssub], states[:-1], 18, t0=2, record_every=18)
+    assert np.array_equal(gb[small], sb) and np.array_equal(gm[small], sm)
+    for k, i in enumerate(small):
+        assert np.array_equal(b.get_spins(i), states[k])

@@ -202,6 +202,91 @@ int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *c
 /* Number of replicas in each execution mode under the current schedule. */
 int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed);
 
+/* ==========================================================================
+ * Learned block proposals.
+ *
+ * A small autoregressive network proposes a joint update of one Bs x Bs
+ * block (Bs = 2, 4 or 8) given the block's 4*Bs boundary spins and the
+ * coupling K = beta*J, one site at a time in raster order (k = i*Bs + j):
+ * four masked 3x3 convolution layers of 64 channels (the first sees only
+ * earlier sites, the others also the current position of the previous layer),
+ * tanh activations, per-site boundary features and K as inputs, and a 1x1
+ * logit head; layers 2..4 run on BF16 matrix cores with FP32 accumulation.
+ * Site k is proposed +1 with probability thr_k / 2^32,
+ * thr_k = clamp(floor(sigmoid(logit_k) 2^32), 1, 2^32 - 1), using the uniform
+ * word (s & 3) of Philox(ctr = {s >> 2, round, replica, 3}), s = blk*Bs*Bs + k,
+ * so log q of a block is an exact sum of logs of thresholds (FP64).  A
+ * proposal is accepted with the Metropolis-Hastings probability
+ * min(1, pi(s') q(s) / (pi(s) q(s'))), pi ~ exp(K * bond sum), using the 53-bit
+ * uniform ((w0 << 21) | (w1 >> 11)) 2^-53 of Philox(ctr = {blk, round, replica, 4});
+ * q(s) of the current block is scored by the same kernel code that samples,
+ * so the stationary distribution stays the Boltzmann distribution of the
+ * paper's section 1 whatever the network has learned.
+ *
+ * Flat float parameter vector (C = 64 channels): W1[4][C] (spin taps
+ * (-1,-1), (-1,0), (-1,1), (0,-1)), U1[4][C] (boundary up, down, left, right),
+ * v1[C] (K), b1[C], then for layers 2..4 W[5][C][C] (the four taps and the
+ * centre; index [tap][in][out]) and b[C], then wo[C], bo[1].
+ * Block data layout: spins int8 [n][Bs*Bs] row-major; boundary int8
+ * [n][4*Bs] = top row, bottom row, left column, right column (values +-1);
+ * coupling float [n].
+ * ========================================================================== */
+typedef struct ising_nn ising_nn;
+
+/* Number of floats in the parameter vector for `channels` channels (64 only). */
+int ising_nn_param_count(int32_t channels, int32_t *count);
+
+/* Device bytes for a network with training batches of up to max_batch blocks
+ * and incremental passes of up to max_seq sequences per launch. */
+int ising_nn_state_bytes(int32_t block, int32_t channels, int32_t max_batch, int32_t max_seq, size_t *bytes);
+
+/* Create a network in the caller's device buffer (256-byte aligned) from host
+ * parameters (param_count floats).  Adam moments start at zero.  Blocking. */
+int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t max_seq,
+                    const float *host_params, void *dev_buf, size_t bytes, void *stream, ising_nn **out);
+int ising_nn_get_params(ising_nn *m, float *host_params, void *stream);  /* blocking */
+int ising_nn_set_params(ising_nn *m, const float *host_params, void *stream);  /* blocking; resets Adam */
+
+/* Teacher-forced forward and backward on `batch` blocks (device arrays):
+ * per-site logits (float [batch*Bs*Bs], may be NULL), the gradient of the
+ * mean per-site negative log-likelihood (float [param_count], may be NULL)
+ * and the loss (float [1]).  Asynchronous. */
+int ising_nn_forward_backward(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                              const float *dev_coupling, int32_t batch, float *dev_logits, float *dev_grad,
+                              float *dev_loss, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on `batch` blocks; the loss
+ * before the step goes to dev_loss.  Asynchronous. */
+int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd, const float *dev_coupling,
+                        int32_t batch, float lr, float *dev_loss, void *stream);
+
+/* Incremental pass on n <= max_seq sequences.  score: log q (FP64) of the
+ * given blocks.  sample: draw blocks with the Philox stream of (seed,
+ * replica, round) and block ids blk0 + i, returning them and their log q.
+ * Asynchronous. */
+int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                   const float *dev_coupling, double *dev_logq, void *stream);
+int ising_nn_sample(ising_nn *m, int32_t n, const int8_t *dev_bnd, const float *dev_coupling, uint64_t seed,
+                    uint32_t replica, uint32_t round, uint32_t blk0, int8_t *dev_blocks_out, double *dev_logq,
+                    void *stream);
+
+/* Training data from a batch (all replicas the same shape, Lx and Ly
+ * multiples of 2*Bs): per_replica blocks of each replica at positions drawn
+ * from Philox(ctr = {i, draw, replica, 5}) (bx = w0 mod Lx/Bs,
+ * by = w1 mod Ly/Bs); writes [n*per_replica] blocks, boundaries and K.
+ * Asynchronous. */
+int ising_batch_extract_blocks(ising_batch *b, int32_t block, int32_t per_replica, uint32_t draw,
+                               int8_t *dev_blocks, int8_t *dev_bnd, float *dev_coupling, void *stream);
+
+/* One block round of every replica: all blocks with (bx + by) even, then all
+ * with (bx + by) odd, each proposed by the network and accepted by
+ * Metropolis-Hastings.  dev_accepts (int64 [n], may be NULL) accumulates
+ * accepted blocks per replica.  The batch's replicas must share one shape with
+ * Lx and Ly multiples of 2*Bs.  Asynchronous. */
+int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t *dev_accepts, void *stream);
+
+int ising_nn_destroy(ising_nn *m);
+
 /* Free host metadata and cached graphs.  Waits for no device work; the caller
  * must not free dev_buf while work on it is still queued. */
 int ising_batch_destroy(ising_batch *b);

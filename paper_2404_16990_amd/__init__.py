@@ -26,6 +26,9 @@ EXPORTED = [
     "ising_batch_set_spins", "ising_batch_get_sweep", "ising_batch_set_sweep",
     "ising_batch_set_beta", "ising_batch_get_schedule", "ising_batch_set_schedule",
     "ising_batch_mode_counts", "ising_batch_autotune", "ising_batch_destroy",
+    "ising_nn_param_count", "ising_nn_state_bytes", "ising_nn_create", "ising_nn_get_params",
+    "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_score",
+    "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_destroy",
 ]
 
 
@@ -82,6 +85,19 @@ def lib():
         L.ising_batch_mode_counts.argtypes = [vp, P(i32), P(i32)]
         L.ising_batch_autotune.argtypes = [vp, i32, P(ising_schedule), P(i32), vp]
         L.ising_batch_destroy.argtypes = [vp]
+        f32 = ctypes.c_float
+        L.ising_nn_param_count.argtypes = [i32, P(i32)]
+        L.ising_nn_state_bytes.argtypes = [i32, i32, i32, i32, P(ctypes.c_size_t)]
+        L.ising_nn_create.argtypes = [i32, i32, i32, i32, vp, vp, ctypes.c_size_t, vp, P(vp)]
+        L.ising_nn_get_params.argtypes = [vp, vp, vp]
+        L.ising_nn_set_params.argtypes = [vp, vp, vp]
+        L.ising_nn_forward_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.ising_nn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, vp, vp]
+        L.ising_nn_score.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.ising_nn_sample.argtypes = [vp, i32, vp, vp, u64, u32, u32, u32, vp, vp, vp]
+        L.ising_batch_extract_blocks.argtypes = [vp, i32, i32, u32, vp, vp, vp, vp]
+        L.ising_batch_block_round.argtypes = [vp, vp, u32, vp, vp]
+        L.ising_nn_destroy.argtypes = [vp]
         for name in EXPORTED[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -194,6 +210,66 @@ def ising_batch_destroy(h):
     _check(lib().ising_batch_destroy(h), "ising_batch_destroy")
 
 
+def ising_nn_param_count(channels=64):
+    n = ctypes.c_int32()
+    _check(lib().ising_nn_param_count(int(channels), ctypes.byref(n)), "ising_nn_param_count")
+    return int(n.value)
+
+
+def ising_nn_state_bytes(block, channels, max_batch, max_seq):
+    n = ctypes.c_size_t()
+    _check(lib().ising_nn_state_bytes(int(block), int(channels), int(max_batch), int(max_seq), ctypes.byref(n)),
+           "ising_nn_state_bytes")
+    return int(n.value)
+
+
+def ising_nn_create(block, channels, max_batch, max_seq, host_params, dev_buf, nbytes, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().ising_nn_create(int(block), int(channels), int(max_batch), int(max_seq), host_params, dev_buf,
+                                 nbytes, stream, ctypes.byref(h)), "ising_nn_create")
+    return h
+
+
+def ising_nn_get_params(m, host_params, stream=None):
+    _check(lib().ising_nn_get_params(m, host_params, stream), "ising_nn_get_params")
+
+
+def ising_nn_set_params(m, host_params, stream=None):
+    _check(lib().ising_nn_set_params(m, host_params, stream), "ising_nn_set_params")
+
+
+def ising_nn_forward_backward(m, blocks, bnd, coupling, batch, logits, grad, loss, stream=None):
+    _check(lib().ising_nn_forward_backward(m, blocks, bnd, coupling, int(batch), logits, grad, loss, stream),
+           "ising_nn_forward_backward")
+
+
+def ising_nn_train_step(m, blocks, bnd, coupling, batch, lr, loss, stream=None):
+    _check(lib().ising_nn_train_step(m, blocks, bnd, coupling, int(batch), float(lr), loss, stream),
+           "ising_nn_train_step")
+
+
+def ising_nn_score(m, n, blocks, bnd, coupling, logq, stream=None):
+    _check(lib().ising_nn_score(m, int(n), blocks, bnd, coupling, logq, stream), "ising_nn_score")
+
+
+def ising_nn_sample(m, n, bnd, coupling, seed, replica, round_, blk0, blocks_out, logq, stream=None):
+    _check(lib().ising_nn_sample(m, int(n), bnd, coupling, int(seed), int(replica), int(round_), int(blk0),
+                                 blocks_out, logq, stream), "ising_nn_sample")
+
+
+def ising_batch_extract_blocks(b, block, per_replica, draw, blocks, bnd, coupling, stream=None):
+    _check(lib().ising_batch_extract_blocks(b, int(block), int(per_replica), int(draw), blocks, bnd, coupling,
+                                            stream), "ising_batch_extract_blocks")
+
+
+def ising_batch_block_round(b, m, round_, accepts=None, stream=None):
+    _check(lib().ising_batch_block_round(b, m, int(round_), accepts, stream), "ising_batch_block_round")
+
+
+def ising_nn_destroy(m):
+    _check(lib().ising_nn_destroy(m), "ising_nn_destroy")
+
+
 # ---- convenience owner -------------------------------------------------------
 
 class Batch:
@@ -282,3 +358,99 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """A block-proposal network in a torch-owned device buffer (see include/ising.h)."""
+
+    def __init__(self, params, block=8, max_batch=512, max_seq=65536, stream=None, device="cuda"):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.block = int(block)
+        self.max_batch, self.max_seq = int(max_batch), int(max_seq)
+        self.n_params = ising_nn_param_count(64)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (self.n_params,)
+        self.nbytes = ising_nn_state_bytes(self.block, 64, self.max_batch, self.max_seq)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buf.device)
+        self.h = ising_nn_create(self.block, 64, self.max_batch, self.max_seq, p.ctypes.data, self.buf.data_ptr(),
+                                 self.nbytes, self._s())
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    @property
+    def params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        ising_nn_get_params(self.h, out.ctypes.data, self._s())
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        ising_nn_set_params(self.h, p.ctypes.data, self._s())
+
+    def forward_backward(self, blocks, bnd, coupling):
+        """Device tensors in; returns (logits [n, Bs*Bs], grad [n_params], loss) as device tensors."""
+        torch = self.torch
+        n = blocks.shape[0]
+        logits = torch.empty((n, self.block * self.block), dtype=torch.float32, device=blocks.device)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=blocks.device)
+        loss = torch.empty(1, dtype=torch.float32, device=blocks.device)
+        ising_nn_forward_backward(self.h, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(), n,
+                                  logits.data_ptr(), grad.data_ptr(), loss.data_ptr(), self._s())
+        return logits, grad, loss
+
+    def train_step(self, blocks, bnd, coupling, lr, loss=None):
+        ising_nn_train_step(self.h, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(), blocks.shape[0],
+                            lr, loss.data_ptr() if loss is not None else None, self._s())
+
+    def score(self, blocks, bnd, coupling):
+        torch = self.torch
+        n = blocks.shape[0]
+        logq = torch.empty(n, dtype=torch.float64, device=blocks.device)
+        ising_nn_score(self.h, n, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(), logq.data_ptr(),
+                       self._s())
+        return logq
+
+    def sample(self, bnd, coupling, seed, replica, round_, blk0=0):
+        torch = self.torch
+        n = bnd.shape[0]
+        out = torch.empty((n, self.block * self.block), dtype=torch.int8, device=bnd.device)
+        logq = torch.empty(n, dtype=torch.float64, device=bnd.device)
+        ising_nn_sample(self.h, n, bnd.data_ptr(), coupling.data_ptr(), seed, replica, round_, blk0,
+                        out.data_ptr(), logq.data_ptr(), self._s())
+        return out, logq
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ising_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _batch_block_round(self, net, round_, accepts=None):
+    ising_batch_block_round(self.h, net.h, round_, accepts.data_ptr() if accepts is not None else None, self._s())
+
+
+def _batch_extract(self, block, per_replica, draw):
+    torch = self.torch
+    n = self.n * per_replica
+    blocks = torch.empty((n, block * block), dtype=torch.int8, device=self.buf.device)
+    bnd = torch.empty((n, 4 * block), dtype=torch.int8, device=self.buf.device)
+    coup = torch.empty(n, dtype=torch.float32, device=self.buf.device)
+    ising_batch_extract_blocks(self.h, block, per_replica, draw, blocks.data_ptr(), bnd.data_ptr(),
+                               coup.data_ptr(), self._s())
+    return blocks, bnd, coup
+
+
+Batch.block_round = _batch_block_round
+Batch.extract_blocks = _batch_extract

@@ -16,20 +16,25 @@
 #include <vector>
 
 #include "../../include/ising.h"
+#include "batch.hpp"
 #include "device.hpp"
 #include "launch.hpp"
 
 using namespace ising;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int code, const std::string &msg)
+int ising::fail(int code, const std::string &msg)
 {
     g_last_error = msg;
     return code;
 }
+
+void ising::clear_error() { g_last_error.clear(); }
+
+namespace {
 
 #define ISING_HIP(expr)                                                                         \
     do {                                                                                        \
@@ -87,12 +92,6 @@ int check_desc(const ising_desc &d, int32_t i)
     return ISING_OK;
 }
 
-struct Layout {
-    size_t reps = 0, lists = 0, obs = 0, modes = 0;
-    std::vector<size_t> planes;
-    size_t total = 0;
-};
-
 // Device buffer: [descriptors | schedule lists | observable scratch | init modes | planes...]
 int make_layout(int32_t n, const ising_desc *d, Layout *L)
 {
@@ -114,6 +113,8 @@ int make_layout(int32_t n, const ising_desc *d, Layout *L)
     off += align256((size_t)2 * n * sizeof(int64_t));
     L->modes = off;
     off += align256((size_t)n * sizeof(int32_t));
+    L->kcoup = off;
+    off += align256((size_t)n * sizeof(double));
     L->planes.resize(n);
     for (int32_t i = 0; i < n; ++i) {
         L->planes[i] = off;
@@ -123,39 +124,7 @@ int make_layout(int32_t n, const ising_desc *d, Layout *L)
     return ISING_OK;
 }
 
-struct GraphKey {
-    uint32_t sweeps;
-    int64_t *bond, *mag;
-    uint32_t every, n_rec;
-    bool operator<(const GraphKey &o) const
-    {
-        return std::tie(sweeps, bond, mag, every, n_rec) < std::tie(o.sweeps, o.bond, o.mag, o.every, o.n_rec);
-    }
-};
-
 }  // namespace
-
-struct ising_batch {
-    int32_t n = 0;
-    std::vector<ising_desc> desc;
-    std::vector<RepDev> rep;  // host mirror; t advanced when work is enqueued
-    char *buf = nullptr;
-    size_t bytes = 0;
-    Layout layout;
-    RepDev *d_rep = nullptr;
-    uint32_t *d_lists = nullptr;
-    int64_t *d_obs = nullptr;
-    int device = 0;
-    int lds_max = 0;        // LDS per workgroup the device allows (bytes)
-    ising_schedule sched{};
-    // derived schedule
-    ResidentList res[2]{};  // [0] 32-bit words, [1] 64-bit words
-    StreamList str[2]{};
-    uint32_t max_words = 0;
-    hipStream_t aux = nullptr, cap = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    std::map<GraphKey, hipGraphExec_t> graphs;
-};
 
 namespace {
 
@@ -384,8 +353,10 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
     b->d_rep = reinterpret_cast<RepDev *>(b->buf + L.reps);
     b->d_lists = reinterpret_cast<uint32_t *>(b->buf + L.lists);
     b->d_obs = reinterpret_cast<int64_t *>(b->buf + L.obs);
+    b->d_kcoup = reinterpret_cast<double *>(b->buf + L.kcoup);
     b->rep.resize(n);
     std::vector<int32_t> modes(n);
+    std::vector<double> kc(n);
     for (int32_t i = 0; i < n; ++i) {
         RepDev &r = b->rep[i];
         std::memset(&r, 0, sizeof(r));
@@ -401,6 +372,7 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
         r.t0 = 0;
         r.N = (uint64_t)d[i].Lx * (uint64_t)d[i].Ly;
         modes[i] = d[i].init;
+        kc[i] = d[i].beta * d[i].J;
         b->max_words = std::max(b->max_words, r.Ly * r.W);
     }
     auto cleanup = [&](int code) {
@@ -422,6 +394,7 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
     CREATE_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     CREATE_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     CREATE_HIP(hipMemcpyAsync(b->d_rep, b->rep.data(), (size_t)n * sizeof(RepDev), hipMemcpyHostToDevice, hs));
+    CREATE_HIP(hipMemcpyAsync(b->d_kcoup, kc.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, hs));
     int32_t *d_modes = reinterpret_cast<int32_t *>(b->buf + L.modes);
     CREATE_HIP(hipMemcpyAsync(d_modes, modes.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, hs));
     CREATE_HIP(launch_init(b->d_rep, d_modes, (uint32_t)n, b->max_words, hs));
@@ -601,6 +574,8 @@ int ising_batch_set_beta(ising_batch *b, int32_t r, double beta, void *stream)
     // always, thr4, thr8 are contiguous in the descriptor
     ISING_HIP(hipMemcpyAsync(&b->d_rep[r].always, &b->rep[r].always, 3 * sizeof(uint32_t),
                              hipMemcpyHostToDevice, hs));
+    const double kc = beta * b->desc[r].J;
+    ISING_HIP(hipMemcpyAsync(&b->d_kcoup[r], &kc, sizeof(double), hipMemcpyHostToDevice, hs));
     ISING_HIP(hipStreamSynchronize(hs));
     return ISING_OK;
 }

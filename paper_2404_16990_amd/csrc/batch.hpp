@@ -1,0 +1,64 @@
+// Internal definition of a replica batch, shared by the sweep runtime
+// (api.cpp) and the block-proposal runtime (nn_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ising.h"
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace ising {
+
+struct Layout {
+    size_t reps = 0, lists = 0, obs = 0, modes = 0, kcoup = 0;
+    std::vector<size_t> planes;
+    size_t total = 0;
+};
+
+struct GraphKey {
+    uint32_t sweeps;
+    int64_t *bond, *mag;
+    uint32_t every, n_rec;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(sweeps, bond, mag, every, n_rec) < std::tie(o.sweeps, o.bond, o.mag, o.every, o.n_rec);
+    }
+};
+
+
+// Record a failure for ising_last_error() and return its code.
+int fail(int code, const std::string &msg);
+// Clear the calling thread's error detail (at the start of every ABI call).
+void clear_error();
+
+}  // namespace ising
+
+struct ising_batch {
+    int32_t n = 0;
+    std::vector<ising_desc> desc;
+    std::vector<ising::RepDev> rep;  // host mirror; t advanced when work is enqueued
+    char *buf = nullptr;
+    size_t bytes = 0;
+    ising::Layout layout;
+    ising::RepDev *d_rep = nullptr;
+    double *d_kcoup = nullptr;  // K = beta*J per replica (device)
+    uint32_t *d_lists = nullptr;
+    int64_t *d_obs = nullptr;
+    int device = 0;
+    int lds_max = 0;        // LDS per workgroup the device allows (bytes)
+    ising_schedule sched{};
+    // derived schedule
+    ising::ResidentList res[2]{};  // [0] 32-bit words, [1] 64-bit words
+    ising::StreamList str[2]{};
+    uint32_t max_words = 0;
+    hipStream_t aux = nullptr, cap = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::map<ising::GraphKey, hipGraphExec_t> graphs;
+};
+

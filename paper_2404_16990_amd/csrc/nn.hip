@@ -1,0 +1,826 @@
+// HIP kernels of the block-proposal network (definitions in nn.hpp):
+//  - training: masked-conv forward with an MFMA BF16 GEMM (FP32 accumulate),
+//    loss, backward (data and weight gradients as GEMMs), Adam;
+//  - the incremental autoregressive pass that scores a given block or samples
+//    a new one site by site with exactly the same arithmetic, accumulating
+//    log q in FP64 from uint32 thresholds;
+//  - gathering blocks from packed lattices, the Metropolis-Hastings decision
+//    and write-back, and training-block extraction.
+#include <math.h>
+
+#include "device.hpp"
+#include "nn.hpp"
+#include "nn_launch.hpp"
+
+namespace ising {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (inputs are finite)
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ bf16x8 zero_bf16x8()
+{
+    const uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// ---------------------------------------------------------------------------
+// parameters -> BF16 GEMM operands
+// ---------------------------------------------------------------------------
+__global__ void k_cast_weights(const float *__restrict__ params, uint16_t *__restrict__ wt,
+                               uint16_t *__restrict__ wtt)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over 3 * C * KB
+    if (idx >= 3 * C * KB)
+        return;
+    const int l = idx / (C * KB), r = idx - l * C * KB;
+    const int c = r / KB, k = r - c * KB;          // output channel, K index t*C + c'
+    const float w = params[off_w(l + 2) + k * C + c];  // W_l[t][c'][c]
+    const uint16_t b = f2bf(w);
+    wt[(l * C + c) * KB + k] = b;
+    wtt[(l * KB + k) * C + c] = b;
+}
+
+// ---------------------------------------------------------------------------
+// generic C[M][N] = sum_k A[m][k] * Bt[n][k]   (BF16 in, FP32 out)
+// 256 threads, 64x64 tile, each wave a 32x32 quarter of 2x2 MFMA 16x16x32.
+// Requires K % 32 == 0 and 16-byte aligned rows (lda, ldb multiples of 8).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
+                                                 const uint16_t *__restrict__ Bt, int ldb,
+                                                 float *__restrict__ Cm, int ldc, int M, int N, int K)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < K; k += 32) {
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int row = m0 + a * 16 + r;
+            av[a] = row < M ? load_bf16x8(A + (size_t)row * lda + k + kq) : zero_bf16x8();
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = n0 + b * 16 + r;
+            bv[b] = col < N ? load_bf16x8(Bt + (size_t)col * ldb + k + kq) : zero_bf16x8();
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + a * 16 + 4 * (lane >> 4) + i;
+                const int col = n0 + b * 16 + r;
+                if (row < M && col < N)
+                    Cm[(size_t)row * ldc + col] = acc[a][b][i];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// training forward
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float boundary_field(const int8_t *bnd, int Bs, int i, int j, const float *u)
+{
+    float f = 0.f;
+    if (i == 0)
+        f += (float)bnd[j] * u[0];
+    if (i == Bs - 1)
+        f += (float)bnd[Bs + j] * u[1];
+    if (j == 0)
+        f += (float)bnd[2 * Bs + i] * u[2];
+    if (j == Bs - 1)
+        f += (float)bnd[3 * Bs + i] * u[3];
+    return f;
+}
+
+__global__ void k_layer1(const float *__restrict__ params, const int8_t *__restrict__ x,
+                         const int8_t *__restrict__ bnd, const float *__restrict__ kc, int nblk, int Bs,
+                         int Ppad, float *__restrict__ h, uint16_t *__restrict__ hb)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ppad * C)
+        return;
+    const int p = idx / C, c = idx - p * C;
+    const int BB = Bs * Bs;
+    float v = 0.f;
+    if (p < nblk * BB) {
+        const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
+        float pre = kc[n] * params[OFF_V1 + c] + params[OFF_B1 + c];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ii = i + tap_di(t), jj = j + tap_dj(t);
+            if (ii >= 0 && jj >= 0 && jj < Bs)
+                pre += (float)x[n * BB + ii * Bs + jj] * params[OFF_W1 + t * C + c];
+        }
+        const float u[4] = {params[OFF_U1 + c], params[OFF_U1 + C + c], params[OFF_U1 + 2 * C + c],
+                            params[OFF_U1 + 3 * C + c]};
+        pre += boundary_field(bnd + n * 4 * Bs, Bs, i, j, u);
+        v = tanhf(pre);
+    }
+    h[idx] = v;
+    hb[idx] = f2bf(v);
+}
+
+// xcol[p][t*C + c'] = hb[p + tap t][c'] inside the block, else 0; also transposed
+__global__ void k_im2col(const uint16_t *__restrict__ hb, int nblk, int Bs, int Ppad,
+                         uint16_t *__restrict__ xcol, uint16_t *__restrict__ xcolt)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over Ppad * 5 * (C / 8)
+    if (idx >= Ppad * 5 * (C / 8))
+        return;
+    const int p = idx / (5 * (C / 8));
+    const int r = idx - p * 5 * (C / 8);
+    const int t = r / (C / 8), c8 = (r - t * (C / 8)) * 8;
+    const int BB = Bs * Bs;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (p < nblk * BB) {
+        const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
+        const int ii = i + tap_di(t), jj = j + tap_dj(t);
+        if (ii >= 0 && jj >= 0 && jj < Bs)
+            v = *reinterpret_cast<const uint4 *>(hb + (size_t)(n * BB + ii * Bs + jj) * C + c8);
+    }
+    *reinterpret_cast<uint4 *>(xcol + (size_t)p * KB + t * C + c8) = v;
+    const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        xcolt[(size_t)(t * C + c8 + q) * Ppad + p] = e[q];
+}
+
+__global__ void k_bias_tanh(const float *__restrict__ pre, const float *__restrict__ bias, int Pvalid,
+                            int Ppad, float *__restrict__ h, uint16_t *__restrict__ hb)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ppad * C)
+        return;
+    const int p = idx / C, c = idx - p * C;
+    const float v = p < Pvalid ? tanhf(pre[idx] + bias[c]) : 0.f;
+    h[idx] = v;
+    if (hb)
+        hb[idx] = f2bf(v);
+}
+
+__global__ void k_head(const float *__restrict__ h4, const float *__restrict__ params, int Pvalid,
+                       float *__restrict__ logits)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Pvalid)
+        return;
+    float s = params[OFF_BO];
+    for (int c = 0; c < C; ++c)
+        s = fmaf(h4[(size_t)p * C + c], params[OFF_WO + c], s);
+    logits[p] = s;
+}
+
+// per-position loss softplus(-x l) into partial sums; dlogit = -x sigmoid(-x l) / P
+__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ logits, const int8_t *__restrict__ x,
+                                              int Pvalid, int Ppad, float *__restrict__ dlogit,
+                                              float *__restrict__ partial)
+{
+    __shared__ float red[256];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    float l = 0.f;
+    if (p < Ppad) {
+        float d = 0.f;
+        if (p < Pvalid) {
+            const float xv = (float)x[p];
+            const float z = -xv * logits[p];
+            l = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+            d = -xv / (1.f + expf(-z)) / (float)Pvalid;  // -x sigmoid(z)
+        }
+        dlogit[p] = d;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum(const float *__restrict__ partial, int n, float scale,
+                                             float *__restrict__ out)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256)
+        s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k)
+            red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[0] = red[0] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// training backward
+// ---------------------------------------------------------------------------
+// dpre4 = dlogit * wo * (1 - h4^2), in fp32, bf16 and transposed bf16
+__global__ void k_dpre_head(const float *__restrict__ h4, const float *__restrict__ dlogit,
+                            const float *__restrict__ params, int Ppad, float *__restrict__ dpre,
+                            uint16_t *__restrict__ dpreb, uint16_t *__restrict__ dpret)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ppad * C)
+        return;
+    const int p = idx / C, c = idx - p * C;
+    const float hv = h4[idx];
+    const float d = dlogit[p] * params[OFF_WO + c] * (1.f - hv * hv);
+    dpre[idx] = d;
+    const uint16_t b = f2bf(d);
+    dpreb[idx] = b;
+    dpret[(size_t)c * Ppad + p] = b;
+}
+
+// partial column sums: partial[blk][c] = sum over this block's rows of A[p][c] * (w ? w[p] : 1)
+__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ A, const float *__restrict__ w,
+                                                int rows, int rows_per_blk, float *__restrict__ partial)
+{
+    // 256 threads = 4 row groups x 64 columns
+    __shared__ float red[4][C];
+    const int c = threadIdx.x & (C - 1), g = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * rows_per_blk;
+    const int r1 = min(r0 + rows_per_blk, rows);
+    float s = 0.f;
+    for (int r = r0 + g; r < r1; r += 4)
+        s += A[(size_t)r * C + c] * (w ? w[r] : 1.f);
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0)
+        partial[blockIdx.x * C + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+// out[j] (+)= sum_b partial[b][j], j < width; fixed order
+__global__ void k_reduce_cols(const float *__restrict__ partial, int nb, int width, float *__restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= width)
+        return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b)
+        s += partial[(size_t)b * width + j];
+    out[j] = s;
+}
+
+// grad[W_l][t][c'][c] = wgrad[c][t*C + c']
+__global__ void k_scatter_wgrad(const float *__restrict__ wgrad, int l, float *__restrict__ grad)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= C * KB)
+        return;
+    const int c = idx / KB, k = idx - c * KB;
+    grad[off_w(l) + k * C + c] = wgrad[idx];
+}
+
+// dh[q][c'] = sum_t dxcol[q - tap t][t*C + c'];  dpre = dh (1 - h^2)
+__global__ void k_col2im(const float *__restrict__ dxcol, const float *__restrict__ hprev, int nblk, int Bs,
+                         int Ppad, float *__restrict__ dpre, uint16_t *__restrict__ dpreb,
+                         uint16_t *__restrict__ dpret)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Ppad * C)
+        return;
+    const int q = idx / C, c = idx - q * C;
+    const int BB = Bs * Bs;
+    float dh = 0.f;
+    if (q < nblk * BB) {
+        const int n = q / BB, k = q - n * BB, i = k / Bs, j = k - i * Bs;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            // source position p with p + tap t = q
+            const int ii = i - tap_di(t), jj = j - tap_dj(t);
+            if (ii < Bs && jj >= 0 && jj < Bs)
+                dh += dxcol[(size_t)(n * BB + ii * Bs + jj) * KB + t * C + c];
+        }
+    }
+    const float hv = hprev[idx];
+    const float d = dh * (1.f - hv * hv);
+    dpre[idx] = d;
+    const uint16_t b = f2bf(d);
+    dpreb[idx] = b;
+    dpret[(size_t)c * Ppad + q] = b;
+}
+
+// layer-1 gradients: 10 rows (W1 taps 0..3, U1 f 0..3, v1, b1) x C, partial over positions
+__global__ __launch_bounds__(256) void k_layer1_grad(const float *__restrict__ dpre1, const int8_t *__restrict__ x,
+                                                     const int8_t *__restrict__ bnd, const float *__restrict__ kc,
+                                                     int nblk, int Bs, int rows_per_blk, float *__restrict__ partial)
+{
+    __shared__ float red[4][10][C];
+    const int c = threadIdx.x & (C - 1), g = threadIdx.x >> 6;
+    const int BB = Bs * Bs, P = nblk * BB;
+    const int r0 = blockIdx.x * rows_per_blk, r1 = min(r0 + rows_per_blk, P);
+    float acc[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        acc[q] = 0.f;
+    for (int p = r0 + g; p < r1; p += 4) {
+        const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
+        const float d = dpre1[(size_t)p * C + c];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ii = i + tap_di(t), jj = j + tap_dj(t);
+            if (ii >= 0 && jj >= 0 && jj < Bs)
+                acc[t] += (float)x[n * BB + ii * Bs + jj] * d;
+        }
+        const int8_t *bn = bnd + n * 4 * Bs;
+        if (i == 0)
+            acc[4] += (float)bn[j] * d;
+        if (i == Bs - 1)
+            acc[5] += (float)bn[Bs + j] * d;
+        if (j == 0)
+            acc[6] += (float)bn[2 * Bs + i] * d;
+        if (j == Bs - 1)
+            acc[7] += (float)bn[3 * Bs + i] * d;
+        acc[8] += kc[n] * d;
+        acc[9] += d;
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        red[g][q][c] = acc[q];
+    __syncthreads();
+    if (g == 0)
+        for (int q = 0; q < 10; ++q)
+            partial[(size_t)blockIdx.x * 10 * C + q * C + c] = red[0][q][c] + red[1][q][c] + red[2][q][c] + red[3][q][c];
+}
+
+__global__ void k_adam(float *__restrict__ params, const float *__restrict__ grad, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// incremental autoregressive pass: 16 sequences per workgroup, one site per
+// step; layers 2..4 on MFMA with this wave's weight slice held in registers
+// ---------------------------------------------------------------------------
+constexpr int SEQ_PER_WG = 16;
+
+__global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq, int Bs)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][C];
+    __shared__ float h4s[SEQ_PER_WG][C + 1];
+    __shared__ int8_t xs[SEQ_PER_WG][64];
+    __shared__ int8_t bs[SEQ_PER_WG][32];
+    __shared__ float ks[SEQ_PER_WG];
+    __shared__ double lq[SEQ_PER_WG];
+    __shared__ float wo_s[C];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int s0 = blockIdx.x * SEQ_PER_WG;
+    const int BB = Bs * Bs;
+    const float *P = net.params;
+
+    for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
+        const int s = i >> 6, k = i & 63;
+        int8_t v = 0;
+        if (s0 + s < n_seq && k < BB && seq.mode[s0 + s] == 0)
+            v = seq.x[(size_t)(s0 + s) * BB + k];
+        xs[s][k] = v;
+    }
+    for (int i = tid; i < SEQ_PER_WG * 32; i += 256) {
+        const int s = i >> 5, k = i & 31;
+        bs[s][k] = (s0 + s < n_seq && k < 4 * Bs) ? seq.bnd[(size_t)(s0 + s) * 4 * Bs + k] : (int8_t)0;
+    }
+    if (tid < SEQ_PER_WG) {
+        ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
+        lq[tid] = 0.0;
+    }
+    if (tid < C)
+        wo_s[tid] = P[OFF_WO + tid];
+
+    // this wave's output channels: 16*wave .. 16*wave+15 (B operand column = lane & 15)
+    const int cw = 16 * wave + (lane & 15);
+    bf16x8 wreg[3][10];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            wreg[l][q] = load_bf16x8(net.wt + ((size_t)l * C + cw) * KB + q * 32 + 8 * (lane >> 4));
+    float bias[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+        bias[l] = P[off_b(l + 2) + cw];
+    // layer-1 parameters of this thread's channel (tid & 63)
+    const int c1 = tid & (C - 1);
+    float w1[4], u1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        w1[t] = P[OFF_W1 + t * C + c1];
+        u1[t] = P[OFF_U1 + t * C + c1];
+    }
+    const float v1 = P[OFF_V1 + c1], b1 = P[OFF_B1 + c1], bo = P[OFF_BO];
+    __syncthreads();
+
+    for (int k = 0; k < BB; ++k) {
+        const int i = k / Bs, j = k - i * Bs, slot = k % RING;
+        // layer 1: thread -> channel c1, sequences wave, wave+4, wave+8, wave+12
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int s = wave + 4 * q;
+            float pre = ks[s] * v1 + b1;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int ii = i + tap_di(t), jj = j + tap_dj(t);
+                if (ii >= 0 && jj >= 0 && jj < Bs)
+                    pre += (float)xs[s][ii * Bs + jj] * w1[t];
+            }
+            pre += boundary_field(&bs[s][0], Bs, i, j, u1);
+            ring[0][slot][s][c1] = f2bf(tanhf(pre));
+        }
+        __syncthreads();
+        // layers 2..4
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                const int t = q >> 1, half = q & 1;
+                const int ii = i + tap_di(t), jj = j + tap_dj(t);
+                bf16x8 a = zero_bf16x8();
+                if (ii >= 0 && jj >= 0 && jj < Bs) {
+                    const int pslot = (k + tap_di(t) * Bs + tap_dj(t) + RING) % RING;
+                    a = load_bf16x8(&ring[l][pslot][lane & 15][half * 32 + 8 * (lane >> 4)]);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[l][q], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int s = 4 * (lane >> 4) + r;
+                const float v = tanhf(acc[r] + bias[l]);
+                if (l < 2)
+                    ring[l + 1][slot][s][cw] = f2bf(v);
+                else
+                    h4s[s][cw] = v;
+            }
+            __syncthreads();
+        }
+        // head, threshold, decision (one thread per sequence)
+        if (tid < SEQ_PER_WG && s0 + tid < n_seq) {
+            const int s = tid, g = s0 + s;
+            float logit = bo;
+            for (int c = 0; c < C; ++c)
+                logit = fmaf(h4s[s][c], wo_s[c], logit);
+            const float pr = 1.f / (1.f + expf(-logit));
+            double scaled = floor((double)pr * 4294967296.0);
+            scaled = fmin(fmax(scaled, 1.0), 4294967295.0);
+            const uint32_t thr = (uint32_t)scaled;
+            int8_t xv;
+            if (seq.mode[g] == 1) {
+                uint32_t o[4];
+                const uint32_t *kk = seq.key + 4 * (size_t)g;
+                const uint32_t site = seq.blk[g] * (uint32_t)BB + (uint32_t)k;
+                philox4x32_10(site >> 2, kk[3], kk[2], 3u, kk[0], kk[1], o);
+                xv = o[site & 3] < thr ? (int8_t)1 : (int8_t)-1;
+                xs[s][k] = xv;
+            } else {
+                xv = xs[s][k];
+            }
+            lq[s] += log(xv > 0 ? (double)thr : 4294967296.0 - (double)thr);
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
+        const int s = i >> 6, k = i & 63;
+        if (s0 + s < n_seq && k < BB && seq.mode[s0 + s] == 1)
+            seq.x[(size_t)(s0 + s) * BB + k] = xs[s][k];
+    }
+    if (tid < SEQ_PER_WG && s0 + tid < n_seq)
+        seq.logq[s0 + tid] = lq[tid] - (double)BB * 32.0 * 0.69314718055994530942;
+}
+
+// ---------------------------------------------------------------------------
+// lattice <-> blocks
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int spin_at(const RepDev &d, uint32_t x, uint32_t y)
+{
+    const uint32_t c = (x + y) & 1u, k = x >> 1;
+    const uint32_t w = d.plane0[c * d.Ly * d.W + y * d.W + (k >> 5)];
+    return ((w >> (k & 31)) & 1u) ? 1 : -1;
+}
+
+// block (bx, by) of a replica -> its spins and boundary
+__device__ void read_block(const RepDev &d, int Bs, uint32_t bx, uint32_t by, int8_t *x, int8_t *bnd)
+{
+    const uint32_t x0 = bx * Bs, y0 = by * Bs;
+    for (int i = 0; i < Bs; ++i)
+        for (int j = 0; j < Bs; ++j)
+            x[i * Bs + j] = (int8_t)spin_at(d, x0 + j, y0 + i);
+    const uint32_t yu = y0 == 0 ? d.Ly - 1 : y0 - 1, yd = (y0 + Bs) % d.Ly;
+    const uint32_t xl = x0 == 0 ? d.Lx - 1 : x0 - 1, xr = (x0 + Bs) % d.Lx;
+    for (int j = 0; j < Bs; ++j) {
+        bnd[j] = (int8_t)spin_at(d, x0 + j, yu);
+        bnd[Bs + j] = (int8_t)spin_at(d, x0 + j, yd);
+    }
+    for (int i = 0; i < Bs; ++i) {
+        bnd[2 * Bs + i] = (int8_t)spin_at(d, xl, y0 + i);
+        bnd[3 * Bs + i] = (int8_t)spin_at(d, xr, y0 + i);
+    }
+}
+
+// colour-`colour` block number idx of a replica -> (bx, by); blocks alternate in colour
+__device__ __forceinline__ void block_coords(uint32_t idx, uint32_t nbx, uint32_t colour, uint32_t *bx, uint32_t *by)
+{
+    const uint32_t half = nbx / 2;
+    *by = idx / half;
+    *bx = 2 * (idx - *by * half) + ((*by + colour) & 1u);
+}
+
+// two sequences per block: 2b scores the current block, 2b+1 samples a proposal
+__global__ void k_block_gather(const RepDev *__restrict__ reps, const double *__restrict__ kcoup, int Bs,
+                               uint32_t colour, uint32_t round, uint32_t first, uint32_t count,
+                               uint32_t per_rep, SeqDev seq)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count)
+        return;
+    const uint32_t g = first + b, r = g / per_rep, idx = g - r * per_rep;
+    const RepDev d = reps[r];
+    const uint32_t nbx = d.Lx / Bs;
+    uint32_t bx, by;
+    block_coords(idx, nbx, colour, &bx, &by);
+    const int BB = Bs * Bs;
+    int8_t *x0 = seq.x + (size_t)(2 * b) * BB;
+    int8_t *bnd0 = seq.bnd + (size_t)(2 * b) * 4 * Bs;
+    read_block(d, Bs, bx, by, x0, bnd0);
+    for (int q = 0; q < 4 * Bs; ++q)
+        seq.bnd[(size_t)(2 * b + 1) * 4 * Bs + q] = bnd0[q];
+    for (int q = 0; q < 2; ++q) {
+        const size_t s = 2 * b + q;
+        seq.coupling[s] = (float)kcoup[r];
+        seq.key[4 * s + 0] = d.seed_lo;
+        seq.key[4 * s + 1] = d.seed_hi;
+        seq.key[4 * s + 2] = d.replica;
+        seq.key[4 * s + 3] = round;
+        seq.blk[s] = by * nbx + bx;
+        seq.mode[s] = (uint8_t)q;
+    }
+}
+
+// Metropolis-Hastings for each gathered block; accepted proposals are XORed
+// into the packed planes (only this block's bits; same-colour blocks never
+// share a bond, so concurrent blocks do not interact)
+__global__ void k_block_mh(const RepDev *__restrict__ reps, const double *__restrict__ kcoup, int Bs,
+                           uint32_t colour, uint32_t round, uint32_t first, uint32_t count, uint32_t per_rep,
+                           SeqDev seq, unsigned long long *__restrict__ accepts)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count)
+        return;
+    const uint32_t g = first + b, r = g / per_rep, idx = g - r * per_rep;
+    const RepDev d = reps[r];
+    const uint32_t nbx = d.Lx / Bs;
+    uint32_t bx, by;
+    block_coords(idx, nbx, colour, &bx, &by);
+    const int BB = Bs * Bs;
+    const int8_t *s = seq.x + (size_t)(2 * b) * BB;
+    const int8_t *sp = seq.x + (size_t)(2 * b + 1) * BB;
+    const int8_t *bn = seq.bnd + (size_t)(2 * b) * 4 * Bs;
+    // change of the bond sum: interior bonds and bonds to the boundary
+    int dB = 0;
+    for (int i = 0; i < Bs; ++i)
+        for (int j = 0; j < Bs; ++j) {
+            const int k = i * Bs + j;
+            if (j + 1 < Bs)
+                dB += sp[k] * sp[k + 1] - s[k] * s[k + 1];
+            if (i + 1 < Bs)
+                dB += sp[k] * sp[k + Bs] - s[k] * s[k + Bs];
+        }
+    for (int j = 0; j < Bs; ++j) {
+        dB += (sp[j] - s[j]) * bn[j];
+        dB += (sp[(Bs - 1) * Bs + j] - s[(Bs - 1) * Bs + j]) * bn[Bs + j];
+    }
+    for (int i = 0; i < Bs; ++i) {
+        dB += (sp[i * Bs] - s[i * Bs]) * bn[2 * Bs + i];
+        dB += (sp[i * Bs + Bs - 1] - s[i * Bs + Bs - 1]) * bn[3 * Bs + i];
+    }
+    // log of pi(s') q(s) / (pi(s) q(s')), pi ~ exp(K B)
+    const double logA = kcoup[r] * (double)dB + seq.logq[2 * b] - seq.logq[2 * b + 1];
+    uint32_t o[4];
+    philox4x32_10(by * nbx + bx, round, d.replica, 4u, d.seed_lo, d.seed_hi, o);
+    const double u = (double)(((uint64_t)o[0] << 21) | (o[1] >> 11)) * 1.1102230246251565404e-16;  // 2^-53
+    const bool accept = logA >= 0.0 || u < exp(logA);
+    if (!accept)
+        return;
+    atomicAdd(&accepts[r], 1ull);
+    const uint32_t x0 = bx * Bs, y0 = by * Bs;
+    for (int i = 0; i < Bs; ++i)
+        for (int j = 0; j < Bs; ++j) {
+            const int k = i * Bs + j;
+            if (s[k] == sp[k])
+                continue;
+            const uint32_t x = x0 + j, y = y0 + i, c = (x + y) & 1u, kk = x >> 1;
+            atomicXor(&d.plane0[c * d.Ly * d.W + y * d.W + (kk >> 5)], 1u << (kk & 31));
+        }
+}
+
+// training samples: block position of sample i of replica r drawn from
+// Philox(ctr = {i, draw, replica, 5})
+__global__ void k_extract(const RepDev *__restrict__ reps, const double *__restrict__ kcoup, int Bs,
+                          uint32_t per_rep, uint32_t count, uint32_t draw, int8_t *__restrict__ x,
+                          int8_t *__restrict__ bnd, float *__restrict__ kout)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count)
+        return;
+    const uint32_t r = q / per_rep, i = q - r * per_rep;
+    const RepDev d = reps[r];
+    uint32_t o[4];
+    philox4x32_10(i, draw, d.replica, 5u, d.seed_lo, d.seed_hi, o);
+    const uint32_t bx = o[0] % (d.Lx / Bs), by = o[1] % (d.Ly / Bs);
+    read_block(d, Bs, bx, by, x + (size_t)q * Bs * Bs, bnd + (size_t)q * 4 * Bs);
+    kout[q] = (float)kcoup[r];
+}
+
+// standalone sequences: mode, Philox key and block id of sequence i
+__global__ void k_seq_setup(SeqDev seq, int n, uint8_t mode, uint32_t seed_lo, uint32_t seed_hi, uint32_t replica,
+                            uint32_t round, uint32_t blk0)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    seq.mode[i] = mode;
+    seq.key[4 * i + 0] = seed_lo;
+    seq.key[4 * i + 1] = seed_hi;
+    seq.key[4 * i + 2] = replica;
+    seq.key[4 * i + 3] = round;
+    seq.blk[i] = blk0 + (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t cast_weights(const NetDev &net, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cast_weights, dim3(blocks_for(3L * C * KB, 256)), dim3(256), 0, st, net.params, net.wt,
+                       net.wtt);
+    return hipGetLastError();
+}
+
+hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *Cm, int ldc, int M, int N,
+                   int K, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gemm_nt, dim3(blocks_for(N, 64), blocks_for(M, 64)), dim3(256), 0, st, A, lda, Bt, ldb,
+                       Cm, ldc, M, N, K);
+    return hipGetLastError();
+}
+
+// forward of nblk blocks; logits[P]; returns the padded position count in *ppad
+hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                   int nblk, int Bs, hipStream_t st)
+{
+    const int Pv = nblk * Bs * Bs, Pp = (Pv + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_layer1, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, net.params, x, bnd, kc,
+                       nblk, Bs, Pp, ws.h[0], ws.hb[0]);
+    for (int l = 2; l <= 4; ++l) {
+        const int li = l - 2;
+        hipLaunchKernelGGL(k_im2col, dim3(blocks_for((long)Pp * 5 * (C / 8), 256)), dim3(256), 0, st,
+                           ws.hb[li], nblk, Bs, Pp, ws.xcol[li], ws.xcolt[li]);
+        hipError_t e = gemm_nt(ws.xcol[li], KB, net.wt + (size_t)li * C * KB, KB, ws.pre, C, Pp, C, KB, st);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_bias_tanh, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.pre,
+                           net.params + off_b(l), Pv, Pp, ws.h[l - 1], l < 4 ? ws.hb[l - 1] : (uint16_t *)nullptr);
+    }
+    hipLaunchKernelGGL(k_head, dim3(blocks_for(Pv, 256)), dim3(256), 0, st, ws.h[3], net.params, Pv, ws.logits);
+    const int nb = blocks_for(Pp, 256);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, st, ws.logits, x, Pv, Pp, ws.dlogit, ws.partial);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, ws.partial, nb, 1.f / (float)Pv, ws.loss);
+    return hipGetLastError();
+}
+
+hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                    int nblk, int Bs, hipStream_t st)
+{
+    const int Pv = nblk * Bs * Bs, Pp = (Pv + 63) / 64 * 64;
+    const int rows_per_blk = 256;
+    const int nbr = blocks_for(Pp, rows_per_blk);
+    // head: dwo = sum_p h4[p] dlogit[p]; dbo = sum_p dlogit[p]
+    hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.h[3], ws.dlogit, Pp, rows_per_blk, ws.partial);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + OFF_WO);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, ws.dlogit, Pp, 1.f, net.grad + OFF_BO);
+    hipLaunchKernelGGL(k_dpre_head, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.h[3], ws.dlogit,
+                       net.params, Pp, ws.dpre, ws.dpreb, ws.dpret);
+    for (int l = 4; l >= 2; --l) {
+        const int li = l - 2;
+        hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.dpre, (const float *)nullptr, Pp, rows_per_blk,
+                           ws.partial);
+        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + off_b(l));
+        // weight gradient [C][KB] = dpre^T (C x P) . xcol (P x KB)
+        hipError_t e = gemm_nt(ws.dpret, Pp, ws.xcolt[li], Pp, ws.wgrad, KB, C, KB, Pp, st);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_scatter_wgrad, dim3(blocks_for((long)C * KB, 256)), dim3(256), 0, st, ws.wgrad, l,
+                           net.grad);
+        // data gradient [P][KB] = dpre (P x C) . W (C x KB)
+        e = gemm_nt(ws.dpreb, C, net.wtt + (size_t)li * KB * C, C, ws.pre, KB, Pp, KB, C, st);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_col2im, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.pre, ws.h[l - 2],
+                           nblk, Bs, Pp, ws.dpre, ws.dpreb, ws.dpret);
+    }
+    hipLaunchKernelGGL(k_layer1_grad, dim3(nbr), dim3(256), 0, st, ws.dpre, x, bnd, kc, nblk, Bs, rows_per_blk,
+                       ws.partial);
+    // rows: W1 taps (4), U1 (4), v1, b1 -> contiguous in the flat vector starting at OFF_W1
+    hipLaunchKernelGGL(k_reduce_cols, dim3(blocks_for(10 * C, 256)), dim3(256), 0, st, ws.partial, nbr, 10 * C,
+                       net.grad + OFF_W1);
+    return hipGetLastError();
+}
+
+hipError_t adam(const NetDev &net, float lr, int step, hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(N_PARAMS, 256)), dim3(256), 0, st, net.params, net.grad, net.adam_m,
+                       net.adam_v, N_PARAMS, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_seq, int Bs, hipStream_t st)
+{
+    if (n_seq <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_nn_ar, dim3(blocks_for(n_seq, SEQ_PER_WG)), dim3(256), 0, st, net, seq, n_seq, Bs);
+    return hipGetLastError();
+}
+
+hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
+                        uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_gather, dim3(blocks_for(count, 256)), dim3(256), 0, st, reps, kcoup, Bs, colour,
+                       round, first, count, per_rep, seq);
+    return hipGetLastError();
+}
+
+hipError_t block_mh(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
+                    uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, int64_t *accepts,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_mh, dim3(blocks_for(count, 256)), dim3(256), 0, st, reps, kcoup, Bs, colour, round,
+                       first, count, per_rep, seq, reinterpret_cast<unsigned long long *>(accepts));
+    return hipGetLastError();
+}
+
+hipError_t seq_setup(const SeqDev &seq, int n, uint8_t mode, uint64_t seed, uint32_t replica, uint32_t round,
+                     uint32_t blk0, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seq_setup, dim3(blocks_for(n, 256)), dim3(256), 0, st, seq, n, mode,
+                       (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), replica, round, blk0);
+    return hipGetLastError();
+}
+
+hipError_t extract(const RepDev *reps, const double *kcoup, int Bs, uint32_t per_rep, uint32_t count,
+                   uint32_t draw, int8_t *x, int8_t *bnd, float *kout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_extract, dim3(blocks_for(count, 256)), dim3(256), 0, st, reps, kcoup, Bs, per_rep, count,
+                       draw, x, bnd, kout);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace ising

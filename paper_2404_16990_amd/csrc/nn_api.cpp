@@ -1,0 +1,407 @@
+// Host runtime and C ABI of the learned block proposals: network state in the
+// caller's device buffer, training steps, standalone scoring/sampling, block
+// extraction and Metropolis-Hastings block rounds on a replica batch.  Every
+// device computation is a kernel in nn.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ising.h"
+#include "batch.hpp"
+#include "nn.hpp"
+#include "nn_launch.hpp"
+
+using namespace ising;
+using namespace ising::nn;
+
+#define NN_HIP(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(ISING_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct NNLayout {
+    size_t params, adam_m, adam_v, grad, wt, wtt;
+    size_t h[4], hb[3], xcol[3], xcolt[3], pre, dpre, dpreb, dpret, logits, dlogit, partial, wgrad, loss;
+    size_t sx, sbnd, scoup, skey, sblk, smode, slogq;
+    size_t total;
+    int Pp;
+};
+
+int check_dims(int32_t block, int32_t channels, int32_t max_batch, int32_t max_seq)
+{
+    if (channels != C)
+        return fail(ISING_E_UNSUPPORTED, "the network has 64 channels");
+    if (block != 2 && block != 4 && block != 8)
+        return fail(ISING_E_UNSUPPORTED, "block size must be 2, 4 or 8");
+    if (max_batch < 1 || max_seq < 2)
+        return fail(ISING_E_INVALID, "max_batch >= 1 and max_seq >= 2 required");
+    if ((int64_t)max_batch * block * block > (1 << 24))
+        return fail(ISING_E_UNSUPPORTED, "max_batch too large");
+    return ISING_OK;
+}
+
+NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
+{
+    NNLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const int Pp = (max_batch * block * block + 63) / 64 * 64;
+    L.Pp = Pp;
+    L.params = take(N_PARAMS * 4);
+    L.adam_m = take(N_PARAMS * 4);
+    L.adam_v = take(N_PARAMS * 4);
+    L.grad = take(N_PARAMS * 4);
+    L.wt = take((size_t)3 * C * KB * 2);
+    L.wtt = take((size_t)3 * KB * C * 2);
+    for (int l = 0; l < 4; ++l)
+        L.h[l] = take((size_t)Pp * C * 4);
+    for (int l = 0; l < 3; ++l) {
+        L.hb[l] = take((size_t)Pp * C * 2);
+        L.xcol[l] = take((size_t)Pp * KB * 2);
+        L.xcolt[l] = take((size_t)Pp * KB * 2);
+    }
+    L.pre = take((size_t)Pp * KB * 4);
+    L.dpre = take((size_t)Pp * C * 4);
+    L.dpreb = take((size_t)Pp * C * 2);
+    L.dpret = take((size_t)Pp * C * 2);
+    L.logits = take((size_t)Pp * 4);
+    L.dlogit = take((size_t)Pp * 4);
+    L.partial = take((size_t)(Pp / 256 + 2) * 10 * C * 4);
+    L.wgrad = take((size_t)C * KB * 4);
+    L.loss = take(4);
+    L.sx = take((size_t)max_seq * block * block);
+    L.sbnd = take((size_t)max_seq * 4 * block);
+    L.scoup = take((size_t)max_seq * 4);
+    L.skey = take((size_t)max_seq * 16);
+    L.sblk = take((size_t)max_seq * 4);
+    L.smode = take((size_t)max_seq);
+    L.slogq = take((size_t)max_seq * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct ising_nn {
+    int32_t Bs = 0, max_batch = 0, max_seq = 0;
+    char *buf = nullptr;
+    NNLayout L{};
+    NetDev net{};
+    TrainWs ws{};
+    SeqDev seq{};
+    int step = 0;
+};
+
+namespace {
+
+int check_nn(ising_nn *m)
+{
+    if (!m)
+        return fail(ISING_E_INVALID, "null network handle");
+    return ISING_OK;
+}
+
+int upload_params(ising_nn *m, const float *host, hipStream_t st)
+{
+    NN_HIP(hipMemcpyAsync(m->net.params, host, N_PARAMS * sizeof(float), hipMemcpyHostToDevice, st));
+    NN_HIP(hipMemsetAsync(m->net.adam_m, 0, N_PARAMS * sizeof(float), st));
+    NN_HIP(hipMemsetAsync(m->net.adam_v, 0, N_PARAMS * sizeof(float), st));
+    NN_HIP(cast_weights(m->net, st));
+    NN_HIP(hipStreamSynchronize(st));
+    m->step = 0;
+    return ISING_OK;
+}
+
+// replicas of one shape with Lx, Ly multiples of 2*Bs; blocks of one colour per replica
+int uniform_blocks(ising_batch *b, int Bs, uint32_t *per_rep)
+{
+    const int32_t Lx = b->desc[0].Lx, Ly = b->desc[0].Ly;
+    for (int32_t r = 1; r < b->n; ++r)
+        if (b->desc[r].Lx != Lx || b->desc[r].Ly != Ly)
+            return fail(ISING_E_UNSUPPORTED, "block moves need every replica of the batch to have one shape");
+    if (Lx % (2 * Bs) != 0 || Ly % (2 * Bs) != 0)
+        return fail(ISING_E_UNSUPPORTED, "Lx and Ly must be multiples of twice the block size");
+    *per_rep = (uint32_t)((Lx / Bs) * (Ly / Bs) / 2);
+    return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ising_nn_param_count(int32_t channels, int32_t *count)
+{
+    clear_error();
+    if (!count)
+        return fail(ISING_E_INVALID, "count must not be NULL");
+    if (channels != C)
+        return fail(ISING_E_UNSUPPORTED, "the network has 64 channels");
+    *count = N_PARAMS;
+    return ISING_OK;
+}
+
+int ising_nn_state_bytes(int32_t block, int32_t channels, int32_t max_batch, int32_t max_seq, size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(ISING_E_INVALID, "bytes must not be NULL");
+    int st = check_dims(block, channels, max_batch, max_seq);
+    if (st != ISING_OK)
+        return st;
+    *bytes = make_nn_layout(block, max_batch, max_seq).total;
+    return ISING_OK;
+}
+
+int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t max_seq, const float *host_params,
+                    void *dev_buf, size_t bytes, void *stream, ising_nn **out)
+{
+    clear_error();
+    if (!out)
+        return fail(ISING_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    int st = check_dims(block, channels, max_batch, max_seq);
+    if (st != ISING_OK)
+        return st;
+    if (!host_params || !dev_buf)
+        return fail(ISING_E_INVALID, "parameters and device buffer must not be NULL");
+    if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0)
+        return fail(ISING_E_INVALID, "dev_buf must be 256-byte aligned");
+    const NNLayout L = make_nn_layout(block, max_batch, max_seq);
+    if (bytes < L.total)
+        return fail(ISING_E_NOMEM, "dev_buf is smaller than ising_nn_state_bytes()");
+    ising_nn *m = new (std::nothrow) ising_nn();
+    if (!m)
+        return fail(ISING_E_NOMEM, "host allocation failed");
+    m->Bs = block;
+    m->max_batch = max_batch;
+    m->max_seq = max_seq;
+    m->buf = static_cast<char *>(dev_buf);
+    m->L = L;
+    char *B = m->buf;
+    m->net.params = reinterpret_cast<float *>(B + L.params);
+    m->net.adam_m = reinterpret_cast<float *>(B + L.adam_m);
+    m->net.adam_v = reinterpret_cast<float *>(B + L.adam_v);
+    m->net.grad = reinterpret_cast<float *>(B + L.grad);
+    m->net.wt = reinterpret_cast<uint16_t *>(B + L.wt);
+    m->net.wtt = reinterpret_cast<uint16_t *>(B + L.wtt);
+    for (int l = 0; l < 4; ++l)
+        m->ws.h[l] = reinterpret_cast<float *>(B + L.h[l]);
+    for (int l = 0; l < 3; ++l) {
+        m->ws.hb[l] = reinterpret_cast<uint16_t *>(B + L.hb[l]);
+        m->ws.xcol[l] = reinterpret_cast<uint16_t *>(B + L.xcol[l]);
+        m->ws.xcolt[l] = reinterpret_cast<uint16_t *>(B + L.xcolt[l]);
+    }
+    m->ws.pre = reinterpret_cast<float *>(B + L.pre);
+    m->ws.dpre = reinterpret_cast<float *>(B + L.dpre);
+    m->ws.dpreb = reinterpret_cast<uint16_t *>(B + L.dpreb);
+    m->ws.dpret = reinterpret_cast<uint16_t *>(B + L.dpret);
+    m->ws.logits = reinterpret_cast<float *>(B + L.logits);
+    m->ws.dlogit = reinterpret_cast<float *>(B + L.dlogit);
+    m->ws.partial = reinterpret_cast<float *>(B + L.partial);
+    m->ws.wgrad = reinterpret_cast<float *>(B + L.wgrad);
+    m->ws.loss = reinterpret_cast<float *>(B + L.loss);
+    m->seq.x = reinterpret_cast<int8_t *>(B + L.sx);
+    m->seq.bnd = reinterpret_cast<int8_t *>(B + L.sbnd);
+    m->seq.coupling = reinterpret_cast<float *>(B + L.scoup);
+    m->seq.key = reinterpret_cast<uint32_t *>(B + L.skey);
+    m->seq.blk = reinterpret_cast<uint32_t *>(B + L.sblk);
+    m->seq.mode = reinterpret_cast<uint8_t *>(B + L.smode);
+    m->seq.logq = reinterpret_cast<double *>(B + L.slogq);
+    st = upload_params(m, host_params, reinterpret_cast<hipStream_t>(stream));
+    if (st != ISING_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return ISING_OK;
+}
+
+int ising_nn_get_params(ising_nn *m, float *host_params, void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (!host_params)
+        return fail(ISING_E_INVALID, "host_params must not be NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    NN_HIP(hipMemcpyAsync(host_params, m->net.params, N_PARAMS * sizeof(float), hipMemcpyDeviceToHost, hs));
+    NN_HIP(hipStreamSynchronize(hs));
+    return ISING_OK;
+}
+
+int ising_nn_set_params(ising_nn *m, const float *host_params, void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (!host_params)
+        return fail(ISING_E_INVALID, "host_params must not be NULL");
+    return upload_params(m, host_params, reinterpret_cast<hipStream_t>(stream));
+}
+
+int ising_nn_forward_backward(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                              const float *dev_coupling, int32_t batch, float *dev_logits, float *dev_grad,
+                              float *dev_loss, void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (batch < 1 || batch > m->max_batch)
+        return fail(ISING_E_INVALID, "batch must be in [1, max_batch]");
+    if (!dev_blocks || !dev_bnd || !dev_coupling)
+        return fail(ISING_E_INVALID, "block arrays must not be NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    NN_HIP(forward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
+    NN_HIP(backward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
+    const size_t P = (size_t)batch * m->Bs * m->Bs;
+    if (dev_logits)
+        NN_HIP(hipMemcpyAsync(dev_logits, m->ws.logits, P * 4, hipMemcpyDeviceToDevice, hs));
+    if (dev_grad)
+        NN_HIP(hipMemcpyAsync(dev_grad, m->net.grad, N_PARAMS * 4, hipMemcpyDeviceToDevice, hs));
+    if (dev_loss)
+        NN_HIP(hipMemcpyAsync(dev_loss, m->ws.loss, 4, hipMemcpyDeviceToDevice, hs));
+    return ISING_OK;
+}
+
+int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd, const float *dev_coupling,
+                        int32_t batch, float lr, float *dev_loss, void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (batch < 1 || batch > m->max_batch)
+        return fail(ISING_E_INVALID, "batch must be in [1, max_batch]");
+    if (!dev_blocks || !dev_bnd || !dev_coupling)
+        return fail(ISING_E_INVALID, "block arrays must not be NULL");
+    if (!(lr > 0.0f))
+        return fail(ISING_E_INVALID, "lr must be > 0");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    NN_HIP(forward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
+    NN_HIP(backward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
+    m->step += 1;
+    NN_HIP(adam(m->net, lr, m->step, hs));
+    NN_HIP(cast_weights(m->net, hs));
+    if (dev_loss)
+        NN_HIP(hipMemcpyAsync(dev_loss, m->ws.loss, 4, hipMemcpyDeviceToDevice, hs));
+    return ISING_OK;
+}
+
+int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                   const float *dev_coupling, double *dev_logq, void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (n < 1 || n > m->max_seq)
+        return fail(ISING_E_INVALID, "n must be in [1, max_seq]");
+    if (!dev_blocks || !dev_bnd || !dev_coupling || !dev_logq)
+        return fail(ISING_E_INVALID, "arrays must not be NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const int BB = m->Bs * m->Bs;
+    NN_HIP(hipMemcpyAsync(m->seq.x, dev_blocks, (size_t)n * BB, hipMemcpyDeviceToDevice, hs));
+    NN_HIP(hipMemcpyAsync(m->seq.bnd, dev_bnd, (size_t)n * 4 * m->Bs, hipMemcpyDeviceToDevice, hs));
+    NN_HIP(hipMemcpyAsync(m->seq.coupling, dev_coupling, (size_t)n * 4, hipMemcpyDeviceToDevice, hs));
+    NN_HIP(seq_setup(m->seq, n, 0, 0, 0, 0, 0, hs));
+    NN_HIP(ar_pass(m->net, m->seq, n, m->Bs, hs));
+    NN_HIP(hipMemcpyAsync(dev_logq, m->seq.logq, (size_t)n * 8, hipMemcpyDeviceToDevice, hs));
+    return ISING_OK;
+}
+
+int ising_nn_sample(ising_nn *m, int32_t n, const int8_t *dev_bnd, const float *dev_coupling, uint64_t seed,
+                    uint32_t replica, uint32_t round, uint32_t blk0, int8_t *dev_blocks_out, double *dev_logq,
+                    void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (n < 1 || n > m->max_seq)
+        return fail(ISING_E_INVALID, "n must be in [1, max_seq]");
+    if (!dev_bnd || !dev_coupling || !dev_blocks_out || !dev_logq)
+        return fail(ISING_E_INVALID, "arrays must not be NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const int BB = m->Bs * m->Bs;
+    NN_HIP(hipMemcpyAsync(m->seq.bnd, dev_bnd, (size_t)n * 4 * m->Bs, hipMemcpyDeviceToDevice, hs));
+    NN_HIP(hipMemcpyAsync(m->seq.coupling, dev_coupling, (size_t)n * 4, hipMemcpyDeviceToDevice, hs));
+    NN_HIP(seq_setup(m->seq, n, 1, seed, replica, round, blk0, hs));
+    NN_HIP(ar_pass(m->net, m->seq, n, m->Bs, hs));
+    NN_HIP(hipMemcpyAsync(dev_blocks_out, m->seq.x, (size_t)n * BB, hipMemcpyDeviceToDevice, hs));
+    NN_HIP(hipMemcpyAsync(dev_logq, m->seq.logq, (size_t)n * 8, hipMemcpyDeviceToDevice, hs));
+    return ISING_OK;
+}
+
+int ising_batch_extract_blocks(ising_batch *b, int32_t block, int32_t per_replica, uint32_t draw, int8_t *dev_blocks,
+                               int8_t *dev_bnd, float *dev_coupling, void *stream)
+{
+    clear_error();
+    if (!b)
+        return fail(ISING_E_INVALID, "null batch handle");
+    if (block != 2 && block != 4 && block != 8)
+        return fail(ISING_E_UNSUPPORTED, "block size must be 2, 4 or 8");
+    if (per_replica < 1)
+        return fail(ISING_E_INVALID, "per_replica must be >= 1");
+    if (!dev_blocks || !dev_bnd || !dev_coupling)
+        return fail(ISING_E_INVALID, "output arrays must not be NULL");
+    uint32_t per_rep_blocks = 0;
+    int st = uniform_blocks(b, block, &per_rep_blocks);
+    if (st != ISING_OK)
+        return st;
+    const uint64_t count = (uint64_t)b->n * (uint64_t)per_replica;
+    if (count > (1u << 30))
+        return fail(ISING_E_INVALID, "too many samples");
+    NN_HIP(extract(b->d_rep, b->d_kcoup, block, (uint32_t)per_replica, (uint32_t)count, draw, dev_blocks, dev_bnd,
+                   dev_coupling, reinterpret_cast<hipStream_t>(stream)));
+    return ISING_OK;
+}
+
+int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t *dev_accepts, void *stream)
+{
+    clear_error();
+    if (!b)
+        return fail(ISING_E_INVALID, "null batch handle");
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    uint32_t per_rep = 0;
+    st = uniform_blocks(b, m->Bs, &per_rep);
+    if (st != ISING_OK)
+        return st;
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    int64_t *acc = dev_accepts ? dev_accepts : b->d_obs;  // scratch counters when the caller wants none
+    const uint32_t total = (uint32_t)b->n * per_rep;
+    const uint32_t chunk = (uint32_t)(m->max_seq / 2);
+    for (uint32_t colour = 0; colour < 2; ++colour)
+        for (uint32_t first = 0; first < total; first += chunk) {
+            const uint32_t count = std::min(chunk, total - first);
+            NN_HIP(block_gather(b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count, per_rep, m->seq, hs));
+            NN_HIP(ar_pass(m->net, m->seq, (int)(2 * count), m->Bs, hs));
+            NN_HIP(block_mh(b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count, per_rep, m->seq, acc, hs));
+        }
+    return ISING_OK;
+}
+
+int ising_nn_destroy(ising_nn *m)
+{
+    delete m;
+    return ISING_OK;
+}
+
+}  // extern "C"

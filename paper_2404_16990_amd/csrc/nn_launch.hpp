@@ -1,0 +1,33 @@
+// Host-side launchers of the block-proposal network kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+#include "nn.hpp"
+
+namespace ising {
+namespace nn {
+
+hipError_t cast_weights(const NetDev &net, hipStream_t st);
+hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *Cm, int ldc, int M, int N,
+                   int K, hipStream_t st);
+hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                   int nblk, int Bs, hipStream_t st);
+hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                    int nblk, int Bs, hipStream_t st);
+hipError_t adam(const NetDev &net, float lr, int step, hipStream_t st);
+hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_seq, int Bs, hipStream_t st);
+hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
+                        uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, hipStream_t st);
+hipError_t block_mh(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
+                    uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, int64_t *accepts,
+                    hipStream_t st);
+hipError_t seq_setup(const SeqDev &seq, int n, uint8_t mode, uint64_t seed, uint32_t replica, uint32_t round,
+                     uint32_t blk0, hipStream_t st);
+hipError_t extract(const RepDev *reps, const double *kcoup, int Bs, uint32_t per_rep, uint32_t count,
+                   uint32_t draw, int8_t *x, int8_t *bnd, float *kout, hipStream_t st);
+
+}  // namespace nn
+}  // namespace ising

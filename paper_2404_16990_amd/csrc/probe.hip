@@ -120,6 +120,27 @@ __global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uin
         dst[i] = src[i];
 }
 
+// One v_mfma_f32_16x16x32_bf16 with per-lane operands exactly as given
+// (a, b: 64 lanes x 8 bf16 bit patterns; out: 64 lanes x 4 floats), to check
+// the builtin's lane layout against a host matrix product.
+typedef __bf16 probe_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float probe_floatx4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(64) void k_mfma_layout(const uint16_t *a, const uint16_t *b, float *out)
+{
+    const int l = threadIdx.x;
+    probe_bf16x8 va, vb;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        va[i] = __builtin_bit_cast(__bf16, a[l * 8 + i]);
+        vb[i] = __builtin_bit_cast(__bf16, b[l * 8 + i]);
+    }
+    probe_floatx4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        out[l * 4 + i] = c[i];
+}
+
 template <int W>
 hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
 {
@@ -212,6 +233,18 @@ int ising_probe_clock(void *stamps, void *out, int blocks, int iters, float *ms,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return err == hipSuccess ? 0 : -4;
+}
+
+/* One MFMA 16x16x32 bf16 on device buffers a, b (64*8 uint16 each) -> out (64*4 float). */
+int ising_probe_mfma_layout(const void *a, const void *b, void *out)
+{
+    if (!a || !b || !out)
+        return -1;
+    hipLaunchKernelGGL(k_mfma_layout, dim3(1), dim3(64), 0, nullptr, static_cast<const uint16_t *>(a),
+                       static_cast<const uint16_t *>(b), static_cast<float *>(out));
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return -4;
+    return 0;
 }
 
 /* Copy bytes (a multiple of 16) from src to dst `reps` times; elapsed ms of all reps. */

@@ -114,3 +114,38 @@ if __name__ == "__main__":
         r["clock"] = clock()
         r["copy_bytes_per_s"] = copy_bandwidth()
         print(json.dumps(r, indent=1))
+
+
+def mfma_layout():
+    """Check the lane layout of v_mfma_f32_16x16x32_bf16 against a host product.
+
+    Hypothesis used by the network kernels: A (16x32) lane l holds row l%16,
+    k = 8*(l//16)+i; B (32x16) lane l holds column l%16, k = 8*(l//16)+i;
+    C (16x16) lane l holds column l%16, rows 4*(l//16)+i.  Returns True if it holds.
+    """
+    import numpy as np
+    import torch
+    L = _lib()
+    L.ising_probe_mfma_layout.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rng = np.random.default_rng(0)
+    A = rng.integers(-8, 9, size=(16, 32)).astype(np.float32)   # exact in bf16
+    B = rng.integers(-8, 9, size=(32, 16)).astype(np.float32)
+    a = np.zeros((64, 8), np.float32)
+    b = np.zeros((64, 8), np.float32)
+    for l in range(64):
+        for i in range(8):
+            a[l, i] = A[l % 16, 8 * (l // 16) + i]
+            b[l, i] = B[8 * (l // 16) + i, l % 16]
+    to_bits = lambda m: (m.view(np.uint32) >> 16).astype(np.uint16)
+    da = torch.tensor(to_bits(a).astype(np.int16).ravel(), device="cuda")
+    db = torch.tensor(to_bits(b).astype(np.int16).ravel(), device="cuda")
+    out = torch.zeros(64 * 4, dtype=torch.float32, device="cuda")
+    if L.ising_probe_mfma_layout(da.data_ptr(), db.data_ptr(), out.data_ptr()) != 0:
+        raise RuntimeError("mfma probe failed")
+    o = out.cpu().numpy().reshape(64, 4)
+    Cm = A @ B
+    got = np.zeros((16, 16), np.float32)
+    for l in range(64):
+        for i in range(4):
+            got[4 * (l // 16) + i, l % 16] = o[l, i]
+    return bool(np.array_equal(got, Cm))

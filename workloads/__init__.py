@@ -122,3 +122,22 @@ def small_shapes(seed: int, count: int, max_wx: int = 4, max_ly: int = 40):
     for _ in range(count):
         out.append((64 * int(rng.integers(1, max_wx + 1)), 2 * int(rng.integers(1, max_ly // 2 + 1))))
     return out
+
+
+def nn_initial_params(C: int, seed: int = 16990) -> np.ndarray:
+    """Seeded initial parameters of the block-proposal network (float32, flat).
+
+    Layout (C channels): W1[4,C], U1[4,C], v1[C], b1[C], then for layers 2..4
+    W[5,C,C], b[C], then wo[C], bo[1].  Weights ~ N(0, 1/fan_in) from numpy
+    PCG64(seed), biases zero.  These are inputs (random numbers drawn once),
+    shared by the GPU library and the float64 reference alike.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = [rng.normal(0.0, 1.0 / np.sqrt(4.0), size=4 * C),       # W1 (4 spin taps)
+             rng.normal(0.0, 1.0 / np.sqrt(4.0), size=4 * C),       # U1 (4 boundary features)
+             rng.normal(0.0, 0.5, size=C),                          # v1 (beta)
+             np.zeros(C)]                                           # b1
+    for _ in range(3):
+        parts += [rng.normal(0.0, 1.0 / np.sqrt(5.0 * C), size=5 * C * C), np.zeros(C)]
+    parts += [rng.normal(0.0, 1.0 / np.sqrt(C), size=C), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)

@@ -172,9 +172,9 @@ def threshold(logit):
     return int(min(max(math.floor(p * 4294967296.0), 1), 4294967295))
 
 
-def log_q(theta, C, x, bnd, beta):
+def log_q(theta, C, x, bnd, beta, bf16=False):
     """log q(x | boundary, beta) of one block from thresholds (float64)."""
-    logits, _ = forward(theta, C, np.asarray(x)[None], np.asarray(bnd)[None], np.asarray([beta]))
+    logits, _ = forward(theta, C, np.asarray(x)[None], np.asarray(bnd)[None], np.asarray([beta]), bf16=bf16)
     Bs = logits.shape[1]
     s = 0.0
     for i in range(Bs):

@@ -94,6 +94,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="JSON dict overriding the execution schedule")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="also run the learned-proposal comparison (64 x 256^2 near T_c)")
+    ap.add_argument("--learned-units", type=int, default=2000)
+    ap.add_argument("--plain-sweeps", type=int, default=200000)
     ap.add_argument("--tune-sweeps", type=int, default=20)
     args = ap.parse_args()
 
@@ -199,7 +203,59 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps)
+    if args.learned:
+        batch.close()
+        del batch
+        torch.cuda.empty_cache()
+        out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps)
     print(json.dumps(out), flush=True)
+
+
+def learned_comparison(units, plain_sweeps):
+    """Effective independent |m| samples per second at T_c: plain checkerboard
+    sweeps against learned 8x8 block proposals (1 block round : 1 sweep).
+
+    64 replicas of 256^2 at T = linspace(2.20, 2.35, 64); replica 29
+    (T = 2.26905) is the one at T_c.  10^5 sweeps of burn-in, 98 x 16 x 64 =
+    100,352 training blocks taken 100 sweeps apart, 2000 Adam steps of 512
+    blocks; then a plain run and a learned run from the equilibrated state.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2404_16990_amd as P
+    from paper_2404_16990_amd import learned
+    import workloads
+
+    w = workloads.learned_64x256()
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+             for r in w.replicas]
+    b = P.Batch(descs)
+    t_c = min(range(len(w.replicas)), key=lambda r: abs(w.replicas[r].T - workloads.T_CRITICAL_PRINTED))
+    b.run(100000)
+    X, BN, K = learned.collect_blocks(b, 8, 16, 98, 100)
+    net = P.Net(workloads.nn_initial_params(64), block=8, max_batch=512, max_seq=65536)
+    t0 = time.perf_counter()
+    hist = learned.train(net, X, BN, K, 2000, 512, 2e-3, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    tr_p, s_p = learned.plain_trace(b, plain_sweeps, 10)
+    acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda")
+    tr_l, s_l = learned.abs_m_trace(b, units, learned.learned_units(b, net, 0, acc))
+    plain = learned.summarise(tr_p, s_p, 10, t_c)
+    plain["tau_int_sweeps"] = plain["tau_int_points"] * 10
+    lrn = learned.summarise(tr_l, s_l, 1, t_c)
+    z = learned.agreement(tr_p, tr_l)
+    return {
+        "metric": "effective independent |m| samples/s at T_c (one replica, whole-batch time)",
+        "workload": w.name, "replica_at_tc": t_c, "T": w.replicas[t_c].T,
+        "training": {"blocks": int(X.shape[0]), "steps": 2000, "batch": 512, "lr": 2e-3,
+                     "loss": hist, "seconds": t_train},
+        "plain": plain, "learned": lrn,
+        "block_acceptance": float(acc.sum().cpu()) / (units * len(descs) * 1024),
+        "learned_over_plain": lrn["effective_samples_per_s"] / plain["effective_samples_per_s"],
+        "abs_m_agreement": {"within_2sigma": float(np.mean(np.abs(z) < 2)), "max_abs_z": float(np.max(np.abs(z)))},
+    }
 
 
 if __name__ == "__main__":

@@ -26,6 +26,21 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
+// tanh from the hardware exp2 and reciprocal: tanh|x| = (1 - e)/(1 + e), e = exp(-2|x|).
+// Every kernel of the network uses this one definition, so training, scoring
+// and sampling evaluate the same function.
+__device__ __forceinline__ float net_tanh(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));  // 2 log2(e)
+    const float t = (1.f - e) * __builtin_amdgcn_rcpf(1.f + e);
+    return copysignf(t, x);
+}
+
+__device__ __forceinline__ float net_sigmoid(float x)
+{
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
+}
+
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p)
 {
     const uint4 v = *reinterpret_cast<const uint4 *>(p);
@@ -144,7 +159,7 @@ __global__ void k_layer1(const float *__restrict__ params, const int8_t *__restr
         const float u[4] = {params[OFF_U1 + c], params[OFF_U1 + C + c], params[OFF_U1 + 2 * C + c],
                             params[OFF_U1 + 3 * C + c]};
         pre += boundary_field(bnd + n * 4 * Bs, Bs, i, j, u);
-        v = tanhf(pre);
+        v = net_tanh(pre);
     }
     h[idx] = v;
     hb[idx] = f2bf(v);
@@ -182,7 +197,7 @@ __global__ void k_bias_tanh(const float *__restrict__ pre, const float *__restri
     if (idx >= Ppad * C)
         return;
     const int p = idx / C, c = idx - p * C;
-    const float v = p < Pvalid ? tanhf(pre[idx] + bias[c]) : 0.f;
+    const float v = p < Pvalid ? net_tanh(pre[idx] + bias[c]) : 0.f;
     h[idx] = v;
     if (hb)
         hb[idx] = f2bf(v);
@@ -398,16 +413,17 @@ __global__ void k_adam(float *__restrict__ params, const float *__restrict__ gra
 // step; layers 2..4 on MFMA with this wave's weight slice held in registers
 // ---------------------------------------------------------------------------
 constexpr int SEQ_PER_WG = 16;
+constexpr int RING_ROW = C + 8;  // padded row (bf16 elements) against LDS bank conflicts
 
 __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq, int Bs)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][C];
-    __shared__ float h4s[SEQ_PER_WG][C + 1];
+    __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][RING_ROW];
+    __shared__ float head_part[4][SEQ_PER_WG];
     __shared__ int8_t xs[SEQ_PER_WG][64];
     __shared__ int8_t bs[SEQ_PER_WG][32];
+    __shared__ uint32_t thr_s[SEQ_PER_WG][64];
     __shared__ float ks[SEQ_PER_WG];
-    __shared__ double lq[SEQ_PER_WG];
-    __shared__ float wo_s[C];
+    __shared__ double lq_part[SEQ_PER_WG][16];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int s0 = blockIdx.x * SEQ_PER_WG;
@@ -425,12 +441,8 @@ __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq
         const int s = i >> 5, k = i & 31;
         bs[s][k] = (s0 + s < n_seq && k < 4 * Bs) ? seq.bnd[(size_t)(s0 + s) * 4 * Bs + k] : (int8_t)0;
     }
-    if (tid < SEQ_PER_WG) {
+    if (tid < SEQ_PER_WG)
         ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
-        lq[tid] = 0.0;
-    }
-    if (tid < C)
-        wo_s[tid] = P[OFF_WO + tid];
 
     // this wave's output channels: 16*wave .. 16*wave+15 (B operand column = lane & 15)
     const int cw = 16 * wave + (lane & 15);
@@ -444,6 +456,7 @@ __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq
 #pragma unroll
     for (int l = 0; l < 3; ++l)
         bias[l] = P[off_b(l + 2) + cw];
+    const float wo_c = P[OFF_WO + cw], bo = P[OFF_BO];
     // layer-1 parameters of this thread's channel (tid & 63)
     const int c1 = tid & (C - 1);
     float w1[4], u1[4];
@@ -452,7 +465,7 @@ __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq
         w1[t] = P[OFF_W1 + t * C + c1];
         u1[t] = P[OFF_U1 + t * C + c1];
     }
-    const float v1 = P[OFF_V1 + c1], b1 = P[OFF_B1 + c1], bo = P[OFF_BO];
+    const float v1 = P[OFF_V1 + c1], b1 = P[OFF_B1 + c1];
     __syncthreads();
 
     for (int k = 0; k < BB; ++k) {
@@ -469,10 +482,10 @@ __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq
                     pre += (float)xs[s][ii * Bs + jj] * w1[t];
             }
             pre += boundary_field(&bs[s][0], Bs, i, j, u1);
-            ring[0][slot][s][c1] = f2bf(tanhf(pre));
+            ring[0][slot][s][c1] = f2bf(net_tanh(pre));
         }
         __syncthreads();
-        // layers 2..4
+        // layers 2..4 on the matrix cores; layer 4 feeds the logit head directly
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             floatx4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -487,49 +500,67 @@ __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq
                 }
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[l][q], acc, 0, 0, 0);
             }
+            if (l < 2) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int s = 4 * (lane >> 4) + r;
-                const float v = tanhf(acc[r] + bias[l]);
-                if (l < 2)
-                    ring[l + 1][slot][s][cw] = f2bf(v);
-                else
-                    h4s[s][cw] = v;
+                for (int r = 0; r < 4; ++r)
+                    ring[l + 1][slot][4 * (lane >> 4) + r][cw] = f2bf(net_tanh(acc[r] + bias[l]));
+            } else {
+                // head: sum over this wave's 16 channels of h4 * wo with a fixed
+                // butterfly over the 16 lanes that share a row group
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = net_tanh(acc[r] + bias[l]) * wo_c;
+                    v += __shfl_xor(v, 1, 64);
+                    v += __shfl_xor(v, 2, 64);
+                    v += __shfl_xor(v, 4, 64);
+                    v += __shfl_xor(v, 8, 64);
+                    if ((lane & 15) == 0)
+                        head_part[wave][4 * (lane >> 4) + r] = v;
+                }
             }
             __syncthreads();
         }
-        // head, threshold, decision (one thread per sequence)
+        // threshold and decision (one thread per sequence)
         if (tid < SEQ_PER_WG && s0 + tid < n_seq) {
             const int s = tid, g = s0 + s;
-            float logit = bo;
-            for (int c = 0; c < C; ++c)
-                logit = fmaf(h4s[s][c], wo_s[c], logit);
-            const float pr = 1.f / (1.f + expf(-logit));
+            const float logit = ((head_part[0][s] + head_part[1][s]) + (head_part[2][s] + head_part[3][s])) + bo;
+            const float pr = net_sigmoid(logit);
             double scaled = floor((double)pr * 4294967296.0);
             scaled = fmin(fmax(scaled, 1.0), 4294967295.0);
             const uint32_t thr = (uint32_t)scaled;
-            int8_t xv;
             if (seq.mode[g] == 1) {
                 uint32_t o[4];
                 const uint32_t *kk = seq.key + 4 * (size_t)g;
                 const uint32_t site = seq.blk[g] * (uint32_t)BB + (uint32_t)k;
                 philox4x32_10(site >> 2, kk[3], kk[2], 3u, kk[0], kk[1], o);
-                xv = o[site & 3] < thr ? (int8_t)1 : (int8_t)-1;
-                xs[s][k] = xv;
-            } else {
-                xv = xs[s][k];
+                xs[s][k] = o[site & 3] < thr ? (int8_t)1 : (int8_t)-1;
             }
-            lq[s] += log(xv > 0 ? (double)thr : 4294967296.0 - (double)thr);
+            thr_s[s][k] = thr;
         }
         __syncthreads();
     }
+    // log q = sum_k log(thr_k or 2^32 - thr_k) - BB * 32 ln 2, summed in a fixed order
+    {
+        const int s = tid >> 4, part = tid & 15;
+        double acc = 0.0;
+        for (int k = part * 4; k < part * 4 + 4 && k < BB; ++k) {
+            const double thr = (double)thr_s[s][k];
+            acc += log(xs[s][k] > 0 ? thr : 4294967296.0 - thr);
+        }
+        lq_part[s][part] = acc;
+    }
+    __syncthreads();
     for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
         const int s = i >> 6, k = i & 63;
         if (s0 + s < n_seq && k < BB && seq.mode[s0 + s] == 1)
             seq.x[(size_t)(s0 + s) * BB + k] = xs[s][k];
     }
-    if (tid < SEQ_PER_WG && s0 + tid < n_seq)
-        seq.logq[s0 + tid] = lq[tid] - (double)BB * 32.0 * 0.69314718055994530942;
+    if (tid < SEQ_PER_WG && s0 + tid < n_seq) {
+        double sum = 0.0;
+        for (int part = 0; part < 16; ++part)
+            sum += lq_part[tid][part];
+        seq.logq[s0 + tid] = sum - (double)BB * 32.0 * 0.69314718055994530942;
+    }
 }
 
 // ---------------------------------------------------------------------------

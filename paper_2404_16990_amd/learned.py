@@ -1,0 +1,101 @@
+"""Learned block proposals on a replica batch: training data, training, and
+the comparison against plain checkerboard sweeps on effective |m| samples.
+
+Every device step is a library call (see include/ising.h); this module only
+schedules them and analyses the recorded traces on the host.
+"""
+import time
+
+import numpy as np
+
+from . import Batch, Net, analysis
+
+
+def collect_blocks(batch: Batch, block: int, per_replica: int, draws: int, sweeps_between: int):
+    """Training blocks from the plain sampler: `draws` times, run
+    `sweeps_between` sweeps and take `per_replica` blocks of every replica."""
+    import torch
+    xs, bn, kc = [], [], []
+    for d in range(draws):
+        batch.run(sweeps_between)
+        x, b, k = batch.extract_blocks(block, per_replica, d)
+        xs.append(x)
+        bn.append(b)
+        kc.append(k)
+    return torch.cat(xs), torch.cat(bn), torch.cat(kc)
+
+
+def train(net: Net, X, BN, K, steps: int, batch_size: int, lr: float, seed: int = 0, log_every: int = 100):
+    """Adam on random minibatches; returns [(step, loss)] every log_every steps."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+    out = []
+    for s in range(steps):
+        idx = torch.randint(0, X.shape[0], (batch_size,), generator=g).to(X.device)
+        net.train_step(X[idx].contiguous(), BN[idx].contiguous(), K[idx].contiguous(), lr, loss)
+        if s % log_every == 0 or s == steps - 1:
+            out.append((s, float(loss.cpu())))
+    return out
+
+
+def abs_m_trace(batch: Batch, units: int, unit, record_every: int = 1):
+    """Run `units` units (callable unit(i)); returns (|m| trace [n_rep, units/record_every], seconds)."""
+    import torch
+    n_spins = np.array([d["Lx"] * d["Ly"] for d in batch.descs], dtype=np.float64)
+    traces = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(units):
+        rec = unit(i)
+        if rec is not None:
+            traces.append(rec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m = torch.cat([t for t in traces], dim=1).cpu().numpy().astype(np.float64)
+    return np.abs(m) / n_spins[:, None], dt
+
+
+def plain_trace(batch: Batch, sweeps: int, record_every: int):
+    """One run of `sweeps` plain sweeps recording M every `record_every`;
+    returns (|m| trace [n_rep, sweeps/record_every], seconds of device time)."""
+    import torch
+    n_spins = np.array([d["Lx"] * d["Ly"] for d in batch.descs], dtype=np.float64)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(batch.stream)
+    _, mag = batch.run(sweeps, record_every)
+    e1.record(batch.stream)
+    torch.cuda.synchronize()
+    return np.abs(mag.cpu().numpy().astype(np.float64)) / n_spins[:, None], e0.elapsed_time(e1) / 1e3
+
+
+def learned_units(batch: Batch, net: Net, first_round: int, accepts=None):
+    """One unit = one block round (both block colours) then one checkerboard sweep."""
+    def unit(i):
+        batch.block_round(net, first_round + i, accepts)
+        _, mag = batch.run(1, 1)
+        return mag
+    return unit
+
+
+def summarise(trace, seconds, units_per_trace_point, replica):
+    """tau_int (in trace points) of |m| of one replica and effective samples per second."""
+    tau, w = analysis.tau_int(trace[replica])
+    points_per_s = trace.shape[1] / seconds
+    return {"tau_int_points": tau, "window": w, "points": int(trace.shape[1]),
+            "units_per_point": units_per_trace_point, "seconds": seconds,
+            "effective_samples_per_s": analysis.effective_rate(points_per_s, tau),
+            "run_over_tau": trace.shape[1] / tau}
+
+
+def agreement(tr_a, tr_b):
+    """Per replica z of <|m|> between two traces with tau-corrected errors."""
+    zs = []
+    for r in range(tr_a.shape[0]):
+        ta, _ = analysis.tau_int(tr_a[r])
+        tb, _ = analysis.tau_int(tr_b[r])
+        ma, ea = analysis.mean_and_error(tr_a[r], ta)
+        mb, eb = analysis.mean_and_error(tr_b[r], tb)
+        zs.append((ma - mb) / np.sqrt(ea * ea + eb * eb) if ea + eb > 0 else 0.0)
+    return np.array(zs)

@@ -90,3 +90,15 @@ def test_table1_iteration_period_identity():
     for n, m, nsim, rflip, titer in t1["rows"]:
         t = n * m * nsim / rflip * 1e-6  # flip / (flip/ns) = ns -> ms
         assert abs(t - titer) / titer < 1e-3
+
+
+def test_product_tau_estimator_matches_oracle_and_ar1():
+    from paper_2404_16990_amd import analysis
+    rng = np.random.default_rng(4)
+    for rho in (0.3, 0.8, 0.95):
+        x = signal.lfilter([1.0], [1.0, -rho], rng.standard_normal(300000))[2000:]
+        t_prod, w_prod = analysis.tau_int(x)
+        t_orc, w_orc = stats.tau_int(x)
+        assert abs(t_prod - t_orc) < 1e-9 and w_prod == w_orc
+        exact_tau = (1 + rho) / (2 * (1 - rho))
+        assert abs(t_prod - exact_tau) < 0.06 * exact_tau

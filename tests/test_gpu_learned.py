@@ -62,9 +62,14 @@ def test_forward_matches_reference_at_bf16_points(Bs):
     torch.cuda.synchronize()
     g = logits.cpu().numpy().reshape(-1, Bs, Bs)
     ref, _ = nn_ref.forward(theta.astype(np.float64), C, x.reshape(-1, Bs, Bs), bnd, kc, bf16=True)
-    # only fp32 accumulation order and fp32 tanh differ from the reference here;
-    # an activation sitting on a bf16 rounding boundary can move one bf16 ulp
-    assert np.max(np.abs(g - ref)) < 2e-3, np.max(np.abs(g - ref))
+    # Only fp32 arithmetic (accumulation order, the exp2/rcp tanh, ~1e-7
+    # absolute) differs from the reference here.  Where that moves an
+    # activation across a bf16 rounding boundary the activation changes by one
+    # bf16 ulp (<= 2^-8), i.e. a logit by ~2^-8 * |w| (|w| ~ 0.1) per crossing;
+    # a few crossings can meet in one logit.  A systematic error would move
+    # the mean deviation, which stays at fp32 level.
+    dev = np.abs(g - ref)
+    assert dev.max() < 5e-3 and dev.mean() < 3e-4, (dev.max(), dev.mean())
     exact_ref, _ = nn_ref.forward(theta.astype(np.float64), C, x.reshape(-1, Bs, Bs), bnd, kc)
     assert abs(float(loss.cpu()) - nn_ref.nll(exact_ref, x.reshape(-1, Bs, Bs))) < 5e-3
 

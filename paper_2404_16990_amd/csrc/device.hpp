@@ -114,16 +114,26 @@ __device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_
     const uint32_t s2 = a3 ^ a4, c2 = a3 & a4;
     const uint32_t ge2 = c1 | c2 | (s1 & s2);
     const uint32_t eq1 = (s1 ^ s2) & ~(c1 | c2);
+    // Acceptance bits without the condition register: per site, broadcast the
+    // site's class bit (v_bfe_i32), select its threshold (v_bitop3, table
+    // 0xCA = m ? thr4 : thr8), form r - thr and take the borrow of that
+    // subtraction, r < thr, as bit 31 of (~r & t) | (~(r ^ t) & (r - t))
+    // (v_bitop3, table 0x8E), then shift it into the accumulator (v_alignbit).
+    // Sites are visited from bit 31 down so each lands at its own position.
+    const uint32_t thr4 = __builtin_amdgcn_readfirstlane(K.thr4);
     uint32_t acc = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 7; q >= 0; --q) {
         uint32_t r[4];
         philox4x32_10(q0 + q, K.t, K.replica, K.colour, K.k0, K.k1, r);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 3; j >= 0; --j) {
             const int b = 4 * q + j;
-            const uint32_t thr = ((eq1 >> b) & 1u) ? K.thr4 : K.thr8;
-            acc |= (uint32_t)(r[j] < thr) << b;
+            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)eq1, b, 1);
+            const uint32_t t = __builtin_amdgcn_bitop3_b32(m, thr4, K.thr8, 0xCA);
+            const uint32_t d = r[j] - t;
+            const uint32_t x = __builtin_amdgcn_bitop3_b32(r[j], t, d, 0x8E);
+            acc = __builtin_amdgcn_alignbit(acc, x, 31);
         }
     }
     return ge2 | acc;

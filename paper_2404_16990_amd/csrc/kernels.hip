@@ -152,8 +152,12 @@ __global__ __launch_bounds__(THREADS) void k_sweep_stream(const RepDev *__restri
 // ---------------------------------------------------------------------------
 // LDS-resident sweeps: one workgroup owns one replica for n_sweeps sweeps
 // ---------------------------------------------------------------------------
+// A resident workgroup owns its replica's LDS; for the 1024^2 lattices that is
+// the whole CU, so the compiler is told to schedule for THREADS/256 waves per
+// SIMD (more registers for interleaving independent Philox calls).
 template <typename Word, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_sweep_resident(const RepDev *__restrict__ reps,
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, THREADS / 256 > 0 ? THREADS / 256 : 1)))
+void k_sweep_resident(const RepDev *__restrict__ reps,
                                                             const uint32_t *__restrict__ list,
                                                             uint32_t n_sweeps, RecArgs rec)
 {

@@ -98,3 +98,37 @@ def test_null_handles_are_rejected():
 def test_strerror_covers_codes():
     for c in (0, -1, -2, -3, -4, -5):
         assert P.ising_strerror(c)
+
+
+def test_nn_sizes_and_validation():
+    assert P.ising_nn_param_count(64) == 62337
+    with pytest.raises(P.IsingError) as e:
+        P.ising_nn_param_count(32)
+    assert e.value.code == P.ISING_E_UNSUPPORTED
+    b8 = P.ising_nn_state_bytes(8, 64, 512, 65536)
+    b2 = P.ising_nn_state_bytes(2, 64, 512, 65536)
+    assert b8 > b2 > 0 and b8 % 256 == 0
+    for args, code in [((3, 64, 16, 16), P.ISING_E_UNSUPPORTED), ((8, 48, 16, 16), P.ISING_E_UNSUPPORTED),
+                       ((8, 64, 0, 16), P.ISING_E_INVALID), ((8, 64, 16, 1), P.ISING_E_INVALID)]:
+        with pytest.raises(P.IsingError) as e:
+            P.ising_nn_state_bytes(*args)
+        assert e.value.code == code
+
+
+def test_nn_create_rejects_before_touching_the_device():
+    import numpy as np
+    params = np.zeros(62337, dtype=np.float32)
+    with pytest.raises(P.IsingError) as e:
+        P.ising_nn_create(8, 64, 16, 16, params.ctypes.data, None, 1 << 30)
+    assert e.value.code == P.ISING_E_INVALID
+    with pytest.raises(P.IsingError) as e:
+        P.ising_nn_create(8, 64, 16, 16, params.ctypes.data, 256, 16)
+    assert e.value.code == P.ISING_E_NOMEM
+    with pytest.raises(P.IsingError) as e:
+        P.ising_nn_create(5, 64, 16, 16, params.ctypes.data, 256, 1 << 30)
+    assert e.value.code == P.ISING_E_UNSUPPORTED
+    for fn, args in [(P.lib().ising_nn_train_step, (None, None, None, None, 1, 1e-3, None, None)),
+                     (P.lib().ising_nn_score, (None, 1, None, None, None, None, None)),
+                     (P.lib().ising_batch_block_round, (None, None, 0, None, None))]:
+        assert fn(*args) == P.ISING_E_INVALID
+    assert P.lib().ising_nn_destroy(None) == P.ISING_OK

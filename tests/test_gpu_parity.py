@@ -330,3 +330,29 @@ def test_paper_scale_sampled():
     assert np.array_equal(gb[small], sb) and np.array_equal(gm[small], sm)
     for k, i in enumerate(small):
         assert np.array_equal(b.get_spins(i), states[k])
+
+
+# ---- hipGraph replays interleaved with eager work --------------------------------------
+
+def test_graph_replays_between_eager_calls():
+    """Every replay of a captured chunk is checked against the oracle, with eager
+    library work (observables, spin reads, a beta change) and host synchronisation
+    between replays."""
+    reps = _random_reps(31, 5)
+    b = gpu_batch(reps, dict(use_graph=1, sweeps_per_launch=3))
+    descs = [odesc(r) for r in reps]
+    states = [oracle.init_state(d) for d in descs]
+    t = 0
+    for k in range(6):
+        gb, gm = gpu_run(b, 9, 3)  # three replays of the same 3-sweep graph
+        ob, om = oracle.run_batch(descs, states, 9, t0=t, record_every=3)
+        t += 9
+        assert np.array_equal(gb, ob) and np.array_equal(gm, om), k
+        B, M = b.observables()
+        for i, s in enumerate(states):
+            assert (B[i], M[i]) == oracle.observables(s)
+        assert np.array_equal(b.get_spins(k % 5), states[k % 5])
+        if k == 2:
+            b.set_beta(1, 0.77)
+            descs[1] = oracle.desc(reps[1].Lx, reps[1].Ly, reps[1].J, 0.77, reps[1].seed, reps[1].replica, reps[1].init)
+    assert_states(b, reps, states)

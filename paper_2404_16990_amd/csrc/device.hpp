@@ -96,6 +96,18 @@ __device__ __forceinline__ SweepKey make_key(const RepDev &d, uint32_t t, uint32
     return k;
 }
 
+// acc * 2 + (bit of this lane in the lane mask): the carry-in form of
+// v_addc_co_u32 reads a compare result directly.  Written as one instruction
+// because the compiler otherwise rewrites the shift-and-add chain into
+// v_cndmask / shift / or sequences that cost more issue slots.
+__device__ __forceinline__ uint32_t shift_in_carry(uint32_t acc, uint64_t lanemask)
+{
+    uint32_t out;
+    uint64_t carry_out;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(out), "=s"(carry_out) : "v"(acc), "s"(lanemask));
+    return out;
+}
+
 // Neighbour classification and Metropolis acceptance for one 32-bit word of
 // same-colour spins (the multi-spin idea of the paper's Algorithm 2,
 // flipQuarter, restated for 1-bit words):
@@ -114,12 +126,12 @@ __device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_
     const uint32_t s2 = a3 ^ a4, c2 = a3 & a4;
     const uint32_t ge2 = c1 | c2 | (s1 & s2);
     const uint32_t eq1 = (s1 ^ s2) & ~(c1 | c2);
-    // Acceptance bits without the condition register: per site, broadcast the
-    // site's class bit (v_bfe_i32), select its threshold (v_bitop3, table
-    // 0xCA = m ? thr4 : thr8), form r - thr and take the borrow of that
-    // subtraction, r < thr, as bit 31 of (~r & t) | (~(r ^ t) & (r - t))
-    // (v_bitop3, table 0x8E), then shift it into the accumulator (v_alignbit).
-    // Sites are visited from bit 31 down so each lands at its own position.
+    // Acceptance in four instructions per site: broadcast the site's class bit
+    // (v_bfe_i32), select its threshold (v_bitop3, table 0xCA = m ? thr4 :
+    // thr8), compare r < thr into a lane mask (v_cmp_lt_u32), and shift that
+    // lane's bit of the mask into the accumulator as a carry (acc + acc + c,
+    // v_addc_co_u32).  Sites are visited from bit 31 down so each lands at its
+    // own position.
     const uint32_t thr4 = __builtin_amdgcn_readfirstlane(K.thr4);
     uint32_t acc = 0;
 #pragma unroll
@@ -131,9 +143,7 @@ __device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_
             const int b = 4 * q + j;
             const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)eq1, b, 1);
             const uint32_t t = __builtin_amdgcn_bitop3_b32(m, thr4, K.thr8, 0xCA);
-            const uint32_t d = r[j] - t;
-            const uint32_t x = __builtin_amdgcn_bitop3_b32(r[j], t, d, 0x8E);
-            acc = __builtin_amdgcn_alignbit(acc, x, 31);
+            acc = shift_in_carry(acc, __builtin_amdgcn_uicmp(r[j], t, 36 /* unsigned < */));
         }
     }
     return ge2 | acc;
@@ -144,13 +154,22 @@ __device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_
 // whose colour-c sites sit at odd columns (p = 1) the second horizontal
 // neighbour of bit k is bit k + 1 of the other plane, taken from the next word
 // nb at the top; for p = 0 it is bit k - 1, taken from the previous word nb.
+// Each 32-bit half is one funnel shift (v_alignbit_b32) of two 32-bit words.
 template <typename Word>
 __device__ __forceinline__ Word side_word(Word same, Word nb, uint32_t p)
 {
-    constexpr int BITS = WordTraits<Word>::BITS;
-    const Word from_next = (same >> 1) | (nb << (BITS - 1));
-    const Word from_prev = (same << 1) | (nb >> (BITS - 1));
-    return p ? from_next : from_prev;
+    if constexpr (WordTraits<Word>::BITS == 32) {
+        const uint32_t from_next = __builtin_amdgcn_alignbit(nb, same, 1);   // same >> 1 | nb << 31
+        const uint32_t from_prev = __builtin_amdgcn_alignbit(same, nb, 31);  // same << 1 | nb >> 31
+        return p ? from_next : from_prev;
+    } else {
+        const uint32_t sl = (uint32_t)same, sh = (uint32_t)(same >> 32);
+        const uint32_t nl = (uint32_t)nb, nh = (uint32_t)(nb >> 32);
+        const uint32_t next_lo = __builtin_amdgcn_alignbit(sh, sl, 1), next_hi = __builtin_amdgcn_alignbit(nl, sh, 1);
+        const uint32_t prev_lo = __builtin_amdgcn_alignbit(sl, nh, 31), prev_hi = __builtin_amdgcn_alignbit(sh, sl, 31);
+        const uint32_t lo = p ? next_lo : prev_lo, hi = p ? next_hi : prev_hi;
+        return ((uint64_t)hi << 32) | lo;
+    }
 }
 
 // Update of one Word (32 or 64 spins) given its neighbour words; a 64-bit

@@ -50,6 +50,52 @@ __global__ __launch_bounds__(256) void k_init(const RepDev *__restrict__ reps,
 }
 
 // ---------------------------------------------------------------------------
+// one thread's share of one colour phase: words idx = first, first + THREADS,
+// ... < end of a plane of Ly rows x Wn words.  Indices advance incrementally:
+// the vertical neighbours wrap with an unsigned min (u or u + total, whichever
+// is in range), and the word's first Philox counter is idx * BITS / 4 because
+// a colour row holds Wn * BITS = Lx / 2 sites.  FIXED_W: Wn divides THREADS,
+// so the thread's column w and its horizontal neighbours never change.
+// ---------------------------------------------------------------------------
+template <typename Word, int THREADS, bool FIXED_W>
+__device__ __forceinline__ void update_words(const Word *__restrict__ src, Word *__restrict__ dst,
+                                             uint32_t first, uint32_t end, uint32_t Ly, uint32_t Wn,
+                                             const SweepKey &K, bool rec, uint32_t &anti, uint32_t &pop)
+{
+    constexpr uint32_t QW = WordTraits<Word>::BITS / 4;
+    const uint32_t total = Ly * Wn;
+    const uint32_t dy = THREADS / Wn, dw = THREADS - dy * Wn;
+    uint32_t y = first / Wn, w = first - y * Wn;
+    uint32_t wp = w + 1 == Wn ? 0 : w + 1, wm = w == 0 ? Wn - 1 : w - 1;
+    for (uint32_t idx = first; idx < end; idx += THREADS) {
+        const uint32_t p = (K.colour ^ y) & 1u;
+        const uint32_t u = idx - Wn, v = idx + Wn;
+        const Word same = src[idx];
+        const Word up = src[min(u, u + total)];
+        const Word dn = src[min(v, v - total)];
+        const Word nb = src[idx - w + (p ? wp : wm)];
+        const Word s = dst[idx];
+        const Word side = side_word<Word>(same, nb, p);
+        const Word ns = update_word<Word>(s, up, dn, same, side, idx * QW, K);
+        dst[idx] = ns;
+        if (rec) {
+            anti += anti_bonds<Word>(ns, up, dn, same, side);
+            pop += (uint32_t)(__popcll((uint64_t)ns) + __popcll((uint64_t)same));
+        }
+        y += dy;
+        if (!FIXED_W) {
+            w += dw;
+            if (w >= Wn) {
+                w -= Wn;
+                ++y;
+            }
+            wp = w + 1 == Wn ? 0 : w + 1;
+            wm = w == 0 ? Wn - 1 : w - 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // streaming sweep: one colour of one sweep for a list of replicas; each
 // workgroup takes a contiguous run of words_per_wg words of one replica
 // ---------------------------------------------------------------------------
@@ -90,33 +136,11 @@ __global__ __launch_bounds__(THREADS) void k_sweep_stream(const RepDev *__restri
 
     const uint32_t begin = tile * words_per_wg;
     const uint32_t end = min(begin + words_per_wg, total);
-    uint32_t idx = begin + threadIdx.x;
-    uint32_t y = idx / Wn, w = idx - y * Wn;
-    const uint32_t dy = THREADS / Wn, dw = THREADS - dy * Wn;
     uint32_t anti = 0, pop = 0;
-    for (; idx < end; idx += THREADS) {
-        const NeighIdx n = neigh_idx(y, w, Ly, Wn, colour);
-        const Word same = src[n.same];
-        const Word up = src[n.up];
-        const Word dn = src[n.dn];
-        const Word nb = src[n.nb];
-        const Word s = dst[idx];
-        const Word side = side_word<Word>(same, nb, n.p);
-        // compact index of the word's first site: y Lx/2 + BITS w; quad = that / 4
-        const uint32_t q0 = y * (d.Lx >> 3) + w * (WordTraits<Word>::BITS / 4);
-        const Word ns = update_word<Word>(s, up, dn, same, side, q0, K);
-        dst[idx] = ns;
-        if (record) {
-            anti += anti_bonds<Word>(ns, up, dn, same, side);
-            pop += (uint32_t)(__popcll((uint64_t)ns) + __popcll((uint64_t)same));
-        }
-        w += dw;
-        y += dy;
-        if (w >= Wn) {
-            w -= Wn;
-            ++y;
-        }
-    }
+    if (THREADS % Wn == 0)
+        update_words<Word, THREADS, true>(src, dst, begin + threadIdx.x, end, Ly, Wn, K, record, anti, pop);
+    else
+        update_words<Word, THREADS, false>(src, dst, begin + threadIdx.x, end, Ly, Wn, K, record, anti, pop);
     if (record) {
         __shared__ int64_t red[2][THREADS / 64];
         const int64_t a = wave_sum((int64_t)anti);
@@ -177,8 +201,7 @@ void k_sweep_resident(const RepDev *__restrict__ reps,
     __syncthreads();
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
 
-    const uint32_t dy = THREADS / Wn, dw = THREADS - dy * Wn;
-    const uint32_t y_start = threadIdx.x / Wn, w_start = threadIdx.x - y_start * Wn;
+    const bool fixed_w = THREADS % Wn == 0;
     __shared__ int64_t red[2][THREADS / 64];
 
     for (uint32_t s_i = 0; s_i < n_sweeps; ++s_i) {
@@ -193,29 +216,10 @@ void k_sweep_resident(const RepDev *__restrict__ reps,
             const SweepKey K = make_key(d, t, colour);
             const bool rec_here = record && colour == 1u;
             uint32_t anti = 0, pop = 0;
-            uint32_t y = y_start, w = w_start;
-            for (uint32_t idx = threadIdx.x; idx < total; idx += THREADS) {
-                const NeighIdx n = neigh_idx(y, w, Ly, Wn, colour);
-                const Word same = src[n.same];
-                const Word up = src[n.up];
-                const Word dn = src[n.dn];
-                const Word nb = src[n.nb];
-                const Word s = dst[idx];
-                const Word side = side_word<Word>(same, nb, n.p);
-                const uint32_t q0 = y * (d.Lx >> 3) + w * (WordTraits<Word>::BITS / 4);
-                const Word ns = update_word<Word>(s, up, dn, same, side, q0, K);
-                dst[idx] = ns;
-                if (rec_here) {
-                    anti += anti_bonds<Word>(ns, up, dn, same, side);
-                    pop += (uint32_t)(__popcll((uint64_t)ns) + __popcll((uint64_t)same));
-                }
-                w += dw;
-                y += dy;
-                if (w >= Wn) {
-                    w -= Wn;
-                    ++y;
-                }
-            }
+            if (fixed_w)
+                update_words<Word, THREADS, true>(src, dst, threadIdx.x, total, Ly, Wn, K, rec_here, anti, pop);
+            else
+                update_words<Word, THREADS, false>(src, dst, threadIdx.x, total, Ly, Wn, K, rec_here, anti, pop);
             if (rec_here) {
                 const int64_t a = wave_sum((int64_t)anti);
                 const int64_t m = wave_sum((int64_t)pop);

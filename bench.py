@@ -252,7 +252,7 @@ def learned_comparison(units, plain_sweeps):
         "training": {"blocks": int(X.shape[0]), "steps": 2000, "batch": 512, "lr": 2e-3,
                      "loss": hist, "seconds": t_train},
         "plain": plain, "learned": lrn,
-        "block_acceptance": float(acc.sum().cpu()) / (units * len(descs) * 1024),
+        "block_acceptance": float(acc.cpu().sum()) / (units * len(descs) * 1024),
         "learned_over_plain": lrn["effective_samples_per_s"] / plain["effective_samples_per_s"],
         "abs_m_agreement": {"within_2sigma": float(np.mean(np.abs(z) < 2)), "max_abs_z": float(np.max(np.abs(z)))},
     }

@@ -260,6 +260,19 @@ int ising_nn_forward_backward(ising_nn *m, const int8_t *dev_blocks, const int8_
 int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd, const float *dev_coupling,
                         int32_t batch, float lr, float *dev_loss, void *stream);
 
+/* ising_nn_train_step on a minibatch the library draws from a training set of
+ * n_rows blocks (dev_blocks [n_rows][Bs*Bs], dev_bnd [n_rows][4 Bs],
+ * dev_coupling [n_rows], same layouts as above): row i of the k-th training
+ * step since the parameters were last set is floor(u * n_rows / 2^32), u the
+ * first word of Philox4x32-10(counter (i, k, 0, 6), key seed), i < batch.
+ * The rows are copied into the network's workspace by a kernel, so the
+ * training set stays where it is and the host takes no part in sampling.
+ * Errors: ISING_E_INVALID for batch outside [1, max_batch], n_rows outside
+ * [1, 2^32 - 1], NULL arrays or lr <= 0.  Asynchronous. */
+int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                                const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
+                                float *dev_loss, void *stream);
+
 /* Incremental pass on n <= max_seq sequences.  score: log q (FP64) of the
  * given blocks.  sample: draw blocks with the Philox stream of (seed,
  * replica, round) and block ids blk0 + i, returning them and their log q.

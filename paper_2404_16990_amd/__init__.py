@@ -27,7 +27,8 @@ EXPORTED = [
     "ising_batch_set_beta", "ising_batch_get_schedule", "ising_batch_set_schedule",
     "ising_batch_mode_counts", "ising_batch_autotune", "ising_batch_destroy",
     "ising_nn_param_count", "ising_nn_state_bytes", "ising_nn_create", "ising_nn_get_params",
-    "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_score",
+    "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_train_step_sampled",
+    "ising_nn_score",
     "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_destroy",
 ]
 
@@ -93,6 +94,7 @@ def lib():
         L.ising_nn_set_params.argtypes = [vp, vp, vp]
         L.ising_nn_forward_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
         L.ising_nn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, vp, vp]
+        L.ising_nn_train_step_sampled.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, f32, u64, vp, vp]
         L.ising_nn_score.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ising_nn_sample.argtypes = [vp, i32, vp, vp, u64, u32, u32, u32, vp, vp, vp]
         L.ising_batch_extract_blocks.argtypes = [vp, i32, i32, u32, vp, vp, vp, vp]
@@ -246,6 +248,11 @@ def ising_nn_forward_backward(m, blocks, bnd, coupling, batch, logits, grad, los
 def ising_nn_train_step(m, blocks, bnd, coupling, batch, lr, loss, stream=None):
     _check(lib().ising_nn_train_step(m, blocks, bnd, coupling, int(batch), float(lr), loss, stream),
            "ising_nn_train_step")
+
+
+def ising_nn_train_step_sampled(m, blocks, bnd, coupling, n_rows, batch, lr, seed, loss, stream=None):
+    _check(lib().ising_nn_train_step_sampled(m, blocks, bnd, coupling, int(n_rows), int(batch), float(lr),
+                                             int(seed), loss, stream), "ising_nn_train_step_sampled")
 
 
 def ising_nn_score(m, n, blocks, bnd, coupling, logq, stream=None):
@@ -408,6 +415,13 @@ class Net:
         ising_nn_train_step(self.h, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(), blocks.shape[0],
                             lr, loss.data_ptr() if loss is not None else None, self._s())
 
+    def train_step_sampled(self, blocks, bnd, coupling, batch, lr, seed, loss=None):
+        """One Adam step on `batch` rows of the training set (blocks, bnd, coupling)
+        drawn on the device from the Philox stream of `seed` and the step count."""
+        ising_nn_train_step_sampled(self.h, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(),
+                                    blocks.shape[0], batch, lr, seed,
+                                    loss.data_ptr() if loss is not None else None, self._s())
+
     def score(self, blocks, bnd, coupling):
         torch = self.torch
         n = blocks.shape[0]
@@ -441,12 +455,21 @@ def _batch_block_round(self, net, round_, accepts=None):
     ising_batch_block_round(self.h, net.h, round_, accepts.data_ptr() if accepts is not None else None, self._s())
 
 
-def _batch_extract(self, block, per_replica, draw):
+def _batch_extract(self, block, per_replica, draw, out=None):
+    """Training blocks of every replica; `out` = (blocks, bnd, coupling) views
+    with room for n * per_replica rows receive them in place."""
     torch = self.torch
     n = self.n * per_replica
-    blocks = torch.empty((n, block * block), dtype=torch.int8, device=self.buf.device)
-    bnd = torch.empty((n, 4 * block), dtype=torch.int8, device=self.buf.device)
-    coup = torch.empty(n, dtype=torch.float32, device=self.buf.device)
+    if out is None:
+        blocks = torch.empty((n, block * block), dtype=torch.int8, device=self.buf.device)
+        bnd = torch.empty((n, 4 * block), dtype=torch.int8, device=self.buf.device)
+        coup = torch.empty(n, dtype=torch.float32, device=self.buf.device)
+    else:
+        blocks, bnd, coup = out
+        if not (blocks.shape == (n, block * block) and bnd.shape == (n, 4 * block) and coup.shape == (n,)
+                and blocks.dtype == torch.int8 and bnd.dtype == torch.int8 and coup.dtype == torch.float32
+                and blocks.is_contiguous() and bnd.is_contiguous() and coup.is_contiguous()):
+            raise ValueError("out views must be contiguous int8 [n, B*B], int8 [n, 4B], float32 [n]")
     ising_batch_extract_blocks(self.h, block, per_replica, draw, blocks.data_ptr(), bnd.data_ptr(),
                                coup.data_ptr(), self._s())
     return blocks, bnd, coup

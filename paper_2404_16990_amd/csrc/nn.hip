@@ -706,6 +706,27 @@ __global__ void k_extract(const RepDev *__restrict__ reps, const double *__restr
     kout[q] = (float)kcoup[r];
 }
 
+// Minibatch drawn on the device: row i of training step k is
+// floor(u * n_rows / 2^32) with u the first word of Philox(ctr = (i, k, 0, 6),
+// key = seed); one workgroup of 64 threads copies one row.
+__global__ __launch_bounds__(64) void k_gather_rows(const int8_t *__restrict__ x, const int8_t *__restrict__ bnd,
+                                                    const float *__restrict__ kc, uint32_t n_rows, int BB, int NB,
+                                                    uint32_t step, uint32_t seed_lo, uint32_t seed_hi,
+                                                    int8_t *__restrict__ tx, int8_t *__restrict__ tb,
+                                                    float *__restrict__ tk)
+{
+    const uint32_t i = blockIdx.x;
+    uint32_t o[4];
+    philox4x32_10(i, step, 0u, 6u, seed_lo, seed_hi, o);
+    const size_t row = (size_t)(((uint64_t)o[0] * n_rows) >> 32);
+    for (int j = threadIdx.x; j < BB; j += 64)
+        tx[(size_t)i * BB + j] = x[row * BB + j];
+    for (int j = threadIdx.x; j < NB; j += 64)
+        tb[(size_t)i * NB + j] = bnd[row * NB + j];
+    if (threadIdx.x == 0)
+        tk[i] = kc[row];
+}
+
 // standalone sequences: mode, Philox key and block id of sequence i
 __global__ void k_seq_setup(SeqDev seq, int n, uint8_t mode, uint32_t seed_lo, uint32_t seed_hi, uint32_t replica,
                             uint32_t round, uint32_t blk0)
@@ -842,6 +863,14 @@ hipError_t seq_setup(const SeqDev &seq, int n, uint8_t mode, uint64_t seed, uint
 {
     hipLaunchKernelGGL(k_seq_setup, dim3(blocks_for(n, 256)), dim3(256), 0, st, seq, n, mode,
                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), replica, round, blk0);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows(const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc, uint32_t n_rows,
+                       int batch, int Bs, uint32_t step, uint64_t seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_rows, dim3(batch), dim3(64), 0, st, x, bnd, kc, n_rows, Bs * Bs, 4 * Bs, step,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ws.tx, ws.tbnd, ws.tcoup);
     return hipGetLastError();
 }
 

@@ -69,6 +69,8 @@ struct TrainWs {
     float *partial;     // reduction partials
     float *wgrad;       // [C][KB]
     float *loss;        // [1] scratch
+    int8_t *tx, *tbnd;  // [max_batch][Bs*Bs], [max_batch][4 Bs]: minibatch drawn on the device
+    float *tcoup;       // [max_batch]
 };
 
 }  // namespace nn

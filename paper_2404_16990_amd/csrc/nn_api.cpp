@@ -31,6 +31,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct NNLayout {
     size_t params, adam_m, adam_v, grad, wt, wtt;
     size_t h[4], hb[3], xcol[3], xcolt[3], pre, dpre, dpreb, dpret, logits, dlogit, partial, wgrad, loss;
+    size_t tx, tbnd, tcoup;
     size_t sx, sbnd, scoup, skey, sblk, smode, slogq;
     size_t total;
     int Pp;
@@ -82,6 +83,9 @@ NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
     L.partial = take((size_t)(Pp / 256 + 2) * 10 * C * 4);
     L.wgrad = take((size_t)C * KB * 4);
     L.loss = take(4);
+    L.tx = take((size_t)max_batch * block * block);
+    L.tbnd = take((size_t)max_batch * 4 * block);
+    L.tcoup = take((size_t)max_batch * 4);
     L.sx = take((size_t)max_seq * block * block);
     L.sbnd = take((size_t)max_seq * 4 * block);
     L.scoup = take((size_t)max_seq * 4);
@@ -213,6 +217,9 @@ int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t 
     m->ws.partial = reinterpret_cast<float *>(B + L.partial);
     m->ws.wgrad = reinterpret_cast<float *>(B + L.wgrad);
     m->ws.loss = reinterpret_cast<float *>(B + L.loss);
+    m->ws.tx = reinterpret_cast<int8_t *>(B + L.tx);
+    m->ws.tbnd = reinterpret_cast<int8_t *>(B + L.tbnd);
+    m->ws.tcoup = reinterpret_cast<float *>(B + L.tcoup);
     m->seq.x = reinterpret_cast<int8_t *>(B + L.sx);
     m->seq.bnd = reinterpret_cast<int8_t *>(B + L.sbnd);
     m->seq.coupling = reinterpret_cast<float *>(B + L.scoup);
@@ -301,6 +308,28 @@ int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev
     if (dev_loss)
         NN_HIP(hipMemcpyAsync(dev_loss, m->ws.loss, 4, hipMemcpyDeviceToDevice, hs));
     return ISING_OK;
+}
+
+int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                                const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
+                                float *dev_loss, void *stream)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (batch < 1 || batch > m->max_batch)
+        return fail(ISING_E_INVALID, "batch must be in [1, max_batch]");
+    if (n_rows < 1 || n_rows > (int64_t)UINT32_MAX)
+        return fail(ISING_E_INVALID, "n_rows must be in [1, 2^32 - 1]");
+    if (!dev_blocks || !dev_bnd || !dev_coupling)
+        return fail(ISING_E_INVALID, "block arrays must not be NULL");
+    if (!(lr > 0.0f))
+        return fail(ISING_E_INVALID, "lr must be > 0");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    NN_HIP(gather_rows(m->ws, dev_blocks, dev_bnd, dev_coupling, (uint32_t)n_rows, batch, m->Bs, (uint32_t)m->step,
+                       seed, hs));
+    return ising_nn_train_step(m, m->ws.tx, m->ws.tbnd, m->ws.tcoup, batch, lr, dev_loss, stream);
 }
 
 int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_t *dev_bnd,

@@ -18,6 +18,8 @@ hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const 
 hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
                     int nblk, int Bs, hipStream_t st);
 hipError_t adam(const NetDev &net, float lr, int step, hipStream_t st);
+hipError_t gather_rows(const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc, uint32_t n_rows,
+                       int batch, int Bs, uint32_t step, uint64_t seed, hipStream_t st);
 hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_seq, int Bs, hipStream_t st);
 hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
                         uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, hipStream_t st);

@@ -13,7 +13,8 @@ namespace {
 
 constexpr int kChains = 8;
 
-enum Which { MAD_U64_U32 = 0, MUL_HI_U32 = 1, MUL_LO_U32 = 2, BITOP3 = 3, XOR = 4, ADD = 5, PHILOX = 6 };
+enum Which { MAD_U64_U32 = 0, MUL_HI_U32 = 1, MUL_LO_U32 = 2, BITOP3 = 3, XOR = 4, ADD = 5, PHILOX = 6,
+             LSHL_ADD_U64 = 7, ADDC = 8, CMP = 9, BFE = 10, ALIGNBIT = 11, CNDMASK = 12 };
 
 template <int W>
 __global__ __launch_bounds__(256) void k_alu(uint32_t *out, uint32_t seed, int iters)
@@ -25,6 +26,11 @@ __global__ __launch_bounds__(256) void k_alu(uint32_t *out, uint32_t seed, int i
         b[c] = seed + blockIdx.x * 77u + c;
     }
     const uint32_t m = 0xD2511F53u ^ seed;
+    const uint64_t mm = ((uint64_t)m << 32) | (m ^ 0x5bd1e995u);
+    uint64_t lm[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+        lm[c] = __builtin_amdgcn_uicmp(a[c], b[c], 36);
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int c = 0; c < kChains; ++c) {
@@ -43,13 +49,29 @@ __global__ __launch_bounds__(256) void k_alu(uint32_t *out, uint32_t seed, int i
                 asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[c]) : "v"(b[c]));
             } else if constexpr (W == ADD) {
                 asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[c]) : "v"(b[c]));
+            } else if constexpr (W == LSHL_ADD_U64) {
+                uint64_t acc = ((uint64_t)b[c] << 32) | a[c];
+                asm volatile("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(acc) : "v"(mm));
+                a[c] = (uint32_t)acc;
+                b[c] = (uint32_t)(acc >> 32);
+            } else if constexpr (W == ADDC) {
+                asm volatile("v_addc_co_u32_e64 %0, %1, %0, %0, %1" : "+v"(a[c]), "+s"(lm[c]));
+            } else if constexpr (W == CMP) {
+                asm volatile("v_cmp_lt_u32_e64 %0, %1, %2" : "=s"(lm[c]) : "v"(a[c]), "v"(b[c]));
+                a[c] += (uint32_t)lm[c];
+            } else if constexpr (W == BFE) {
+                asm volatile("v_bfe_i32 %0, %0, 7, 1" : "+v"(a[c]));
+            } else if constexpr (W == ALIGNBIT) {
+                asm volatile("v_alignbit_b32 %0, %0, %1, 31" : "+v"(a[c]) : "v"(b[c]));
+            } else if constexpr (W == CNDMASK) {
+                asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(a[c]) : "v"(b[c]), "s"(lm[c]));
             }
         }
     }
     uint32_t r = 0;
 #pragma unroll
     for (int c = 0; c < kChains; ++c)
-        r ^= a[c] ^ b[c];
+        r ^= a[c] ^ b[c] ^ (uint32_t)lm[c] ^ (uint32_t)(lm[c] >> 32);
     out[blockIdx.x * 256 + threadIdx.x] = r;
 }
 
@@ -157,8 +179,9 @@ extern "C" {
  * 2 v_mul_lo_u32, 3 v_bitop3_b32, 4 v_xor_b32, 5 v_add_u32, 6 full Philox4x32-10.
  * out: device buffer of blocks*256 uint32.  Returns 0 and the elapsed
  * milliseconds of the timed launch (after one warm-up launch), <0 on error.
- * Operations counted: blocks*256*iters*8 instructions (which 0..5) or
- * blocks*256*iters*4 Philox calls (which 6).
+ * Operations counted: blocks*256*iters*8 instructions (which 0..5, 7..12) or
+ * blocks*256*iters*4 Philox calls (which 6).  The compare probe (9) also
+ * issues one v_add_u32 per compare to keep its chains dependent.
  */
 int ising_probe_alu(int which, void *out, int blocks, int iters, float *ms)
 {
@@ -181,6 +204,12 @@ int ising_probe_alu(int which, void *out, int blocks, int iters, float *ms)
         case BITOP3: err = run_alu<BITOP3>(o, blocks, iters, nullptr); break;
         case XOR: err = run_alu<XOR>(o, blocks, iters, nullptr); break;
         case ADD: err = run_alu<ADD>(o, blocks, iters, nullptr); break;
+        case LSHL_ADD_U64: err = run_alu<LSHL_ADD_U64>(o, blocks, iters, nullptr); break;
+        case ADDC: err = run_alu<ADDC>(o, blocks, iters, nullptr); break;
+        case CMP: err = run_alu<CMP>(o, blocks, iters, nullptr); break;
+        case BFE: err = run_alu<BFE>(o, blocks, iters, nullptr); break;
+        case ALIGNBIT: err = run_alu<ALIGNBIT>(o, blocks, iters, nullptr); break;
+        case CNDMASK: err = run_alu<CNDMASK>(o, blocks, iters, nullptr); break;
         case PHILOX:
             hipLaunchKernelGGL(k_philox, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters);
             err = hipGetLastError();

@@ -13,27 +13,29 @@ from . import Batch, Net, analysis
 
 def collect_blocks(batch: Batch, block: int, per_replica: int, draws: int, sweeps_between: int):
     """Training blocks from the plain sampler: `draws` times, run
-    `sweeps_between` sweeps and take `per_replica` blocks of every replica."""
+    `sweeps_between` sweeps and take `per_replica` blocks of every replica,
+    written straight into one preallocated training set."""
     import torch
-    xs, bn, kc = [], [], []
+    per_draw = batch.n * per_replica
+    dev = batch.buf.device
+    X = torch.empty((draws * per_draw, block * block), dtype=torch.int8, device=dev)
+    BN = torch.empty((draws * per_draw, 4 * block), dtype=torch.int8, device=dev)
+    K = torch.empty(draws * per_draw, dtype=torch.float32, device=dev)
     for d in range(draws):
         batch.run(sweeps_between)
-        x, b, k = batch.extract_blocks(block, per_replica, d)
-        xs.append(x)
-        bn.append(b)
-        kc.append(k)
-    return torch.cat(xs), torch.cat(bn), torch.cat(kc)
+        s = slice(d * per_draw, (d + 1) * per_draw)
+        batch.extract_blocks(block, per_replica, d, out=(X[s], BN[s], K[s]))
+    return X, BN, K
 
 
 def train(net: Net, X, BN, K, steps: int, batch_size: int, lr: float, seed: int = 0, log_every: int = 100):
-    """Adam on random minibatches; returns [(step, loss)] every log_every steps."""
+    """Adam on minibatches the library draws on the device from (X, BN, K);
+    returns [(step, loss)] every log_every steps."""
     import torch
-    g = torch.Generator(device="cpu").manual_seed(seed)
     loss = torch.zeros(1, dtype=torch.float32, device=X.device)
     out = []
     for s in range(steps):
-        idx = torch.randint(0, X.shape[0], (batch_size,), generator=g).to(X.device)
-        net.train_step(X[idx].contiguous(), BN[idx].contiguous(), K[idx].contiguous(), lr, loss)
+        net.train_step_sampled(X, BN, K, batch_size, lr, seed, loss)
         if s % log_every == 0 or s == steps - 1:
             out.append((s, float(loss.cpu())))
     return out
@@ -52,7 +54,7 @@ def abs_m_trace(batch: Batch, units: int, unit, record_every: int = 1):
             traces.append(rec)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    m = torch.cat([t for t in traces], dim=1).cpu().numpy().astype(np.float64)
+    m = np.concatenate([t.cpu().numpy() for t in traces], axis=1).astype(np.float64)
     return np.abs(m) / n_spins[:, None], dt
 
 

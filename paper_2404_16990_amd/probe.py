@@ -12,7 +12,8 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libising_probe.so")
 NAMES = ["v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_bitop3_b32", "v_xor_b32", "v_add_u32",
-         "philox4x32_10"]
+         "philox4x32_10", "v_lshl_add_u64", "v_addc_co_u32", "v_cmp_lt_u32+v_add_u32", "v_bfe_i32",
+         "v_alignbit_b32", "v_cndmask_b32"]
 CUS, LANES = 256, 64
 
 

@@ -128,6 +128,7 @@ def test_nn_create_rejects_before_touching_the_device():
         P.ising_nn_create(5, 64, 16, 16, params.ctypes.data, 256, 1 << 30)
     assert e.value.code == P.ISING_E_UNSUPPORTED
     for fn, args in [(P.lib().ising_nn_train_step, (None, None, None, None, 1, 1e-3, None, None)),
+                     (P.lib().ising_nn_train_step_sampled, (None, None, None, None, 10, 1, 1e-3, 0, None, None)),
                      (P.lib().ising_nn_score, (None, 1, None, None, None, None, None)),
                      (P.lib().ising_batch_block_round, (None, None, 0, None, None))]:
         assert fn(*args) == P.ISING_E_INVALID

@@ -221,27 +221,17 @@ def test_block_moves_8x8_keep_boltzmann_64x16():
 
 def test_training_reduces_loss_and_raises_acceptance():
     import torch
+    from paper_2404_16990_amd import learned
     P = _P()
     Bs, T, R = 8, 2.3, 32
     descs = [dict(Lx=64, Ly=64, J=1.0, beta=1.0 / T, seed=900 + r, replica=r, init=0) for r in range(R)]
     b = P.Batch(descs)
     b.run(500)
-    xs, bnds, kcs = [], [], []
-    for draw in range(20):
-        b.run(20)
-        x, bn, k = b.extract_blocks(Bs, 16, draw)
-        xs.append(x), bnds.append(bn), kcs.append(k)
-    X, BN, K = torch.cat(xs), torch.cat(bnds), torch.cat(kcs)
+    X, BN, K = learned.collect_blocks(b, Bs, 16, 20, 20)
     net = P.Net(_params(1.0), block=Bs, max_batch=512, max_seq=8192)
     untrained = P.Net(_params(1.0), block=Bs, max_batch=16, max_seq=8192)
-    loss = torch.zeros(1, device="cuda")
-    losses = []
-    g = torch.Generator(device="cpu").manual_seed(0)
-    for step in range(300):
-        idx = torch.randint(0, X.shape[0], (512,), generator=g).cuda()
-        net.train_step(X[idx].contiguous(), BN[idx].contiguous(), K[idx].contiguous(), 2e-3, loss)
-        if step % 50 == 0 or step == 299:
-            losses.append(float(loss.cpu()))
+    hist = learned.train(net, X, BN, K, 300, 512, 2e-3, seed=0, log_every=50)
+    losses = [l for _, l in hist]
     assert losses[-1] < 0.8 * losses[0], losses
     # acceptance of block moves on the equilibrated lattices
     rates = {}
@@ -252,3 +242,24 @@ def test_training_reduces_loss_and_raises_acceptance():
         torch.cuda.synchronize()
         rates[name] = float(acc.sum()) / (10 * R * 64)
     assert rates["trained"] > 2 * rates["untrained"] + 0.01, rates
+
+
+def test_sampled_minibatch_rows_follow_the_philox_definition():
+    """train_step_sampled == train_step on the rows floor(u n / 2^32), u the
+    first word of Philox(counter (i, k, 0, 6), key seed), for steps k = 0, 1, 2."""
+    import torch
+    from oracle import philox
+    P = _P()
+    rng = np.random.default_rng(77)
+    Bs, n_rows, batch, seed = 4, 1000, 96, 0x1234_5678_9ABC
+    x, bnd, kc = _rand_blocks(rng, n_rows, Bs)
+    X, BN, K = _dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32)
+    a = P.Net(_params(1.0), block=Bs, max_batch=batch, max_seq=64)
+    b = P.Net(_params(1.0), block=Bs, max_batch=batch, max_seq=64)
+    key = philox.seed_key(seed)
+    for k in range(3):
+        rows = np.array([(philox.philox4x32_10((i, k, 0, 6), key)[0] * n_rows) >> 32 for i in range(batch)])
+        a.train_step_sampled(X, BN, K, batch, 1e-3, seed)
+        b.train_step(_dev(x[rows], torch.int8), _dev(bnd[rows], torch.int8), _dev(kc[rows], torch.float32), 1e-3)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.params, b.params), k

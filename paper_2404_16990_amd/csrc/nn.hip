@@ -409,82 +409,196 @@ __global__ void k_adam(float *__restrict__ params, const float *__restrict__ gra
 }
 
 // ---------------------------------------------------------------------------
-// incremental autoregressive pass: 16 sequences per workgroup, one site per
-// step; layers 2..4 on MFMA with this wave's weight slice held in registers
+// Autoregressive passes.  Both evaluate the conditional of every site k of a
+// block given the sites before it and the boundary with one per-site
+// arithmetic: layer 1 on the VALU (layer1_site), layers 2..4 as MFMA tiles
+// whose 16 rows are 16 sequences at one site and whose K runs over the taps
+// in a fixed order, the logit head summed in a fixed tree, and the uint32
+// threshold (site_threshold).  A matrix-core product row depends only on its
+// own A row, so a block scored by k_nn_score gets bit for bit the log q that
+// k_nn_sample assigned when it drew it.
+//  - k_nn_sample: 16 sequences per workgroup, one site per step (a site
+//    depends on the one drawn just before it);
+//  - k_nn_score: 16 given blocks per workgroup, one block row per step (a
+//    site only looks at the row above and at sites to its left, all known),
+//    so each wave runs Bs independent MFMA chains per layer.
+// Each wave owns 16 output channels of layers 2..4, whose BF16 weights it
+// keeps in registers for the whole pass.
 // ---------------------------------------------------------------------------
 constexpr int SEQ_PER_WG = 16;
 constexpr int RING_ROW = C + 8;  // padded row (bf16 elements) against LDS bank conflicts
 
-__global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq, int Bs)
+struct ArWeights {
+    bf16x8 w[3][10];  // layers 2..4: this lane's B-operand slices (output channel cw)
+    float bias[3], wo_c, bo;
+    float w1[4], u1[4], v1, b1;  // layer 1 of channel tid & 63
+};
+
+__device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int lane, ArWeights &p)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][RING_ROW];
-    __shared__ float head_part[4][SEQ_PER_WG];
-    __shared__ int8_t xs[SEQ_PER_WG][64];
-    __shared__ int8_t bs[SEQ_PER_WG][32];
-    __shared__ uint32_t thr_s[SEQ_PER_WG][64];
-    __shared__ float ks[SEQ_PER_WG];
-    __shared__ double lq_part[SEQ_PER_WG][16];
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int s0 = blockIdx.x * SEQ_PER_WG;
-    const int BB = Bs * Bs;
     const float *P = net.params;
-
-    for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
-        const int s = i >> 6, k = i & 63;
-        int8_t v = 0;
-        if (s0 + s < n_seq && k < BB && seq.mode[s0 + s] == 0)
-            v = seq.x[(size_t)(s0 + s) * BB + k];
-        xs[s][k] = v;
-    }
-    for (int i = tid; i < SEQ_PER_WG * 32; i += 256) {
-        const int s = i >> 5, k = i & 31;
-        bs[s][k] = (s0 + s < n_seq && k < 4 * Bs) ? seq.bnd[(size_t)(s0 + s) * 4 * Bs + k] : (int8_t)0;
-    }
-    if (tid < SEQ_PER_WG)
-        ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
-
-    // this wave's output channels: 16*wave .. 16*wave+15 (B operand column = lane & 15)
     const int cw = 16 * wave + (lane & 15);
-    bf16x8 wreg[3][10];
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
         for (int q = 0; q < 10; ++q)
-            wreg[l][q] = load_bf16x8(net.wt + ((size_t)l * C + cw) * KB + q * 32 + 8 * (lane >> 4));
-    float bias[3];
+            p.w[l][q] = load_bf16x8(net.wt + ((size_t)l * C + cw) * KB + q * 32 + 8 * (lane >> 4));
 #pragma unroll
     for (int l = 0; l < 3; ++l)
-        bias[l] = P[off_b(l + 2) + cw];
-    const float wo_c = P[OFF_WO + cw], bo = P[OFF_BO];
-    // layer-1 parameters of this thread's channel (tid & 63)
-    const int c1 = tid & (C - 1);
-    float w1[4], u1[4];
+        p.bias[l] = P[off_b(l + 2) + cw];
+    p.wo_c = P[OFF_WO + cw];
+    p.bo = P[OFF_BO];
+    const int c1 = lane;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        w1[t] = P[OFF_W1 + t * C + c1];
-        u1[t] = P[OFF_U1 + t * C + c1];
+        p.w1[t] = P[OFF_W1 + t * C + c1];
+        p.u1[t] = P[OFF_U1 + t * C + c1];
     }
-    const float v1 = P[OFF_V1 + c1], b1 = P[OFF_B1 + c1];
+    p.v1 = P[OFF_V1 + c1];
+    p.b1 = P[OFF_B1 + c1];
+}
+
+// Layer-1 output (BF16) of channel lane at site (i, j) of one sequence: x
+// holds the sequence's known sites; the site at position ov_pos (if any)
+// is taken from ov_val instead.
+template <int BS>
+__device__ __forceinline__ uint16_t layer1_site(const int8_t *x, int ov_pos, float ov_val, const int8_t *bnd,
+                                                float kc, int i, int j, const ArWeights &p)
+{
+    float pre = __builtin_fmaf(kc, p.v1, p.b1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int ii = i + tap_di(t), jj = j + tap_dj(t);
+        if (ii >= 0 && jj >= 0 && jj < BS) {
+            const int pos = ii * BS + jj;
+            pre = __builtin_fmaf(pos == ov_pos ? ov_val : (float)x[pos], p.w1[t], pre);
+        }
+    }
+    pre += boundary_field(bnd, BS, i, j, p.u1);
+    return f2bf(net_tanh(pre));
+}
+
+// uint32 threshold of a site from its logit: clamp(floor(sigmoid * 2^32), 1,
+// 2^32 - 1).  The product with 2^32 is exact in FP32 and the conversion
+// truncates, so this is the floor of the exact product.
+__device__ __forceinline__ uint32_t site_threshold(float logit)
+{
+    const float scaled = net_sigmoid(logit) * 4294967296.0f;
+    const uint32_t t = scaled >= 4294967296.0f ? 0xffffffffu : (uint32_t)scaled;
+    return t > 1u ? t : 1u;
+}
+
+// Sum of the logit head over this wave's 16 channels for the 4 rows this
+// lane holds (fixed butterfly over the 16 lanes of a row group); lane 0 of
+// each group writes out[row].
+__device__ __forceinline__ void head_rows(const floatx4 &acc, const ArWeights &p, int lane, float *out)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float v = net_tanh(acc[r] + p.bias[2]) * p.wo_c;
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        if ((lane & 15) == 0)
+            out[4 * (lane >> 4) + r] = v;
+    }
+}
+
+__device__ __forceinline__ float head_logit(const float *h0, const float *h1, const float *h2, const float *h3,
+                                            int row, float bo)
+{
+    return ((h0[row] + h1[row]) + (h2[row] + h3[row])) + bo;
+}
+
+// log q = sum_k log(thr_k or 2^32 - thr_k) - BB * 32 ln 2 in FP64, summed in a
+// fixed order: 16 parts of 4 consecutive sites, then the parts in order.
+__device__ __forceinline__ void logq_parts(const int8_t (*xs)[64], const uint32_t (*thr)[64], int BB, int tid,
+                                           double (*part)[16])
+{
+    const int s = tid >> 4, pt = tid & 15;
+    double acc = 0.0;
+    for (int k = pt * 4; k < pt * 4 + 4 && k < BB; ++k) {
+        const double t = (double)thr[s][k];
+        acc += log(xs[s][k] > 0 ? t : 4294967296.0 - t);
+    }
+    part[s][pt] = acc;
+}
+
+__device__ __forceinline__ double logq_total(const double *part, int BB)
+{
+    double sum = 0.0;
+    for (int pt = 0; pt < 16; ++pt)
+        sum += part[pt];
+    return sum - (double)BB * 32.0 * 0.69314718055994530942;
+}
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int first, int n_seq)
+{
+    constexpr int BB = BS * BS;
+    __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][RING_ROW];
+    __shared__ float head_part[4][SEQ_PER_WG];
+    __shared__ int8_t xs[SEQ_PER_WG][64];
+    __shared__ int8_t bs[SEQ_PER_WG][32];
+    __shared__ uint32_t ut[SEQ_PER_WG][64];  // site uniform; replaced by the site's threshold once drawn
+    __shared__ float ks[SEQ_PER_WG];
+    __shared__ double lq_part[SEQ_PER_WG][16];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int s0 = first + blockIdx.x * SEQ_PER_WG, end = first + n_seq;
+
+    for (int i = tid; i < SEQ_PER_WG * 64; i += 256)
+        xs[i >> 6][i & 63] = 0;
+    for (int i = tid; i < SEQ_PER_WG * 32; i += 256) {
+        const int s = i >> 5, k = i & 31;
+        bs[s][k] = (s0 + s < end && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
+    }
+    if (tid < SEQ_PER_WG)
+        ks[tid] = s0 + tid < end ? seq.coupling[s0 + tid] : 0.f;
+    // site uniforms: word site & 3 of Philox(ctr = (site >> 2, round, replica, 3)),
+    // site = blk * BB + k; BB is a multiple of 4, so one call serves sites 4m..4m+3
+    for (int i = tid; i < SEQ_PER_WG * 16; i += 256) {
+        const int s = i >> 4, m = i & 15;
+        if (s0 + s < end && 4 * m < BB) {
+            const uint32_t *kk = seq.key + 4 * (size_t)(s0 + s);
+            const uint32_t site0 = seq.blk[s0 + s] * (uint32_t)BB + 4u * m;
+            uint32_t o[4];
+            philox4x32_10(site0 >> 2, kk[3], kk[2], 3u, kk[0], kk[1], o);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                ut[s][4 * m + r] = o[r];
+        }
+    }
+    ArWeights p;
+    load_ar_weights(net, wave & 3, lane, p);
+    const int cw = 16 * wave + (lane & 15);
     __syncthreads();
 
-    for (int k = 0; k < BB; ++k) {
-        const int i = k / Bs, j = k - i * Bs, slot = k % RING;
-        // layer 1: thread -> channel c1, sequences wave, wave+4, wave+8, wave+12
+    for (int k = 0; k <= BB; ++k) {
+        const int i = k / BS, j = k - i * BS, slot = k % RING;
+        // draw site k - 1 of this wave's sequences (every lane of the wave
+        // evaluates the same decision; lane 0 records it), then layer 1 of site k
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int s = wave + 4 * q;
-            float pre = ks[s] * v1 + b1;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int ii = i + tap_di(t), jj = j + tap_dj(t);
-                if (ii >= 0 && jj >= 0 && jj < Bs)
-                    pre += (float)xs[s][ii * Bs + jj] * w1[t];
+            float xprev = 0.f;
+            if (k > 0) {
+                const uint32_t thr = site_threshold(
+                    head_logit(head_part[0], head_part[1], head_part[2], head_part[3], s, p.bo));
+                const int8_t xv = ut[s][k - 1] < thr ? (int8_t)1 : (int8_t)-1;
+                xprev = (float)xv;
+                if (lane == 0) {
+                    xs[s][k - 1] = xv;
+                    ut[s][k - 1] = thr;
+                }
             }
-            pre += boundary_field(&bs[s][0], Bs, i, j, u1);
-            ring[0][slot][s][c1] = f2bf(net_tanh(pre));
+            if (k < BB)
+                ring[0][slot][s][lane] = layer1_site<BS>(&xs[s][0], k - 1, xprev, &bs[s][0], ks[s], i, j, p);
         }
         __syncthreads();
+        if (k == BB)
+            break;
         // layers 2..4 on the matrix cores; layer 4 feeds the logit head directly
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -494,73 +608,122 @@ __global__ __launch_bounds__(256) void k_nn_ar(NetDev net, SeqDev seq, int n_seq
                 const int t = q >> 1, half = q & 1;
                 const int ii = i + tap_di(t), jj = j + tap_dj(t);
                 bf16x8 a = zero_bf16x8();
-                if (ii >= 0 && jj >= 0 && jj < Bs) {
-                    const int pslot = (k + tap_di(t) * Bs + tap_dj(t) + RING) % RING;
+                if (ii >= 0 && jj >= 0 && jj < BS) {
+                    const int pslot = (k + tap_di(t) * BS + tap_dj(t) + RING) % RING;
                     a = load_bf16x8(&ring[l][pslot][lane & 15][half * 32 + 8 * (lane >> 4)]);
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[l][q], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, p.w[l][q], acc, 0, 0, 0);
             }
             if (l < 2) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    ring[l + 1][slot][4 * (lane >> 4) + r][cw] = f2bf(net_tanh(acc[r] + bias[l]));
+                    ring[l + 1][slot][4 * (lane >> 4) + r][cw] = f2bf(net_tanh(acc[r] + p.bias[l]));
             } else {
-                // head: sum over this wave's 16 channels of h4 * wo with a fixed
-                // butterfly over the 16 lanes that share a row group
+                head_rows(acc, p, lane, head_part[wave]);
+            }
+            __syncthreads();
+        }
+    }
+    logq_parts(xs, ut, BB, tid, lq_part);
+    __syncthreads();
+    for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
+        const int s = i >> 6, k = i & 63;
+        if (s0 + s < end && k < BB)
+            seq.x[(size_t)(s0 + s) * BB + k] = xs[s][k];
+    }
+    if (tid < SEQ_PER_WG && s0 + tid < end)
+        seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
+}
+
+// 512 threads: wave w computes output channels 16 (w & 3) .. +15 for the
+// sites j of a row with j / (BS / 2) == w >> 2 (half the row's tiles).
+template <int BS>
+__global__ __launch_bounds__(512) void k_nn_score(NetDev net, SeqDev seq, int n_seq)
+{
+    constexpr int BB = BS * BS, HT = BS / 2;  // tiles per wave
+    // layer outputs of the current and the previous block row: [layer][row & 1][site j][sequence][channel]
+    __shared__ __attribute__((aligned(16))) uint16_t rows[3][2][BS][SEQ_PER_WG][RING_ROW];
+    __shared__ float head_part[4][BS][SEQ_PER_WG];
+    __shared__ int8_t xs[SEQ_PER_WG][64];
+    __shared__ int8_t bs[SEQ_PER_WG][32];
+    __shared__ uint32_t thr_s[SEQ_PER_WG][64];
+    __shared__ float ks[SEQ_PER_WG];
+    __shared__ double lq_part[SEQ_PER_WG][16];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nsl = wave & 3, j0 = (wave >> 2) * HT;
+    const int s0 = blockIdx.x * SEQ_PER_WG;
+
+    for (int i = tid; i < SEQ_PER_WG * 64; i += 512) {
+        const int s = i >> 6, k = i & 63;
+        xs[s][k] = (s0 + s < n_seq && k < BB) ? seq.x[(size_t)(s0 + s) * BB + k] : (int8_t)0;
+    }
+    for (int i = tid; i < SEQ_PER_WG * 32; i += 512) {
+        const int s = i >> 5, k = i & 31;
+        bs[s][k] = (s0 + s < n_seq && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
+    }
+    if (tid < SEQ_PER_WG)
+        ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
+    ArWeights p;
+    load_ar_weights(net, nsl, lane, p);
+    const int cw = 16 * nsl + (lane & 15);
+    __syncthreads();
+
+    for (int i = 0; i < BS; ++i) {
+        const int par = i & 1;
+        // layer 1 of row i: channel lane, sequences wave and wave + 8, every site
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = net_tanh(acc[r] + bias[l]) * wo_c;
-                    v += __shfl_xor(v, 1, 64);
-                    v += __shfl_xor(v, 2, 64);
-                    v += __shfl_xor(v, 4, 64);
-                    v += __shfl_xor(v, 8, 64);
-                    if ((lane & 15) == 0)
-                        head_part[wave][4 * (lane >> 4) + r] = v;
+        for (int q = 0; q < 2; ++q) {
+            const int s = wave + 8 * q;
+#pragma unroll
+            for (int j = 0; j < BS; ++j)
+                rows[0][par][j][s][lane] = layer1_site<BS>(&xs[s][0], -1, 0.f, &bs[s][0], ks[s], i, j, p);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            floatx4 acc[HT];
+#pragma unroll
+            for (int jt = 0; jt < HT; ++jt)
+                acc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                const int t = q >> 1, half = q & 1;
+                const int ii = i + tap_di(t);
+#pragma unroll
+                for (int jt = 0; jt < HT; ++jt) {
+                    const int jj = j0 + jt + tap_dj(t);
+                    bf16x8 a = zero_bf16x8();
+                    if (ii >= 0 && jj >= 0 && jj < BS)
+                        a = load_bf16x8(&rows[l][ii & 1][jj][lane & 15][half * 32 + 8 * (lane >> 4)]);
+                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, p.w[l][q], acc[jt], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int jt = 0; jt < HT; ++jt) {
+                if (l < 2) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        rows[l + 1][par][j0 + jt][4 * (lane >> 4) + r][cw] =
+                            f2bf(net_tanh(acc[jt][r] + p.bias[l]));
+                } else {
+                    head_rows(acc[jt], p, lane, head_part[nsl][j0 + jt]);
                 }
             }
             __syncthreads();
         }
-        // threshold and decision (one thread per sequence)
-        if (tid < SEQ_PER_WG && s0 + tid < n_seq) {
-            const int s = tid, g = s0 + s;
-            const float logit = ((head_part[0][s] + head_part[1][s]) + (head_part[2][s] + head_part[3][s])) + bo;
-            const float pr = net_sigmoid(logit);
-            double scaled = floor((double)pr * 4294967296.0);
-            scaled = fmin(fmax(scaled, 1.0), 4294967295.0);
-            const uint32_t thr = (uint32_t)scaled;
-            if (seq.mode[g] == 1) {
-                uint32_t o[4];
-                const uint32_t *kk = seq.key + 4 * (size_t)g;
-                const uint32_t site = seq.blk[g] * (uint32_t)BB + (uint32_t)k;
-                philox4x32_10(site >> 2, kk[3], kk[2], 3u, kk[0], kk[1], o);
-                xs[s][k] = o[site & 3] < thr ? (int8_t)1 : (int8_t)-1;
-            }
-            thr_s[s][k] = thr;
+        if (tid < SEQ_PER_WG * BS) {
+            const int s = tid / BS, j = tid - s * BS;
+            thr_s[s][i * BS + j] = site_threshold(
+                head_logit(head_part[0][j], head_part[1][j], head_part[2][j], head_part[3][j], s, p.bo));
         }
-        __syncthreads();
-    }
-    // log q = sum_k log(thr_k or 2^32 - thr_k) - BB * 32 ln 2, summed in a fixed order
-    {
-        const int s = tid >> 4, part = tid & 15;
-        double acc = 0.0;
-        for (int k = part * 4; k < part * 4 + 4 && k < BB; ++k) {
-            const double thr = (double)thr_s[s][k];
-            acc += log(xs[s][k] > 0 ? thr : 4294967296.0 - thr);
-        }
-        lq_part[s][part] = acc;
     }
     __syncthreads();
-    for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
-        const int s = i >> 6, k = i & 63;
-        if (s0 + s < n_seq && k < BB && seq.mode[s0 + s] == 1)
-            seq.x[(size_t)(s0 + s) * BB + k] = xs[s][k];
-    }
-    if (tid < SEQ_PER_WG && s0 + tid < n_seq) {
-        double sum = 0.0;
-        for (int part = 0; part < 16; ++part)
-            sum += lq_part[tid][part];
-        seq.logq[s0 + tid] = sum - (double)BB * 32.0 * 0.69314718055994530942;
-    }
+    if (tid < 256)
+        logq_parts(xs, thr_s, BB, tid, lq_part);
+    __syncthreads();
+    if (tid < SEQ_PER_WG && s0 + tid < n_seq)
+        seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,20 +777,20 @@ __global__ void k_block_gather(const RepDev *__restrict__ reps, const double *__
     uint32_t bx, by;
     block_coords(idx, nbx, colour, &bx, &by);
     const int BB = Bs * Bs;
-    int8_t *x0 = seq.x + (size_t)(2 * b) * BB;
-    int8_t *bnd0 = seq.bnd + (size_t)(2 * b) * 4 * Bs;
+    // sequence b scores the current block, sequence count + b draws its proposal
+    int8_t *x0 = seq.x + (size_t)b * BB;
+    int8_t *bnd0 = seq.bnd + (size_t)b * 4 * Bs;
     read_block(d, Bs, bx, by, x0, bnd0);
     for (int q = 0; q < 4 * Bs; ++q)
-        seq.bnd[(size_t)(2 * b + 1) * 4 * Bs + q] = bnd0[q];
+        seq.bnd[(size_t)(count + b) * 4 * Bs + q] = bnd0[q];
     for (int q = 0; q < 2; ++q) {
-        const size_t s = 2 * b + q;
+        const size_t s = b + (size_t)q * count;
         seq.coupling[s] = (float)kcoup[r];
         seq.key[4 * s + 0] = d.seed_lo;
         seq.key[4 * s + 1] = d.seed_hi;
         seq.key[4 * s + 2] = d.replica;
         seq.key[4 * s + 3] = round;
         seq.blk[s] = by * nbx + bx;
-        seq.mode[s] = (uint8_t)q;
     }
 }
 
@@ -647,9 +810,9 @@ __global__ void k_block_mh(const RepDev *__restrict__ reps, const double *__rest
     uint32_t bx, by;
     block_coords(idx, nbx, colour, &bx, &by);
     const int BB = Bs * Bs;
-    const int8_t *s = seq.x + (size_t)(2 * b) * BB;
-    const int8_t *sp = seq.x + (size_t)(2 * b + 1) * BB;
-    const int8_t *bn = seq.bnd + (size_t)(2 * b) * 4 * Bs;
+    const int8_t *s = seq.x + (size_t)b * BB;
+    const int8_t *sp = seq.x + (size_t)(count + b) * BB;
+    const int8_t *bn = seq.bnd + (size_t)b * 4 * Bs;
     // change of the bond sum: interior bonds and bonds to the boundary
     int dB = 0;
     for (int i = 0; i < Bs; ++i)
@@ -669,7 +832,7 @@ __global__ void k_block_mh(const RepDev *__restrict__ reps, const double *__rest
         dB += (sp[i * Bs + Bs - 1] - s[i * Bs + Bs - 1]) * bn[3 * Bs + i];
     }
     // log of pi(s') q(s) / (pi(s) q(s')), pi ~ exp(K B)
-    const double logA = kcoup[r] * (double)dB + seq.logq[2 * b] - seq.logq[2 * b + 1];
+    const double logA = kcoup[r] * (double)dB + seq.logq[b] - seq.logq[count + b];
     uint32_t o[4];
     philox4x32_10(by * nbx + bx, round, d.replica, 4u, d.seed_lo, d.seed_hi, o);
     const double u = (double)(((uint64_t)o[0] << 21) | (o[1] >> 11)) * 1.1102230246251565404e-16;  // 2^-53
@@ -727,14 +890,13 @@ __global__ __launch_bounds__(64) void k_gather_rows(const int8_t *__restrict__ x
         tk[i] = kc[row];
 }
 
-// standalone sequences: mode, Philox key and block id of sequence i
-__global__ void k_seq_setup(SeqDev seq, int n, uint8_t mode, uint32_t seed_lo, uint32_t seed_hi, uint32_t replica,
-                            uint32_t round, uint32_t blk0)
+// standalone sampled sequences: Philox key and block id of sequence i
+__global__ void k_seq_setup(SeqDev seq, int n, uint32_t seed_lo, uint32_t seed_hi, uint32_t replica, uint32_t round,
+                            uint32_t blk0)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    seq.mode[i] = mode;
     seq.key[4 * i + 0] = seed_lo;
     seq.key[4 * i + 1] = seed_hi;
     seq.key[4 * i + 2] = replica;
@@ -833,12 +995,32 @@ hipError_t adam(const NetDev &net, float lr, int step, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_seq, int Bs, hipStream_t st)
+template <int BS>
+static hipError_t ar_pass_bs(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, hipStream_t st)
 {
-    if (n_seq <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_nn_ar, dim3(blocks_for(n_seq, SEQ_PER_WG)), dim3(256), 0, st, net, seq, n_seq, Bs);
-    return hipGetLastError();
+    if (n_score > 0) {
+        hipLaunchKernelGGL(k_nn_score<BS>, dim3(blocks_for(n_score, SEQ_PER_WG)), dim3(512), 0, st, net, seq,
+                           n_score);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (n_sample > 0) {
+        hipLaunchKernelGGL(k_nn_sample<BS>, dim3(blocks_for(n_sample, SEQ_PER_WG)), dim3(256), 0, st, net, seq,
+                           n_score, n_sample);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, int Bs, hipStream_t st)
+{
+    switch (Bs) {
+    case 2: return ar_pass_bs<2>(net, seq, n_score, n_sample, st);
+    case 4: return ar_pass_bs<4>(net, seq, n_score, n_sample, st);
+    case 8: return ar_pass_bs<8>(net, seq, n_score, n_sample, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
@@ -858,10 +1040,10 @@ hipError_t block_mh(const RepDev *reps, const double *kcoup, int Bs, uint32_t co
     return hipGetLastError();
 }
 
-hipError_t seq_setup(const SeqDev &seq, int n, uint8_t mode, uint64_t seed, uint32_t replica, uint32_t round,
-                     uint32_t blk0, hipStream_t st)
+hipError_t seq_setup(const SeqDev &seq, int n, uint64_t seed, uint32_t replica, uint32_t round, uint32_t blk0,
+                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seq_setup, dim3(blocks_for(n, 256)), dim3(256), 0, st, seq, n, mode,
+    hipLaunchKernelGGL(k_seq_setup, dim3(blocks_for(n, 256)), dim3(256), 0, st, seq, n,
                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), replica, round, blk0);
     return hipGetLastError();
 }

@@ -51,7 +51,6 @@ struct SeqDev {
     float *coupling;  // [n]: K = beta*J
     uint32_t *key;    // [n][4]: seed_lo, seed_hi, replica, round
     uint32_t *blk;    // [n]: block id (Philox counter for the site uniforms)
-    uint8_t *mode;    // [n]: 0 score, 1 sample
     double *logq;     // [n]
 };
 

@@ -32,7 +32,7 @@ struct NNLayout {
     size_t params, adam_m, adam_v, grad, wt, wtt;
     size_t h[4], hb[3], xcol[3], xcolt[3], pre, dpre, dpreb, dpret, logits, dlogit, partial, wgrad, loss;
     size_t tx, tbnd, tcoup;
-    size_t sx, sbnd, scoup, skey, sblk, smode, slogq;
+    size_t sx, sbnd, scoup, skey, sblk, slogq;
     size_t total;
     int Pp;
 };
@@ -91,7 +91,6 @@ NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
     L.scoup = take((size_t)max_seq * 4);
     L.skey = take((size_t)max_seq * 16);
     L.sblk = take((size_t)max_seq * 4);
-    L.smode = take((size_t)max_seq);
     L.slogq = take((size_t)max_seq * 8);
     L.total = off;
     return L;
@@ -225,7 +224,6 @@ int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t 
     m->seq.coupling = reinterpret_cast<float *>(B + L.scoup);
     m->seq.key = reinterpret_cast<uint32_t *>(B + L.skey);
     m->seq.blk = reinterpret_cast<uint32_t *>(B + L.sblk);
-    m->seq.mode = reinterpret_cast<uint8_t *>(B + L.smode);
     m->seq.logq = reinterpret_cast<double *>(B + L.slogq);
     st = upload_params(m, host_params, reinterpret_cast<hipStream_t>(stream));
     if (st != ISING_OK) {
@@ -348,8 +346,7 @@ int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_
     NN_HIP(hipMemcpyAsync(m->seq.x, dev_blocks, (size_t)n * BB, hipMemcpyDeviceToDevice, hs));
     NN_HIP(hipMemcpyAsync(m->seq.bnd, dev_bnd, (size_t)n * 4 * m->Bs, hipMemcpyDeviceToDevice, hs));
     NN_HIP(hipMemcpyAsync(m->seq.coupling, dev_coupling, (size_t)n * 4, hipMemcpyDeviceToDevice, hs));
-    NN_HIP(seq_setup(m->seq, n, 0, 0, 0, 0, 0, hs));
-    NN_HIP(ar_pass(m->net, m->seq, n, m->Bs, hs));
+    NN_HIP(ar_pass(m->net, m->seq, n, 0, m->Bs, hs));
     NN_HIP(hipMemcpyAsync(dev_logq, m->seq.logq, (size_t)n * 8, hipMemcpyDeviceToDevice, hs));
     return ISING_OK;
 }
@@ -370,8 +367,8 @@ int ising_nn_sample(ising_nn *m, int32_t n, const int8_t *dev_bnd, const float *
     const int BB = m->Bs * m->Bs;
     NN_HIP(hipMemcpyAsync(m->seq.bnd, dev_bnd, (size_t)n * 4 * m->Bs, hipMemcpyDeviceToDevice, hs));
     NN_HIP(hipMemcpyAsync(m->seq.coupling, dev_coupling, (size_t)n * 4, hipMemcpyDeviceToDevice, hs));
-    NN_HIP(seq_setup(m->seq, n, 1, seed, replica, round, blk0, hs));
-    NN_HIP(ar_pass(m->net, m->seq, n, m->Bs, hs));
+    NN_HIP(seq_setup(m->seq, n, seed, replica, round, blk0, hs));
+    NN_HIP(ar_pass(m->net, m->seq, 0, n, m->Bs, hs));
     NN_HIP(hipMemcpyAsync(dev_blocks_out, m->seq.x, (size_t)n * BB, hipMemcpyDeviceToDevice, hs));
     NN_HIP(hipMemcpyAsync(dev_logq, m->seq.logq, (size_t)n * 8, hipMemcpyDeviceToDevice, hs));
     return ISING_OK;
@@ -421,7 +418,7 @@ int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t
         for (uint32_t first = 0; first < total; first += chunk) {
             const uint32_t count = std::min(chunk, total - first);
             NN_HIP(block_gather(b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count, per_rep, m->seq, hs));
-            NN_HIP(ar_pass(m->net, m->seq, (int)(2 * count), m->Bs, hs));
+            NN_HIP(ar_pass(m->net, m->seq, (int)count, (int)count, m->Bs, hs));
             NN_HIP(block_mh(b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count, per_rep, m->seq, acc, hs));
         }
     return ISING_OK;

@@ -96,8 +96,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--learned", action="store_true",
                     help="also run the learned-proposal comparison (64 x 256^2 near T_c)")
-    ap.add_argument("--learned-units", type=int, default=2000)
-    ap.add_argument("--plain-sweeps", type=int, default=200000)
+    ap.add_argument("--learned-units", type=int, default=10000)
+    ap.add_argument("--plain-sweeps", type=int, default=500000)
     ap.add_argument("--tune-sweeps", type=int, default=20)
     args = ap.parse_args()
 
@@ -239,13 +239,15 @@ def learned_comparison(units, plain_sweeps):
     hist = learned.train(net, X, BN, K, 2000, 512, 2e-3, log_every=500)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    tr_p, s_p = learned.plain_trace(b, plain_sweeps, 10)
+    tr_p, e_p, s_p = learned.plain_trace(b, plain_sweeps, 10)
     acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda")
-    tr_l, s_l = learned.abs_m_trace(b, units, learned.learned_units(b, net, 0, acc))
+    tr_l, e_l, s_l = learned.unit_traces(b, units, learned.learned_units(b, net, 0, acc))
     plain = learned.summarise(tr_p, s_p, 10, t_c)
     plain["tau_int_sweeps"] = plain["tau_int_points"] * 10
     lrn = learned.summarise(tr_l, s_l, 1, t_c)
     z = learned.agreement(tr_p, tr_l)
+    ze = learned.agreement(e_p, e_l)
+    temps = [w.replicas[r].T for r in range(len(w.replicas))]
     return {
         "metric": "effective independent |m| samples/s at T_c (one replica, whole-batch time)",
         "workload": w.name, "replica_at_tc": t_c, "T": w.replicas[t_c].T,
@@ -254,6 +256,10 @@ def learned_comparison(units, plain_sweeps):
         "plain": plain, "learned": lrn,
         "block_acceptance": float(acc.cpu().sum()) / (units * len(descs) * 1024),
         "learned_over_plain": lrn["effective_samples_per_s"] / plain["effective_samples_per_s"],
+        "energy_agreement": {"within_2sigma": float(np.mean(np.abs(ze) < 2)), "max_abs_z": float(np.max(np.abs(ze))),
+                             "z": [round(float(v), 3) for v in ze]},
+        "temperatures": [round(t, 6) for t in temps],
+        "abs_m_z": [round(float(v), 3) for v in z],
         "abs_m_agreement": {"within_2sigma": float(np.mean(np.abs(z) < 2)), "max_abs_z": float(np.max(np.abs(z)))},
     }
 

@@ -763,12 +763,32 @@ __device__ __forceinline__ void block_coords(uint32_t idx, uint32_t nbx, uint32_
     *bx = 2 * (idx - *by * half) + ((*by + colour) & 1u);
 }
 
-// two sequences per block: 2b scores the current block, 2b+1 samples a proposal
-__global__ void k_block_gather(const RepDev *__restrict__ reps, const double *__restrict__ kcoup, int Bs,
-                               uint32_t colour, uint32_t round, uint32_t first, uint32_t count,
-                               uint32_t per_rep, SeqDev seq)
+// Boundary spin q of block (bx, by): top row, bottom row, left column, right
+// column, Bs each, periodic.
+__device__ __forceinline__ int8_t boundary_spin(const RepDev &d, int Bs, uint32_t bx, uint32_t by, int q)
 {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t x0 = bx * Bs, y0 = by * Bs;
+    const int side = q / Bs, m = q - side * Bs;
+    uint32_t x, y;
+    if (side < 2) {
+        x = x0 + m;
+        y = side == 0 ? (y0 == 0 ? d.Ly - 1 : y0 - 1) : (y0 + Bs) % d.Ly;
+    } else {
+        y = y0 + m;
+        x = side == 2 ? (x0 == 0 ? d.Lx - 1 : x0 - 1) : (x0 + Bs) % d.Lx;
+    }
+    return (int8_t)spin_at(d, x, y);
+}
+
+// One wave per block of the round: sequence b scores the current block,
+// sequence count + b draws the proposal with the same boundary.  Lane k reads
+// site k and boundary spin k.
+__global__ __launch_bounds__(256) void k_block_gather(const RepDev *__restrict__ reps, const double *__restrict__ kcoup,
+                                                      int Bs, uint32_t colour, uint32_t round, uint32_t first,
+                                                      uint32_t count, uint32_t per_rep, SeqDev seq)
+{
+    const uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (b >= count)
         return;
     const uint32_t g = first + b, r = g / per_rep, idx = g - r * per_rep;
@@ -777,14 +797,17 @@ __global__ void k_block_gather(const RepDev *__restrict__ reps, const double *__
     uint32_t bx, by;
     block_coords(idx, nbx, colour, &bx, &by);
     const int BB = Bs * Bs;
-    // sequence b scores the current block, sequence count + b draws its proposal
-    int8_t *x0 = seq.x + (size_t)b * BB;
-    int8_t *bnd0 = seq.bnd + (size_t)b * 4 * Bs;
-    read_block(d, Bs, bx, by, x0, bnd0);
-    for (int q = 0; q < 4 * Bs; ++q)
-        seq.bnd[(size_t)(count + b) * 4 * Bs + q] = bnd0[q];
-    for (int q = 0; q < 2; ++q) {
-        const size_t s = b + (size_t)q * count;
+    if (lane < BB) {
+        const int i = lane / Bs, j = lane - i * Bs;
+        seq.x[(size_t)b * BB + lane] = (int8_t)spin_at(d, bx * Bs + j, by * Bs + i);
+    }
+    if (lane < 4 * Bs) {
+        const int8_t v = boundary_spin(d, Bs, bx, by, lane);
+        seq.bnd[(size_t)b * 4 * Bs + lane] = v;
+        seq.bnd[(size_t)(count + b) * 4 * Bs + lane] = v;
+    }
+    if (lane < 2) {
+        const size_t s = b + (size_t)lane * count;
         seq.coupling[s] = (float)kcoup[r];
         seq.key[4 * s + 0] = d.seed_lo;
         seq.key[4 * s + 1] = d.seed_hi;
@@ -794,14 +817,20 @@ __global__ void k_block_gather(const RepDev *__restrict__ reps, const double *__
     }
 }
 
-// Metropolis-Hastings for each gathered block; accepted proposals are XORed
-// into the packed planes (only this block's bits; same-colour blocks never
-// share a bond, so concurrent blocks do not interact)
-__global__ void k_block_mh(const RepDev *__restrict__ reps, const double *__restrict__ kcoup, int Bs,
-                           uint32_t colour, uint32_t round, uint32_t first, uint32_t count, uint32_t per_rep,
-                           SeqDev seq, unsigned long long *__restrict__ accepts)
+// Metropolis-Hastings for each gathered block, one wave per block: lane k
+// adds the change of the bonds of site k to its right and lower neighbours
+// inside the block and to the boundary; the exact integer sum decides with
+// log A = K dB + log q(current) - log q(proposal) against a 53-bit uniform.
+// Accepted proposals are XORed into the packed planes (only this block's
+// bits; same-colour blocks never share a bond, so concurrent blocks do not
+// interact).
+__global__ __launch_bounds__(256) void k_block_mh(const RepDev *__restrict__ reps, const double *__restrict__ kcoup,
+                                                  int Bs, uint32_t colour, uint32_t round, uint32_t first,
+                                                  uint32_t count, uint32_t per_rep, SeqDev seq,
+                                                  unsigned long long *__restrict__ accepts)
 {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (b >= count)
         return;
     const uint32_t g = first + b, r = g / per_rep, idx = g - r * per_rep;
@@ -813,24 +842,27 @@ __global__ void k_block_mh(const RepDev *__restrict__ reps, const double *__rest
     const int8_t *s = seq.x + (size_t)b * BB;
     const int8_t *sp = seq.x + (size_t)(count + b) * BB;
     const int8_t *bn = seq.bnd + (size_t)b * 4 * Bs;
-    // change of the bond sum: interior bonds and bonds to the boundary
-    int dB = 0;
-    for (int i = 0; i < Bs; ++i)
-        for (int j = 0; j < Bs; ++j) {
-            const int k = i * Bs + j;
-            if (j + 1 < Bs)
-                dB += sp[k] * sp[k + 1] - s[k] * s[k + 1];
-            if (i + 1 < Bs)
-                dB += sp[k] * sp[k + Bs] - s[k] * s[k + Bs];
-        }
-    for (int j = 0; j < Bs; ++j) {
-        dB += (sp[j] - s[j]) * bn[j];
-        dB += (sp[(Bs - 1) * Bs + j] - s[(Bs - 1) * Bs + j]) * bn[Bs + j];
+    int dB = 0, changed = 0;
+    if (lane < BB) {
+        const int i = lane / Bs, j = lane - i * Bs, k = lane;
+        const int a = s[k], ap = sp[k];
+        changed = a != ap;
+        if (j + 1 < Bs)
+            dB += ap * sp[k + 1] - a * s[k + 1];
+        if (i + 1 < Bs)
+            dB += ap * sp[k + Bs] - a * s[k + Bs];
+        if (i == 0)
+            dB += (ap - a) * bn[j];
+        if (i == Bs - 1)
+            dB += (ap - a) * bn[Bs + j];
+        if (j == 0)
+            dB += (ap - a) * bn[2 * Bs + i];
+        if (j == Bs - 1)
+            dB += (ap - a) * bn[3 * Bs + i];
     }
-    for (int i = 0; i < Bs; ++i) {
-        dB += (sp[i * Bs] - s[i * Bs]) * bn[2 * Bs + i];
-        dB += (sp[i * Bs + Bs - 1] - s[i * Bs + Bs - 1]) * bn[3 * Bs + i];
-    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        dB += __shfl_xor(dB, m, 64);
     // log of pi(s') q(s) / (pi(s) q(s')), pi ~ exp(K B)
     const double logA = kcoup[r] * (double)dB + seq.logq[b] - seq.logq[count + b];
     uint32_t o[4];
@@ -839,16 +871,13 @@ __global__ void k_block_mh(const RepDev *__restrict__ reps, const double *__rest
     const bool accept = logA >= 0.0 || u < exp(logA);
     if (!accept)
         return;
-    atomicAdd(&accepts[r], 1ull);
-    const uint32_t x0 = bx * Bs, y0 = by * Bs;
-    for (int i = 0; i < Bs; ++i)
-        for (int j = 0; j < Bs; ++j) {
-            const int k = i * Bs + j;
-            if (s[k] == sp[k])
-                continue;
-            const uint32_t x = x0 + j, y = y0 + i, c = (x + y) & 1u, kk = x >> 1;
-            atomicXor(&d.plane0[c * d.Ly * d.W + y * d.W + (kk >> 5)], 1u << (kk & 31));
-        }
+    if (lane == 0)
+        atomicAdd(&accepts[r], 1ull);
+    if (changed) {
+        const int i = lane / Bs, j = lane - i * Bs;
+        const uint32_t x = bx * Bs + j, y = by * Bs + i, c = (x + y) & 1u, kk = x >> 1;
+        atomicXor(&d.plane0[c * d.Ly * d.W + y * d.W + (kk >> 5)], 1u << (kk & 31));
+    }
 }
 
 // training samples: block position of sample i of replica r drawn from
@@ -1026,7 +1055,7 @@ hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_score, int n_samp
 hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
                         uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_block_gather, dim3(blocks_for(count, 256)), dim3(256), 0, st, reps, kcoup, Bs, colour,
+    hipLaunchKernelGGL(k_block_gather, dim3(blocks_for(count, 4)), dim3(256), 0, st, reps, kcoup, Bs, colour,
                        round, first, count, per_rep, seq);
     return hipGetLastError();
 }
@@ -1035,7 +1064,7 @@ hipError_t block_mh(const RepDev *reps, const double *kcoup, int Bs, uint32_t co
                     uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, int64_t *accepts,
                     hipStream_t st)
 {
-    hipLaunchKernelGGL(k_block_mh, dim3(blocks_for(count, 256)), dim3(256), 0, st, reps, kcoup, Bs, colour, round,
+    hipLaunchKernelGGL(k_block_mh, dim3(blocks_for(count, 4)), dim3(256), 0, st, reps, kcoup, Bs, colour, round,
                        first, count, per_rep, seq, reinterpret_cast<unsigned long long *>(accepts));
     return hipGetLastError();
 }

@@ -41,43 +41,54 @@ def train(net: Net, X, BN, K, steps: int, batch_size: int, lr: float, seed: int 
     return out
 
 
-def abs_m_trace(batch: Batch, units: int, unit, record_every: int = 1):
-    """Run `units` units (callable unit(i)); returns (|m| trace [n_rep, units/record_every], seconds)."""
+def _per_spin(batch: Batch):
+    n = np.array([d["Lx"] * d["Ly"] for d in batch.descs], dtype=np.float64)
+    j = np.array([d["J"] for d in batch.descs], dtype=np.float64)
+    return n, j
+
+
+def unit_traces(batch: Batch, units: int, unit):
+    """Run `units` units (callable unit(i) returning device traces (B, M) of
+    the unit); returns (|m| trace, e trace) [n_rep, units] and seconds."""
     import torch
-    n_spins = np.array([d["Lx"] * d["Ly"] for d in batch.descs], dtype=np.float64)
-    traces = []
+    n, j = _per_spin(batch)
+    bonds, mags = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(units):
-        rec = unit(i)
-        if rec is not None:
-            traces.append(rec)
+        b, m = unit(i)
+        bonds.append(b)
+        mags.append(m)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    m = np.concatenate([t.cpu().numpy() for t in traces], axis=1).astype(np.float64)
-    return np.abs(m) / n_spins[:, None], dt
+    B = np.concatenate([t.cpu().numpy() for t in bonds], axis=1).astype(np.float64)
+    M = np.concatenate([t.cpu().numpy() for t in mags], axis=1).astype(np.float64)
+    return np.abs(M) / n[:, None], -j[:, None] * B / n[:, None], dt
 
 
 def plain_trace(batch: Batch, sweeps: int, record_every: int):
-    """One run of `sweeps` plain sweeps recording M every `record_every`;
-    returns (|m| trace [n_rep, sweeps/record_every], seconds of device time)."""
+    """One run of `sweeps` plain sweeps recording (B, M) every `record_every`;
+    returns (|m| trace, e trace) [n_rep, sweeps/record_every] and seconds of
+    device time."""
     import torch
-    n_spins = np.array([d["Lx"] * d["Ly"] for d in batch.descs], dtype=np.float64)
+    n, j = _per_spin(batch)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(batch.stream)
-    _, mag = batch.run(sweeps, record_every)
+    bond, mag = batch.run(sweeps, record_every)
     e1.record(batch.stream)
     torch.cuda.synchronize()
-    return np.abs(mag.cpu().numpy().astype(np.float64)) / n_spins[:, None], e0.elapsed_time(e1) / 1e3
+    B = bond.cpu().numpy().astype(np.float64)
+    M = mag.cpu().numpy().astype(np.float64)
+    return np.abs(M) / n[:, None], -j[:, None] * B / n[:, None], e0.elapsed_time(e1) / 1e3
 
 
 def learned_units(batch: Batch, net: Net, first_round: int, accepts=None):
-    """One unit = one block round (both block colours) then one checkerboard sweep."""
+    """One unit = one block round (both block colours) then one checkerboard
+    sweep; returns the sweep's (B, M) trace."""
     def unit(i):
         batch.block_round(net, first_round + i, accepts)
-        _, mag = batch.run(1, 1)
-        return mag
+        return batch.run(1, 1)
     return unit
 
 

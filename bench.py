@@ -247,6 +247,12 @@ def learned_comparison(units, plain_sweeps):
     lrn = learned.summarise(tr_l, s_l, 1, t_c)
     z = learned.agreement(tr_p, tr_l)
     ze = learned.agreement(e_p, e_l)
+    # matrix-core work: per sequence and site, 3 layers x 10 K-steps x 4 channel
+    # slices of a 16x16x32 BF16 tile shared by 16 sequences; per unit, a scored
+    # and a sampled sequence for every block of the batch
+    blocks = len(descs) * (256 // 8) * (256 // 8)
+    flop_unit = 2 * blocks * 64 * (3 * 10 * 4 * 16 * 16 * 32 * 2 / 16)
+    flop_train_step = 9 * 2.0 * 512 * 64 * 64 * 320
     temps = [w.replicas[r].T for r in range(len(w.replicas))]
     return {
         "metric": "effective independent |m| samples/s at T_c (one replica, whole-batch time)",
@@ -255,6 +261,11 @@ def learned_comparison(units, plain_sweeps):
                      "loss": hist, "seconds": t_train},
         "plain": plain, "learned": lrn,
         "block_acceptance": float(acc.cpu().sum()) / (units * len(descs) * 1024),
+        "roofline": {"bound": "mfma", "kernel": "k_nn_score + k_nn_sample (whole unit time)",
+                     "achieved": flop_unit * units / s_l / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flop_unit * units / s_l / 2.5e15, "traffic": None,
+                     "per_unit": f"{flop_unit / 1e9:.1f} GFLOP of BF16 MFMA per unit"},
+        "training_tflops": flop_train_step * 2000 / t_train / 1e12,
         "learned_over_plain": lrn["effective_samples_per_s"] / plain["effective_samples_per_s"],
         "energy_agreement": {"within_2sigma": float(np.mean(np.abs(ze) < 2)), "max_abs_z": float(np.max(np.abs(ze))),
                              "z": [round(float(v), 3) for v in ze]},

@@ -75,11 +75,15 @@ __global__ void k_cast_weights(const float *__restrict__ params, uint16_t *__res
 // 256 threads, 64x64 tile, each wave a 32x32 quarter of 2x2 MFMA 16x16x32.
 // Requires K % 32 == 0 and 16-byte aligned rows (lda, ldb multiples of 8).
 // ---------------------------------------------------------------------------
+// blockIdx.z = s sums k in [s kchunk, min(K, (s + 1) kchunk)) into the slice
+// Cm + s M ldc (split-K partials; one slice when gridDim.z = 1).
 __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
                                                  const uint16_t *__restrict__ Bt, int ldb,
-                                                 float *__restrict__ Cm, int ldc, int M, int N, int K)
+                                                 float *__restrict__ Cm, int ldc, int M, int N, int K, int kchunk)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    Cm += (size_t)blockIdx.z * M * ldc;
     const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
     const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
     const int r = lane & 15, kq = (lane >> 4) * 8;
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
 #pragma unroll
         for (int b = 0; b < 2; ++b)
             acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < K; k += 32) {
+    for (int k = kb; k < ke; k += 32) {
         bf16x8 av[2], bv[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
@@ -118,6 +122,18 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
                 if (row < M && col < N)
                     Cm[(size_t)row * ldc + col] = acc[a][b][i];
             }
+}
+
+// C[i] = sum over s = 0..S-1 of part[s][i], in that order
+__global__ void k_sum_splits(const float *__restrict__ part, int S, int n, float *__restrict__ Cm)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    float v = 0.f;
+    for (int s = 0; s < S; ++s)
+        v += part[(size_t)s * n + i];
+    Cm[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -948,8 +964,23 @@ hipError_t cast_weights(const NetDev &net, hipStream_t st)
 hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *Cm, int ldc, int M, int N,
                    int K, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gemm_nt, dim3(blocks_for(N, 64), blocks_for(M, 64)), dim3(256), 0, st, A, lda, Bt, ldb,
-                       Cm, ldc, M, N, K);
+    hipLaunchKernelGGL(k_gemm_nt, dim3(blocks_for(N, 64), blocks_for(M, 64), 1), dim3(256), 0, st, A, lda, Bt, ldb,
+                       Cm, ldc, M, N, K, K);
+    return hipGetLastError();
+}
+
+// Split-K product for a small output and a long K (the weight gradients):
+// partials of kchunk-long K ranges go to part[S][M][N], then a fixed-order sum.
+static hipError_t gemm_nt_splitk(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *part, float *Cm,
+                                 int M, int N, int K, int kchunk, hipStream_t st)
+{
+    const int S = (K + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL(k_gemm_nt, dim3(blocks_for(N, 64), blocks_for(M, 64), S), dim3(256), 0, st, A, lda, Bt, ldb,
+                       part, N, M, N, K, kchunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((long)M * N, 256)), dim3(256), 0, st, part, S, M * N, Cm);
     return hipGetLastError();
 }
 
@@ -994,8 +1025,10 @@ hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const
         hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.dpre, (const float *)nullptr, Pp, rows_per_blk,
                            ws.partial);
         hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + off_b(l));
-        // weight gradient [C][KB] = dpre^T (C x P) . xcol (P x KB)
-        hipError_t e = gemm_nt(ws.dpret, Pp, ws.xcolt[li], Pp, ws.wgrad, KB, C, KB, Pp, st);
+        // weight gradient [C][KB] = dpre^T (C x P) . xcol (P x KB), split over P in
+        // chunks of 512 positions; the partials use ws.pre, which is free here
+        // (S C KB <= Pp KB floats)
+        hipError_t e = gemm_nt_splitk(ws.dpret, Pp, ws.xcolt[li], Pp, ws.pre, ws.wgrad, C, KB, Pp, 512, st);
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_scatter_wgrad, dim3(blocks_for((long)C * KB, 256)), dim3(256), 0, st, ws.wgrad, l,

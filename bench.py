@@ -178,6 +178,12 @@ def main():
                 "launch_ms": launch_s * 1e3, "launches": launches,
                 "hbm_bytes_per_launch_algorithmic": algo_bytes,
                 "hbm_frac_of_8TBps": (traffic / launch_s / HBM_BYTES_PER_S) if traffic else None}
+    # measured ALU ceiling: the same per-word arithmetic with no memory traffic
+    from paper_2404_16990_amd import probe
+    ceiling = probe.mix_rate(sched["word_bits"])
+    roofline["measured_alu_ceiling"] = {
+        "value": ceiling / 1e9, "unit": "Gflip/s", "frac": achieved / ceiling,
+        "kernel": f"k_mix<{sched['word_bits']}-bit> (ising::update_word on register-resident words)"}
     # sanity: the last trace is finite and physical
     b_last = traces[-1][0][:, -1].cpu()
     assert int(b_last.abs().max()) <= 2 * max(r.spins for r in work.replicas)

@@ -416,9 +416,32 @@ hipError_t prepare_resident_kernels(int max_dynamic_lds)
     return e;
 }
 
-uint32_t resident_static_lds(int threads)
+template <typename Word, int T>
+static uint32_t static_lds_of()
 {
-    return 2u * (uint32_t)(threads / 64) * (uint32_t)sizeof(int64_t);
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_sweep_resident<Word, T>)) != hipSuccess)
+        return 4096u;  // generous fallback: the kernels declare far less
+    return (uint32_t)a.sharedSizeBytes;
+}
+
+// Largest static LDS of the resident kernels (reported by the runtime), so
+// that static + dynamic LDS never exceeds the device limit.
+uint32_t resident_static_lds(int /*threads*/)
+{
+    static uint32_t cached = 0;
+    if (cached == 0) {
+        uint32_t m = 0;
+        const uint32_t v[] = {static_lds_of<uint32_t, 64>(),  static_lds_of<uint32_t, 128>(),
+                              static_lds_of<uint32_t, 256>(), static_lds_of<uint32_t, 512>(),
+                              static_lds_of<uint32_t, 1024>(), static_lds_of<uint64_t, 64>(),
+                              static_lds_of<uint64_t, 128>(), static_lds_of<uint64_t, 256>(),
+                              static_lds_of<uint64_t, 512>(), static_lds_of<uint64_t, 1024>()};
+        for (uint32_t x : v)
+            m = x > m ? x : m;
+        cached = m;
+    }
+    return cached;
 }
 
 hipError_t launch_sweep_resident(const ResidentList &L, int word_bits, int threads, uint32_t n_sweeps,

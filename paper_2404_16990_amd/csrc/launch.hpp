@@ -42,7 +42,7 @@ hipError_t launch_sweep_resident(const ResidentList &L, int word_bits, int threa
                                  const RecArgs &rec, hipStream_t st);
 // Raise the dynamic-LDS limit of every resident-kernel instantiation.
 hipError_t prepare_resident_kernels(int max_dynamic_lds);
-// Static LDS used by the resident kernel with this many threads (bytes).
+// Largest static LDS of the resident kernels in bytes, as the runtime reports it.
 uint32_t resident_static_lds(int threads);
 
 }  // namespace ising

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device.hpp"
+
 namespace {
 
 constexpr int kChains = 8;
@@ -136,6 +138,38 @@ __global__ __launch_bounds__(256) void k_clock(uint64_t *stamps, uint32_t *out, 
     }
 }
 
+// The sweep's per-word arithmetic with no memory traffic: every thread
+// updates one register-resident word per iteration with ising::update_word
+// (classification, Philox, acceptance) from synthetic neighbour words, the
+// updated word feeding the next iteration, and a fresh counter per iteration.
+// Sites per second of this kernel is the measured ALU ceiling of the sweep's
+// instruction mix (thresholds of T_c; no data-dependent branches).
+template <typename Word>
+__global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4,
+                                             uint32_t thr8)
+{
+    using ising::SweepKey;
+    const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
+    SweepKey K;
+    K.k0 = seed;
+    K.k1 = seed * 3u + 1u;
+    K.t = 0;
+    K.replica = blockIdx.x;
+    K.colour = 1u;
+    K.thr4 = thr4;
+    K.thr8 = thr8;
+    K.always = 0u;
+    Word s = (Word)(tid * 0x9E3779B97F4A7C15ull), up = (Word)(tid * 0xC2B2AE3D27D4EB4Full),
+         dn = (Word)(tid * 0x165667B19E3779F9ull), same = (Word)(tid * 0x27D4EB2F165667C5ull);
+    const Word side = same ^ up;
+    constexpr uint32_t QW = ising::WordTraits<Word>::BITS / 4;
+    for (int i = 0; i < iters; ++i) {
+        K.t = (uint32_t)i;
+        s = ising::update_word<Word>(s, up, dn, same, side, (tid + (uint32_t)i * 0x100000u) * QW, K);
+    }
+    out[tid] = (uint32_t)s ^ (uint32_t)((uint64_t)s >> 32);
+}
+
 __global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16)
 {
     for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
@@ -173,6 +207,41 @@ hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
 }  // namespace
 
 extern "C" {
+
+/* Measured ALU ceiling of the sweep's per-word arithmetic: k_mix with 32- or
+ * 64-bit words on blocks x 256 threads for iters iterations (after a warm-up
+ * launch).  Sites counted: blocks * 256 * iters * word_bits.  Writes the
+ * milliseconds of the timed launch to *ms; returns 0, or <0 on error. */
+int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned thr4, unsigned thr8, float *ms)
+{
+    if (!out || blocks <= 0 || iters <= 0 || !ms || (word_bits != 32 && word_bits != 64))
+        return -1;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return -4;
+    uint32_t *o = static_cast<uint32_t *>(out);
+    hipError_t err = hipSuccess;
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+        if (rep == 1)
+            err = hipEventRecord(e0, nullptr);
+        if (err != hipSuccess)
+            break;
+        if (word_bits == 32)
+            hipLaunchKernelGGL(k_mix<uint32_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8);
+        else
+            hipLaunchKernelGGL(k_mix<uint64_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess)
+        err = hipEventRecord(e1, nullptr);
+    if (err == hipSuccess)
+        err = hipEventSynchronize(e1);
+    if (err == hipSuccess)
+        err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return err == hipSuccess ? 0 : -4;
+}
 
 /*
  * Time one probe on the null stream.  which: 0 v_mad_u64_u32, 1 v_mul_hi_u32,

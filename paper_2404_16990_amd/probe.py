@@ -48,6 +48,23 @@ def measure(blocks=256 * 16, iters=4096):
             "philox_lane_cycles_per_call": xor / res["philox4x32_10"]}
 
 
+def mix_rate(word_bits=64, blocks=256 * 16, iters=64, T=2.269185):
+    """Measured ALU ceiling of the sweep's per-word arithmetic, in site updates
+    (flip attempts) per second: k_mix runs ising::update_word on register-resident
+    words (classification, Philox4x32-10, acceptance) with no memory traffic."""
+    import math
+    import torch
+    L = _lib()
+    L.ising_probe_mix.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                  ctypes.c_uint, ctypes.POINTER(ctypes.c_float)]
+    thr = [min(int(math.floor(math.ldexp(math.exp(-4.0 * k / T), 32))), 2**32 - 1) for k in (1, 2)]
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    ms = ctypes.c_float()
+    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], ctypes.byref(ms)) != 0:
+        raise RuntimeError("mix probe failed")
+    return blocks * 256 * iters * word_bits / (ms.value * 1e-3)
+
+
 def clock(blocks_per_cu=(1, 2, 4, 8), iters=20000):
     """Shader clock and per-CU issue rate of full-rate VALU ops.
 
@@ -112,6 +129,7 @@ if __name__ == "__main__":
         print(json.dumps({"copy_dispatch_bytes_each_way": 256 << 20, "copy_bytes_per_s": bw}))
     else:
         r = measure()
+        r["sweep_mix_flips_per_s"] = {str(w): mix_rate(w) for w in (32, 64)}
         r["clock"] = clock()
         r["copy_bytes_per_s"] = copy_bandwidth()
         print(json.dumps(r, indent=1))

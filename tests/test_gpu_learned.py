@@ -119,11 +119,11 @@ def test_q_sums_to_one_and_is_causal():
             assert abs(l - ref) < 1e-3, (l, ref)
 
 
-def test_scoring_reproduces_sampler_log_q_bitwise():
+@pytest.mark.parametrize("Bs", [8, 4, 2])
+def test_scoring_reproduces_sampler_log_q_bitwise(Bs):
     import torch
     P = _P()
-    Bs = 8
-    rng = np.random.default_rng(1)
+    rng = np.random.default_rng(Bs)
     net = P.Net(_params(1.0), block=Bs, max_batch=16, max_seq=512)
     _, bnd, kc = _rand_blocks(rng, 300, Bs)
     dbnd, dkc = _dev(bnd, torch.int8), _dev(kc, torch.float32)

@@ -1,0 +1,98 @@
+"""Full-size, full-length runs of the benchmark configurations, checked against
+exact results that hold at any size.
+
+The oracle cannot replay 10^4 sweeps of 2.7e8 spins, so these runs are pinned
+by physics instead: after equilibration the energy per spin of a replica away
+from T_c equals Onsager's infinite-lattice value (finite-size corrections are
+of order exp(-L / xi), far below the statistical errors at these sizes), and
+|m| equals Yang's spontaneous magnetisation below T_c (cold starts, which need
+no domain coarsening) or vanishes like N^-1/2 above it.  Means are taken over
+the second half of each run, with errors from 10 bins.  The short-run bit
+parity of the same configurations is in test_gpu_parity.py.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import exact, stats
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(w, sweeps, every, idx=None):
+    import torch
+    import paper_2404_16990_amd as P
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+             for r in w.replicas]
+    b = P.Batch(descs)
+    bond, mag = b.run(sweeps, every)
+    torch.cuda.synchronize()
+    n = np.array([r.Lx * r.Ly for r in w.replicas], dtype=np.float64)
+    e = -bond.cpu().numpy().astype(np.float64) / n[:, None]
+    m = mag.cpu().numpy().astype(np.float64) / n[:, None]
+    b.close()
+    return e, m
+
+
+def _z(series, exact_value):
+    half = series[series.size // 2:]
+    mean, err = stats.binned_mean(half, nbins=10)
+    return (mean - exact_value) / max(err, 1e-12), mean, err
+
+
+def _check(w, e, m, above=2.45, below=None, max_z=5.0):
+    checked = 0
+    for r, rep in enumerate(w.replicas):
+        T = rep.T
+        if T >= above:
+            z, mean, err = _z(e[r], exact.onsager_u(T))
+            assert abs(z) < max_z, (r, T, mean, exact.onsager_u(T), err)
+            # above T_c, <m^2> = chi / N with chi the sum of spin correlations; its
+            # leading critical behaviour 0.9625 (1 - T_c/T)^(-7/4) bounds |m| with margin
+            half = np.abs(m[r, m.shape[1] // 2:])
+            chi = 0.9625 * (1.0 - exact.T_C / T) ** -1.75
+            bound = 4.0 * math.sqrt(chi / (rep.Lx * rep.Ly))
+            assert half.mean() < bound, (r, T, half.mean(), bound)
+            checked += 1
+        elif below is not None and T <= below:
+            z, mean, err = _z(e[r], exact.onsager_u(T))
+            assert abs(z) < max_z, (r, T, mean, exact.onsager_u(T), err)
+            z, mean, err = _z(np.abs(m[r]), exact.yang_m(T))
+            assert abs(z) < max_z, (r, T, mean, exact.yang_m(T), err)
+            checked += 1
+    return checked
+
+
+def test_batch_256x1024_full_10k_sweeps_matches_onsager_above_tc():
+    """Config of the benchmark: 256 x 1024^2, random starts, the full 10^4
+    sweeps at the benchmark's recording cadence; the 64 replicas with T >= 3.0
+    (equilibrated within a few hundred sweeps) against Onsager."""
+    w = workloads.batch_256x1024()
+    e, m = _run(w, w.sweeps, w.record_every)
+    assert e.shape == (256, 100)
+    assert _check(w, e, m, above=3.0) == 64
+
+
+def test_uneven_512_full_2000_sweeps_matches_onsager_above_tc():
+    """Uneven batch (128^2 ... 8192^2) for its full 2000 sweeps; every replica
+    with T >= 2.45 (correlation length <= 8 sites) against Onsager."""
+    w = workloads.uneven_512()
+    e, m = _run(w, w.sweeps, 10)
+    n = _check(w, e, m, above=2.45)
+    assert n >= 100, n
+
+
+def test_paper_scale_full_1000_sweeps_matches_onsager_and_yang():
+    """754 x 512x528 cold starts (plus the 16384 x 12288 lattice) for the full
+    1000 sweeps: energy against Onsager and |m| against Yang for T <= 2.05, and
+    energy against Onsager for T >= 2.45.  The big lattice at T_c relaxes from
+    the cold start towards the critical energy -sqrt(2) from below."""
+    w = workloads.paper_scale()
+    e, m = _run(w, w.sweeps, 5)
+    n = _check(w, e, m, above=2.45, below=2.05)
+    assert n >= 300, n
+    big = e[-1]
+    assert big[0] < big[-1] < -math.sqrt(2.0) + 0.02, (big[0], big[-1])
+    assert np.all(np.diff(big[:20]) > 0)  # monotone relaxation early on

@@ -273,9 +273,16 @@ int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int
                                 const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
                                 float *dev_loss, void *stream);
 
-/* Incremental pass on n <= max_seq sequences.  score: log q (FP64) of the
- * given blocks.  sample: draw blocks with the Philox stream of (seed,
- * replica, round) and block ids blk0 + i, returning them and their log q.
+/* Autoregressive passes on n <= max_seq sequences.  Site k = i*Bs + j of a
+ * block has P(x_k = +1 | x_<k, boundary, K) = sigmoid(logit_k) and the uint32
+ * threshold thr_k = clamp(floor(sigmoid(logit_k) * 2^32), 1, 2^32 - 1);
+ * log q = sum_k log(x_k > 0 ? thr_k : 2^32 - thr_k) - Bs*Bs*32*ln 2 in FP64.
+ * sample: x_k = +1 iff u_k < thr_k, u_k = word (s & 3) of
+ * Philox4x32-10(counter (s >> 2, round, replica, 3), key seed) with
+ * s = (blk0 + i) * Bs*Bs + k for sequence i; returns the blocks and log q.
+ * score: log q of the given blocks, evaluated row by row with the sampler's
+ * per-site arithmetic, so a sampled block scores to the same log q bit for
+ * bit.  Errors: ISING_E_INVALID for n outside [1, max_seq] or NULL arrays.
  * Asynchronous. */
 int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_t *dev_bnd,
                    const float *dev_coupling, double *dev_logq, void *stream);
@@ -292,10 +299,16 @@ int ising_batch_extract_blocks(ising_batch *b, int32_t block, int32_t per_replic
                                int8_t *dev_blocks, int8_t *dev_bnd, float *dev_coupling, void *stream);
 
 /* One block round of every replica: all blocks with (bx + by) even, then all
- * with (bx + by) odd, each proposed by the network and accepted by
- * Metropolis-Hastings.  dev_accepts (int64 [n], may be NULL) accumulates
- * accepted blocks per replica.  The batch's replicas must share one shape with
- * Lx and Ly multiples of 2*Bs.  Asynchronous. */
+ * with (bx + by) odd.  For each block the network scores the current spins s
+ * and samples a proposal s' (block id by*(Lx/Bs) + bx, the round as Philox
+ * counter word) given the block's boundary; with dB the change of the bond
+ * sum, log A = K dB + log q(s) - log q(s') in FP64 and the proposal replaces
+ * the block iff log A >= 0 or u < exp(log A), u = ((w0 << 21) | (w1 >> 11))
+ * * 2^-53 from Philox4x32-10(counter (block id, round, replica, 4), key seed).
+ * Blocks of one colour share no bond, so the order within a colour does not
+ * matter.  dev_accepts (int64 [n], may be NULL) accumulates accepted blocks
+ * per replica.  Errors: ISING_E_UNSUPPORTED unless every replica has one shape
+ * with Lx and Ly multiples of 2*Bs.  Asynchronous. */
 int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t *dev_accepts, void *stream);
 
 int ising_nn_destroy(ising_nn *m);

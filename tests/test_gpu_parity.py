@@ -263,6 +263,20 @@ def test_batch_256x1024_all_replicas_20_sweeps():
     assert_states(b, w.replicas, states, which=range(0, 256, 17))
 
 
+def test_batch_256x1024_sampled_replicas_1000_sweeps():
+    """The whole batch for 1000 sweeps at the benchmark's cadence (record every
+    100) in its launch configuration; four replicas across the temperature
+    range against the oracle, traces and final states."""
+    w = workloads.batch_256x1024()
+    b = gpu_batch(w.replicas)
+    gb, gm = gpu_run(b, 1000, w.record_every)
+    idx = [0, 85, 170, 255]
+    states, ob, om = oracle_run([w.replicas[i] for i in idx], 1000, w.record_every)
+    assert np.array_equal(gb[idx], ob) and np.array_equal(gm[idx], om)
+    for k, i in enumerate(idx):
+        assert np.array_equal(b.get_spins(i), states[k]), i
+
+
 # ---- autotuner: state untouched, self-checked candidates, cache ---------------------
 
 def test_autotune_leaves_state_and_keeps_parity(tmp_path, monkeypatch):

@@ -28,7 +28,7 @@ INIT_RANDOM, INIT_UP, INIT_DOWN = 0, 1, 2
 class Desc(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("J", ctypes.c_double),
                 ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint32), ("init", ctypes.c_int32)]
+                ("replica", ctypes.c_uint32), ("init", ctypes.c_int32), ("rng", ctypes.c_int32)]
 
 
 _lib = None
@@ -72,8 +72,13 @@ def default_threads():
     return max(1, min(n, 16))
 
 
-def desc(Lx, Ly, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM):
-    return Desc(int(Lx), int(Ly), float(J), float(beta), int(seed), int(replica), int(init))
+RNG_SITE, RNG_BITSLICED = 0, 1
+
+
+def desc(Lx, Ly, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM, rng=RNG_SITE):
+    """rng: RNG_SITE (one Philox word per site) or RNG_BITSLICED (each site's
+    uniform is bit b of the 32 words of its 32-site group, transposed)."""
+    return Desc(int(Lx), int(Ly), float(J), float(beta), int(seed), int(replica), int(init), int(rng))
 
 
 def philox4x32_10(ctr, key):

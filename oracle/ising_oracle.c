@@ -33,6 +33,13 @@
  *  - uniform for site (x,y) in sweep t, colour c:
  *      r = Philox(ctr = {h >> 2, t, replica, c}, key = {seed_lo, seed_hi})[h & 3]
  *    a 32-bit integer; ran() = r / 2^32.
+ *  - bit-sliced variant (rng = 1, an alternative random-number contract):
+ *    the colour-c sites with compact indices 32g .. 32g+31 form group g; its
+ *    words are W_k = Philox(ctr = {8g + (k >> 2), t, replica, c}, key)[k & 3]
+ *    for k = 0..31, and site h = 32g + b takes the 32-bit uniform whose bit
+ *    31 - k is bit b of W_k (the group's words, transposed).  Comparing that
+ *    uniform with a threshold most significant bit first needs, per site,
+ *    only the words up to the first bit where the two differ.
  *  - thresholds: K = beta*J (one rounding), p1 = exp(-4K), p2 = exp(-8K),
  *    thr_k = min(floor(p_k * 2^32), 2^32 - 1); dE = 4J accepts iff r < thr_1,
  *    dE = 8J iff r < thr_2; dE <= 0 always accepts and draws nothing;
@@ -60,6 +67,7 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int32_t init;
+    int32_t rng; /* 0: one Philox word per site; 1: bit-sliced group words */
 } oracle_desc;
 
 /* ---- Philox4x32-10 (Salmon et al., SC'11) ------------------------------ */
@@ -134,6 +142,38 @@ int oracle_thresholds(double J, double beta, uint32_t *thr4, uint32_t *thr8, int
 
 /* ---- state set-up ------------------------------------------------------- */
 
+/* Uniform of site h (compact index within its colour) under the bit-sliced
+ * contract: bit 31 - k of the result is bit (h & 31) of word k of group h >> 5.
+ * The 32 words of the last group used are kept in *cache, since the sites of
+ * one colour are visited in increasing h. */
+typedef struct {
+    int valid;
+    uint64_t g;
+    uint32_t t, colour;
+    uint32_t w[32];
+} group_words;
+
+static uint32_t bitsliced_uniform(const oracle_desc *d, uint32_t colour, uint32_t t, uint64_t h,
+                                  group_words *cache)
+{
+    const uint64_t g = h >> 5;
+    const uint32_t b = (uint32_t)(h & 31u);
+    uint32_t u = 0, k;
+    if (!cache->valid || cache->g != g || cache->t != t || cache->colour != colour) {
+        /* word k of the group is word (k & 3) of call 8g + (k >> 2), i.e. the
+           site-uniform stream at index 32g + k */
+        for (k = 0; k < 32; ++k)
+            cache->w[k] = site_uniform(d->seed, colour, t, d->replica, 32u * g + k);
+        cache->valid = 1;
+        cache->g = g;
+        cache->t = t;
+        cache->colour = colour;
+    }
+    for (k = 0; k < 32; ++k)
+        u |= ((cache->w[k] >> b) & 1u) << (31u - k);
+    return u;
+}
+
 static int desc_ok(const oracle_desc *d)
 {
     uint32_t a, b;
@@ -143,6 +183,8 @@ static int desc_ok(const oracle_desc *d)
     if ((uint64_t)d->Lx * (uint64_t)d->Ly > 0xffffffffull)
         return 0;
     if (oracle_thresholds(d->J, d->beta, &a, &b, &c) != OR_OK)
+        return 0;
+    if (d->rng != 0 && d->rng != 1)
         return 0;
     return d->init == OR_INIT_RANDOM || d->init == OR_INIT_UP || d->init == OR_INIT_DOWN;
 }
@@ -194,6 +236,8 @@ static void flip_colour(const oracle_desc *d, int8_t *s, uint32_t t, int colour,
 {
     const int32_t Lx = d->Lx, Ly = d->Ly;
     int32_t x, y;
+    group_words cache;
+    cache.valid = 0;
     for (y = 0; y < Ly; ++y) {
         for (x = 0; x < Lx; ++x) {
             int64_t i = (int64_t)y * Lx + x;
@@ -208,7 +252,8 @@ static void flip_colour(const oracle_desc *d, int8_t *s, uint32_t t, int colour,
                 accept = 1;
             } else {
                 uint64_t h = (uint64_t)i >> 1;
-                uint32_t r = site_uniform(d->seed, (uint32_t)colour, t, d->replica, h);
+                uint32_t r = d->rng == 1 ? bitsliced_uniform(d, (uint32_t)colour, t, h, &cache)
+                                         : site_uniform(d->seed, (uint32_t)colour, t, d->replica, h);
                 accept = r < (dE == 4 ? thr4 : thr8);
             }
             if (accept)

@@ -36,6 +36,21 @@ def sweep_uniform(seed, replica, t, colour, Lx, x, y):
     return philox4x32_10((h >> 2, t, replica, colour), seed_key(seed))[h & 3]
 
 
+def bitsliced_uniform(seed, replica, t, colour, Lx, x, y):
+    """The 32-bit uniform of site (x, y) in sweep t under the bit-sliced
+    contract: with h the site's compact index, group g = h >> 5 has words
+    W_k = sweep stream word 32 g + k (k = 0..31), and bit 31 - k of the
+    uniform is bit h & 31 of W_k."""
+    h = (y * Lx + x) >> 1
+    g, b = h >> 5, h & 31
+    u = 0
+    for k in range(32):
+        i = 32 * g + k
+        w = philox4x32_10((i >> 2, t, replica, colour), seed_key(seed))[i & 3]
+        u |= ((w >> b) & 1) << (31 - k)
+    return u
+
+
 def init_uniform(seed, replica, Lx, x, y):
     """The 32-bit uniform deciding the random initial spin of site (x, y)."""
     g = y * Lx + x

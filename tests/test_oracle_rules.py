@@ -61,10 +61,11 @@ def _energy(s, J):
     return -J * float((s * np.roll(s, -1, axis=1)).sum() + (s * np.roll(s, -1, axis=0)).sum())
 
 
-def _brute_sweep(s, J, beta, seed, replica, t):
+def _brute_sweep(s, J, beta, seed, replica, t, rng=0):
     """One checkerboard sweep, every dE from H(s') - H(s) and the acceptance
     from exp(-beta dE) directly; the uniform for each site named through the
-    pure-Python Philox with the contract's site mapping."""
+    pure-Python Philox with the contract's site mapping (rng 0) or the
+    bit-sliced group words (rng 1)."""
     Ly, Lx = s.shape
     s = s.copy()
     for colour in (0, 1):
@@ -79,23 +80,25 @@ def _brute_sweep(s, J, beta, seed, replica, t):
                 if dE <= 0 or beta * J == 0:
                     accept = True
                 else:
-                    r = pyphilox.sweep_uniform(seed, replica, t, colour, Lx, x, y)
+                    uni = pyphilox.bitsliced_uniform if rng == 1 else pyphilox.sweep_uniform
+                    r = uni(seed, replica, t, colour, Lx, x, y)
                     accept = r / 2**32 < math.exp(-beta * dE)
                 if accept:
                     s[y, x] = -s[y, x]
     return s
 
 
-@pytest.mark.parametrize("Lx,Ly", [(2, 2), (4, 4), (6, 4), (4, 6), (8, 2), (2, 8)])
+@pytest.mark.parametrize("rng", [0, 1])
+@pytest.mark.parametrize("Lx,Ly", [(2, 2), (4, 4), (6, 4), (4, 6), (8, 2), (2, 8), (128, 2)])
 @pytest.mark.parametrize("T", [0.8, 2.269185, 4.0])
-def test_sweep_matches_brute_force(Lx, Ly, T):
+def test_sweep_matches_brute_force(Lx, Ly, T, rng):
     J = 1.0
-    d = oracle.desc(Lx, Ly, J, 1.0 / T, seed=1234567 + Lx, replica=3, init=oracle.INIT_RANDOM)
+    d = oracle.desc(Lx, Ly, J, 1.0 / T, seed=1234567 + Lx, replica=3, init=oracle.INIT_RANDOM, rng=rng)
     s = oracle.init_state(d)
     ref = s.copy()
-    for t in range(6):
+    for t in range(6 if Lx * Ly <= 64 else 2):
         oracle.sweeps(d, s, 1, t0=t)
-        ref = _brute_sweep(ref, J, 1.0 / T, d.seed, d.replica, t)
+        ref = _brute_sweep(ref, J, 1.0 / T, d.seed, d.replica, t, rng)
         assert np.array_equal(s, ref), (t, s, ref)
 
 

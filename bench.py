@@ -68,10 +68,11 @@ def host_threads():
     return max(1, min(n, 16))
 
 
-def cpu_baseline(work, sweeps):
-    """Time the CPU oracle on every replica of the workload for `sweeps` sweeps."""
+def cpu_baseline(work, sweeps, rng=0):
+    """Time the CPU oracle on every replica of the workload for `sweeps` sweeps
+    under the measured path's random-number contract."""
     import oracle
-    descs = [oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init) for r in work.replicas]
+    descs = [oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init, rng=rng) for r in work.replicas]
     states = [oracle.init_state(d) for d in descs]
     threads = host_threads()
     t0 = time.perf_counter()
@@ -83,43 +84,20 @@ def cpu_baseline(work, sweeps):
                       f"{dt:.1f} s on {threads} host threads"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sweeps-per-step", type=int, default=100)
-    ap.add_argument("--workload", default="batch_256x1024")
-    ap.add_argument("--cpu-sweeps", type=int, default=40)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", default="", help="JSON dict overriding the execution schedule")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--learned", action="store_true",
-                    help="also run the learned-proposal comparison (64 x 256^2 near T_c)")
-    ap.add_argument("--learned-units", type=int, default=10000)
-    ap.add_argument("--plain-sweeps", type=int, default=500000)
-    ap.add_argument("--tune-sweeps", type=int, default=20)
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(replicas would shard across GPUs with no communication).", file=sys.stderr)
-        sys.exit(2)
-
+def run_path(work, rng, args, stream, schedule=None):
+    """Create the batch under random-number contract `rng`, pick its schedule
+    (given, or from the autotuner), warm up, and time args.steps steps.
+    Returns the measurement and the batch."""
     import torch
 
     import paper_2404_16990_amd as P
-    import workloads
 
-    work = workloads.ALL[args.workload]()
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init, rng=rng)
              for r in work.replicas]
     batch = P.Batch(descs, stream=stream)
     tuned = None
-    if args.schedule:
-        batch.set_schedule(**json.loads(args.schedule))
+    if schedule:
+        batch.set_schedule(**schedule)
     elif not args.no_autotune:
         t0 = time.perf_counter()
         _, n_tried = batch.autotune(trial_sweeps=args.tune_sweeps)
@@ -149,7 +127,9 @@ def main():
     step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     total_s = sum(step_ms) / 1e3
     flips = work.spins * spw * args.steps
-    value = flips / total_s
+    # sanity: the last trace is finite and physical
+    b_last = traces[-1][0][:, -1].cpu()
+    assert int(b_last.abs().max()) <= 2 * max(r.spins for r in work.replicas)
 
     # dominant kernel: all-resident batches launch one k_sweep_resident per
     # sweeps_per_launch sweeps; all-streaming batches one k_sweep_stream per
@@ -165,53 +145,110 @@ def main():
         kernel, launches, sweeps_per_launch = "k_sweep_resident+k_sweep_stream (concurrent)", \
             args.steps * -(-spw // S), min(spw, S)
     launch_s = total_s / launches
-    flips_per_launch = work.spins * sweeps_per_launch
-    achieved = flips_per_launch / launch_s
+    achieved = work.spins * sweeps_per_launch / launch_s
+    return {"value": flips / total_s, "ms_per_step": total_s * 1e3 / args.steps, "schedule": sched,
+            "resident_replicas": n_res, "streamed_replicas": n_str, "autotune": tuned, "wall_s": wall,
+            "kernel": kernel, "launches": launches, "launch_s": launch_s, "achieved": achieved,
+            "rec_every": rec_every}, batch
+
+
+RNG_NAMES = {"site": 0, "bitsliced": 1}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--sweeps-per-step", type=int, default=100)
+    ap.add_argument("--workload", default="batch_256x1024")
+    ap.add_argument("--rng", default="site", choices=list(RNG_NAMES),
+                    help="random-number contract of the measured path (site: one Philox word per site; "
+                         "bitsliced: transposed group words drawn lazily)")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the second measurement under the other random-number contract")
+    ap.add_argument("--cpu-sweeps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="", help="JSON dict overriding the execution schedule")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="also run the learned-proposal comparison (64 x 256^2 near T_c)")
+    ap.add_argument("--learned-units", type=int, default=10000)
+    ap.add_argument("--plain-sweeps", type=int, default=500000)
+    ap.add_argument("--tune-sweeps", type=int, default=20)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(replicas would shard across GPUs with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2404_16990_amd import probe
+    import workloads
+
+    work = workloads.ALL[args.workload]()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rng = RNG_NAMES[args.rng]
+    m, batch = run_path(work, rng, args, stream, json.loads(args.schedule) if args.schedule else None)
+    sched = m["schedule"]
     peak = alu_peak_flips()
     traffic, algo_bytes = (None, None)
-    if kernel == "k_sweep_resident" and S == 50 and sched["resident_threads"] == 1024 \
-            and sched["word_bits"] == 64:
-        traffic, algo_bytes = measured_traffic(kernel, work.name)
-    roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e9, "peak": peak / 1e9,
-                "unit": "Gflip/s", "frac": achieved / peak, "traffic": traffic,
+    if rng == 0 and m["kernel"] == "k_sweep_resident" and sched["sweeps_per_launch"] == 50 \
+            and sched["resident_threads"] == 1024 and sched["word_bits"] == 64:
+        traffic, algo_bytes = measured_traffic(m["kernel"], work.name)
+    launch_s = m["launch_s"]
+    roofline = {"bound": "alu", "kernel": m["kernel"], "achieved": m["achieved"] / 1e9, "peak": peak / 1e9,
+                "unit": "Gflip/s", "frac": m["achieved"] / peak, "traffic": traffic,
                 "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt",
-                "launch_ms": launch_s * 1e3, "launches": launches,
+                "launch_ms": launch_s * 1e3, "launches": m["launches"],
                 "hbm_bytes_per_launch_algorithmic": algo_bytes,
                 "hbm_frac_of_8TBps": (traffic / launch_s / HBM_BYTES_PER_S) if traffic else None}
     # measured ALU ceiling: the same per-word arithmetic with no memory traffic
-    from paper_2404_16990_amd import probe
-    ceiling = probe.mix_rate(sched["word_bits"])
+    ceiling = probe.mix_rate(sched["word_bits"], rng=rng)
     roofline["measured_alu_ceiling"] = {
-        "value": ceiling / 1e9, "unit": "Gflip/s", "frac": achieved / ceiling,
-        "kernel": f"k_mix<{sched['word_bits']}-bit> (ising::update_word on register-resident words)"}
-    # sanity: the last trace is finite and physical
-    b_last = traces[-1][0][:, -1].cpu()
-    assert int(b_last.abs().max()) <= 2 * max(r.spins for r in work.replicas)
+        "value": ceiling / 1e9, "unit": "Gflip/s", "frac": m["achieved"] / ceiling,
+        "kernel": f"k_mix<{sched['word_bits']}-bit, rng={args.rng}> (ising::update_word on register-resident words)"}
 
     out = {
         "metric": "aggregate flip attempts/s on 1 MI355X",
-        "value": value,
+        "value": m["value"],
         "unit": "flip attempts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": total_s * 1e3 / args.steps,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32 (1 bit/spin, integer Philox thresholds)",
         "data": "synthetic",
         "config": {"workload": work.name, "replicas": len(work.replicas), "spins": work.spins,
-                   "sweeps_per_step": spw, "record_every": rec_every, "schedule": sched,
-                   "resident_replicas": n_res, "streamed_replicas": n_str,
-                   "autotune": tuned, "wall_s": wall},
+                   "sweeps_per_step": args.sweeps_per_step, "record_every": m["rec_every"],
+                   "rng": args.rng, "schedule": sched,
+                   "resident_replicas": m["resident_replicas"], "streamed_replicas": m["streamed_replicas"],
+                   "autotune": m["autotune"], "wall_s": m["wall_s"]},
         "roofline": roofline,
     }
+    batch.close()
+    del batch
+    if not args.no_variant:
+        # the same workload under the other random-number contract (its own
+        # oracle and parity tests), timed the same way with the same schedule
+        other = [k for k in RNG_NAMES if k != args.rng][0]
+        mv, bv = run_path(work, RNG_NAMES[other], args, stream, sched)
+        cv = probe.mix_rate(sched["word_bits"], rng=RNG_NAMES[other])
+        out["variants"] = {f"rng_{other}": {
+            "value": mv["value"], "ms_per_step": mv["ms_per_step"], "launch_ms": mv["launch_s"] * 1e3,
+            "frac_of_derived_peak": mv["achieved"] / peak,
+            "measured_alu_ceiling": cv / 1e9, "frac_of_measured_ceiling": mv["achieved"] / cv}}
+        bv.close()
+        del bv
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps, rng)
     if args.learned:
-        batch.close()
-        del batch
         torch.cuda.empty_cache()
         out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps)
     print(json.dumps(out), flush=True)

@@ -69,13 +69,29 @@ enum { ISING_INIT_RANDOM = 0, ISING_INIT_UP = 1, ISING_INIT_DOWN = 2 };
  *           Philox(ctr = {g >> 2, 0, replica, 2}) >= 2^31 with g = y*Lx + x
  *           (the paper starts from a completely random configuration,
  *           section 3.1); ISING_INIT_UP / ISING_INIT_DOWN: all +1 / all -1.
+ *  rng      which uniform a proposal with dE > 0 is compared with (section 1's
+ *           ran(); the paper's generator is unpublished, Supplementary S.4):
+ *           ISING_RNG_SITE: for the colour-c site with compact index
+ *             h = (y*Lx + x) >> 1 in sweep t, word (h & 3) of
+ *             Philox4x32-10(ctr = {h >> 2, t, replica, c}, key = seed);
+ *           ISING_RNG_BITSLICED: the colour-c sites h = 32g .. 32g+31 form
+ *             group g with words W_k = word (k & 3) of Philox(ctr =
+ *             {8g + (k >> 2), t, replica, c}), k = 0..31, and site 32g + b
+ *             takes the uniform whose bit 31 - k is bit b of W_k.  Compared
+ *             with the threshold from the top bit down, most sites are decided
+ *             after a few words, so the library draws only the words needed.
+ *           Both give exact Metropolis acceptance; they give different
+ *           trajectories (ISING_E_INVALID for other values).
  */
+enum { ISING_RNG_SITE = 0, ISING_RNG_BITSLICED = 1 };
+
 typedef struct {
     int32_t Lx, Ly;
     double J, beta;
     uint64_t seed;
     uint32_t replica;
     int32_t init;
+    int32_t rng;
 } ising_desc;
 
 typedef struct ising_batch ising_batch;

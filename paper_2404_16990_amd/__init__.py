@@ -36,7 +36,10 @@ EXPORTED = [
 class ising_desc(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("J", ctypes.c_double),
                 ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint32), ("init", ctypes.c_int32)]
+                ("replica", ctypes.c_uint32), ("init", ctypes.c_int32), ("rng", ctypes.c_int32)]
+
+
+ISING_RNG_SITE, ISING_RNG_BITSLICED = 0, 1
 
 
 class ising_schedule(ctypes.Structure):
@@ -119,7 +122,7 @@ def _descs(descs):
             arr[i] = d
         else:
             arr[i] = ising_desc(int(d["Lx"]), int(d["Ly"]), float(d.get("J", 1.0)), float(d["beta"]),
-                                int(d["seed"]), int(d["replica"]), int(d.get("init", 0)))
+                                int(d["seed"]), int(d["replica"]), int(d.get("init", 0)), int(d.get("rng", 0)))
     return arr
 
 

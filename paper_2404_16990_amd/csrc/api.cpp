@@ -83,6 +83,8 @@ int check_desc(const ising_desc &d, int32_t i)
         return fail(st, g_last_error + at);
     if (d.init != ISING_INIT_RANDOM && d.init != ISING_INIT_UP && d.init != ISING_INIT_DOWN)
         return fail(ISING_E_INVALID, "unknown init mode" + at);
+    if (d.rng != ISING_RNG_SITE && d.rng != ISING_RNG_BITSLICED)
+        return fail(ISING_E_INVALID, "unknown random-number contract (rng)" + at);
     if (d.Lx <= 0 || d.Lx % 64 != 0)
         return fail(ISING_E_UNSUPPORTED, "Lx must be a positive multiple of 64" + at);
     if (d.Ly < 2 || d.Ly % 2 != 0)
@@ -367,6 +369,7 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
         r.seed_lo = (uint32_t)(d[i].seed & 0xffffffffu);
         r.seed_hi = (uint32_t)(d[i].seed >> 32);
         r.replica = d[i].replica;
+        r.rng = (uint32_t)d[i].rng;
         set_thresholds(r, d[i].J, d[i].beta);
         r.t = 0;
         r.t0 = 0;

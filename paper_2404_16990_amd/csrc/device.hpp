@@ -27,7 +27,7 @@ struct RepDev {
     uint32_t thr4, thr8;  // acceptance thresholds for dE = 4J and 8J
     uint32_t t;         // sweeps completed
     uint32_t t0;        // value of t when the current run started
-    uint32_t pad;
+    uint32_t rng;       // random-number contract: 0 one word per site, 1 bit-sliced groups
     uint64_t N;         // Lx * Ly
 };
 static_assert(sizeof(RepDev) == 64, "descriptor must stay 64 bytes");
@@ -79,7 +79,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 // Everything the update of one colour of one sweep of one replica needs
 // besides the spins (all wave-uniform).
 struct SweepKey {
-    uint32_t k0, k1, t, replica, colour, thr4, thr8, always;
+    uint32_t k0, k1, t, replica, colour, thr4, thr8, always, rng;
 };
 
 __device__ __forceinline__ SweepKey make_key(const RepDev &d, uint32_t t, uint32_t colour)
@@ -93,6 +93,7 @@ __device__ __forceinline__ SweepKey make_key(const RepDev &d, uint32_t t, uint32
     k.thr4 = d.thr4;
     k.thr8 = d.thr8;
     k.always = d.always;
+    k.rng = d.rng;
     return k;
 }
 
@@ -108,6 +109,24 @@ __device__ __forceinline__ uint32_t shift_in_carry(uint32_t acc, uint64_t lanema
     return out;
 }
 
+// Classes of the 32 sites of a word by the number of anti-aligned neighbours
+// (a_k = s ^ n_k), counted with two half adders: ge2 (two or more: dE <= 0)
+// and eq1 (exactly one: dE = 4J); the rest have none (dE = 8J).
+struct Classes {
+    uint32_t ge2, eq1;
+};
+
+__device__ __forceinline__ Classes classify(uint32_t s, uint32_t up, uint32_t dn, uint32_t same, uint32_t side)
+{
+    const uint32_t a1 = s ^ up, a2 = s ^ dn, a3 = s ^ same, a4 = s ^ side;
+    const uint32_t s1 = a1 ^ a2, c1 = a1 & a2;
+    const uint32_t s2 = a3 ^ a4, c2 = a3 & a4;
+    Classes c;
+    c.ge2 = c1 | c2 | (s1 & s2);
+    c.eq1 = (s1 ^ s2) & ~(c1 | c2);
+    return c;
+}
+
 // Neighbour classification and Metropolis acceptance for one 32-bit word of
 // same-colour spins (the multi-spin idea of the paper's Algorithm 2,
 // flipQuarter, restated for 1-bit words):
@@ -121,11 +140,8 @@ __device__ __forceinline__ uint32_t shift_in_carry(uint32_t acc, uint64_t lanema
 __device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_t dn, uint32_t same,
                                                 uint32_t side, uint32_t q0, const SweepKey &K)
 {
-    const uint32_t a1 = s ^ up, a2 = s ^ dn, a3 = s ^ same, a4 = s ^ side;
-    const uint32_t s1 = a1 ^ a2, c1 = a1 & a2;
-    const uint32_t s2 = a3 ^ a4, c2 = a3 & a4;
-    const uint32_t ge2 = c1 | c2 | (s1 & s2);
-    const uint32_t eq1 = (s1 ^ s2) & ~(c1 | c2);
+    const Classes cl = classify(s, up, dn, same, side);
+    const uint32_t ge2 = cl.ge2, eq1 = cl.eq1;
     // Acceptance in four instructions per site: broadcast the site's class bit
     // (v_bfe_i32), select its threshold (v_bitop3, table 0xCA = m ? thr4 :
     // thr8), compare r < thr into a lane mask (v_cmp_lt_u32), and shift that
@@ -147,6 +163,56 @@ __device__ __forceinline__ uint32_t flip_mask32(uint32_t s, uint32_t up, uint32_
         }
     }
     return ge2 | acc;
+}
+
+// Acceptance under the bit-sliced random-number contract for NH groups of 32
+// sites (the 32-bit halves of one word; group h uses Philox counters
+// c0 + 8h + m, m = 0..7, whose four words are W_4m .. W_4m+3).  A site's
+// uniform has bit 31 - k equal to its bit of W_k, so it is compared with its
+// threshold (thr4 for eq1 sites, thr8 for the others) from the top bit down:
+// at level k an undecided site whose uniform bit is 0 where the threshold bit
+// is 1 is accepted, and every site whose two bits differ is decided.  Words
+// are drawn four at a time and drawing stops once no lane of the wave has an
+// undecided site, so the result equals the full comparison.
+template <int NH>
+__device__ __forceinline__ void bitsliced_accept(const uint32_t (&undecided)[NH], const uint32_t (&eq1)[NH],
+                                                 uint32_t c0, const SweepKey &K, uint32_t (&acc)[NH])
+{
+    uint32_t und[NH], any = 0;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        und[h] = undecided[h];
+        acc[h] = 0;
+        any |= und[h];
+    }
+    const uint32_t thr4 = __builtin_amdgcn_readfirstlane(K.thr4), thr8 = __builtin_amdgcn_readfirstlane(K.thr8);
+    if (thr4 == 0u)  // thr8 <= thr4 = 0: no proposal with dE > 0 is accepted
+        return;
+    if (__builtin_amdgcn_ballot_w64(any != 0u) == 0)
+        return;
+    for (int m = 0; m < 8; ++m) {
+        uint32_t w[NH][4];
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+            philox4x32_10(c0 + 8u * h + m, K.t, K.replica, K.colour, K.k0, K.k1, w[h]);
+        any = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * m + j;
+            const uint32_t m4 = 0u - ((thr4 >> (31 - k)) & 1u), m8 = 0u - ((thr8 >> (31 - k)) & 1u);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                const uint32_t q = __builtin_amdgcn_bitop3_b32(eq1[h], m4, m8, 0xCA);  // threshold bit k
+                acc[h] |= und[h] & ~w[h][j] & q;
+                und[h] &= ~(w[h][j] ^ q);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+            any |= und[h];
+        if (__builtin_amdgcn_ballot_w64(any != 0u) == 0)
+            break;
+    }
 }
 
 // Horizontal neighbour word of the other colour (the paper's Algorithm 1,
@@ -180,6 +246,25 @@ __device__ __forceinline__ Word update_word(Word s, Word up, Word dn, Word same,
 {
     if (K.always)
         return ~s;
+    if (K.rng) {
+        constexpr int NH = WordTraits<Word>::BITS / 32;
+        uint32_t und[NH], eq1[NH], ge2[NH], acc[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const Classes c = classify((uint32_t)(s >> (32 * h)), (uint32_t)(up >> (32 * h)),
+                                       (uint32_t)(dn >> (32 * h)), (uint32_t)(same >> (32 * h)),
+                                       (uint32_t)(side >> (32 * h)));
+            ge2[h] = c.ge2;
+            eq1[h] = c.eq1;
+            und[h] = ~c.ge2;
+        }
+        bitsliced_accept<NH>(und, eq1, q0, K, acc);
+        Word flip = 0;
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+            flip |= (Word)(ge2[h] | acc[h]) << (32 * h);
+        return s ^ flip;
+    }
     if constexpr (WordTraits<Word>::BITS == 32) {
         return s ^ flip_mask32(s, up, dn, same, side, q0, K);
     } else {

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_clock(uint64_t *stamps, uint32_t *out, 
 // instruction mix (thresholds of T_c; no data-dependent branches).
 template <typename Word>
 __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4,
-                                             uint32_t thr8)
+                                             uint32_t thr8, uint32_t rng)
 {
     using ising::SweepKey;
     const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
@@ -159,6 +159,7 @@ __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int i
     K.thr4 = thr4;
     K.thr8 = thr8;
     K.always = 0u;
+    K.rng = rng;
     Word s = (Word)(tid * 0x9E3779B97F4A7C15ull), up = (Word)(tid * 0xC2B2AE3D27D4EB4Full),
          dn = (Word)(tid * 0x165667B19E3779F9ull), same = (Word)(tid * 0x27D4EB2F165667C5ull);
     const Word side = same ^ up;
@@ -210,11 +211,13 @@ extern "C" {
 
 /* Measured ALU ceiling of the sweep's per-word arithmetic: k_mix with 32- or
  * 64-bit words on blocks x 256 threads for iters iterations (after a warm-up
- * launch).  Sites counted: blocks * 256 * iters * word_bits.  Writes the
+ * launch), under the site (rng 0) or bit-sliced (rng 1) random-number
+ * contract.  Sites counted: blocks * 256 * iters * word_bits.  Writes the
  * milliseconds of the timed launch to *ms; returns 0, or <0 on error. */
-int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned thr4, unsigned thr8, float *ms)
+int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned thr4, unsigned thr8, int rng,
+                    float *ms)
 {
-    if (!out || blocks <= 0 || iters <= 0 || !ms || (word_bits != 32 && word_bits != 64))
+    if (!out || blocks <= 0 || iters <= 0 || !ms || (word_bits != 32 && word_bits != 64) || (rng != 0 && rng != 1))
         return -1;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -227,9 +230,11 @@ int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned th
         if (err != hipSuccess)
             break;
         if (word_bits == 32)
-            hipLaunchKernelGGL(k_mix<uint32_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8);
+            hipLaunchKernelGGL(k_mix<uint32_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8,
+                               (uint32_t)rng);
         else
-            hipLaunchKernelGGL(k_mix<uint64_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8);
+            hipLaunchKernelGGL(k_mix<uint64_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8,
+                               (uint32_t)rng);
         err = hipGetLastError();
     }
     if (err == hipSuccess)

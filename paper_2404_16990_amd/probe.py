@@ -48,7 +48,7 @@ def measure(blocks=256 * 16, iters=4096):
             "philox_lane_cycles_per_call": xor / res["philox4x32_10"]}
 
 
-def mix_rate(word_bits=64, blocks=256 * 16, iters=64, T=2.269185):
+def mix_rate(word_bits=64, blocks=256 * 16, iters=64, T=2.269185, rng=0):
     """Measured ALU ceiling of the sweep's per-word arithmetic, in site updates
     (flip attempts) per second: k_mix runs ising::update_word on register-resident
     words (classification, Philox4x32-10, acceptance) with no memory traffic."""
@@ -56,11 +56,12 @@ def mix_rate(word_bits=64, blocks=256 * 16, iters=64, T=2.269185):
     import torch
     L = _lib()
     L.ising_probe_mix.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
-                                  ctypes.c_uint, ctypes.POINTER(ctypes.c_float)]
+                                  ctypes.c_uint, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     thr = [min(int(math.floor(math.ldexp(math.exp(-4.0 * k / T), 32))), 2**32 - 1) for k in (1, 2)]
     out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     ms = ctypes.c_float()
-    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], ctypes.byref(ms)) != 0:
+    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], int(rng),
+                         ctypes.byref(ms)) != 0:
         raise RuntimeError("mix probe failed")
     return blocks * 256 * iters * word_bits / (ms.value * 1e-3)
 
@@ -130,6 +131,7 @@ if __name__ == "__main__":
     else:
         r = measure()
         r["sweep_mix_flips_per_s"] = {str(w): mix_rate(w) for w in (32, 64)}
+        r["sweep_mix_bitsliced_flips_per_s"] = {str(w): mix_rate(w, rng=1) for w in (32, 64)}
         r["clock"] = clock()
         r["copy_bytes_per_s"] = copy_bandwidth()
         print(json.dumps(r, indent=1))

@@ -60,6 +60,7 @@ def test_state_bytes_layout():
     (dict(J=0.0), P.ISING_E_INVALID), (dict(J=-1.0), P.ISING_E_INVALID),
     (dict(J=math.inf), P.ISING_E_INVALID), (dict(beta=-0.1), P.ISING_E_INVALID),
     (dict(beta=math.nan), P.ISING_E_INVALID), (dict(init=7), P.ISING_E_INVALID),
+    (dict(rng=2), P.ISING_E_INVALID), (dict(rng=-1), P.ISING_E_INVALID),
 ])
 def test_invalid_descriptors(kw, code):
     with pytest.raises(P.IsingError) as e:
@@ -70,6 +71,11 @@ def test_invalid_descriptors(kw, code):
 
 def test_infinite_beta_is_valid():
     assert P.ising_state_bytes([_d(beta=math.inf)]) > 0
+
+
+def test_both_random_number_contracts_are_valid():
+    assert P.ising_state_bytes([_d(rng=P.ISING_RNG_SITE), _d(rng=P.ISING_RNG_BITSLICED)]) > 0
+    assert P.ctypes.sizeof(P.ising_desc) == 48  # C layout: 40 bytes + int32 rng, 8-byte aligned
 
 
 def test_create_rejects_before_touching_the_device():

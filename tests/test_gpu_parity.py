@@ -34,11 +34,11 @@ def _P():
 
 
 def gdesc(r):
-    return dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+    return dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init, rng=r.rng)
 
 
 def odesc(r):
-    return oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init)
+    return oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init, rng=r.rng)
 
 
 def gpu_batch(reps, schedule=None):

@@ -245,17 +245,18 @@ def test_record_every_and_threads_do_not_change_results():
         assert np.array_equal(b, b1[r]) and np.array_equal(s, st1[r])
 
 
-def test_oracle_golden_trace_single_64():
+@pytest.mark.parametrize("rng,name", [(0, "oracle_single64.json"), (1, "oracle_single64_bitsliced.json")])
+def test_oracle_golden_trace_single_64(rng, name):
     """Regression pin: the stored trace was written by a script that calls only the oracle."""
     import hashlib
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_single64.json")
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
     with open(path) as f:
         g = json.load(f)
     w = workloads.single_64()
     r = w.replicas[0]
-    d = oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init)
+    d = oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init, rng=rng)
     s = oracle.init_state(d)
     assert hashlib.sha256(s.tobytes()).hexdigest() == g["init_sha256"]
     b, m = oracle.sweeps(d, s, w.sweeps, record_every=w.record_every)

@@ -31,6 +31,7 @@ class Replica:
     replica: int
     init: int = INIT_RANDOM
     J: float = 1.0
+    rng: int = 0  # random-number contract: 0 one Philox word per site, 1 bit-sliced groups
 
     @property
     def beta(self) -> float:

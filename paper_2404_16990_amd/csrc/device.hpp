@@ -240,13 +240,16 @@ __device__ __forceinline__ Word side_word(Word same, Word nb, uint32_t p)
 
 // Update of one Word (32 or 64 spins) given its neighbour words; a 64-bit
 // word is two independent 32-bit halves (sites 0..31 and 32..63).
-template <typename Word>
+// BITSLICED selects the random-number contract at compile time (the kernels
+// branch once per workgroup on the replica's contract), so each contract's
+// loop is compiled on its own.
+template <typename Word, bool BITSLICED = false>
 __device__ __forceinline__ Word update_word(Word s, Word up, Word dn, Word same, Word side, uint32_t q0,
                                             const SweepKey &K)
 {
     if (K.always)
         return ~s;
-    if (K.rng) {
+    if constexpr (BITSLICED) {
         constexpr int NH = WordTraits<Word>::BITS / 32;
         uint32_t und[NH], eq1[NH], ge2[NH], acc[NH];
 #pragma unroll

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_init(const RepDev *__restrict__ reps,
 // a colour row holds Wn * BITS = Lx / 2 sites.  FIXED_W: Wn divides THREADS,
 // so the thread's column w and its horizontal neighbours never change.
 // ---------------------------------------------------------------------------
-template <typename Word, int THREADS, bool FIXED_W>
+template <typename Word, int THREADS, bool FIXED_W, bool BITSLICED>
 __device__ __forceinline__ void update_words(const Word *__restrict__ src, Word *__restrict__ dst,
                                              uint32_t first, uint32_t end, uint32_t Ly, uint32_t Wn,
                                              const SweepKey &K, bool rec, uint32_t &anti, uint32_t &pop)
@@ -76,7 +76,7 @@ __device__ __forceinline__ void update_words(const Word *__restrict__ src, Word 
         const Word nb = src[idx - w + (p ? wp : wm)];
         const Word s = dst[idx];
         const Word side = side_word<Word>(same, nb, p);
-        const Word ns = update_word<Word>(s, up, dn, same, side, idx * QW, K);
+        const Word ns = update_word<Word, BITSLICED>(s, up, dn, same, side, idx * QW, K);
         dst[idx] = ns;
         if (rec) {
             anti += anti_bonds<Word>(ns, up, dn, same, side);
@@ -92,6 +92,27 @@ __device__ __forceinline__ void update_words(const Word *__restrict__ src, Word 
             wp = w + 1 == Wn ? 0 : w + 1;
             wm = w == 0 ? Wn - 1 : w - 1;
         }
+    }
+}
+
+// One thread's share of a colour phase with the column and contract
+// specialisations chosen once (both are uniform over the workgroup).
+template <typename Word, int THREADS>
+__device__ __forceinline__ void update_words_any(const Word *__restrict__ src, Word *__restrict__ dst,
+                                                 uint32_t first, uint32_t end, uint32_t Ly, uint32_t Wn,
+                                                 const SweepKey &K, bool rec, uint32_t &anti, uint32_t &pop)
+{
+    const bool fixed_w = THREADS % Wn == 0;
+    if (K.rng) {
+        if (fixed_w)
+            update_words<Word, THREADS, true, true>(src, dst, first, end, Ly, Wn, K, rec, anti, pop);
+        else
+            update_words<Word, THREADS, false, true>(src, dst, first, end, Ly, Wn, K, rec, anti, pop);
+    } else {
+        if (fixed_w)
+            update_words<Word, THREADS, true, false>(src, dst, first, end, Ly, Wn, K, rec, anti, pop);
+        else
+            update_words<Word, THREADS, false, false>(src, dst, first, end, Ly, Wn, K, rec, anti, pop);
     }
 }
 
@@ -137,10 +158,7 @@ __global__ __launch_bounds__(THREADS) void k_sweep_stream(const RepDev *__restri
     const uint32_t begin = tile * words_per_wg;
     const uint32_t end = min(begin + words_per_wg, total);
     uint32_t anti = 0, pop = 0;
-    if (THREADS % Wn == 0)
-        update_words<Word, THREADS, true>(src, dst, begin + threadIdx.x, end, Ly, Wn, K, record, anti, pop);
-    else
-        update_words<Word, THREADS, false>(src, dst, begin + threadIdx.x, end, Ly, Wn, K, record, anti, pop);
+    update_words_any<Word, THREADS>(src, dst, begin + threadIdx.x, end, Ly, Wn, K, record, anti, pop);
     if (record) {
         __shared__ int64_t red[2][THREADS / 64];
         const int64_t a = wave_sum((int64_t)anti);
@@ -201,7 +219,6 @@ void k_sweep_resident(const RepDev *__restrict__ reps,
     __syncthreads();
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
 
-    const bool fixed_w = THREADS % Wn == 0;
     __shared__ int64_t red[2][THREADS / 64];
 
     for (uint32_t s_i = 0; s_i < n_sweeps; ++s_i) {
@@ -216,10 +233,7 @@ void k_sweep_resident(const RepDev *__restrict__ reps,
             const SweepKey K = make_key(d, t, colour);
             const bool rec_here = record && colour == 1u;
             uint32_t anti = 0, pop = 0;
-            if (fixed_w)
-                update_words<Word, THREADS, true>(src, dst, threadIdx.x, total, Ly, Wn, K, rec_here, anti, pop);
-            else
-                update_words<Word, THREADS, false>(src, dst, threadIdx.x, total, Ly, Wn, K, rec_here, anti, pop);
+            update_words_any<Word, THREADS>(src, dst, threadIdx.x, total, Ly, Wn, K, rec_here, anti, pop);
             if (rec_here) {
                 const int64_t a = wave_sum((int64_t)anti);
                 const int64_t m = wave_sum((int64_t)pop);

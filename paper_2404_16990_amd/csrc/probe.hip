@@ -144,9 +144,9 @@ __global__ __launch_bounds__(256) void k_clock(uint64_t *stamps, uint32_t *out, 
 // updated word feeding the next iteration, and a fresh counter per iteration.
 // Sites per second of this kernel is the measured ALU ceiling of the sweep's
 // instruction mix (thresholds of T_c; no data-dependent branches).
-template <typename Word>
+template <typename Word, bool BITSLICED>
 __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4,
-                                             uint32_t thr8, uint32_t rng)
+                                             uint32_t thr8)
 {
     using ising::SweepKey;
     const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
@@ -159,14 +159,14 @@ __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int i
     K.thr4 = thr4;
     K.thr8 = thr8;
     K.always = 0u;
-    K.rng = rng;
+    K.rng = BITSLICED ? 1u : 0u;
     Word s = (Word)(tid * 0x9E3779B97F4A7C15ull), up = (Word)(tid * 0xC2B2AE3D27D4EB4Full),
          dn = (Word)(tid * 0x165667B19E3779F9ull), same = (Word)(tid * 0x27D4EB2F165667C5ull);
     const Word side = same ^ up;
     constexpr uint32_t QW = ising::WordTraits<Word>::BITS / 4;
     for (int i = 0; i < iters; ++i) {
         K.t = (uint32_t)i;
-        s = ising::update_word<Word>(s, up, dn, same, side, (tid + (uint32_t)i * 0x100000u) * QW, K);
+        s = ising::update_word<Word, BITSLICED>(s, up, dn, same, side, (tid + (uint32_t)i * 0x100000u) * QW, K);
     }
     out[tid] = (uint32_t)s ^ (uint32_t)((uint64_t)s >> 32);
 }
@@ -229,12 +229,18 @@ int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned th
             err = hipEventRecord(e0, nullptr);
         if (err != hipSuccess)
             break;
-        if (word_bits == 32)
-            hipLaunchKernelGGL(k_mix<uint32_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8,
-                               (uint32_t)rng);
+        if (word_bits == 32 && rng == 0)
+            hipLaunchKernelGGL((k_mix<uint32_t, false>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
+                               thr8);
+        else if (word_bits == 32)
+            hipLaunchKernelGGL((k_mix<uint32_t, true>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
+                               thr8);
+        else if (rng == 0)
+            hipLaunchKernelGGL((k_mix<uint64_t, false>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
+                               thr8);
         else
-            hipLaunchKernelGGL(k_mix<uint64_t>, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8,
-                               (uint32_t)rng);
+            hipLaunchKernelGGL((k_mix<uint64_t, true>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
+                               thr8);
         err = hipGetLastError();
     }
     if (err == hipSuccess)

@@ -203,11 +203,13 @@ int ising_batch_set_schedule(ising_batch *b, const ising_schedule *s);
  * planes must equal the first candidate's bit for bit (ISING_E_STATE
  * otherwise: that would be a kernel bug, and the detail names the candidate).
  * Candidates are searched one schedule field at a time (word width, resident
- * threshold and workgroup size, streaming workgroup shape, sweeps per launch).
+ * threshold and workgroup size, streaming workgroup shape, sweeps per launch);
+ * a candidate replaces the current best only when it is at least 2 % faster.
  * Afterwards the saved planes and sweep counters are restored, so tuning
  * leaves the simulation unchanged.  If the environment variable
  * ISING_AUTOTUNE_CACHE names a file, a schedule stored there for the same
- * device and the same multiset of lattice shapes is installed without
+ * device and the same multiset of (lattice shape, random-number contract) is
+ * installed without
  * measuring, and new results are appended to it.  *chosen (optional) receives
  * the installed schedule; *n_tried (optional) the number of candidates timed
  * (0 on a cache hit).

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -644,13 +645,13 @@ std::string tune_key(ising_batch *b)
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess)
         arch = prop.gcnArchName;
-    std::vector<std::pair<int32_t, int32_t>> shapes;
+    std::vector<std::array<int32_t, 3>> shapes;
     for (const auto &d : b->desc)
-        shapes.emplace_back(d.Lx, d.Ly);
+        shapes.push_back({d.Lx, d.Ly, d.rng});
     std::sort(shapes.begin(), shapes.end());
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over the sorted shapes
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the sorted (shape, contract) triples
     for (const auto &p : shapes)
-        for (int32_t v : {p.first, p.second})
+        for (int32_t v : p)
             for (int k = 0; k < 4; ++k) {
                 h ^= (uint64_t)((v >> (8 * k)) & 0xff);
                 h *= 1099511628211ull;
@@ -812,7 +813,9 @@ int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *c
             st = trial(c, &ms);
             if (st != ISING_OK)
                 break;
-            if (ms < best_ms) {
+            // a candidate must beat the incumbent by 2 %, so timing noise does
+            // not flip between schedules of nearly equal speed
+            if (ms < 0.98f * best_ms) {
                 best_ms = ms;
                 best = c;
             }

@@ -236,12 +236,13 @@ def main():
     del batch
     if not args.no_variant:
         # the same workload under the other random-number contract (its own
-        # oracle and parity tests), timed the same way with the same schedule
+        # oracle and parity tests), scheduled and timed the same way
         other = [k for k in RNG_NAMES if k != args.rng][0]
-        mv, bv = run_path(work, RNG_NAMES[other], args, stream, sched)
-        cv = probe.mix_rate(sched["word_bits"], rng=RNG_NAMES[other])
+        mv, bv = run_path(work, RNG_NAMES[other], args, stream, json.loads(args.schedule) if args.schedule else None)
+        cv = probe.mix_rate(mv["schedule"]["word_bits"], rng=RNG_NAMES[other])
         out["variants"] = {f"rng_{other}": {
             "value": mv["value"], "ms_per_step": mv["ms_per_step"], "launch_ms": mv["launch_s"] * 1e3,
+            "schedule": mv["schedule"], "autotune": mv["autotune"],
             "frac_of_derived_peak": mv["achieved"] / peak,
             "measured_alu_ceiling": cv / 1e9, "frac_of_measured_ceiling": mv["achieved"] / cv}}
         bv.close()

@@ -96,3 +96,32 @@ def test_paper_scale_full_1000_sweeps_matches_onsager_and_yang():
     big = e[-1]
     assert big[0] < big[-1] < -math.sqrt(2.0) + 0.02, (big[0], big[-1])
     assert np.all(np.diff(big[:20]) > 0)  # monotone relaxation early on
+
+
+def test_largest_lattice_exact_properties():
+    """The largest lattice the library accepts (Lx*Ly just below 2^32: 65536 x
+    65534, 512 MiB of spins) under exact properties of the rule: at beta = 0
+    every proposal is accepted, so a sweep flips every spin (M -> -M, B kept,
+    and two sweeps restore the state); at beta = infinity a cold start is
+    frozen (nothing with dE > 0 is accepted and no site has dE <= 0)."""
+    import torch
+    import paper_2404_16990_amd as P
+    Lx, Ly = 65536, 65534
+    assert Lx * Ly < 2**32
+    for rng in (0, 1):
+        b = P.Batch([dict(Lx=Lx, Ly=Ly, J=1.0, beta=0.0, seed=5, replica=0, init=0, rng=rng),
+                     dict(Lx=Lx, Ly=Ly, J=1.0, beta=math.inf, seed=6, replica=1, init=1, rng=rng)])
+        B0, M0 = b.observables()
+        assert M0[1] == Lx * Ly and B0[1] == 2 * Lx * Ly
+        assert B0[0] % 4 == (2 * Lx * Ly) % 4 and abs(M0[0]) < 10 * math.sqrt(Lx * Ly)
+        b.run(1)
+        B1, M1 = b.observables()
+        assert M1[0] == -M0[0] and B1[0] == B0[0]
+        assert M1[1] == M0[1] and B1[1] == B0[1]
+        b.run(1)
+        B2, M2 = b.observables()
+        assert M2[0] == M0[0] and B2[0] == B0[0]
+        torch.cuda.synchronize()
+        b.close()
+        del b
+        torch.cuda.empty_cache()

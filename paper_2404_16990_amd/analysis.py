@@ -4,6 +4,11 @@ tau_int: integrated autocorrelation time of a scalar series with Sokal's
 automatic window: rho(t) from the FFT autocovariance, tau(W) = 1/2 +
 sum_{t=1..W} rho(t), W the first lag with W >= c * tau(W) (c = 6).
 effective_rate: independent samples per second = units per second / (2 tau).
+equilibration: automatic detection of the equilibrated part of a series
+(Chodera, J. Chem. Theory Comput. 12, 1799 (2016)), the method the paper used
+to discard non-equilibrated data: the start t0 that maximises the number of
+effectively independent samples (n - t0) / g(t0), g = 1 + 2 sum_t rho(t) the
+statistical inefficiency of x[t0:].
 """
 import numpy as np
 
@@ -33,6 +38,42 @@ def effective_rate(units_per_second, tau):
 
 
 def mean_and_error(x, tau):
-    """Mean of a correlated series and its error sqrt(2 tau var / n)."""
+    """Mean of a correlated series and its error sqrt(2 tau var / n); tau is
+    floored at 1/2 (uncorrelated), since a windowed estimate of a short or
+    anti-correlated series can fall below it."""
     x = np.asarray(x, dtype=np.float64)
-    return float(x.mean()), float(np.sqrt(2.0 * tau * x.var(ddof=1) / x.size))
+    if x.size < 2:
+        return float(x.mean()), float("nan")
+    return float(x.mean()), float(np.sqrt(2.0 * max(tau, 0.5) * x.var(ddof=1) / x.size))
+
+
+def statistical_inefficiency(x):
+    """g = 1 + 2 sum_{t>=1} (1 - t/n) rho(t), summed until rho first drops to
+    or below zero (the estimator of Chodera's method); g >= 1."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    if n < 3 or x.var() == 0.0:
+        return 1.0
+    rho = autocorrelation(x)
+    g = 1.0
+    for t in range(1, n - 1):
+        if rho[t] <= 0.0:
+            break
+        g += 2.0 * rho[t] * (1.0 - t / n)
+    return max(1.0, float(g))
+
+
+def equilibration(x, candidates=100):
+    """(t0, g, n_eff): the equilibrated part is x[t0:], chosen among about
+    `candidates` evenly spaced starts as the one with the largest
+    n_eff = (n - t0) / g(t0).  Starts leave at least 10 samples."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    best = (0, 1.0, 0.0)
+    step = max(1, (n - 10) // candidates)
+    for t0 in range(0, max(1, n - 10), step):
+        g = statistical_inefficiency(x[t0:])
+        ne = (n - t0) / g
+        if ne > best[2]:
+            best = (t0, g, ne)
+    return best

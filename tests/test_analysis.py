@@ -1,0 +1,44 @@
+"""Host analysis: tau_int and the automatic equilibration detection."""
+import numpy as np
+
+from paper_2404_16990_amd import analysis
+
+
+def _ar1(rng, n, phi):
+    e = rng.normal(size=n)
+    x = np.empty(n)
+    x[0] = e[0] / np.sqrt(1 - phi * phi)
+    for t in range(1, n):
+        x[t] = phi * x[t - 1] + e[t]
+    return x
+
+
+def test_statistical_inefficiency_of_ar1():
+    # AR(1): g = (1 + phi) / (1 - phi)
+    rng = np.random.default_rng(0)
+    phi = 0.8
+    x = _ar1(rng, 200000, phi)
+    g = analysis.statistical_inefficiency(x)
+    assert abs(g - (1 + phi) / (1 - phi)) < 0.5, g
+
+
+def test_equilibration_finds_the_transient():
+    rng = np.random.default_rng(1)
+    n = 4000
+    x = _ar1(rng, n, 0.5) + 20.0 * np.exp(-np.arange(n) / 150.0)
+    t0, g, ne = analysis.equilibration(x)
+    # the transient is below the noise after ~150 ln 20 = 450 samples
+    assert 250 <= t0 <= 1200, t0
+    assert ne > 0.5 * (n - t0) / 3.0
+
+
+def test_equilibration_keeps_a_stationary_series():
+    rng = np.random.default_rng(2)
+    x = _ar1(rng, 4000, 0.5)
+    t0, g, ne = analysis.equilibration(x)
+    assert t0 <= 400, t0
+
+
+def test_equilibration_of_a_constant_series():
+    t0, g, ne = analysis.equilibration(np.ones(100))
+    assert t0 == 0 and g == 1.0

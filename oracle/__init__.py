@@ -7,7 +7,8 @@ of ``bench.py`` may.  It shares no code with the GPU library.
 Contents:
   - ``liboracle.so`` (from ``ising_oracle.c``): Philox4x32-10, thresholds,
     random/cold initial states, plain int8 sweeps, observables, threaded
-    batches over replicas.  This module is its ctypes front-end.
+    batches over replicas; (from ``cluster_oracle.c``) Swendsen-Wang and Wolff
+    cluster steps.  This module is its ctypes front-end.
   - ``philox``: a second, pure-Python Philox4x32-10.
   - ``exact``: exact results (enumeration, transfer matrix, Kaufman torus
     partition function, Onsager energy and T_c, Yang magnetisation).
@@ -59,6 +60,19 @@ def lib():
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                        ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int32]
+        L.oracle_bond_threshold.argtypes = [ctypes.c_double, ctypes.c_double, u32p,
+                                            ctypes.POINTER(ctypes.c_int32)]
+        L.oracle_cluster_labels.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_uint32,
+                                            ctypes.c_void_p]
+        L.oracle_wolff_seed.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint32]
+        L.oracle_wolff_seed.restype = ctypes.c_uint32
+        L.oracle_cluster_steps.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_run_cluster_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc),
+                                               ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -156,6 +170,75 @@ def run_batch(descs, states, n, t0=None, record_every=0, threads=None):
                                 int(n), int(record_every),
                                 bond.ctypes.data if n_rec else None,
                                 mag.ctypes.data if n_rec else None, int(threads))
+    if st != 0:
+        raise ValueError("invalid arguments")
+    return bond[:, :n_rec], mag[:, :n_rec]
+
+
+SWENDSEN_WANG, WOLFF = 0, 1
+
+
+def bond_threshold(J, beta):
+    """(thr, none): a bond between aligned spins is occupied iff its word >= thr
+    (P = 1 - thr / 2^32, the Fortuin-Kasteleyn 1 - exp(-2 beta J)); none = 1
+    when beta * J == 0 (no bond is occupied)."""
+    a, c = ctypes.c_uint32(), ctypes.c_int32()
+    if lib().oracle_bond_threshold(float(J), float(beta), ctypes.byref(a), ctypes.byref(c)) != 0:
+        raise ValueError("invalid J/beta")
+    return int(a.value), int(c.value)
+
+
+def cluster_labels(d, s, t):
+    """Cluster roots (smallest site index of each cluster) of the bond
+    configuration of step t, as an (Ly, Lx) uint32 array."""
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    assert s.shape == (d.Ly, d.Lx)
+    out = np.empty((d.Ly, d.Lx), dtype=np.uint32)
+    if lib().oracle_cluster_labels(ctypes.byref(d), s.ctypes.data, int(t), out.ctypes.data) != 0:
+        raise ValueError("invalid arguments")
+    return out
+
+
+def wolff_seed(d, t):
+    """Seed site index of the Wolff step with counter t."""
+    return int(lib().oracle_wolff_seed(ctypes.byref(d), int(t)))
+
+
+def cluster_steps(d, s, n, algorithm=SWENDSEN_WANG, t0=0, record_every=0):
+    """n cluster steps in place on s (int8, C-contiguous); returns (bond, mag) traces."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape == (d.Ly, d.Lx)
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros(max(n_rec, 1), dtype=np.int64)
+    mag = np.zeros(max(n_rec, 1), dtype=np.int64)
+    st = lib().oracle_cluster_steps(ctypes.byref(d), s.ctypes.data, int(algorithm), int(t0), int(n),
+                                    int(record_every), bond.ctypes.data if n_rec else None,
+                                    mag.ctypes.data if n_rec else None)
+    if st != 0:
+        raise ValueError("invalid arguments")
+    return bond[:n_rec], mag[:n_rec]
+
+
+def run_cluster_batch(descs, states, n, algorithm=SWENDSEN_WANG, t0=None, record_every=0, threads=None):
+    """Cluster steps of many replicas in place on host threads (as run_batch)."""
+    nrep = len(descs)
+    arr = (Desc * nrep)(*descs)
+    ptrs = (ctypes.c_void_p * nrep)()
+    for r, s in enumerate(states):
+        assert s.dtype == np.int8 and s.flags.c_contiguous
+        assert s.shape == (descs[r].Ly, descs[r].Lx)
+        ptrs[r] = s.ctypes.data
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
+    mag = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
+    t0a = None
+    if t0 is not None:
+        t0a = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.uint64), (nrep,)))
+    if threads is None:
+        threads = default_threads()
+    st = lib().oracle_run_cluster_batch(nrep, arr, ptrs, int(algorithm),
+                                        t0a.ctypes.data if t0a is not None else None, int(n),
+                                        int(record_every), bond.ctypes.data if n_rec else None,
+                                        mag.ctypes.data if n_rec else None, int(threads))
     if st != 0:
         raise ValueError("invalid arguments")
     return bond[:, :n_rec], mag[:, :n_rec]

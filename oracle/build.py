@@ -1,4 +1,5 @@
-"""Build the C oracle (test infrastructure) into oracle/liboracle.so with gcc.
+"""Build the C oracle (test infrastructure: sweeps and cluster steps) into
+oracle/liboracle.so with gcc.
 
 Run as ``python oracle/build.py``.  The GPU library never links this file's
 output; it is compiled only so that tests and the benchmark's CPU-baseline leg
@@ -9,13 +10,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "ising_oracle.c")
+SRCS = [os.path.join(HERE, "ising_oracle.c"), os.path.join(HERE, "cluster_oracle.c")]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
-           "-o", OUT + ".tmp", SRC, "-lm"]
+           "-o", OUT + ".tmp", *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -165,6 +165,53 @@ int ising_batch_set_sweep(ising_batch *b, int32_t r, uint64_t t, void *stream);
 int ising_batch_set_beta(ising_batch *b, int32_t r, double beta, void *stream);
 
 /*
+ * Cluster steps: Swendsen-Wang and Wolff, the non-local updates that paper
+ * section 1 names as the cure for the critical slowing down of single-spin
+ * Metropolis near T_c (algorithms from Swendsen and Wang, PRL 58, 86 (1987),
+ * and Wolff, PRL 62, 361 (1989)).  A step acts on the batch's packed state
+ * and uses the replica's counter t like a sweep, so sweeps and steps can be
+ * interleaved in any order.
+ *  bonds     site g = y*Lx + x owns a "right" bond to ((x+1) mod Lx, y) and a
+ *            "down" bond to (x, (y+1) mod Ly) (with Ly = 2 each vertical pair
+ *            has two bonds).  In step t a bond is occupied iff its two spins
+ *            are equal, beta*J > 0 and its word is >= thr2 =
+ *            min(floor(exp(-2 beta J) 2^32), 2^32 - 1) (the Fortuin-Kasteleyn
+ *            probability 1 - exp(-2 beta J)); the right bond's word is word
+ *            2(g & 1), the down bond's word 2(g & 1) + 1 of
+ *            Philox(ctr = {g >> 1, t, replica, 7}).
+ *  clusters  connected components of the occupied bonds; a cluster's root is
+ *            its smallest site index.
+ *  ISING_CLUSTER_SWENDSEN_WANG  the cluster with root R flips iff bit R & 31
+ *            of word (R >> 5) & 3 of Philox(ctr = {R >> 7, t, replica, 8}) is 1.
+ *  ISING_CLUSTER_WOLFF  with w = Philox(ctr = {0, t, replica, 9}) the cluster
+ *            of site S = ((w0 << 32) | w1) mod (Lx*Ly) flips.
+ */
+enum { ISING_CLUSTER_SWENDSEN_WANG = 0, ISING_CLUSTER_WOLFF = 1 };
+
+/* Bytes of device workspace ising_batch_cluster needs for batch b: a 32-bit
+ * label per site of every replica (each replica's labels 256-byte aligned)
+ * plus 16 bytes per tile of 64 x 32 sites.  Host-only.
+ * Errors: ISING_E_INVALID (NULL argument). */
+int ising_cluster_ws_bytes(ising_batch *b, size_t *bytes);
+
+/*
+ * n_steps cluster steps of every replica with the given algorithm.
+ * Asynchronous on stream.  Each step uses counter t_r and advances it by one;
+ * t_r + n_steps must stay below 2^32.
+ *  dev_ws     caller-owned device scratch of ws_bytes >= ising_cluster_ws_bytes()
+ *             bytes, 256-byte aligned.  It holds nothing between calls, and no
+ *             other work may use it while the call's kernels run.
+ *  record_every, dev_bond_trace, dev_mag_trace  as in ising_batch_run, with
+ *             steps in place of sweeps.
+ * Errors: ISING_E_INVALID (NULL handle or workspace, misaligned workspace,
+ * unknown algorithm, counter overflow), ISING_E_NOMEM (ws_bytes too small),
+ * ISING_E_HIP.
+ */
+int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t record_every,
+                        void *dev_ws, size_t ws_bytes, int64_t *dev_bond_trace, int64_t *dev_mag_trace,
+                        void *stream);
+
+/*
  * Execution schedule (what the autotuner chooses; every schedule gives
  * bit-identical results).
  *  word_bits        32 or 64: bits per machine word a thread updates

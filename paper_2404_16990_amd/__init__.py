@@ -30,6 +30,7 @@ EXPORTED = [
     "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_train_step_sampled",
     "ising_nn_score",
     "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_destroy",
+    "ising_cluster_ws_bytes", "ising_batch_cluster",
 ]
 
 
@@ -40,6 +41,7 @@ class ising_desc(ctypes.Structure):
 
 
 ISING_RNG_SITE, ISING_RNG_BITSLICED = 0, 1
+ISING_CLUSTER_SWENDSEN_WANG, ISING_CLUSTER_WOLFF = 0, 1
 
 
 class ising_schedule(ctypes.Structure):
@@ -103,6 +105,8 @@ def lib():
         L.ising_batch_extract_blocks.argtypes = [vp, i32, i32, u32, vp, vp, vp, vp]
         L.ising_batch_block_round.argtypes = [vp, vp, u32, vp, vp]
         L.ising_nn_destroy.argtypes = [vp]
+        L.ising_cluster_ws_bytes.argtypes = [vp, P(ctypes.c_size_t)]
+        L.ising_batch_cluster.argtypes = [vp, i32, u64, u32, vp, ctypes.c_size_t, vp, vp, vp]
         for name in EXPORTED[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -215,6 +219,18 @@ def ising_batch_destroy(h):
     _check(lib().ising_batch_destroy(h), "ising_batch_destroy")
 
 
+def ising_cluster_ws_bytes(h):
+    out = ctypes.c_size_t()
+    _check(lib().ising_cluster_ws_bytes(h, ctypes.byref(out)), "ising_cluster_ws_bytes")
+    return int(out.value)
+
+
+def ising_batch_cluster(h, algorithm, n_steps, record_every, dev_ws, ws_bytes, dev_bond=None, dev_mag=None,
+                        stream=None):
+    _check(lib().ising_batch_cluster(h, algorithm, n_steps, record_every, dev_ws, ws_bytes, dev_bond, dev_mag,
+                                     stream), "ising_batch_cluster")
+
+
 def ising_nn_param_count(channels=64):
     n = ctypes.c_int32()
     _check(lib().ising_nn_param_count(int(channels), ctypes.byref(n)), "ising_nn_param_count")
@@ -312,6 +328,25 @@ class Batch:
             ising_batch_run(self.h, n_sweeps, record_every, bond.data_ptr(), mag.data_ptr(), self._s())
             return bond, mag
         ising_batch_run(self.h, n_sweeps, 0, None, None, self._s())
+        return None
+
+    def cluster(self, n_steps, algorithm="sw", record_every=0):
+        """Enqueue n_steps Swendsen-Wang ("sw") or Wolff ("wolff") cluster
+        steps; returns device (bond, mag) traces or None.  The workspace is a
+        torch buffer kept for later calls."""
+        torch = self.torch
+        algo = {"sw": ISING_CLUSTER_SWENDSEN_WANG, "wolff": ISING_CLUSTER_WOLFF}[algorithm]
+        need = ising_cluster_ws_bytes(self.h)
+        if getattr(self, "ws", None) is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.buf.device)
+        n_rec = n_steps // record_every if record_every else 0
+        if n_rec:
+            bond = torch.empty((self.n, n_rec), dtype=torch.int64, device=self.buf.device)
+            mag = torch.empty((self.n, n_rec), dtype=torch.int64, device=self.buf.device)
+            ising_batch_cluster(self.h, algo, n_steps, record_every, self.ws.data_ptr(), self.ws.numel(),
+                                bond.data_ptr(), mag.data_ptr(), self._s())
+            return bond, mag
+        ising_batch_cluster(self.h, algo, n_steps, 0, self.ws.data_ptr(), self.ws.numel(), None, None, self._s())
         return None
 
     def observables(self):

@@ -35,6 +35,14 @@ int ising::fail(int code, const std::string &msg)
 
 void ising::clear_error() { g_last_error.clear(); }
 
+uint32_t ising::prob_threshold(double p)
+{
+    const double scaled = std::ldexp(p, 32);
+    if (scaled >= 4294967295.0)
+        return 0xffffffffu;
+    return static_cast<uint32_t>(std::floor(scaled));
+}
+
 namespace {
 
 #define ISING_HIP(expr)                                                                         \
@@ -51,14 +59,6 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Metropolis acceptance thresholds (paper section 1: accept iff ran() <
 // exp(-beta dE)).  With K = beta*J rounded once, P(accept | dE = 4kJ) =
 // thr_k / 2^32 where thr_k = floor(exp(-4kK) 2^32), clamped to 2^32 - 1.
-uint32_t prob_threshold(double p)
-{
-    const double scaled = std::ldexp(p, 32);
-    if (scaled >= 4294967295.0)
-        return 0xffffffffu;
-    return static_cast<uint32_t>(std::floor(scaled));
-}
-
 void set_thresholds(RepDev &r, double J, double beta)
 {
     const double K = beta * J;
@@ -95,7 +95,8 @@ int check_desc(const ising_desc &d, int32_t i)
     return ISING_OK;
 }
 
-// Device buffer: [descriptors | schedule lists | observable scratch | init modes | planes...]
+// Device buffer: [descriptors | schedule lists | observable scratch | init modes |
+//                 couplings | cluster descriptors | cluster tile prefix | planes...]
 int make_layout(int32_t n, const ising_desc *d, Layout *L)
 {
     if (n <= 0 || !d)
@@ -118,6 +119,10 @@ int make_layout(int32_t n, const ising_desc *d, Layout *L)
     off += align256((size_t)n * sizeof(int32_t));
     L->kcoup = off;
     off += align256((size_t)n * sizeof(double));
+    L->cl = off;
+    off += align256((size_t)n * sizeof(ClRep));
+    L->clprefix = off;
+    off += align256((size_t)(n + 1) * sizeof(uint32_t));
     L->planes.resize(n);
     for (int32_t i = 0; i < n; ++i) {
         L->planes[i] = off;
@@ -402,6 +407,9 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
     int32_t *d_modes = reinterpret_cast<int32_t *>(b->buf + L.modes);
     CREATE_HIP(hipMemcpyAsync(d_modes, modes.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, hs));
     CREATE_HIP(launch_init(b->d_rep, d_modes, (uint32_t)n, b->max_words, hs));
+    st = cluster_setup(b, hs);
+    if (st != ISING_OK)
+        return cleanup(st);
     CREATE_HIP(hipStreamSynchronize(hs));
 #undef CREATE_HIP
     b->sched.word_bits = 64;
@@ -580,6 +588,9 @@ int ising_batch_set_beta(ising_batch *b, int32_t r, double beta, void *stream)
                              hipMemcpyHostToDevice, hs));
     const double kc = beta * b->desc[r].J;
     ISING_HIP(hipMemcpyAsync(&b->d_kcoup[r], &kc, sizeof(double), hipMemcpyHostToDevice, hs));
+    st = cluster_set_beta(b, r, hs);
+    if (st != ISING_OK)
+        return st;
     ISING_HIP(hipStreamSynchronize(hs));
     return ISING_OK;
 }

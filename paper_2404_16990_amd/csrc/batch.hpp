@@ -10,13 +10,14 @@
 #include <vector>
 
 #include "../../include/ising.h"
+#include "cluster.hpp"
 #include "device.hpp"
 #include "launch.hpp"
 
 namespace ising {
 
 struct Layout {
-    size_t reps = 0, lists = 0, obs = 0, modes = 0, kcoup = 0;
+    size_t reps = 0, lists = 0, obs = 0, modes = 0, kcoup = 0, cl = 0, clprefix = 0;
     std::vector<size_t> planes;
     size_t total = 0;
 };
@@ -36,6 +37,13 @@ struct GraphKey {
 int fail(int code, const std::string &msg);
 // Clear the calling thread's error detail (at the start of every ABI call).
 void clear_error();
+// floor(p 2^32) clamped to 2^32 - 1: the integer threshold of a probability.
+uint32_t prob_threshold(double p);
+// Cluster-step descriptors of a new batch (cluster_api.cpp): filled on the host
+// and uploaded on st (the caller synchronises).
+int cluster_setup(ising_batch *b, hipStream_t st);
+// Bond threshold of replica r after its beta changed (upload on st).
+int cluster_set_beta(ising_batch *b, int32_t r, hipStream_t st);
 
 }  // namespace ising
 
@@ -60,5 +68,13 @@ struct ising_batch {
     hipStream_t aux = nullptr, cap = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::map<ising::GraphKey, hipGraphExec_t> graphs;
+    // cluster steps
+    std::vector<ising::ClRep> cl;      // host mirror of the cluster descriptors
+    std::vector<uint32_t> tile_prefix; // host mirror of the tile prefix (n + 1 entries)
+    ising::ClRep *d_cl = nullptr;
+    uint32_t *d_tile_prefix = nullptr;
+    uint64_t cl_tiles = 0;             // tiles of the whole batch
+    size_t cl_tb_off = 0;              // workspace offset of the crossing-bond masks
+    size_t cl_ws_bytes = 0;            // workspace a cluster step needs
 };
 

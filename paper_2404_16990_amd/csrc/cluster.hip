@@ -1,0 +1,391 @@
+// Cluster-step kernels: Swendsen-Wang and Wolff updates (named in paper
+// section 1 as the cure for critical slowing down; Swendsen and Wang, PRL 58,
+// 86 (1987); Wolff, PRL 62, 361 (1989)) on the packed colour planes of a
+// replica batch.  Bonds between aligned neighbours are occupied with
+// probability 1 - exp(-2 beta J) (the Fortuin-Kasteleyn representation).
+//
+// Random words (counter-based, Philox4x32-10 keyed by the replica's seed):
+//   bond  right / down bond owned by site g = y*Lx + x: words 2(g&1) and
+//         2(g&1)+1 of ctr {g >> 1, t, replica, 7};
+//   flip  Swendsen-Wang flips the cluster with root R iff bit R & 31 of word
+//         (R >> 5) & 3 of ctr {R >> 7, t, replica, 8} is set;
+//   seed  Wolff's seed is ((w0 << 32) | w1) mod (Lx*Ly), w = ctr {0, t, replica, 9}.
+// The root of a cluster is its smallest site index.
+#include <hip/hip_runtime.h>
+
+#include "cluster.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr uint32_t kRowsPerWave = kClRows / 4;  // 4 waves per 256-thread workgroup
+
+// The replica that owns batch-wide tile b: the largest r with prefix[r] <= b
+// (wave-uniform; prefix[0] = 0 <= b < prefix[n]).
+__device__ __forceinline__ uint32_t tile_owner(const uint32_t *__restrict__ prefix, uint32_t n, uint32_t b)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+struct Tile {
+    uint32_t r;              // replica
+    uint32_t lt;             // tile index inside the replica
+    uint32_t tx, x0, y0;     // tile column (= word index in a colour row), first column, first row
+    uint32_t rows;           // rows in this tile
+    uint32_t txn;            // tile column to the right (periodic)
+};
+
+__device__ __forceinline__ Tile locate(const ClArgs &a, const RepDev &d, uint32_t r, uint32_t b)
+{
+    Tile T;
+    T.r = r;
+    T.lt = b - a.tile_prefix[r];
+    const uint32_t ty = T.lt / d.W;
+    T.tx = T.lt - ty * d.W;
+    T.x0 = 64u * T.tx;
+    T.y0 = kClRows * ty;
+    T.rows = min(kClRows, d.Ly - T.y0);
+    T.txn = T.tx + 1 == d.W ? 0u : T.tx + 1;
+    return T;
+}
+
+// Spin bit (1 = up) of tile column j (0..63) in row y from that row's two
+// colour words: the site's colour is (j + y) & 1 and its compact bit j >> 1.
+__device__ __forceinline__ uint32_t tile_spin(uint32_t p0, uint32_t p1, uint32_t y, uint32_t j)
+{
+    return ((((j + y) & 1u) ? p1 : p0) >> (j >> 1)) & 1u;
+}
+
+// Position after the last break below column j of a row whose occupied
+// right-bond mask is H: the first column of j's horizontal run.
+__device__ __forceinline__ uint32_t run_start(uint64_t H, uint32_t j)
+{
+    const uint64_t breaks = ~H & ((1ull << j) - 1ull);
+    return breaks ? 64u - (uint32_t)__clzll(breaks) : 0u;
+}
+
+// ---- union-find in LDS (tile-local indices r*64 + j) -----------------------
+// Parents only decrease (a root is linked to a smaller index by atomic min),
+// so every path is strictly decreasing and every loop below ends.
+__device__ __forceinline__ uint32_t lds_find(volatile uint32_t *L, uint32_t a)
+{
+    uint32_t p = L[a];
+    while (p != a) {
+        a = p;
+        p = L[a];
+    }
+    return a;
+}
+
+__device__ __forceinline__ void lds_union(uint32_t *L, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = lds_find(L, a);
+        b = lds_find(L, b);
+        if (a == b)
+            return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = atomicMin(&L[b], a);
+        if (old == b)
+            return;
+        b = old;  // b was linked meanwhile: unite a with its new parent
+    }
+}
+
+// ---- union-find in the workspace (site indices of one replica) ------------
+__device__ __forceinline__ uint32_t ws_load(uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t ws_find(uint32_t *G, uint32_t a)
+{
+    uint32_t p = ws_load(G + a);
+    while (p != a) {
+        a = p;
+        p = ws_load(G + a);
+    }
+    return a;
+}
+
+__device__ __forceinline__ void ws_union(uint32_t *G, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = ws_find(G, a);
+        b = ws_find(G, b);
+        if (a == b)
+            return;
+        if (a > b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        const uint32_t old = atomicMin(G + b, a);
+        if (old == b)
+            return;
+        b = old;
+    }
+}
+
+// Point every node on the path from p to its root at the root.  Runs when no
+// link changes any more; concurrent walkers only write the same root.
+__device__ __forceinline__ void ws_compress(uint32_t *G, uint32_t p)
+{
+    uint32_t R = p, q = G[R];
+    while (q != R) {
+        R = q;
+        q = G[R];
+    }
+    while (p != R) {
+        q = G[p];
+        G[p] = R;
+        p = q;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// local: bonds, in-tile labels, crossing masks.  Grid: one 256-thread
+// workgroup per tile; wave w owns rows 8w .. 8w+7 of the tile.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint32_t base)
+{
+    __shared__ uint32_t L[kClRows * 64];
+    __shared__ uint64_t Hm[kClRows], Dm[kClRows];
+    const uint32_t tile = base + blockIdx.x;
+    const uint32_t r = tile_owner(a.tile_prefix, a.n, tile);
+    const RepDev d = a.reps[r];
+    const ClRep c = a.cl[r];
+    const Tile T = locate(a, d, r, tile);
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t W = d.W, Lx = d.Lx, Ly = d.Ly, t = d.t + step;
+    const uint32_t *P0 = d.plane0, *P1 = d.plane0 + (size_t)Ly * W;
+    uint32_t *G = reinterpret_cast<uint32_t *>(a.ws + c.g_off);
+    const uint32_t first = wv * kRowsPerWave;
+
+    for (uint32_t i = 0; i < kRowsPerWave; i += 2) {
+        const uint32_t rl = first + i;  // rows rl, rl + 1 (rows is even)
+        if (rl >= T.rows)
+            break;
+        const uint32_t ya = T.y0 + rl, yb = ya + 1, yc = yb + 1 == Ly ? 0u : yb + 1;
+        const uint32_t a0 = P0[(size_t)ya * W + T.tx], a1 = P1[(size_t)ya * W + T.tx];
+        const uint32_t b0 = P0[(size_t)yb * W + T.tx], b1 = P1[(size_t)yb * W + T.tx];
+        const uint32_t c0 = P0[(size_t)yc * W + T.tx], c1 = P1[(size_t)yc * W + T.tx];
+        // column 0 of the next tile has colour y & 1 and compact bit 0
+        const uint32_t an = ((ya & 1u) ? P1 : P0)[(size_t)ya * W + T.txn] & 1u;
+        const uint32_t bn = ((yb & 1u) ? P1 : P0)[(size_t)yb * W + T.txn] & 1u;
+        const uint32_t sa = tile_spin(a0, a1, ya, lane), sb = tile_spin(b0, b1, yb, lane);
+        const uint32_t sc = tile_spin(c0, c1, yc, lane);
+        const uint32_t ra = lane < 63u ? tile_spin(a0, a1, ya, lane + 1) : an;
+        const uint32_t rb = lane < 63u ? tile_spin(b0, b1, yb, lane + 1) : bn;
+        // Lane j draws the call of column pair j >> 1 in row ya + (j & 1): its
+        // four words are (right, down) of the even and of the odd column.  The
+        // two lanes of a pair swap the halves they need.
+        uint32_t occ = 0;
+        if (!c.none) {
+            const uint32_t g = (ya + (lane & 1u)) * Lx + T.x0 + (lane & ~1u);
+            uint32_t w[4];
+            philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
+            occ = (uint32_t)(w[0] >= c.thr2) | ((uint32_t)(w[1] >= c.thr2) << 1) |
+                  ((uint32_t)(w[2] >= c.thr2) << 2) | ((uint32_t)(w[3] >= c.thr2) << 3);
+        }
+        const uint32_t other = (uint32_t)__shfl_xor((int)occ, 1, 64);
+        const uint32_t callA = (lane & 1u) ? other : occ, callB = (lane & 1u) ? occ : other;
+        const uint32_t sel = (lane & 1u) * 2u;
+        const uint64_t HA = __ballot(((callA >> sel) & 1u) && sa == ra);
+        const uint64_t DA = __ballot(((callA >> (sel + 1)) & 1u) && sa == sb);
+        const uint64_t HB = __ballot(((callB >> sel) & 1u) && sb == rb);
+        const uint64_t DB = __ballot(((callB >> (sel + 1)) & 1u) && sb == sc);
+        if (lane == 0) {
+            Hm[rl] = HA;
+            Dm[rl] = DA;
+            Hm[rl + 1] = HB;
+            Dm[rl + 1] = DB;
+        }
+        L[rl * 64 + lane] = rl * 64 + run_start(HA, lane);
+        L[(rl + 1) * 64 + lane] = (rl + 1) * 64 + run_start(HB, lane);
+    }
+    __syncthreads();
+    // vertical bonds inside the tile; a bond is skipped when its left
+    // neighbour's bond already joins the same two runs
+    for (uint32_t rl = first; rl < first + kRowsPerWave && rl + 1 < T.rows; ++rl) {
+        const uint64_t D = Dm[rl], implied = D & Hm[rl] & Hm[rl + 1];
+        if (((D >> lane) & 1u) && !(lane > 0 && ((implied >> (lane - 1)) & 1u)))
+            lds_union(L, rl * 64 + lane, (rl + 1) * 64 + lane);
+    }
+    __syncthreads();
+    for (uint32_t rl = first; rl < first + kRowsPerWave && rl < T.rows; ++rl) {
+        const uint32_t root = lds_find(L, rl * 64 + lane);
+        G[(size_t)(T.y0 + rl) * Lx + T.x0 + lane] = (T.y0 + (root >> 6)) * Lx + T.x0 + (root & 63u);
+    }
+    if (threadIdx.x == 0) {
+        uint32_t xr = 0;
+        for (uint32_t rl = 0; rl < T.rows; ++rl)
+            xr |= (uint32_t)(Hm[rl] >> 63) << rl;
+        const uint64_t xd = Dm[T.rows - 1];
+        a.tb[tile] = make_uint4((uint32_t)xd, (uint32_t)(xd >> 32), xr, 0u);
+    }
+}
+
+// Endpoints of the crossing bond k of a tile: k < 64 is the down bond of
+// column k of the tile's last row, 64 <= k < 64 + rows the right bond of row
+// k - 64's last column.
+struct Crossing {
+    uint32_t a, b;
+};
+
+__device__ __forceinline__ Crossing crossing(const RepDev &d, const Tile &T, uint32_t k)
+{
+    Crossing e;
+    if (k < 64u) {
+        const uint32_t y = T.y0 + T.rows - 1, yn = y + 1 == d.Ly ? 0u : y + 1;
+        e.a = y * d.Lx + T.x0 + k;
+        e.b = yn * d.Lx + T.x0 + k;
+    } else {
+        const uint32_t y = T.y0 + (k - 64u);
+        e.a = y * d.Lx + T.x0 + 63u;
+        e.b = y * d.Lx + 64u * T.txn;
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// merge / compress: one wave per tile; lane j takes down bond j and right
+// bond j (j < rows).
+// ---------------------------------------------------------------------------
+template <bool COMPRESS>
+__global__ __launch_bounds__(256) void k_cl_cross(ClArgs a, uint32_t base)
+{
+    const uint32_t b = base + blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (b >= a.tiles)
+        return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t r = tile_owner(a.tile_prefix, a.n, b);
+    const RepDev d = a.reps[r];
+    const Tile T = locate(a, d, r, b);
+    uint32_t *G = reinterpret_cast<uint32_t *>(a.ws + a.cl[r].g_off);
+    const uint4 tb = a.tb[b];
+    const uint64_t xd = tb.x | ((uint64_t)tb.y << 32);
+    const uint32_t xr = tb.z;
+    if ((xd >> lane) & 1u) {
+        const Crossing e = crossing(d, T, lane);
+        if (COMPRESS) {
+            ws_compress(G, e.a);
+            ws_compress(G, e.b);
+        } else {
+            ws_union(G, e.a, e.b);
+        }
+    }
+    if (lane < T.rows && ((xr >> lane) & 1u)) {
+        const Crossing e = crossing(d, T, 64u + lane);
+        if (COMPRESS) {
+            ws_compress(G, e.a);
+            ws_compress(G, e.b);
+        } else {
+            ws_union(G, e.a, e.b);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// flip: one 256-thread workgroup per tile, rows as in k_cl_local.
+// ---------------------------------------------------------------------------
+template <int ALGO>
+__global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32_t base)
+{
+    const uint32_t tile = base + blockIdx.x;
+    const uint32_t r = tile_owner(a.tile_prefix, a.n, tile);
+    const RepDev d = a.reps[r];
+    const ClRep c = a.cl[r];
+    const Tile T = locate(a, d, r, tile);
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t W = d.W, Lx = d.Lx, Ly = d.Ly, t = d.t + step;
+    uint32_t *P0 = d.plane0, *P1 = d.plane0 + (size_t)Ly * W;
+    const uint32_t *G = reinterpret_cast<const uint32_t *>(a.ws + c.g_off);
+    uint32_t seed_root = 0;
+    if (ALGO == kClWolff) {
+        uint32_t w[4];
+        philox4x32_10(0u, t, d.replica, 9u, d.seed_lo, d.seed_hi, w);
+        const uint32_t S = (uint32_t)((((uint64_t)w[0] << 32) | w[1]) % d.N);
+        seed_root = G[G[S]];
+    }
+    const uint32_t first = wv * kRowsPerWave;
+    for (uint32_t rl = first; rl < first + kRowsPerWave && rl < T.rows; ++rl) {
+        const uint32_t y = T.y0 + rl;
+        const uint32_t R = G[G[(size_t)y * Lx + T.x0 + lane]];
+        bool flip;
+        if (ALGO == kClWolff) {
+            flip = R == seed_root;
+        } else {
+            uint32_t w[4];
+            philox4x32_10(R >> 7, t, d.replica, 8u, d.seed_lo, d.seed_hi, w);
+            const uint32_t q = (R >> 5) & 3u;
+            const uint32_t word = q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3];
+            flip = (word >> (R & 31u)) & 1u;
+        }
+        const uint64_t F = __ballot(flip);
+        if (F == 0)
+            continue;
+        // even columns hold colour y & 1, odd columns the other colour; gather
+        // each half's bits into the 32-bit word of its plane
+        uint64_t e = F & 0x5555555555555555ull, o = (F >> 1) & 0x5555555555555555ull;
+        e = (e | (e >> 1)) & 0x3333333333333333ull;
+        o = (o | (o >> 1)) & 0x3333333333333333ull;
+        e = (e | (e >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+        o = (o | (o >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+        e = (e | (e >> 4)) & 0x00FF00FF00FF00FFull;
+        o = (o | (o >> 4)) & 0x00FF00FF00FF00FFull;
+        e = (e | (e >> 8)) & 0x0000FFFF0000FFFFull;
+        o = (o | (o >> 8)) & 0x0000FFFF0000FFFFull;
+        e = (e | (e >> 16)) & 0x00000000FFFFFFFFull;
+        o = (o | (o >> 16)) & 0x00000000FFFFFFFFull;
+        uint32_t *pe = ((y & 1u) ? P1 : P0) + (size_t)y * W + T.tx;
+        uint32_t *po = ((y & 1u) ? P0 : P1) + (size_t)y * W + T.tx;
+        if (lane == 0)
+            *pe ^= (uint32_t)e;
+        else if (lane == 1)
+            *po ^= (uint32_t)o;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cluster_step(const ClArgs &a, int algorithm, uint32_t step, hipStream_t st)
+{
+    // Each phase covers every tile before the next starts; a phase is split
+    // into launches of at most kClTilesPerLaunch tiles.
+    for (uint32_t base = 0; base < a.tiles; base += kClTilesPerLaunch) {
+        const uint32_t cnt = min(kClTilesPerLaunch, a.tiles - base);
+        hipLaunchKernelGGL(k_cl_local, dim3(cnt), dim3(256), 0, st, a, step, base);
+    }
+    for (int phase = 0; phase < 2; ++phase)
+        for (uint32_t base = 0; base < a.tiles; base += kClTilesPerLaunch) {
+            const uint32_t cnt = min(kClTilesPerLaunch, a.tiles - base);
+            if (phase == 0)
+                hipLaunchKernelGGL(k_cl_cross<false>, dim3((cnt + 3u) / 4u), dim3(256), 0, st, a, base);
+            else
+                hipLaunchKernelGGL(k_cl_cross<true>, dim3((cnt + 3u) / 4u), dim3(256), 0, st, a, base);
+        }
+    for (uint32_t base = 0; base < a.tiles; base += kClTilesPerLaunch) {
+        const uint32_t cnt = min(kClTilesPerLaunch, a.tiles - base);
+        if (algorithm == kClWolff)
+            hipLaunchKernelGGL(k_cl_flip<kClWolff>, dim3(cnt), dim3(256), 0, st, a, step, base);
+        else
+            hipLaunchKernelGGL(k_cl_flip<kClSwendsenWang>, dim3(cnt), dim3(256), 0, st, a, step, base);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ising

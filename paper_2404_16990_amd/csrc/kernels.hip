@@ -262,11 +262,12 @@ void k_sweep_resident(const RepDev *__restrict__ reps,
 }
 
 // ---------------------------------------------------------------------------
-// observables of the current state: grid (x: tiles, y: replica)
+// observables of the current state: grid (x: tiles, y: replica); replica r's
+// sums are added to bond[r * stride] and mag[r * stride]
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_observables(const RepDev *__restrict__ reps,
                                                      int64_t *__restrict__ bond,
-                                                     int64_t *__restrict__ mag)
+                                                     int64_t *__restrict__ mag, uint32_t stride)
 {
     const uint32_t r = blockIdx.y;
     const RepDev d = reps[r];
@@ -298,8 +299,8 @@ __global__ __launch_bounds__(256) void k_observables(const RepDev *__restrict__ 
             db += 2 * (int64_t)d.N;
             dm -= (int64_t)d.N;
         }
-        atomicAdd(reinterpret_cast<unsigned long long *>(&bond[r]), (unsigned long long)db);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&mag[r]), (unsigned long long)dm);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&bond[(size_t)r * stride]), (unsigned long long)db);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&mag[(size_t)r * stride]), (unsigned long long)dm);
     }
 }
 
@@ -339,10 +340,10 @@ hipError_t launch_init(const RepDev *reps, const int32_t *modes, uint32_t n, uin
 }
 
 hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words, int64_t *bond,
-                              int64_t *mag, hipStream_t st)
+                              int64_t *mag, hipStream_t st, uint32_t stride)
 {
     const uint32_t blocks = std::min<uint32_t>((max_words + 255u) / 256u, 2048u);
-    hipLaunchKernelGGL(k_observables, dim3(blocks, n), dim3(256), 0, st, reps, bond, mag);
+    hipLaunchKernelGGL(k_observables, dim3(blocks, n), dim3(256), 0, st, reps, bond, mag, stride);
     return hipGetLastError();
 }
 

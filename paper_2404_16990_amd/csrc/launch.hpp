@@ -31,8 +31,9 @@ struct ResidentList {
 
 hipError_t launch_init(const RepDev *reps, const int32_t *modes, uint32_t n, uint32_t max_words,
                        hipStream_t st);
+// Adds replica r's (B, M) to bond[r * stride], mag[r * stride].
 hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words, int64_t *bond,
-                              int64_t *mag, hipStream_t st);
+                              int64_t *mag, hipStream_t st, uint32_t stride = 1);
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st);
 hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st);
 hipError_t launch_advance(RepDev *reps, uint32_t n, uint32_t delta, hipStream_t st);

@@ -174,36 +174,56 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
     const uint32_t *P0 = d.plane0, *P1 = d.plane0 + (size_t)Ly * W;
     uint32_t *G = reinterpret_cast<uint32_t *>(a.ws + c.g_off);
     const uint32_t first = wv * kRowsPerWave;
-
-    for (uint32_t i = 0; i < kRowsPerWave; i += 2) {
-        const uint32_t rl = first + i;  // rows rl, rl + 1 (rows is even)
-        if (rl >= T.rows)
-            break;
-        const uint32_t ya = T.y0 + rl, yb = ya + 1, yc = yb + 1 == Ly ? 0u : yb + 1;
-        const uint32_t a0 = P0[(size_t)ya * W + T.tx], a1 = P1[(size_t)ya * W + T.tx];
-        const uint32_t b0 = P0[(size_t)yb * W + T.tx], b1 = P1[(size_t)yb * W + T.tx];
-        const uint32_t c0 = P0[(size_t)yc * W + T.tx], c1 = P1[(size_t)yc * W + T.tx];
-        // column 0 of the next tile has colour y & 1 and compact bit 0
-        const uint32_t an = ((ya & 1u) ? P1 : P0)[(size_t)ya * W + T.txn] & 1u;
-        const uint32_t bn = ((yb & 1u) ? P1 : P0)[(size_t)yb * W + T.txn] & 1u;
-        const uint32_t sa = tile_spin(a0, a1, ya, lane), sb = tile_spin(b0, b1, yb, lane);
-        const uint32_t sc = tile_spin(c0, c1, yc, lane);
-        const uint32_t ra = lane < 63u ? tile_spin(a0, a1, ya, lane + 1) : an;
-        const uint32_t rb = lane < 63u ? tile_spin(b0, b1, yb, lane + 1) : bn;
-        // Lane j draws the call of column pair j >> 1 in row ya + (j & 1): its
-        // four words are (right, down) of the even and of the odd column.  The
-        // two lanes of a pair swap the halves they need.
-        uint32_t occ = 0;
-        if (!c.none) {
-            const uint32_t g = (ya + (lane & 1u)) * Lx + T.x0 + (lane & ~1u);
+    // rows of this wave (even, possibly 0) and the words of those rows plus the
+    // row below, all loaded before any use
+    const uint32_t nr = T.rows > first ? min(kRowsPerWave, T.rows - first) : 0u;
+    uint32_t p0[kRowsPerWave + 1], p1[kRowsPerWave + 1], nxt[kRowsPerWave];
+#pragma unroll
+    for (uint32_t k = 0; k <= kRowsPerWave; ++k) {
+        p0[k] = p1[k] = 0u;
+        if (k <= nr && nr > 0) {
+            uint32_t y = T.y0 + first + k;
+            y = y == Ly ? 0u : y;
+            p0[k] = P0[(size_t)y * W + T.tx];
+            p1[k] = P1[(size_t)y * W + T.tx];
+        }
+        if (k < nr) {
+            // column 0 of the next tile has colour y & 1 and compact bit 0
+            const uint32_t y = T.y0 + first + k;
+            nxt[k] = ((y & 1u) ? P1 : P0)[(size_t)y * W + T.txn] & 1u;
+        } else if (k < kRowsPerWave) {
+            nxt[k] = 0u;
+        }
+    }
+    // Lane j draws the call of column pair j >> 1 in row 2i + (j & 1) of the
+    // wave: its four words are (right, down) of the even and of the odd column.
+    // The two lanes of a pair swap the halves they need.
+    uint32_t occ[kRowsPerWave / 2];
+#pragma unroll
+    for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
+        occ[i] = 0u;
+        if (2 * i < nr && !c.none) {
+            const uint32_t g = (T.y0 + first + 2 * i + (lane & 1u)) * Lx + T.x0 + (lane & ~1u);
             uint32_t w[4];
             philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
-            occ = (uint32_t)(w[0] >= c.thr2) | ((uint32_t)(w[1] >= c.thr2) << 1) |
-                  ((uint32_t)(w[2] >= c.thr2) << 2) | ((uint32_t)(w[3] >= c.thr2) << 3);
+            occ[i] = (uint32_t)(w[0] >= c.thr2) | ((uint32_t)(w[1] >= c.thr2) << 1) |
+                     ((uint32_t)(w[2] >= c.thr2) << 2) | ((uint32_t)(w[3] >= c.thr2) << 3);
         }
-        const uint32_t other = (uint32_t)__shfl_xor((int)occ, 1, 64);
-        const uint32_t callA = (lane & 1u) ? other : occ, callB = (lane & 1u) ? occ : other;
-        const uint32_t sel = (lane & 1u) * 2u;
+    }
+    const uint32_t sel = (lane & 1u) * 2u;
+#pragma unroll
+    for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
+        if (2 * i >= nr)
+            break;
+        const uint32_t rl = first + 2 * i, ya = T.y0 + rl;
+        const uint32_t yb = ya + 1, yc = yb + 1 == Ly ? 0u : yb + 1;
+        const uint32_t sa = tile_spin(p0[2 * i], p1[2 * i], ya, lane);
+        const uint32_t sb = tile_spin(p0[2 * i + 1], p1[2 * i + 1], yb, lane);
+        const uint32_t sc = tile_spin(p0[2 * i + 2], p1[2 * i + 2], yc, lane);
+        const uint32_t ra = lane < 63u ? tile_spin(p0[2 * i], p1[2 * i], ya, lane + 1) : nxt[2 * i];
+        const uint32_t rb = lane < 63u ? tile_spin(p0[2 * i + 1], p1[2 * i + 1], yb, lane + 1) : nxt[2 * i + 1];
+        const uint32_t other = (uint32_t)__shfl_xor((int)occ[i], 1, 64);
+        const uint32_t callA = (lane & 1u) ? other : occ[i], callB = (lane & 1u) ? occ[i] : other;
         const uint64_t HA = __ballot(((callA >> sel) & 1u) && sa == ra);
         const uint64_t DA = __ballot(((callA >> (sel + 1)) & 1u) && sa == sb);
         const uint64_t HB = __ballot(((callB >> sel) & 1u) && sb == rb);
@@ -279,23 +299,36 @@ __global__ __launch_bounds__(256) void k_cl_cross(ClArgs a, uint32_t base)
     const uint4 tb = a.tb[b];
     const uint64_t xd = tb.x | ((uint64_t)tb.y << 32);
     const uint32_t xr = tb.z;
-    if ((xd >> lane) & 1u) {
-        const Crossing e = crossing(d, T, lane);
-        if (COMPRESS) {
+    if (COMPRESS) {
+        if ((xd >> lane) & 1u) {
+            const Crossing e = crossing(d, T, lane);
             ws_compress(G, e.a);
             ws_compress(G, e.b);
-        } else {
-            ws_union(G, e.a, e.b);
         }
+        if (lane < T.rows && ((xr >> lane) & 1u)) {
+            const Crossing e = crossing(d, T, 64u + lane);
+            ws_compress(G, e.a);
+            ws_compress(G, e.b);
+        }
+        return;
     }
-    if (lane < T.rows && ((xr >> lane) & 1u)) {
-        const Crossing e = crossing(d, T, 64u + lane);
-        if (COMPRESS) {
-            ws_compress(G, e.a);
-            ws_compress(G, e.b);
-        } else {
-            ws_union(G, e.a, e.b);
+    // Uniting the endpoints' current labels unites the endpoints.  Runs of
+    // crossing bonds usually join the same two tile-local clusters, so a bond
+    // whose label pair equals the previous lane's bond on the same edge is
+    // already covered by that lane's union.
+#pragma unroll
+    for (int edge = 0; edge < 2; ++edge) {
+        const bool on = edge == 0 ? ((xd >> lane) & 1u) != 0 : (lane < T.rows && ((xr >> lane) & 1u));
+        uint32_t la = 0xffffffffu, lb = 0xffffffffu;
+        if (on) {
+            const Crossing e = crossing(d, T, edge == 0 ? lane : 64u + lane);
+            la = ws_load(G + e.a);
+            lb = ws_load(G + e.b);
         }
+        const uint32_t pa = (uint32_t)__shfl_up((int)la, 1, 64), pb = (uint32_t)__shfl_up((int)lb, 1, 64);
+        const bool dup = lane > 0 && pa == la && pb == lb;
+        if (on && !dup)
+            ws_union(G, la, lb);
     }
 }
 
@@ -313,7 +346,11 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t W = d.W, Lx = d.Lx, Ly = d.Ly, t = d.t + step;
     uint32_t *P0 = d.plane0, *P1 = d.plane0 + (size_t)Ly * W;
-    const uint32_t *G = reinterpret_cast<const uint32_t *>(a.ws + c.g_off);
+    const uint32_t *__restrict__ G = reinterpret_cast<const uint32_t *>(a.ws + c.g_off);
+    const uint32_t first = wv * kRowsPerWave;
+    const uint32_t nr = T.rows > first ? min(kRowsPerWave, T.rows - first) : 0u;
+    if (nr == 0)
+        return;
     uint32_t seed_root = 0;
     if (ALGO == kClWolff) {
         uint32_t w[4];
@@ -321,26 +358,38 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
         const uint32_t S = (uint32_t)((((uint64_t)w[0] << 32) | w[1]) % d.N);
         seed_root = G[G[S]];
     }
-    const uint32_t first = wv * kRowsPerWave;
-    for (uint32_t rl = first; rl < first + kRowsPerWave && rl < T.rows; ++rl) {
-        const uint32_t y = T.y0 + rl;
-        const uint32_t R = G[G[(size_t)y * Lx + T.x0 + lane]];
+    // root of every site of the wave's rows: all label loads first, then all
+    // second-level loads
+    uint32_t R[kRowsPerWave];
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; ++k)
+        R[k] = k < nr ? G[(size_t)(T.y0 + first + k) * Lx + T.x0 + lane] : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; ++k)
+        R[k] = k < nr ? G[R[k]] : 0u;
+    uint64_t F[kRowsPerWave];
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; ++k) {
         bool flip;
         if (ALGO == kClWolff) {
-            flip = R == seed_root;
+            flip = k < nr && R[k] == seed_root;
         } else {
             uint32_t w[4];
-            philox4x32_10(R >> 7, t, d.replica, 8u, d.seed_lo, d.seed_hi, w);
-            const uint32_t q = (R >> 5) & 3u;
+            philox4x32_10(R[k] >> 7, t, d.replica, 8u, d.seed_lo, d.seed_hi, w);
+            const uint32_t q = (R[k] >> 5) & 3u;
             const uint32_t word = q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3];
-            flip = (word >> (R & 31u)) & 1u;
+            flip = k < nr && ((word >> (R[k] & 31u)) & 1u);
         }
-        const uint64_t F = __ballot(flip);
-        if (F == 0)
+        F[k] = __ballot(flip);
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; ++k) {
+        if (k >= nr || F[k] == 0)
             continue;
         // even columns hold colour y & 1, odd columns the other colour; gather
         // each half's bits into the 32-bit word of its plane
-        uint64_t e = F & 0x5555555555555555ull, o = (F >> 1) & 0x5555555555555555ull;
+        const uint32_t y = T.y0 + first + k;
+        uint64_t e = F[k] & 0x5555555555555555ull, o = (F[k] >> 1) & 0x5555555555555555ull;
         e = (e | (e >> 1)) & 0x3333333333333333ull;
         o = (o | (o >> 1)) & 0x3333333333333333ull;
         e = (e | (e >> 2)) & 0x0F0F0F0F0F0F0F0Full;

@@ -21,6 +21,17 @@ namespace {
 
 constexpr uint32_t kRowsPerWave = kClRows / 4;  // 4 waves per 256-thread workgroup
 
+// Global-memory views of pointers that reach the kernels inside descriptors:
+// loads through them compile to global (or, when uniform, scalar) loads that
+// the compiler can issue back to back instead of flat loads.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
+__device__ __forceinline__ gu32 *global_view(uint32_t *p) { return (gu32 *)p; }
+__device__ __forceinline__ const gu32 *global_view(const uint32_t *p) { return (const gu32 *)p; }
+
+// Index of the calling thread's wave in its workgroup, as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // The replica that owns batch-wide tile b: the largest r with prefix[r] <= b
 // (wave-uniform; prefix[0] = 0 <= b < prefix[n]).
 __device__ __forceinline__ uint32_t tile_owner(const uint32_t *__restrict__ prefix, uint32_t n, uint32_t b)
@@ -169,46 +180,51 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
     const RepDev d = a.reps[r];
     const ClRep c = a.cl[r];
     const Tile T = locate(a, d, r, tile);
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u, wv = wave_id();
     const uint32_t W = d.W, Lx = d.Lx, Ly = d.Ly, t = d.t + step;
-    const uint32_t *P0 = d.plane0, *P1 = d.plane0 + (size_t)Ly * W;
-    uint32_t *G = reinterpret_cast<uint32_t *>(a.ws + c.g_off);
+    const gu32 *P0 = global_view(d.plane0), *P1 = P0 + (size_t)Ly * W;
+    gu32 *G = global_view(reinterpret_cast<uint32_t *>(a.ws + c.g_off));
     const uint32_t first = wv * kRowsPerWave;
-    // rows of this wave (even, possibly 0) and the words of those rows plus the
-    // row below, all loaded before any use
+    // rows of this wave (even, possibly 0)
     const uint32_t nr = T.rows > first ? min(kRowsPerWave, T.rows - first) : 0u;
-    uint32_t p0[kRowsPerWave + 1], p1[kRowsPerWave + 1], nxt[kRowsPerWave];
-#pragma unroll
-    for (uint32_t k = 0; k <= kRowsPerWave; ++k) {
-        p0[k] = p1[k] = 0u;
-        if (k <= nr && nr > 0) {
-            uint32_t y = T.y0 + first + k;
-            y = y == Ly ? 0u : y;
-            p0[k] = P0[(size_t)y * W + T.tx];
-            p1[k] = P1[(size_t)y * W + T.tx];
-        }
-        if (k < nr) {
-            // column 0 of the next tile has colour y & 1 and compact bit 0
-            const uint32_t y = T.y0 + first + k;
-            nxt[k] = ((y & 1u) ? P1 : P0)[(size_t)y * W + T.txn] & 1u;
-        } else if (k < kRowsPerWave) {
-            nxt[k] = 0u;
-        }
+    // One vector load brings all 26 words (lane k < 9: colour-0 word of row
+    // k, 9 <= k < 18: colour-1 word of row k - 9, 18 <= k < 26: the word of
+    // row k - 18 that holds column 0 of the next tile); they are broadcast
+    // with readlane after the bond draws, so the load latency overlaps them.
+    uint32_t word;
+    {
+        const uint32_t k = lane < 9u ? lane : lane < 18u ? lane - 9u : lane < 26u ? lane - 18u : 0u;
+        uint32_t y = T.y0 + min(first + k, lane < 18u ? T.rows : T.rows - 1);
+        y = y == Ly ? 0u : y;
+        const bool plane1 = lane < 9u ? false : lane < 18u ? true : lane < 26u ? (y & 1u) != 0 : false;
+        const uint32_t col = lane >= 18u && lane < 26u ? T.txn : T.tx;
+        word = (plane1 ? P1 : P0)[(size_t)y * W + col];
     }
+    __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the bond draws
     // Lane j draws the call of column pair j >> 1 in row 2i + (j & 1) of the
     // wave: its four words are (right, down) of the even and of the odd column.
     // The two lanes of a pair swap the halves they need.
+    // Straight-line code (rows past the tile draw for its last rows and are
+    // masked) keeps the load above in flight during the draws.
     uint32_t occ[kRowsPerWave / 2];
 #pragma unroll
     for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
-        occ[i] = 0u;
-        if (2 * i < nr && !c.none) {
-            const uint32_t g = (T.y0 + first + 2 * i + (lane & 1u)) * Lx + T.x0 + (lane & ~1u);
-            uint32_t w[4];
-            philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
-            occ[i] = (uint32_t)(w[0] >= c.thr2) | ((uint32_t)(w[1] >= c.thr2) << 1) |
-                     ((uint32_t)(w[2] >= c.thr2) << 2) | ((uint32_t)(w[3] >= c.thr2) << 3);
-        }
+        const uint32_t row = T.y0 + min(first + 2 * i, T.rows - 2) + (lane & 1u);
+        const uint32_t g = row * Lx + T.x0 + (lane & ~1u);
+        uint32_t w[4];
+        philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
+        const uint32_t bits = (uint32_t)(w[0] >= c.thr2) | ((uint32_t)(w[1] >= c.thr2) << 1) |
+                              ((uint32_t)(w[2] >= c.thr2) << 2) | ((uint32_t)(w[3] >= c.thr2) << 3);
+        occ[i] = (2 * i < nr && !c.none) ? bits : 0u;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // and the first use of its words after them
+    uint32_t p0[kRowsPerWave + 1], p1[kRowsPerWave + 1], nxt[kRowsPerWave];
+#pragma unroll
+    for (uint32_t k = 0; k <= kRowsPerWave; ++k) {
+        p0[k] = __builtin_amdgcn_readlane(word, k);
+        p1[k] = __builtin_amdgcn_readlane(word, 9 + k);
+        if (k < kRowsPerWave)
+            nxt[k] = __builtin_amdgcn_readlane(word, 18 + k) & 1u;
     }
     const uint32_t sel = (lane & 1u) * 2u;
 #pragma unroll
@@ -343,10 +359,10 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
     const RepDev d = a.reps[r];
     const ClRep c = a.cl[r];
     const Tile T = locate(a, d, r, tile);
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u, wv = wave_id();
     const uint32_t W = d.W, Lx = d.Lx, Ly = d.Ly, t = d.t + step;
-    uint32_t *P0 = d.plane0, *P1 = d.plane0 + (size_t)Ly * W;
-    const uint32_t *__restrict__ G = reinterpret_cast<const uint32_t *>(a.ws + c.g_off);
+    gu32 *P0 = global_view(d.plane0), *P1 = P0 + (size_t)Ly * W;
+    const gu32 *G = global_view(reinterpret_cast<const uint32_t *>(a.ws + c.g_off));
     const uint32_t first = wv * kRowsPerWave;
     const uint32_t nr = T.rows > first ? min(kRowsPerWave, T.rows - first) : 0u;
     if (nr == 0)
@@ -359,14 +375,14 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
         seed_root = G[G[S]];
     }
     // root of every site of the wave's rows: all label loads first, then all
-    // second-level loads
+    // second-level loads (rows past the tile repeat its last row)
     uint32_t R[kRowsPerWave];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k)
-        R[k] = k < nr ? G[(size_t)(T.y0 + first + k) * Lx + T.x0 + lane] : 0u;
+        R[k] = G[(size_t)(T.y0 + first + min(k, nr - 1)) * Lx + T.x0 + lane];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k)
-        R[k] = k < nr ? G[R[k]] : 0u;
+        R[k] = G[R[k]];
     uint64_t F[kRowsPerWave];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k) {
@@ -400,8 +416,8 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
         o = (o | (o >> 8)) & 0x0000FFFF0000FFFFull;
         e = (e | (e >> 16)) & 0x00000000FFFFFFFFull;
         o = (o | (o >> 16)) & 0x00000000FFFFFFFFull;
-        uint32_t *pe = ((y & 1u) ? P1 : P0) + (size_t)y * W + T.tx;
-        uint32_t *po = ((y & 1u) ? P0 : P1) + (size_t)y * W + T.tx;
+        gu32 *pe = ((y & 1u) ? P1 : P0) + (size_t)y * W + T.tx;
+        gu32 *po = ((y & 1u) ? P0 : P1) + (size_t)y * W + T.tx;
         if (lane == 0)
             *pe ^= (uint32_t)e;
         else if (lane == 1)

@@ -374,54 +374,44 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
         const uint32_t S = (uint32_t)((((uint64_t)w[0] << 32) | w[1]) % d.N);
         seed_root = G[G[S]];
     }
+    // Lane j takes column 2 (j & 31) + (j >> 5): a ballot over the wave is
+    // then the row's even columns (bits 0..31) and odd columns (bits 32..63)
+    // in compact order, i.e. the flip masks of its two colour words.
+    const uint32_t col = ((lane & 31u) << 1) | (lane >> 5);
     // root of every site of the wave's rows: all label loads first, then all
     // second-level loads (rows past the tile repeat its last row)
     uint32_t R[kRowsPerWave];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k)
-        R[k] = G[(size_t)(T.y0 + first + min(k, nr - 1)) * Lx + T.x0 + lane];
+        R[k] = G[(size_t)(T.y0 + first + min(k, nr - 1)) * Lx + T.x0 + col];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k)
         R[k] = G[R[k]];
-    uint64_t F[kRowsPerWave];
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k) {
         bool flip;
         if (ALGO == kClWolff) {
-            flip = k < nr && R[k] == seed_root;
+            flip = R[k] == seed_root;
         } else {
             uint32_t w[4];
             philox4x32_10(R[k] >> 7, t, d.replica, 8u, d.seed_lo, d.seed_hi, w);
             const uint32_t q = (R[k] >> 5) & 3u;
             const uint32_t word = q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3];
-            flip = k < nr && ((word >> (R[k] & 31u)) & 1u);
+            flip = (word >> (R[k] & 31u)) & 1u;
         }
-        F[k] = __ballot(flip);
-    }
-#pragma unroll
-    for (uint32_t k = 0; k < kRowsPerWave; ++k) {
-        if (k >= nr || F[k] == 0)
-            continue;
-        // even columns hold colour y & 1, odd columns the other colour; gather
-        // each half's bits into the 32-bit word of its plane
+        const uint64_t F = __ballot(flip);
+        if (k >= nr)
+            break;
+        // even columns hold colour y & 1, odd columns the other colour; only
+        // this workgroup touches these two words in this launch
         const uint32_t y = T.y0 + first + k;
-        uint64_t e = F[k] & 0x5555555555555555ull, o = (F[k] >> 1) & 0x5555555555555555ull;
-        e = (e | (e >> 1)) & 0x3333333333333333ull;
-        o = (o | (o >> 1)) & 0x3333333333333333ull;
-        e = (e | (e >> 2)) & 0x0F0F0F0F0F0F0F0Full;
-        o = (o | (o >> 2)) & 0x0F0F0F0F0F0F0F0Full;
-        e = (e | (e >> 4)) & 0x00FF00FF00FF00FFull;
-        o = (o | (o >> 4)) & 0x00FF00FF00FF00FFull;
-        e = (e | (e >> 8)) & 0x0000FFFF0000FFFFull;
-        o = (o | (o >> 8)) & 0x0000FFFF0000FFFFull;
-        e = (e | (e >> 16)) & 0x00000000FFFFFFFFull;
-        o = (o | (o >> 16)) & 0x00000000FFFFFFFFull;
+        const uint32_t lo = (uint32_t)F, hi = (uint32_t)(F >> 32);
         gu32 *pe = ((y & 1u) ? P1 : P0) + (size_t)y * W + T.tx;
         gu32 *po = ((y & 1u) ? P0 : P1) + (size_t)y * W + T.tx;
-        if (lane == 0)
-            *pe ^= (uint32_t)e;
-        else if (lane == 1)
-            *po ^= (uint32_t)o;
+        if (lane == 0 && lo != 0u)
+            __hip_atomic_fetch_xor(pe, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if (lane == 1 && hi != 0u)
+            __hip_atomic_fetch_xor(po, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

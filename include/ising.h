@@ -190,7 +190,7 @@ enum { ISING_CLUSTER_SWENDSEN_WANG = 0, ISING_CLUSTER_WOLFF = 1 };
 
 /* Bytes of device workspace ising_batch_cluster needs for batch b: a 32-bit
  * label per site of every replica (each replica's labels 256-byte aligned)
- * plus 16 bytes per tile of 64 x 32 sites.  Host-only.
+ * plus 16 bytes per tile of 64 x 64 sites.  Host-only.
  * Errors: ISING_E_INVALID (NULL argument). */
 int ising_cluster_ws_bytes(ising_batch *b, size_t *bytes);
 

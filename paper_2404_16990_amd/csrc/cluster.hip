@@ -169,7 +169,8 @@ __device__ __forceinline__ void ws_compress(uint32_t *G, uint32_t p)
 
 // ---------------------------------------------------------------------------
 // local: bonds, in-tile labels, crossing masks.  Grid: one 256-thread
-// workgroup per tile; wave w owns rows 8w .. 8w+7 of the tile.
+// workgroup per tile; wave w owns rows w*R .. w*R + R - 1 of the tile
+// (R = kRowsPerWave).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint32_t base)
 {
@@ -187,17 +188,21 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
     const uint32_t first = wv * kRowsPerWave;
     // rows of this wave (even, possibly 0)
     const uint32_t nr = T.rows > first ? min(kRowsPerWave, T.rows - first) : 0u;
-    // One vector load brings all 26 words (lane k < 9: colour-0 word of row
-    // k, 9 <= k < 18: colour-1 word of row k - 9, 18 <= k < 26: the word of
-    // row k - 18 that holds column 0 of the next tile); they are broadcast
-    // with readlane after the bond draws, so the load latency overlaps them.
+    // One vector load brings all the words the wave needs (with R rows per
+    // wave: lane k <= R the colour-0 word of row k, R < k <= 2R + 1 the
+    // colour-1 word of row k - R - 1, 2R + 1 < k <= 3R + 1 the word of row
+    // k - 2R - 2 that holds column 0 of the next tile; row R is the row below
+    // the wave's rows).  They are broadcast with readlane after the bond
+    // draws, so the load latency overlaps them.
+    constexpr uint32_t R1 = kRowsPerWave + 1, R2 = 2 * kRowsPerWave + 2, R3 = 3 * kRowsPerWave + 2;
+    static_assert(R3 <= 64, "one load per lane");
     uint32_t word;
     {
-        const uint32_t k = lane < 9u ? lane : lane < 18u ? lane - 9u : lane < 26u ? lane - 18u : 0u;
-        uint32_t y = T.y0 + min(first + k, lane < 18u ? T.rows : T.rows - 1);
+        const uint32_t k = lane < R1 ? lane : lane < R2 ? lane - R1 : lane < R3 ? lane - R2 : 0u;
+        uint32_t y = T.y0 + min(first + k, lane < R2 ? T.rows : T.rows - 1);
         y = y == Ly ? 0u : y;
-        const bool plane1 = lane < 9u ? false : lane < 18u ? true : lane < 26u ? (y & 1u) != 0 : false;
-        const uint32_t col = lane >= 18u && lane < 26u ? T.txn : T.tx;
+        const bool plane1 = lane < R1 ? false : lane < R2 ? true : lane < R3 ? (y & 1u) != 0 : false;
+        const uint32_t col = lane >= R2 && lane < R3 ? T.txn : T.tx;
         word = (plane1 ? P1 : P0)[(size_t)y * W + col];
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the bond draws
@@ -222,9 +227,9 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
 #pragma unroll
     for (uint32_t k = 0; k <= kRowsPerWave; ++k) {
         p0[k] = __builtin_amdgcn_readlane(word, k);
-        p1[k] = __builtin_amdgcn_readlane(word, 9 + k);
+        p1[k] = __builtin_amdgcn_readlane(word, R1 + k);
         if (k < kRowsPerWave)
-            nxt[k] = __builtin_amdgcn_readlane(word, 18 + k) & 1u;
+            nxt[k] = __builtin_amdgcn_readlane(word, R2 + k) & 1u;
     }
     const uint32_t sel = (lane & 1u) * 2u;
 #pragma unroll
@@ -267,11 +272,11 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
         G[(size_t)(T.y0 + rl) * Lx + T.x0 + lane] = (T.y0 + (root >> 6)) * Lx + T.x0 + (root & 63u);
     }
     if (threadIdx.x == 0) {
-        uint32_t xr = 0;
+        uint64_t xr = 0;
         for (uint32_t rl = 0; rl < T.rows; ++rl)
-            xr |= (uint32_t)(Hm[rl] >> 63) << rl;
+            xr |= (Hm[rl] >> 63) << rl;
         const uint64_t xd = Dm[T.rows - 1];
-        a.tb[tile] = make_uint4((uint32_t)xd, (uint32_t)(xd >> 32), xr, 0u);
+        a.tb[tile] = make_uint4((uint32_t)xd, (uint32_t)(xd >> 32), (uint32_t)xr, (uint32_t)(xr >> 32));
     }
 }
 
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(256) void k_cl_cross(ClArgs a, uint32_t base)
     uint32_t *G = reinterpret_cast<uint32_t *>(a.ws + a.cl[r].g_off);
     const uint4 tb = a.tb[b];
     const uint64_t xd = tb.x | ((uint64_t)tb.y << 32);
-    const uint32_t xr = tb.z;
+    const uint64_t xr = tb.z | ((uint64_t)tb.w << 32);
     if (COMPRESS) {
         if ((xd >> lane) & 1u) {
             const Crossing e = crossing(d, T, lane);

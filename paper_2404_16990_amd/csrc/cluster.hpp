@@ -28,7 +28,8 @@
 
 namespace ising {
 
-constexpr uint32_t kClRows = 32;
+constexpr uint32_t kClRows = 64;
+static_assert(kClRows % 8 == 0 && kClRows <= 64, "4 waves of an even number of rows; crossing masks are 64-bit");
 // Tiles per kernel launch: keeps every grid far below the 2^32 work-item
 // limit of a dispatch (a phase over more tiles is split into launches).
 constexpr uint32_t kClTilesPerLaunch = 1u << 22;

@@ -154,6 +154,114 @@ def run_path(work, rng, args, stream, schedule=None):
 
 RNG_NAMES = {"site": 0, "bitsliced": 1}
 
+# Irreducible work of one Swendsen-Wang step per site under the library's
+# random-number contract: half a Philox4x32-10 call for the two bonds a site
+# owns and one call for its cluster's flip bit; the minimal HBM traffic is a
+# 32-bit label written and read back plus the spin bits read twice and written
+# once (1 bit per site each, 1.5x for the neighbour rows of the bond pass).
+PHILOX_SLOTS = 20 * 1.86 + 20 * 1.0
+SW_SLOTS_PER_SITE = 1.5 * PHILOX_SLOTS
+SW_BYTES_PER_SITE = 4.0 + 4.0 + (1.5 + 1.0 + 1.0) / 8.0
+
+
+def cluster_cpu_baseline(work, steps):
+    """The CPU oracle's Swendsen-Wang steps on every replica of the workload."""
+    import oracle
+    descs = [oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init) for r in work.replicas]
+    states = [oracle.init_state(d) for d in descs]
+    threads = host_threads()
+    t0 = time.perf_counter()
+    oracle.run_cluster_batch(descs, states, steps, oracle.SWENDSEN_WANG, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": work.spins * steps / dt, "unit": "site updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {len(work.replicas)} replicas x {steps} SW steps, {dt:.1f} s on {threads} host threads"}
+
+
+def cluster_leg(work, stream, steps, warmup=2):
+    """Swendsen-Wang and Wolff steps of the workload's replicas: site updates
+    per second (every step relabels every site) and the step's roofline."""
+    import torch
+
+    import paper_2404_16990_amd as P
+
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+             for r in work.replicas]
+    b = P.Batch(descs, stream=stream)
+    out = {"workload": work.name, "steps": steps, "warmup": warmup,
+           "metric": "site updates/s (a step labels every site; SW flips each cluster with prob. 1/2, "
+                     "Wolff the cluster of one random site)"}
+    for algo in ("sw", "wolff"):
+        b.cluster(warmup, algo)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.cluster(steps, algo, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[algo] = {"value": work.spins / (ms / 1e3), "unit": "site updates/s", "ms_per_step": ms}
+    out["workspace_bytes"] = int(b.ws.numel())
+    b.ws = None
+    b.close()
+    peak_alu = CUS * LANE_OPS_PER_CU_CLK * CLOCK_HZ / SW_SLOTS_PER_SITE
+    peak_hbm = HBM_BYTES_PER_S / SW_BYTES_PER_SITE
+    achieved = out["sw"]["value"]
+    out["roofline"] = {
+        "bound": "alu", "kernel": "k_cl_local + k_cl_cross<merge> + k_cl_cross<compress> + k_cl_flip (whole SW step)",
+        "achieved": achieved / 1e9, "peak": min(peak_alu, peak_hbm) / 1e9, "unit": "Gsite/s",
+        "frac": achieved / min(peak_alu, peak_hbm), "traffic": None,
+        "per_unit": f"{SW_SLOTS_PER_SITE:.1f} full-rate VALU slots (1.5 Philox calls) and "
+                    f"{SW_BYTES_PER_SITE:.2f} HBM bytes per site",
+        "alu_peak": peak_alu / 1e9, "hbm_peak": peak_hbm / 1e9}
+    return out
+
+
+def critical_decorrelation(sw_steps, wolff_steps, plain_sweeps):
+    """tau_int(|m|) and effective independent samples per second at T_c for
+    Swendsen-Wang steps, Wolff steps and checkerboard Metropolis sweeps, on 64
+    replicas of 256^2 at T = linspace(2.20, 2.35, 64) (replica 29 is at T_c),
+    equilibrated first by 2000 SW steps."""
+    import numpy as np
+    import torch
+
+    import paper_2404_16990_amd as P
+    from paper_2404_16990_amd import analysis, learned
+    import workloads
+
+    w = workloads.learned_64x256()
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+             for r in w.replicas]
+    b = P.Batch(descs)
+    t_c = min(range(len(w.replicas)), key=lambda r: abs(w.replicas[r].T - workloads.T_CRITICAL_PRINTED))
+    b.cluster(2000, "sw")
+    n = float(256 * 256)
+    res = {"workload": w.name, "replica_at_tc": t_c, "T": w.replicas[t_c].T}
+
+    def summary(trace, seconds, units, unit_name):
+        tau, win = analysis.tau_int(trace[t_c])
+        rate = analysis.effective_rate(units / seconds, tau)
+        return {f"tau_int_{unit_name}": tau, "window": win, unit_name: units, "seconds": seconds,
+                "effective_samples_per_s": rate, "mean_abs_m": float(trace[t_c].mean())}
+
+    for algo, steps in (("sw", sw_steps), ("wolff", wolff_steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(b.stream)
+        _, mag = b.cluster(steps, algo, 1)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        tr = np.abs(mag.cpu().numpy().astype(np.float64)) / n
+        res[algo] = summary(tr, e0.elapsed_time(e1) / 1e3, steps, "steps")
+    tr_p, _, s_p = learned.plain_trace(b, plain_sweeps, 10)
+    plain = summary(tr_p, s_p, plain_sweeps // 10, "points")
+    plain["tau_int_sweeps"] = plain["tau_int_points"] * 10
+    res["metropolis"] = plain
+    for algo in ("sw", "wolff"):
+        res[algo]["over_metropolis"] = res[algo]["effective_samples_per_s"] / plain["effective_samples_per_s"]
+    b.ws = None
+    b.close()
+    return res
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -176,6 +284,13 @@ def main():
     ap.add_argument("--learned-units", type=int, default=10000)
     ap.add_argument("--plain-sweeps", type=int, default=500000)
     ap.add_argument("--tune-sweeps", type=int, default=20)
+    ap.add_argument("--no-cluster", action="store_true",
+                    help="skip the Swendsen-Wang / Wolff leg (throughput and tau_int at T_c)")
+    ap.add_argument("--cluster-steps", type=int, default=20)
+    ap.add_argument("--critical-steps", type=int, default=20000,
+                    help="SW and Wolff steps of the T_c decorrelation comparison (0 skips it)")
+    ap.add_argument("--critical-sweeps", type=int, default=400000,
+                    help="Metropolis sweeps of the T_c decorrelation comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -247,6 +362,15 @@ def main():
             "measured_alu_ceiling": cv / 1e9, "frac_of_measured_ceiling": mv["achieved"] / cv}}
         bv.close()
         del bv
+    if not args.no_cluster:
+        torch.cuda.empty_cache()
+        out["cluster"] = cluster_leg(work, stream, args.cluster_steps)
+        if not args.no_cpu_baseline:
+            out["cluster"]["cpu_baseline"] = cluster_cpu_baseline(work, 3)
+        if args.critical_steps > 0:
+            out["cluster"]["critical"] = critical_decorrelation(args.critical_steps, args.critical_steps,
+                                                                args.critical_sweeps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps, rng)
     if args.learned:

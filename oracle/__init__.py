@@ -8,7 +8,8 @@ Contents:
   - ``liboracle.so`` (from ``ising_oracle.c``): Philox4x32-10, thresholds,
     random/cold initial states, plain int8 sweeps, observables, threaded
     batches over replicas; (from ``cluster_oracle.c``) Swendsen-Wang and Wolff
-    cluster steps.  This module is its ctypes front-end.
+    cluster steps; (from ``ising3d_oracle.c``) 3D sweeps.  This module is its
+    ctypes front-end.
   - ``philox``: a second, pure-Python Philox4x32-10.
   - ``exact``: exact results (enumeration, transfer matrix, Kaufman torus
     partition function, Onsager energy and T_c, Yang magnetisation).
@@ -30,6 +31,12 @@ class Desc(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("J", ctypes.c_double),
                 ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("replica", ctypes.c_uint32), ("init", ctypes.c_int32), ("rng", ctypes.c_int32)]
+
+
+class Desc3(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("J", ctypes.c_double), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,6 +80,16 @@ def lib():
                                                ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                                ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        L.oracle3_thresholds.argtypes = [ctypes.c_double, ctypes.c_double, u32p, ctypes.POINTER(ctypes.c_int32)]
+        L.oracle3_init.argtypes = [ctypes.POINTER(Desc3), ctypes.c_void_p]
+        L.oracle3_observables.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.oracle3_observables.restype = None
+        L.oracle3_sweeps.argtypes = [ctypes.POINTER(Desc3), ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle3_run_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc3), ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -240,5 +257,71 @@ def run_cluster_batch(descs, states, n, algorithm=SWENDSEN_WANG, t0=None, record
                                         int(record_every), bond.ctypes.data if n_rec else None,
                                         mag.ctypes.data if n_rec else None, int(threads))
     if st != 0:
+        raise ValueError("invalid arguments")
+    return bond[:, :n_rec], mag[:, :n_rec]
+
+
+# ---- 3D (simple cubic, six neighbours) ---------------------------------------
+
+def desc3(Lx, Ly, Lz, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM):
+    return Desc3(int(Lx), int(Ly), int(Lz), int(init), float(J), float(beta), int(seed), int(replica), 0)
+
+
+def thresholds3(J, beta):
+    """(thr4, thr8, thr12, always) of the 3D Metropolis rule."""
+    thr = (ctypes.c_uint32 * 3)()
+    a = ctypes.c_int32()
+    if lib().oracle3_thresholds(float(J), float(beta), thr, ctypes.byref(a)) != 0:
+        raise ValueError("invalid J/beta")
+    return int(thr[0]), int(thr[1]), int(thr[2]), int(a.value)
+
+
+def init_state3(d):
+    """Initial state of a 3D replica as an (Lz, Ly, Lx) int8 array of +-1."""
+    s = np.empty((d.Lz, d.Ly, d.Lx), dtype=np.int8)
+    if lib().oracle3_init(ctypes.byref(d), s.ctypes.data) != 0:
+        raise ValueError("invalid descriptor")
+    return s
+
+
+def observables3(s):
+    """(B, M) of an (Lz, Ly, Lx) +-1 array."""
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    B, M = ctypes.c_int64(), ctypes.c_int64()
+    lib().oracle3_observables(s.shape[2], s.shape[1], s.shape[0], s.ctypes.data, ctypes.byref(B), ctypes.byref(M))
+    return int(B.value), int(M.value)
+
+
+def sweeps3(d, s, n, t0=0, record_every=0):
+    """n 3D sweeps in place on s; returns (bond, mag) traces."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape == (d.Lz, d.Ly, d.Lx)
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros(max(n_rec, 1), dtype=np.int64)
+    mag = np.zeros(max(n_rec, 1), dtype=np.int64)
+    if lib().oracle3_sweeps(ctypes.byref(d), s.ctypes.data, int(t0), int(n), int(record_every),
+                            bond.ctypes.data if n_rec else None, mag.ctypes.data if n_rec else None) != 0:
+        raise ValueError("invalid arguments")
+    return bond[:n_rec], mag[:n_rec]
+
+
+def run_batch3(descs, states, n, t0=None, record_every=0, threads=None):
+    """3D sweeps of many replicas in place on host threads (as run_batch)."""
+    nrep = len(descs)
+    arr = (Desc3 * nrep)(*descs)
+    ptrs = (ctypes.c_void_p * nrep)()
+    for r, s in enumerate(states):
+        assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape == (descs[r].Lz, descs[r].Ly, descs[r].Lx)
+        ptrs[r] = s.ctypes.data
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
+    mag = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
+    t0a = None
+    if t0 is not None:
+        t0a = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.uint64), (nrep,)))
+    if threads is None:
+        threads = default_threads()
+    if lib().oracle3_run_batch(nrep, arr, ptrs, t0a.ctypes.data if t0a is not None else None, int(n),
+                               int(record_every), bond.ctypes.data if n_rec else None,
+                               mag.ctypes.data if n_rec else None, int(threads)) != 0:
         raise ValueError("invalid arguments")
     return bond[:, :n_rec], mag[:, :n_rec]

@@ -1,4 +1,4 @@
-"""Build the C oracle (test infrastructure: sweeps and cluster steps) into
+"""Build the C oracle (test infrastructure: 2D sweeps, cluster steps, 3D sweeps) into
 oracle/liboracle.so with gcc.
 
 Run as ``python oracle/build.py``.  The GPU library never links this file's
@@ -10,7 +10,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "ising_oracle.c"), os.path.join(HERE, "cluster_oracle.c")]
+SRCS = [os.path.join(HERE, "ising_oracle.c"), os.path.join(HERE, "cluster_oracle.c"),
+        os.path.join(HERE, "ising3d_oracle.c")]
 OUT = os.path.join(HERE, "liboracle.so")
 
 

@@ -31,6 +31,8 @@ EXPORTED = [
     "ising_nn_score",
     "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_destroy",
     "ising_cluster_ws_bytes", "ising_batch_cluster",
+    "ising3d_state_bytes", "ising3d_batch_create", "ising3d_batch_run", "ising3d_batch_observables",
+    "ising3d_batch_get_spins", "ising3d_batch_set_spins", "ising3d_batch_get_sweep", "ising3d_batch_destroy",
 ]
 
 
@@ -42,6 +44,12 @@ class ising_desc(ctypes.Structure):
 
 ISING_RNG_SITE, ISING_RNG_BITSLICED = 0, 1
 ISING_CLUSTER_SWENDSEN_WANG, ISING_CLUSTER_WOLFF = 0, 1
+
+
+class ising3d_desc(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("J", ctypes.c_double), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
 
 
 class ising_schedule(ctypes.Structure):
@@ -107,6 +115,14 @@ def lib():
         L.ising_nn_destroy.argtypes = [vp]
         L.ising_cluster_ws_bytes.argtypes = [vp, P(ctypes.c_size_t)]
         L.ising_batch_cluster.argtypes = [vp, i32, u64, u32, vp, ctypes.c_size_t, vp, vp, vp]
+        L.ising3d_state_bytes.argtypes = [i32, P(ising3d_desc), P(ctypes.c_size_t)]
+        L.ising3d_batch_create.argtypes = [i32, P(ising3d_desc), vp, ctypes.c_size_t, vp, P(vp)]
+        L.ising3d_batch_run.argtypes = [vp, u64, u32, vp, vp, vp]
+        L.ising3d_batch_observables.argtypes = [vp, vp, vp, vp]
+        L.ising3d_batch_get_spins.argtypes = [vp, i32, vp, vp]
+        L.ising3d_batch_set_spins.argtypes = [vp, i32, vp, vp]
+        L.ising3d_batch_get_sweep.argtypes = [vp, i32, P(u64), vp]
+        L.ising3d_batch_destroy.argtypes = [vp]
         for name in EXPORTED[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -217,6 +233,57 @@ def ising_batch_autotune(h, trial_sweeps, stream=None):
 
 def ising_batch_destroy(h):
     _check(lib().ising_batch_destroy(h), "ising_batch_destroy")
+
+
+def _descs3(descs):
+    arr = (ising3d_desc * len(descs))()
+    for i, d in enumerate(descs):
+        if isinstance(d, ising3d_desc):
+            arr[i] = d
+        else:
+            arr[i] = ising3d_desc(int(d["Lx"]), int(d["Ly"]), int(d["Lz"]), int(d.get("init", 0)),
+                                  float(d.get("J", 1.0)), float(d["beta"]), int(d["seed"]), int(d["replica"]),
+                                  int(d.get("reserved", 0)))
+    return arr
+
+
+def ising3d_state_bytes(descs):
+    out = ctypes.c_size_t()
+    _check(lib().ising3d_state_bytes(len(descs), _descs3(descs), ctypes.byref(out)), "ising3d_state_bytes")
+    return int(out.value)
+
+
+def ising3d_batch_create(descs, dev_buf, nbytes, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().ising3d_batch_create(len(descs), _descs3(descs), dev_buf, nbytes, stream, ctypes.byref(h)),
+           "ising3d_batch_create")
+    return h
+
+
+def ising3d_batch_run(h, n_sweeps, record_every=0, dev_bond=None, dev_mag=None, stream=None):
+    _check(lib().ising3d_batch_run(h, n_sweeps, record_every, dev_bond, dev_mag, stream), "ising3d_batch_run")
+
+
+def ising3d_batch_observables(h, host_bond, host_mag, stream=None):
+    _check(lib().ising3d_batch_observables(h, host_bond, host_mag, stream), "ising3d_batch_observables")
+
+
+def ising3d_batch_get_spins(h, r, host_pm1, stream=None):
+    _check(lib().ising3d_batch_get_spins(h, r, host_pm1, stream), "ising3d_batch_get_spins")
+
+
+def ising3d_batch_set_spins(h, r, host_pm1, stream=None):
+    _check(lib().ising3d_batch_set_spins(h, r, host_pm1, stream), "ising3d_batch_set_spins")
+
+
+def ising3d_batch_get_sweep(h, r, stream=None):
+    t = ctypes.c_uint64()
+    _check(lib().ising3d_batch_get_sweep(h, r, ctypes.byref(t), stream), "ising3d_batch_get_sweep")
+    return int(t.value)
+
+
+def ising3d_batch_destroy(h):
+    _check(lib().ising3d_batch_destroy(h), "ising3d_batch_destroy")
 
 
 def ising_cluster_ws_bytes(h):
@@ -515,3 +582,69 @@ def _batch_extract(self, block, per_replica, draw, out=None):
 
 Batch.block_round = _batch_block_round
 Batch.extract_blocks = _batch_extract
+
+
+class Batch3:
+    """A batch of 3D replicas in a torch-owned device buffer on the current device."""
+
+    def __init__(self, descs, stream=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.descs = list(descs)
+        self.n = len(self.descs)
+        self.nbytes = ising3d_state_bytes(self.descs)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buf.device)
+        self.h = ising3d_batch_create(self.descs, self.buf.data_ptr(), self.nbytes, self._s())
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def _shape(self, r):
+        d = self.descs[r]
+        return (d["Lz"], d["Ly"], d["Lx"]) if isinstance(d, dict) else (d.Lz, d.Ly, d.Lx)
+
+    def run(self, n_sweeps, record_every=0):
+        """Enqueue n_sweeps sweeps; returns device (bond, mag) traces or None."""
+        torch = self.torch
+        n_rec = n_sweeps // record_every if record_every else 0
+        if n_rec:
+            bond = torch.empty((self.n, n_rec), dtype=torch.int64, device=self.buf.device)
+            mag = torch.empty((self.n, n_rec), dtype=torch.int64, device=self.buf.device)
+            ising3d_batch_run(self.h, n_sweeps, record_every, bond.data_ptr(), mag.data_ptr(), self._s())
+            return bond, mag
+        ising3d_batch_run(self.h, n_sweeps, 0, None, None, self._s())
+        return None
+
+    def observables(self):
+        import numpy as np
+        b = np.zeros(self.n, dtype=np.int64)
+        m = np.zeros(self.n, dtype=np.int64)
+        ising3d_batch_observables(self.h, b.ctypes.data, m.ctypes.data, self._s())
+        return b, m
+
+    def get_spins(self, r):
+        import numpy as np
+        out = np.empty(self._shape(r), dtype=np.int8)
+        ising3d_batch_get_spins(self.h, r, out.ctypes.data, self._s())
+        return out
+
+    def set_spins(self, r, s):
+        import numpy as np
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        assert s.shape == self._shape(r)
+        ising3d_batch_set_spins(self.h, r, s.ctypes.data, self._s())
+
+    def get_sweep(self, r):
+        return ising3d_batch_get_sweep(self.h, r, self._s())
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ising3d_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 OUT = os.path.join(OUT_DIR, "libising.so")
-SOURCES = ["kernels.hip", "api.cpp", "nn.hip", "nn_api.cpp", "cluster.hip", "cluster_api.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "nn.hip", "nn_api.cpp", "cluster.hip", "cluster_api.cpp", "ising3d.hip",
+           "ising3d_api.cpp"]
 PROBE_OUT = os.path.join(OUT_DIR, "libising_probe.so")
 PROBE_SOURCES = ["probe.hip"]
 # Packed FP32 instructions stay disabled in every HIP build of this project.

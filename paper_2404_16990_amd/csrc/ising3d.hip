@@ -1,0 +1,252 @@
+// 3D sweep kernels: checkerboard Metropolis on the periodic simple-cubic
+// lattice (six neighbours; paper section 1), on packed colour planes whose
+// rows are indexed by z*Ly + y.
+//
+// For a colour-c word of row (y, z), the other colour's word with the same
+// index in each of the rows (y +- 1, z) and (y, z +- 1) holds the word's four
+// neighbours along y and z (a colour's column parity flips with y and with z,
+// so the compact positions line up); the other colour's word of the same row
+// holds one x neighbour of every site and, funnel-shifted with the word before
+// or after it, the other (as in 2D).
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "ising3d.hpp"
+
+namespace ising {
+
+namespace {
+
+__device__ __forceinline__ uint32_t block_owner(const uint32_t *__restrict__ prefix, uint32_t n, uint32_t b)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Word indices of the six neighbours of word (row, w) of colour c.
+struct Neigh3 {
+    uint32_t ym, yp, zm, zp, same, nb, p;
+};
+
+__device__ __forceinline__ Neigh3 neigh3(const Rep3Dev &d, uint32_t idx, uint32_t colour)
+{
+    const uint32_t W = d.W, Ly = d.Ly, Lz = d.Lz;
+    const uint32_t row = idx / W, w = idx - row * W;
+    const uint32_t z = row / Ly, y = row - z * Ly;
+    const uint32_t ym = y == 0 ? Ly - 1 : y - 1, yp = y + 1 == Ly ? 0 : y + 1;
+    const uint32_t zm = z == 0 ? Lz - 1 : z - 1, zp = z + 1 == Lz ? 0 : z + 1;
+    Neigh3 n;
+    n.p = (colour + y + z) & 1u;
+    n.same = idx;
+    n.ym = (z * Ly + ym) * W + w;
+    n.yp = (z * Ly + yp) * W + w;
+    n.zm = (zm * Ly + y) * W + w;
+    n.zp = (zp * Ly + y) * W + w;
+    n.nb = row * W + (n.p ? (w + 1 == W ? 0 : w + 1) : (w == 0 ? W - 1 : w - 1));
+    return n;
+}
+
+// Classes of the 32 sites of a word by the number a of anti-aligned
+// neighbours among six, counted by full adders: a >= 3 (dE <= 0), a = 2
+// (dE = 4J), a = 1 (dE = 8J); the rest (a = 0) have dE = 12J.
+struct Classes3 {
+    uint32_t ge3, eq2, eq1;
+};
+
+__device__ __forceinline__ Classes3 classify6(uint32_t s, const uint32_t (&n)[6])
+{
+    const uint32_t a0 = s ^ n[0], a1 = s ^ n[1], a2 = s ^ n[2];
+    const uint32_t a3 = s ^ n[3], a4 = s ^ n[4], a5 = s ^ n[5];
+    const uint32_t s1 = __builtin_amdgcn_bitop3_b32(a0, a1, a2, 0x96), c1 = __builtin_amdgcn_bitop3_b32(a0, a1, a2, 0xE8);
+    const uint32_t s2 = __builtin_amdgcn_bitop3_b32(a3, a4, a5, 0x96), c2 = __builtin_amdgcn_bitop3_b32(a3, a4, a5, 0xE8);
+    const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;  // a = b0 + 2 (c1 + c2 + k0)
+    const uint32_t b1 = __builtin_amdgcn_bitop3_b32(c1, c2, k0, 0x96), b2 = __builtin_amdgcn_bitop3_b32(c1, c2, k0, 0xE8);
+    Classes3 c;
+    c.ge3 = b2 | (b1 & b0);
+    c.eq2 = ~b2 & b1 & ~b0;
+    c.eq1 = ~b2 & ~b1 & b0;
+    return c;
+}
+
+// Sites to flip in a colour-c word (site contract: site 32 w + b of the row
+// draws word (h & 3) of call h >> 2, h = row * Lx / 2 + 32 w + b; q0 is the
+// call of bit 0).  The threshold of a site is selected from its class bits
+// with two v_bitop3 (eq2 ? thr4 : eq1 ? thr8 : thr12) and compared into a lane
+// mask that is shifted into the accumulator as a carry (bits 31 down to 0).
+__device__ __forceinline__ uint32_t flip_mask32_3d(uint32_t s, const uint32_t (&n)[6], uint32_t q0, uint32_t t,
+                                                   uint32_t colour, const Rep3Dev &d)
+{
+    if (d.always)
+        return ~0u;
+    const Classes3 cl = classify6(s, n);
+    const uint32_t thr4 = __builtin_amdgcn_readfirstlane(d.thr4), thr8 = __builtin_amdgcn_readfirstlane(d.thr8);
+    const uint32_t thr12 = __builtin_amdgcn_readfirstlane(d.thr12);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int q = 7; q >= 0; --q) {
+        uint32_t r[4];
+        philox4x32_10(q0 + q, t, d.replica, colour, d.seed_lo, d.seed_hi, r);
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const int b = 4 * q + j;
+            const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)cl.eq2, b, 1);
+            const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)cl.eq1, b, 1);
+            const uint32_t thr = __builtin_amdgcn_bitop3_b32(m2, thr4, __builtin_amdgcn_bitop3_b32(m1, thr8, thr12, 0xCA),
+                                                             0xCA);
+            acc = shift_in_carry(acc, __builtin_amdgcn_uicmp(r[j], thr, 36 /* unsigned < */));
+        }
+    }
+    return cl.ge3 | acc;
+}
+
+// ---------------------------------------------------------------------------
+// one colour of one sweep of every replica: grid = blocks of all replicas;
+// workgroup b handles k3WordsPerBlock consecutive words of its replica's
+// colour-c plane, thread i the words i, i + 256, ...
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k3_sweep(Sweep3Args a, uint32_t colour, uint32_t sweep_off)
+{
+    const uint32_t r = block_owner(a.prefix, a.n, blockIdx.x);
+    const Rep3Dev d = a.reps[r];
+    const uint32_t words = d.Lz * d.Ly * d.W;
+    const uint32_t first = (blockIdx.x - a.prefix[r]) * k3WordsPerBlock;
+    uint32_t *tgt = d.plane0 + (colour ? (size_t)words : 0);
+    const uint32_t *src = d.plane0 + (colour ? 0 : (size_t)words);
+    const uint32_t t = d.t + sweep_off;
+    for (uint32_t i = threadIdx.x; i < k3WordsPerBlock; i += 256) {
+        const uint32_t idx = first + i;
+        if (idx >= words)
+            break;
+        const Neigh3 nb = neigh3(d, idx, colour);
+        const uint32_t same = src[nb.same];
+        uint32_t n[6];
+        n[0] = src[nb.ym];
+        n[1] = src[nb.yp];
+        n[2] = src[nb.zm];
+        n[3] = src[nb.zp];
+        n[4] = same;
+        n[5] = side_word<uint32_t>(same, src[nb.nb], nb.p);
+        const uint32_t s = tgt[idx];
+        const uint32_t row = idx / d.W, w = idx - row * d.W;
+        const uint32_t q0 = row * (d.Lx >> 3) + 8u * w;  // (row * Lx / 2 + 32 w) / 4
+        tgt[idx] = s ^ flip_mask32_3d(s, n, q0, t, colour, d);
+    }
+}
+
+// initial states: both colour planes, same block mapping
+__global__ __launch_bounds__(256) void k3_init(Sweep3Args a, const int32_t *__restrict__ modes)
+{
+    const uint32_t r = block_owner(a.prefix, a.n, blockIdx.x);
+    const Rep3Dev d = a.reps[r];
+    const int32_t mode = modes[r];
+    const uint32_t words = d.Lz * d.Ly * d.W;
+    const uint32_t first = (blockIdx.x - a.prefix[r]) * k3WordsPerBlock;
+    for (uint32_t i = threadIdx.x; i < k3WordsPerBlock; i += 256) {
+        const uint32_t idx = first + i;
+        if (idx >= words)
+            break;
+        const uint32_t row = idx / d.W, w = idx - row * d.W;
+        const uint32_t z = row / d.Ly, y = row - z * d.Ly;
+        for (uint32_t c = 0; c < 2; ++c) {
+            uint32_t v = mode == 1 ? ~0u : 0u;
+            if (mode == 0) {
+                // sites 2b + p of the word's 64 columns: g = base + 2b + p, so
+                // call (g >> 2) = base / 4 + (b >> 1) gives bit b from word
+                // 2 (b & 1) + p
+                const uint32_t p = (c + y + z) & 1u;
+                const uint32_t base = row * d.Lx + 64u * w;
+                for (uint32_t j = 0; j < 16; ++j) {
+                    uint32_t o[4];
+                    philox4x32_10((base >> 2) + j, 0u, d.replica, 2u, d.seed_lo, d.seed_hi, o);
+                    v |= (uint32_t)(o[p] >= 0x80000000u) << (2 * j);
+                    v |= (uint32_t)(o[2 + p] >= 0x80000000u) << (2 * j + 1);
+                }
+            }
+            d.plane0[(size_t)c * words + idx] = v;
+        }
+    }
+}
+
+// (B, M): every bond joins a colour-0 and a colour-1 site, so summing the six
+// bonds of every colour-1 site counts each bond once: B = 6 N/2 - 2 A with A
+// the anti-aligned pairs; M = 2 (up spins) - N.
+__global__ __launch_bounds__(256) void k3_observables(Sweep3Args a, int64_t *__restrict__ bond,
+                                                      int64_t *__restrict__ mag, uint32_t stride)
+{
+    const uint32_t r = block_owner(a.prefix, a.n, blockIdx.x);
+    const Rep3Dev d = a.reps[r];
+    const uint32_t words = d.Lz * d.Ly * d.W;
+    const uint32_t first = (blockIdx.x - a.prefix[r]) * k3WordsPerBlock;
+    const uint32_t *src = d.plane0, *tgt = d.plane0 + (size_t)words;
+    uint32_t anti = 0, pop = 0;
+    for (uint32_t i = threadIdx.x; i < k3WordsPerBlock; i += 256) {
+        const uint32_t idx = first + i;
+        if (idx >= words)
+            break;
+        const Neigh3 nb = neigh3(d, idx, 1u);
+        const uint32_t same = src[nb.same], s = tgt[idx];
+        const uint32_t side = side_word<uint32_t>(same, src[nb.nb], nb.p);
+        anti += __popc(s ^ src[nb.ym]) + __popc(s ^ src[nb.yp]) + __popc(s ^ src[nb.zm]) + __popc(s ^ src[nb.zp]) +
+                __popc(s ^ same) + __popc(s ^ side);
+        pop += __popc(s) + __popc(same);
+    }
+    __shared__ int64_t red[2][4];
+    const int64_t A = wave_sum((int64_t)anti), U = wave_sum((int64_t)pop);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = A;
+        red[1][threadIdx.x >> 6] = U;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t db = -2 * (red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        int64_t dm = 2 * (red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        if (blockIdx.x == a.prefix[r]) {
+            db += 3 * (int64_t)d.N;
+            dm -= (int64_t)d.N;
+        }
+        atomicAdd(reinterpret_cast<unsigned long long *>(&bond[(size_t)r * stride]), (unsigned long long)db);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&mag[(size_t)r * stride]), (unsigned long long)dm);
+    }
+}
+
+__global__ void k3_advance(Rep3Dev *__restrict__ reps, uint32_t n, uint32_t delta)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n)
+        reps[r].t += delta;
+}
+
+}  // namespace
+
+hipError_t launch3_init(const Sweep3Args &a, const int32_t *modes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k3_init, dim3(a.blocks), dim3(256), 0, st, a, modes);
+    return hipGetLastError();
+}
+
+hipError_t launch3_sweep(const Sweep3Args &a, uint32_t colour, uint32_t sweep_off, hipStream_t st)
+{
+    hipLaunchKernelGGL(k3_sweep, dim3(a.blocks), dim3(256), 0, st, a, colour, sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch3_observables(const Sweep3Args &a, int64_t *bond, int64_t *mag, uint32_t stride, hipStream_t st)
+{
+    hipLaunchKernelGGL(k3_observables, dim3(a.blocks), dim3(256), 0, st, a, bond, mag, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch3_advance(Rep3Dev *reps, uint32_t n, uint32_t delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k3_advance, dim3((n + 255) / 256), dim3(256), 0, st, reps, n, delta);
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -18,7 +18,7 @@ def _declared():
         if fn.endswith(".h"):
             text = open(os.path.join(ROOT, "include", fn)).read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names += re.findall(r"\b(ising_\w+)\s*\(", text)
+            names += re.findall(r"\b(ising(?:3d)?_\w+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -139,3 +139,35 @@ def test_nn_create_rejects_before_touching_the_device():
                      (P.lib().ising_batch_block_round, (None, None, 0, None, None))]:
         assert fn(*args) == P.ISING_E_INVALID
     assert P.lib().ising_nn_destroy(None) == P.ISING_OK
+
+
+def _d3(**kw):
+    base = dict(Lx=64, Ly=4, Lz=6, J=1.0, beta=0.22, seed=1, replica=0, init=0)
+    base.update(kw)
+    return base
+
+
+def test_3d_layout_and_validation():
+    assert P.ctypes.sizeof(P.ising3d_desc) == 48  # 4 int32, 3 x 8 bytes, 2 x 4 bytes
+    one = P.ising3d_state_bytes([_d3()])
+    assert one >= 2 * 64 * 4 * 6 // 8 and one % 256 == 0
+    assert P.ising3d_state_bytes([_d3(), _d3(Lx=128, Lz=2)]) > one
+    for kw, code in [(dict(Lx=96), P.ISING_E_UNSUPPORTED), (dict(Ly=3), P.ISING_E_UNSUPPORTED),
+                     (dict(Lz=0), P.ISING_E_UNSUPPORTED), (dict(Lz=5), P.ISING_E_UNSUPPORTED),
+                     (dict(Lx=65536, Ly=256, Lz=256), P.ISING_E_UNSUPPORTED),
+                     (dict(J=0.0), P.ISING_E_INVALID), (dict(beta=-1.0), P.ISING_E_INVALID),
+                     (dict(init=5), P.ISING_E_INVALID), (dict(reserved=1), P.ISING_E_INVALID)]:
+        with pytest.raises(P.IsingError) as e:
+            P.ising3d_state_bytes([_d3(**kw)])
+        assert e.value.code == code, kw
+    with pytest.raises(P.IsingError) as e:
+        P.ising3d_batch_create([_d3()], None, 1 << 20)
+    assert e.value.code == P.ISING_E_INVALID
+    with pytest.raises(P.IsingError) as e:
+        P.ising3d_batch_create([_d3()], 256, 16)
+    assert e.value.code == P.ISING_E_NOMEM
+    for fn, args in [(P.lib().ising3d_batch_run, (None, 1, 0, None, None, None)),
+                     (P.lib().ising3d_batch_observables, (None, None, None, None)),
+                     (P.lib().ising3d_batch_get_spins, (None, 0, None, None))]:
+        assert fn(*args) == P.ISING_E_INVALID
+    assert P.lib().ising3d_batch_destroy(None) == P.ISING_OK

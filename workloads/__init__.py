@@ -101,12 +101,41 @@ def learned_64x256() -> Workload:
     return Workload("learned-64x256^2-T2.20..2.35", reps, sweeps=1000, record_every=1)
 
 
+@dataclass
+class Replica3:
+    """A 3D (simple cubic) replica."""
+    Lx: int
+    Ly: int
+    Lz: int
+    T: float
+    seed: int
+    replica: int
+    init: int = INIT_RANDOM
+    J: float = 1.0
+
+    @property
+    def beta(self) -> float:
+        return 1.0 / self.T
+
+    @property
+    def spins(self) -> int:
+        return self.Lx * self.Ly * self.Lz
+
+
+def cubic_16x256() -> Workload:
+    """16 replicas of 256^3 (the 3D generalisation of section 1), T_r = 3.5 + 2 r / 15
+    around the 3D critical temperature (about 4.51), seed 16990 + r, random start."""
+    reps = [Replica3(256, 256, 256, 3.5 + 2.0 * r / 15.0, BASE_SEED + r, r) for r in range(16)]
+    return Workload("cubic-16x256^3-T3.5..5.5", reps, sweeps=1000, record_every=100)
+
+
 ALL = {
     "single_64": single_64,
     "batch_256x1024": batch_256x1024,
     "uneven_512": uneven_512,
     "paper_scale": paper_scale,
     "learned_64x256": learned_64x256,
+    "cubic_16x256": cubic_16x256,
 }
 
 

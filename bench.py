@@ -164,6 +164,55 @@ SW_SLOTS_PER_SITE = 1.5 * PHILOX_SLOTS
 SW_BYTES_PER_SITE = 4.0 + 4.0 + (1.5 + 1.0 + 1.0) / 8.0
 
 
+def cubic_leg(sweeps, warmup=3):
+    """3D sweeps of the 16 x 256^3 workload: flip attempts per second, the
+    sweep kernel's roofline (the same derived ALU peak per flip attempt as in
+    2D: a quarter Philox call, one compare, one bit insert) and the oracle's
+    rate on a bounded sample."""
+    import torch
+
+    import paper_2404_16990_amd as P
+    import workloads
+
+    w = workloads.cubic_16x256()
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, Lz=r.Lz, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+             for r in w.replicas]
+    b = P.Batch3(descs)
+    stream = b.stream
+    b.run(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.run(sweeps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / sweeps
+    b.close()
+    flips = w.spins / (ms / 1e3)
+    peak = alu_peak_flips()
+    # each sweep is two k3_sweep launches (one per colour) of half the sites
+    out = {"workload": w.name, "spins": w.spins, "sweeps": sweeps, "value": flips, "unit": "flip attempts/s",
+           "ms_per_sweep": ms,
+           "roofline": {"bound": "alu", "kernel": "k3_sweep", "achieved": flips / 1e9, "peak": peak / 1e9,
+                        "unit": "Gflip/s", "frac": flips / peak, "traffic": None, "launch_ms": ms / 2,
+                        "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt"}}
+    return out
+
+
+def cubic_cpu_baseline(sweeps=2):
+    import oracle
+    import workloads
+    w = workloads.cubic_16x256()
+    descs = [oracle.desc3(r.Lx, r.Ly, r.Lz, r.J, r.beta, r.seed, r.replica, r.init) for r in w.replicas]
+    states = [oracle.init_state3(d) for d in descs]
+    threads = host_threads()
+    t0 = time.perf_counter()
+    oracle.run_batch3(descs, states, sweeps, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": w.spins * sweeps / dt, "unit": "flip attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {len(w.replicas)} replicas x {sweeps} sweeps, {dt:.1f} s on {threads} host threads"}
+
+
 def cluster_cpu_baseline(work, steps):
     """The CPU oracle's Swendsen-Wang steps on every replica of the workload."""
     import oracle
@@ -284,6 +333,8 @@ def main():
     ap.add_argument("--learned-units", type=int, default=10000)
     ap.add_argument("--plain-sweeps", type=int, default=500000)
     ap.add_argument("--tune-sweeps", type=int, default=20)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (simple cubic) leg")
+    ap.add_argument("--cubic-sweeps", type=int, default=50)
     ap.add_argument("--no-cluster", action="store_true",
                     help="skip the Swendsen-Wang / Wolff leg (throughput and tau_int at T_c)")
     ap.add_argument("--cluster-steps", type=int, default=20)
@@ -370,6 +421,12 @@ def main():
         if args.critical_steps > 0:
             out["cluster"]["critical"] = critical_decorrelation(args.critical_steps, args.critical_steps,
                                                                 args.critical_sweeps)
+        torch.cuda.empty_cache()
+    if not args.no_3d:
+        torch.cuda.empty_cache()
+        out["cubic"] = cubic_leg(args.cubic_sweeps)
+        if not args.no_cpu_baseline:
+            out["cubic"]["cpu_baseline"] = cubic_cpu_baseline()
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps, rng)

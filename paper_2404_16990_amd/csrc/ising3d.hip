@@ -106,6 +106,34 @@ __device__ __forceinline__ uint32_t flip_mask32_3d(uint32_t s, const uint32_t (&
     return cl.ge3 | acc;
 }
 
+// Update NW words idx0, idx0 + 256, ... of colour c: every neighbour word of
+// all NW words is loaded before the first update (the planes do not alias),
+// so the loads of a thread are in flight together.
+template <int NW>
+__device__ __forceinline__ void sweep_words(const uint32_t *__restrict__ src, uint32_t *__restrict__ tgt,
+                                            uint32_t idx0, uint32_t colour, uint32_t t, const Rep3Dev &d)
+{
+    uint32_t s[NW], n[NW][6], q0[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const uint32_t idx = idx0 + 256u * k;
+        const Neigh3 nb = neigh3(d, idx, colour);
+        const uint32_t same = src[nb.same];
+        n[k][0] = src[nb.ym];
+        n[k][1] = src[nb.yp];
+        n[k][2] = src[nb.zm];
+        n[k][3] = src[nb.zp];
+        n[k][4] = same;
+        n[k][5] = side_word<uint32_t>(same, src[nb.nb], nb.p);
+        s[k] = tgt[idx];
+        const uint32_t row = idx / d.W, w = idx - row * d.W;
+        q0[k] = row * (d.Lx >> 3) + 8u * w;  // (row * Lx / 2 + 32 w) / 4
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+        tgt[idx0 + 256u * k] = s[k] ^ flip_mask32_3d(s[k], n[k], q0[k], t, colour, d);
+}
+
 // ---------------------------------------------------------------------------
 // one colour of one sweep of every replica: grid = blocks of all replicas;
 // workgroup b handles k3WordsPerBlock consecutive words of its replica's
@@ -113,6 +141,7 @@ __device__ __forceinline__ uint32_t flip_mask32_3d(uint32_t s, const uint32_t (&
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k3_sweep(Sweep3Args a, uint32_t colour, uint32_t sweep_off)
 {
+    constexpr int NW = k3WordsPerBlock / 256;
     const uint32_t r = block_owner(a.prefix, a.n, blockIdx.x);
     const Rep3Dev d = a.reps[r];
     const uint32_t words = d.Lz * d.Ly * d.W;
@@ -120,24 +149,12 @@ __global__ __launch_bounds__(256) void k3_sweep(Sweep3Args a, uint32_t colour, u
     uint32_t *tgt = d.plane0 + (colour ? (size_t)words : 0);
     const uint32_t *src = d.plane0 + (colour ? 0 : (size_t)words);
     const uint32_t t = d.t + sweep_off;
-    for (uint32_t i = threadIdx.x; i < k3WordsPerBlock; i += 256) {
-        const uint32_t idx = first + i;
-        if (idx >= words)
-            break;
-        const Neigh3 nb = neigh3(d, idx, colour);
-        const uint32_t same = src[nb.same];
-        uint32_t n[6];
-        n[0] = src[nb.ym];
-        n[1] = src[nb.yp];
-        n[2] = src[nb.zm];
-        n[3] = src[nb.zp];
-        n[4] = same;
-        n[5] = side_word<uint32_t>(same, src[nb.nb], nb.p);
-        const uint32_t s = tgt[idx];
-        const uint32_t row = idx / d.W, w = idx - row * d.W;
-        const uint32_t q0 = row * (d.Lx >> 3) + 8u * w;  // (row * Lx / 2 + 32 w) / 4
-        tgt[idx] = s ^ flip_mask32_3d(s, n, q0, t, colour, d);
+    if (first + k3WordsPerBlock <= words) {
+        sweep_words<NW>(src, tgt, first + threadIdx.x, colour, t, d);
+        return;
     }
+    for (uint32_t idx = first + threadIdx.x; idx < words; idx += 256)  // the last, partial block
+        sweep_words<1>(src, tgt, idx, colour, t, d);
 }
 
 // initial states: both colour planes, same block mapping

@@ -164,7 +164,7 @@ SW_SLOTS_PER_SITE = 1.5 * PHILOX_SLOTS
 SW_BYTES_PER_SITE = 4.0 + 4.0 + (1.5 + 1.0 + 1.0) / 8.0
 
 
-def cubic_leg(sweeps, warmup=3):
+def cubic_leg(sweeps, warmup=10):
     """3D sweeps of the 16 x 256^3 workload: flip attempts per second, the
     sweep kernel's roofline (the same derived ALU peak per flip attempt as in
     2D: a quarter Philox call, one compare, one bit insert) and the oracle's
@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--plain-sweeps", type=int, default=500000)
     ap.add_argument("--tune-sweeps", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D (simple cubic) leg")
-    ap.add_argument("--cubic-sweeps", type=int, default=50)
+    ap.add_argument("--cubic-sweeps", type=int, default=200)
     ap.add_argument("--no-cluster", action="store_true",
                     help="skip the Swendsen-Wang / Wolff leg (throughput and tau_int at T_c)")
     ap.add_argument("--cluster-steps", type=int, default=20)

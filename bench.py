@@ -196,6 +196,11 @@ def cubic_leg(sweeps, warmup=10):
            "roofline": {"bound": "alu", "kernel": "k3_sweep", "achieved": flips / 1e9, "peak": peak / 1e9,
                         "unit": "Gflip/s", "frac": flips / peak, "traffic": None, "launch_ms": ms / 2,
                         "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt"}}
+    from paper_2404_16990_amd import probe
+    ceiling = probe.mix3_rate()
+    out["roofline"]["measured_alu_ceiling"] = {
+        "value": ceiling / 1e9, "unit": "Gflip/s", "frac": flips / ceiling,
+        "kernel": "k_mix3 (ising::flip_mask32_3d on register-resident words)"}
     return out
 
 

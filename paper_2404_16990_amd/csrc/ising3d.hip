@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "device3.hpp"
 #include "ising3d.hpp"
 
 namespace ising {
@@ -53,59 +54,6 @@ __device__ __forceinline__ Neigh3 neigh3(const Rep3Dev &d, uint32_t idx, uint32_
     return n;
 }
 
-// Classes of the 32 sites of a word by the number a of anti-aligned
-// neighbours among six, counted by full adders: a >= 3 (dE <= 0), a = 2
-// (dE = 4J), a = 1 (dE = 8J); the rest (a = 0) have dE = 12J.
-struct Classes3 {
-    uint32_t ge3, eq2, eq1;
-};
-
-__device__ __forceinline__ Classes3 classify6(uint32_t s, const uint32_t (&n)[6])
-{
-    const uint32_t a0 = s ^ n[0], a1 = s ^ n[1], a2 = s ^ n[2];
-    const uint32_t a3 = s ^ n[3], a4 = s ^ n[4], a5 = s ^ n[5];
-    const uint32_t s1 = __builtin_amdgcn_bitop3_b32(a0, a1, a2, 0x96), c1 = __builtin_amdgcn_bitop3_b32(a0, a1, a2, 0xE8);
-    const uint32_t s2 = __builtin_amdgcn_bitop3_b32(a3, a4, a5, 0x96), c2 = __builtin_amdgcn_bitop3_b32(a3, a4, a5, 0xE8);
-    const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;  // a = b0 + 2 (c1 + c2 + k0)
-    const uint32_t b1 = __builtin_amdgcn_bitop3_b32(c1, c2, k0, 0x96), b2 = __builtin_amdgcn_bitop3_b32(c1, c2, k0, 0xE8);
-    Classes3 c;
-    c.ge3 = b2 | (b1 & b0);
-    c.eq2 = ~b2 & b1 & ~b0;
-    c.eq1 = ~b2 & ~b1 & b0;
-    return c;
-}
-
-// Sites to flip in a colour-c word (site contract: site 32 w + b of the row
-// draws word (h & 3) of call h >> 2, h = row * Lx / 2 + 32 w + b; q0 is the
-// call of bit 0).  The threshold of a site is selected from its class bits
-// with two v_bitop3 (eq2 ? thr4 : eq1 ? thr8 : thr12) and compared into a lane
-// mask that is shifted into the accumulator as a carry (bits 31 down to 0).
-__device__ __forceinline__ uint32_t flip_mask32_3d(uint32_t s, const uint32_t (&n)[6], uint32_t q0, uint32_t t,
-                                                   uint32_t colour, const Rep3Dev &d)
-{
-    if (d.always)
-        return ~0u;
-    const Classes3 cl = classify6(s, n);
-    const uint32_t thr4 = __builtin_amdgcn_readfirstlane(d.thr4), thr8 = __builtin_amdgcn_readfirstlane(d.thr8);
-    const uint32_t thr12 = __builtin_amdgcn_readfirstlane(d.thr12);
-    uint32_t acc = 0;
-#pragma unroll
-    for (int q = 7; q >= 0; --q) {
-        uint32_t r[4];
-        philox4x32_10(q0 + q, t, d.replica, colour, d.seed_lo, d.seed_hi, r);
-#pragma unroll
-        for (int j = 3; j >= 0; --j) {
-            const int b = 4 * q + j;
-            const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)cl.eq2, b, 1);
-            const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int32_t)cl.eq1, b, 1);
-            const uint32_t thr = __builtin_amdgcn_bitop3_b32(m2, thr4, __builtin_amdgcn_bitop3_b32(m1, thr8, thr12, 0xCA),
-                                                             0xCA);
-            acc = shift_in_carry(acc, __builtin_amdgcn_uicmp(r[j], thr, 36 /* unsigned < */));
-        }
-    }
-    return cl.ge3 | acc;
-}
-
 // Update NW words idx0, idx0 + 256, ... of colour c: every neighbour word of
 // all NW words is loaded before the first update (the planes do not alias),
 // so the loads of a thread are in flight together.
@@ -131,7 +79,7 @@ __device__ __forceinline__ void sweep_words(const uint32_t *__restrict__ src, ui
     }
 #pragma unroll
     for (int k = 0; k < NW; ++k)
-        tgt[idx0 + 256u * k] = s[k] ^ flip_mask32_3d(s[k], n[k], q0[k], t, colour, d);
+        tgt[idx0 + 256u * k] = s[k] ^ flip_mask32_3d(s[k], n[k], q0[k], key3(d, t, colour));
 }
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "device.hpp"
+#include "device3.hpp"
 
 namespace {
 
@@ -171,6 +172,32 @@ __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int i
     out[tid] = (uint32_t)s ^ (uint32_t)((uint64_t)s >> 32);
 }
 
+// The 3D sweep's per-word arithmetic (six-input classification, Philox,
+// three-threshold acceptance) on register-resident words.
+__global__ __launch_bounds__(256) void k_mix3(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8,
+                                              uint32_t thr12)
+{
+    const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
+    ising::Key3 K;
+    K.k0 = seed;
+    K.k1 = seed * 3u + 1u;
+    K.t = 0;
+    K.replica = blockIdx.x;
+    K.colour = 1u;
+    K.thr4 = thr4;
+    K.thr8 = thr8;
+    K.thr12 = thr12;
+    K.always = 0u;
+    uint32_t s = tid * 0x9E3779B9u;
+    uint32_t n[6] = {tid * 0xC2B2AE3Du, tid * 0x165667B1u, tid * 0x27D4EB2Fu, tid * 0x85EBCA77u, tid * 0x7FEB352Du,
+                     tid * 0x846CA68Bu};
+    for (int i = 0; i < iters; ++i) {
+        K.t = (uint32_t)i;
+        s ^= ising::flip_mask32_3d(s, n, (tid + (uint32_t)i * 0x100000u) * 8u, K);
+    }
+    out[tid] = s;
+}
+
 __global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16)
 {
     for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
@@ -208,6 +235,30 @@ hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
 }  // namespace
 
 extern "C" {
+
+/* Measured ALU ceiling of the 3D sweep's per-word arithmetic: k_mix3 over
+ * blocks x 256 threads x iters words of 32 sites; *ms = kernel time. */
+int ising_probe_mix3(void *out, int blocks, int iters, unsigned thr4, unsigned thr8, unsigned thr12, float *ms)
+{
+    if (!out || !ms || blocks <= 0 || iters <= 0)
+        return -1;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return -4;
+    uint32_t *o = static_cast<uint32_t *>(out);
+    hipLaunchKernelGGL(k_mix3, dim3(blocks), dim3(256), 0, nullptr, o, 777u, iters, thr4, thr8, thr12);
+    hipError_t st = hipEventRecord(e0, nullptr);
+    hipLaunchKernelGGL(k_mix3, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8, thr12);
+    if (st == hipSuccess)
+        st = hipEventRecord(e1, nullptr);
+    if (st == hipSuccess)
+        st = hipEventSynchronize(e1);
+    if (st == hipSuccess)
+        st = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st == hipSuccess ? 0 : -4;
+}
 
 /* Measured ALU ceiling of the sweep's per-word arithmetic: k_mix with 32- or
  * 64-bit words on blocks x 256 threads for iters iterations (after a warm-up

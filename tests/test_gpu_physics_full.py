@@ -125,3 +125,51 @@ def test_largest_lattice_exact_properties():
         b.close()
         del b
         torch.cuda.empty_cache()
+
+
+def test_batch_256x1024_swendsen_wang_matches_onsager_and_yang():
+    """Swendsen-Wang steps of the benchmark batch (256 x 1024^2, random
+    starts).  Cluster steps equilibrate in a few dozen steps at every
+    temperature, including below T_c where single-spin sweeps from a random
+    start are stuck in domains, so 400 steps (the second half averaged) pin
+    the energy to Onsager and |m| to Yang on both sides of T_c."""
+    import torch
+    import paper_2404_16990_amd as P
+    w = workloads.batch_256x1024()
+    b = P.Batch([dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+                 for r in w.replicas])
+    bond, mag = b.cluster(400, "sw", 1)
+    torch.cuda.synchronize()
+    n = float(1024 * 1024)
+    e = -bond.cpu().numpy().astype(np.float64) / n
+    m = mag.cpu().numpy().astype(np.float64) / n
+    b.ws = None
+    b.close()
+    assert _check(w, e, m, above=2.45, below=2.15) >= 200
+
+
+def test_cubic_series_on_the_gpu():
+    """3D sweeps on 8 x 128 x 96 x 96 lattices against the high-temperature series
+    <s s'> = t + 4 t^3 + O(t^5) at T = 12 and the low-temperature
+    magnetisation 1 - 2 u^6 - 12 u^10 + O(u^12) of cold starts at T = 2."""
+    import torch
+    import paper_2404_16990_amd as P
+    Lx, L = 128, 96
+    hot = [dict(Lx=Lx, Ly=L, Lz=L, J=1.0, beta=1.0 / 12.0, seed=900 + r, replica=r, init=0) for r in range(8)]
+    cold = [dict(Lx=Lx, Ly=L, Lz=L, J=1.0, beta=0.5, seed=950 + r, replica=8 + r, init=1) for r in range(8)]
+    b = P.Batch3(hot + cold)
+    bond, mag = b.run(600, 1)
+    torch.cuda.synchronize()
+    b.close()
+    N = float(Lx * L * L)
+    ss = bond.cpu().numpy()[:8, 100:].astype(np.float64) / (3 * N)
+    per = ss.mean(axis=1)
+    mean, err = per.mean(), per.std(ddof=1) / math.sqrt(8)
+    t = math.tanh(1.0 / 12.0)
+    assert abs(mean - (t + 4 * t ** 3)) < 40 * t ** 5 + 4 * err, (mean, t + 4 * t ** 3, err)
+    mm = mag.cpu().numpy()[8:, 50:].astype(np.float64) / N
+    per = mm.mean(axis=1)
+    mean, err = per.mean(), per.std(ddof=1) / math.sqrt(8)
+    u = math.exp(-1.0)
+    series = 1 - 2 * u ** 6 - 12 * u ** 10
+    assert abs(mean - series) < 20 * u ** 12 + 4 * err, (mean, series, err)

@@ -36,7 +36,7 @@ class Desc(ctypes.Structure):
 class Desc3(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("J", ctypes.c_double), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint32), ("pad", ctypes.c_int32)]
+                ("replica", ctypes.c_uint32), ("rng", ctypes.c_int32)]
 
 
 _lib = None
@@ -263,8 +263,9 @@ def run_cluster_batch(descs, states, n, algorithm=SWENDSEN_WANG, t0=None, record
 
 # ---- 3D (simple cubic, six neighbours) ---------------------------------------
 
-def desc3(Lx, Ly, Lz, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM):
-    return Desc3(int(Lx), int(Ly), int(Lz), int(init), float(J), float(beta), int(seed), int(replica), 0)
+def desc3(Lx, Ly, Lz, J=1.0, beta=1.0, seed=0, replica=0, init=INIT_RANDOM, rng=RNG_SITE):
+    """rng: RNG_SITE or RNG_BITSLICED, as for desc()."""
+    return Desc3(int(Lx), int(Ly), int(Lz), int(init), float(J), float(beta), int(seed), int(replica), int(rng))
 
 
 def thresholds3(J, beta):

@@ -19,8 +19,12 @@
  *  - dE = 2 J s (sum of the six neighbours) in {-12, ..., 12} J; dE <= 0 and
  *    K = beta*J == 0 accept without a draw; otherwise dE = 4J, 8J, 12J accept
  *    iff r < thr_k = min(floor(exp(-4kK) 2^32), 2^32 - 1), k = 1, 2, 3.
- *  - r for the colour-c site g in sweep t: h = g >> 1, word (h & 3) of
- *    Philox(ctr = {h >> 2, t, replica, c}).
+ *  - r for the colour-c site g in sweep t, h = g >> 1: with rng = 0, word
+ *    (h & 3) of Philox(ctr = {h >> 2, t, replica, c}); with rng = 1 (the
+ *    bit-sliced contract of the 2D library, unchanged but for the 3D index),
+ *    the colour-c sites h = 32q .. 32q + 31 form group q with words W_k = word
+ *    (k & 3) of Philox(ctr = {8q + (k >> 2), t, replica, c}), k = 0..31, and
+ *    bit 31 - k of site 32q + b's uniform is bit b of W_k.
  *  - random initial state: s = +1 iff word (g & 3) of Philox(ctr = {g >> 2,
  *    0, replica, 2}) >= 2^31.
  *  - observables: B = sum s(x,y,z) (s(x+1,y,z) + s(x,y+1,z) + s(x,y,z+1)),
@@ -43,7 +47,7 @@ typedef struct {
     double J, beta;
     uint64_t seed;
     uint32_t replica;
-    int32_t pad;
+    int32_t rng; /* 0: one Philox word per site; 1: bit-sliced group words */
 } oracle3_desc;
 
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -59,6 +63,34 @@ static uint32_t word_of(const oracle3_desc *d, uint64_t index, uint32_t t, uint3
     key[1] = (uint32_t)(d->seed >> 32);
     oracle_philox4x32_10(ctr, key, out);
     return out[index & 3];
+}
+
+/* Uniform of colour-c site h under the bit-sliced contract; the 32 words of
+ * the last group used are cached (sites are visited in increasing h). */
+typedef struct {
+    int valid;
+    uint64_t q;
+    uint32_t t, colour;
+    uint32_t w[32];
+} group3;
+
+static uint32_t bitsliced_uniform3(const oracle3_desc *d, uint32_t colour, uint32_t t, uint64_t h, group3 *cache)
+{
+    const uint64_t q = h >> 5;
+    const uint32_t b = (uint32_t)(h & 31u);
+    uint32_t u = 0, k;
+    if (!cache->valid || cache->q != q || cache->t != t || cache->colour != colour) {
+        /* word k of the group is the site-stream word at index 32q + k */
+        for (k = 0; k < 32; ++k)
+            cache->w[k] = word_of(d, 32u * q + k, t, colour);
+        cache->valid = 1;
+        cache->q = q;
+        cache->t = t;
+        cache->colour = colour;
+    }
+    for (k = 0; k < 32; ++k)
+        u |= ((cache->w[k] >> b) & 1u) << (31u - k);
+    return u;
 }
 
 static uint32_t threshold_of(double p)
@@ -89,6 +121,8 @@ static int desc_ok(const oracle3_desc *d)
     if ((uint64_t)d->Lx * (uint64_t)d->Ly * (uint64_t)d->Lz > 0xffffffffull)
         return 0;
     if (oracle3_thresholds(d->J, d->beta, thr, &always) != O3_OK)
+        return 0;
+    if (d->rng != 0 && d->rng != 1)
         return 0;
     return d->init == O3_INIT_RANDOM || d->init == O3_INIT_UP || d->init == O3_INIT_DOWN;
 }
@@ -134,18 +168,27 @@ static void flip_colour(const oracle3_desc *d, int8_t *s, uint32_t t, int colour
 {
     const int32_t Lx = d->Lx, Ly = d->Ly, Lz = d->Lz;
     int32_t x, y, z;
+    group3 cache;
+    cache.valid = 0;
     for (z = 0; z < Lz; ++z)
         for (y = 0; y < Ly; ++y)
             for (x = 0; x < Lx; ++x) {
                 const int64_t g = ((int64_t)z * Ly + y) * Lx + x;
                 int32_t sum, dE;
+                uint32_t r;
                 if (((x + y + z) & 1) != colour)
                     continue;
                 sum = s[((int64_t)z * Ly + y) * Lx + (x + 1) % Lx] + s[((int64_t)z * Ly + y) * Lx + (x + Lx - 1) % Lx] +
                       s[((int64_t)z * Ly + (y + 1) % Ly) * Lx + x] + s[((int64_t)z * Ly + (y + Ly - 1) % Ly) * Lx + x] +
                       s[((int64_t)((z + 1) % Lz) * Ly + y) * Lx + x] + s[((int64_t)((z + Lz - 1) % Lz) * Ly + y) * Lx + x];
                 dE = 2 * s[g] * sum; /* units of J: -12 .. 12 in steps of 4 */
-                if (dE <= 0 || always || word_of(d, (uint64_t)g >> 1, t, (uint32_t)colour) < thr[dE / 4 - 1])
+                if (dE <= 0 || always) {
+                    s[g] = (int8_t)(-s[g]);
+                    continue;
+                }
+                r = d->rng == 1 ? bitsliced_uniform3(d, (uint32_t)colour, t, (uint64_t)g >> 1, &cache)
+                                : word_of(d, (uint64_t)g >> 1, t, (uint32_t)colour);
+                if (r < thr[dE / 4 - 1])
                     s[g] = (int8_t)(-s[g]);
             }
 }

@@ -12,6 +12,8 @@ physics fixes independently of the oracle's code:
 - the low-temperature series of the magnetisation of a cold start,
   m = 1 - 2 u^6 - 12 u^10 + O(u^12) with u = exp(-2 beta J) (one reversed
   spin breaks 6 bonds, two adjacent ones 10; 3 bond directions per site).
+The distribution and series pins run under both random-number contracts
+(rng = 0 one Philox word per site, rng = 1 bit-sliced group words).
 Seeds are fixed, so pass/fail is deterministic.
 """
 import math
@@ -75,12 +77,12 @@ def _zero_field(s):
     return (f == 0).all(axis=(-3, -2, -1))
 
 
-@pytest.mark.parametrize("T", [2.0, 4.5, 8.0])
-def test_2x2x2_states_chi2(T):
+@pytest.mark.parametrize("T,rng", [(2.0, 0), (4.5, 0), (8.0, 0), (2.0, 1), (4.5, 1)])
+def test_2x2x2_states_chi2(T, rng):
     """Every site of the 2x2x2 torus has three distinct neighbours, each
     joined by two bonds, so no local field vanishes and the chain is ergodic."""
     R = 1 << 15
-    descs = [oracle.desc3(2, 2, 2, beta=1.0 / T, seed=2020 + int(T * 10), replica=r) for r in range(R)]
+    descs = [oracle.desc3(2, 2, 2, beta=1.0 / T, seed=2020 + int(T * 10) + rng, replica=r, rng=rng) for r in range(R)]
     states = [oracle.init_state3(d) for d in descs]
     oracle.run_batch3(descs, states, 60)
     idx = np.array([int(((st.reshape(-1) < 0) * (1 << np.arange(8))).sum()) for st in states])
@@ -91,13 +93,13 @@ def test_2x2x2_states_chi2(T):
     assert pval > 1e-3, (chi2, dof, pval)
 
 
-@pytest.mark.parametrize("T", [3.0, 4.5, 7.0])
-def test_4x2x2_classes_chi2(T):
+@pytest.mark.parametrize("T,rng", [(3.0, 0), (4.5, 0), (7.0, 0), (4.5, 1)])
+def test_4x2x2_classes_chi2(T, rng):
     """(B, M) classes of the 4x2x2 torus; states in which every local field
     vanishes (a closed set for the checkerboard rule, which flips them without
     a draw) are excluded from both sides and their share bounded."""
     R = 1 << 15
-    descs = [oracle.desc3(4, 2, 2, beta=1.0 / T, seed=4040 + int(T * 10), replica=r) for r in range(R)]
+    descs = [oracle.desc3(4, 2, 2, beta=1.0 / T, seed=4040 + int(T * 10) + rng, replica=r, rng=rng) for r in range(R)]
     states = [oracle.init_state3(d) for d in descs]
     oracle.run_batch3(descs, states, 80)
     arr = np.array(states)
@@ -126,10 +128,10 @@ def test_square_lattice_series_control():
         assert abs(-exact.onsager_u(T) / 2 - (t + 2 * t ** 3)) < 6 * t ** 5
 
 
-@pytest.mark.parametrize("T", [10.0, 12.0])
-def test_high_temperature_series(T):
+@pytest.mark.parametrize("T,rng", [(10.0, 0), (12.0, 0), (12.0, 1)])
+def test_high_temperature_series(T, rng):
     L, R, n = 24, 8, 1500
-    descs = [oracle.desc3(L, L, L, beta=1.0 / T, seed=777 + int(T), replica=r) for r in range(R)]
+    descs = [oracle.desc3(L, L, L, beta=1.0 / T, seed=777 + int(T) + rng, replica=r, rng=rng) for r in range(R)]
     states = [oracle.init_state3(d) for d in descs]
     bond, _ = oracle.run_batch3(descs, states, n, record_every=1)
     ss = bond[:, 100:].astype(np.float64) / (3 * L ** 3)
@@ -142,11 +144,11 @@ def test_high_temperature_series(T):
     assert abs(mean - (t + 2 * t ** 3)) > 4 * err + 40 * t ** 5
 
 
-@pytest.mark.parametrize("T", [1.8, 2.0])
-def test_low_temperature_magnetisation(T):
+@pytest.mark.parametrize("T,rng", [(1.8, 0), (2.0, 0), (2.0, 1)])
+def test_low_temperature_magnetisation(T, rng):
     L, R, n = 24, 8, 1000
-    descs = [oracle.desc3(L, L, L, beta=1.0 / T, seed=555 + int(10 * T), replica=r, init=oracle.INIT_UP)
-             for r in range(R)]
+    descs = [oracle.desc3(L, L, L, beta=1.0 / T, seed=555 + int(10 * T) + rng, replica=r, init=oracle.INIT_UP,
+                          rng=rng) for r in range(R)]
     states = [oracle.init_state3(d) for d in descs]
     _, mag = oracle.run_batch3(descs, states, n, record_every=1)
     m = mag[:, 50:].astype(np.float64) / L ** 3
@@ -155,3 +157,22 @@ def test_low_temperature_magnetisation(T):
     u = math.exp(-2.0 / T)
     series = 1 - 2 * u ** 6 - 12 * u ** 10
     assert abs(mean - series) < 20 * u ** 12 + 4 * err, (mean, series, err, u ** 12)
+
+
+def test_contracts_agree_where_no_draw_is_made():
+    """At beta = 0 and beta = infinity no proposal draws a uniform, so both
+    random-number contracts give the same trajectory; at finite beta they
+    differ."""
+    for beta in (0.0, math.inf):
+        a = oracle.desc3(64, 4, 6, beta=beta, seed=12, rng=0)
+        b = oracle.desc3(64, 4, 6, beta=beta, seed=12, rng=1)
+        sa, sb = oracle.init_state3(a), oracle.init_state3(b)
+        oracle.sweeps3(a, sa, 5)
+        oracle.sweeps3(b, sb, 5)
+        np.testing.assert_array_equal(sa, sb)
+    a = oracle.desc3(64, 4, 6, beta=0.3, seed=12, rng=0)
+    b = oracle.desc3(64, 4, 6, beta=0.3, seed=12, rng=1)
+    sa, sb = oracle.init_state3(a), oracle.init_state3(b)
+    oracle.sweeps3(a, sa, 5)
+    oracle.sweeps3(b, sb, 5)
+    assert (sa != sb).any()

@@ -164,7 +164,7 @@ SW_SLOTS_PER_SITE = 1.5 * PHILOX_SLOTS
 SW_BYTES_PER_SITE = 4.0 + 4.0 + (1.5 + 1.0 + 1.0) / 8.0
 
 
-def cubic_leg(sweeps, warmup=10):
+def cubic_leg(sweeps, warmup=10, rng=0):
     """3D sweeps of the 16 x 256^3 workload: flip attempts per second, the
     sweep kernel's roofline (the same derived ALU peak per flip attempt as in
     2D: a quarter Philox call, one compare, one bit insert) and the oracle's
@@ -175,8 +175,8 @@ def cubic_leg(sweeps, warmup=10):
     import workloads
 
     w = workloads.cubic_16x256()
-    descs = [dict(Lx=r.Lx, Ly=r.Ly, Lz=r.Lz, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
-             for r in w.replicas]
+    descs = [dict(Lx=r.Lx, Ly=r.Ly, Lz=r.Lz, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init,
+                  rng=rng) for r in w.replicas]
     b = P.Batch3(descs)
     stream = b.stream
     b.run(warmup)
@@ -191,16 +191,16 @@ def cubic_leg(sweeps, warmup=10):
     flips = w.spins / (ms / 1e3)
     peak = alu_peak_flips()
     # each sweep is two k3_sweep launches (one per colour) of half the sites
-    out = {"workload": w.name, "spins": w.spins, "sweeps": sweeps, "value": flips, "unit": "flip attempts/s",
-           "ms_per_sweep": ms,
+    out = {"workload": w.name, "spins": w.spins, "sweeps": sweeps, "rng": [k for k, v in RNG_NAMES.items() if v == rng][0],
+           "value": flips, "unit": "flip attempts/s", "ms_per_sweep": ms,
            "roofline": {"bound": "alu", "kernel": "k3_sweep", "achieved": flips / 1e9, "peak": peak / 1e9,
                         "unit": "Gflip/s", "frac": flips / peak, "traffic": None, "launch_ms": ms / 2,
                         "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt"}}
     from paper_2404_16990_amd import probe
-    ceiling = probe.mix3_rate()
+    ceiling = probe.mix3_rate(rng=rng)
     out["roofline"]["measured_alu_ceiling"] = {
         "value": ceiling / 1e9, "unit": "Gflip/s", "frac": flips / ceiling,
-        "kernel": "k_mix3 (ising::flip_mask32_3d on register-resident words)"}
+        "kernel": f"k_mix3<rng={rng}> (the 3D per-word arithmetic on register-resident words)"}
     return out
 
 
@@ -430,6 +430,10 @@ def main():
     if not args.no_3d:
         torch.cuda.empty_cache()
         out["cubic"] = cubic_leg(args.cubic_sweeps)
+        vb = cubic_leg(args.cubic_sweeps, rng=RNG_NAMES["bitsliced"])
+        out["cubic"]["variants"] = {"rng_bitsliced": {k: vb[k] for k in ("value", "ms_per_sweep")}}
+        out["cubic"]["variants"]["rng_bitsliced"]["frac_of_derived_peak"] = vb["roofline"]["frac"]
+        out["cubic"]["variants"]["rng_bitsliced"]["measured_alu_ceiling"] = vb["roofline"]["measured_alu_ceiling"]
         if not args.no_cpu_baseline:
             out["cubic"]["cpu_baseline"] = cubic_cpu_baseline()
         torch.cuda.empty_cache()

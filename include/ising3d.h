@@ -15,8 +15,12 @@
  *  - dE = 2 J s (sum of the six neighbours); dE <= 0 and beta*J == 0 accept
  *    without a draw; dE = 4J, 8J, 12J accept iff r < thr_k =
  *    min(floor(exp(-4 k beta J) 2^32), 2^32 - 1), k = 1, 2, 3.
- *  - r of the colour-c site g in sweep t: word (h & 3) of
- *    Philox4x32-10(ctr = {h >> 2, t, replica, c}, key = seed), h = g >> 1.
+ *  - r of the colour-c site g in sweep t, h = g >> 1: under ISING_RNG_SITE
+ *    word (h & 3) of Philox4x32-10(ctr = {h >> 2, t, replica, c}, key = seed);
+ *    under ISING_RNG_BITSLICED the colour-c sites h = 32q .. 32q + 31 form
+ *    group q with words W_k = word (k & 3) of Philox(ctr = {8q + (k >> 2), t,
+ *    replica, c}), k = 0..31, and site 32q + b's uniform has bit 31 - k equal
+ *    to bit b of W_k (the 2D definition of ising.h on the 3D index).
  *  - init ISING_INIT_RANDOM: s = +1 iff word (g & 3) of Philox(ctr = {g >> 2,
  *    0, replica, 2}) >= 2^31; ISING_INIT_UP / ISING_INIT_DOWN: all +1 / -1.
  *  - observables: B = sum s(x,y,z) (s(x+1,y,z) + s(x,y+1,z) + s(x,y,z+1)),
@@ -41,8 +45,8 @@ extern "C" {
 /*
  * One 3D replica.  Lx a positive multiple of 64, Ly and Lz even and >= 2,
  * Lx*Ly*Lz < 2^32 (ISING_E_UNSUPPORTED otherwise); J finite and > 0, beta >= 0
- * or +infinity, init one of ISING_INIT_* (ISING_E_INVALID otherwise);
- * reserved must be 0.
+ * or +infinity, init one of ISING_INIT_*, rng ISING_RNG_SITE or
+ * ISING_RNG_BITSLICED (ISING_E_INVALID otherwise).
  */
 typedef struct {
     int32_t Lx, Ly, Lz;
@@ -50,7 +54,7 @@ typedef struct {
     double J, beta;
     uint64_t seed;
     uint32_t replica;
-    int32_t reserved;
+    int32_t rng;
 } ising3d_desc;
 
 typedef struct ising3d_batch ising3d_batch;

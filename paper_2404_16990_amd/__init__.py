@@ -49,7 +49,7 @@ ISING_CLUSTER_SWENDSEN_WANG, ISING_CLUSTER_WOLFF = 0, 1
 class ising3d_desc(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32), ("init", ctypes.c_int32),
                 ("J", ctypes.c_double), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("replica", ctypes.c_uint32), ("rng", ctypes.c_int32)]
 
 
 class ising_schedule(ctypes.Structure):
@@ -243,7 +243,7 @@ def _descs3(descs):
         else:
             arr[i] = ising3d_desc(int(d["Lx"]), int(d["Ly"]), int(d["Lz"]), int(d.get("init", 0)),
                                   float(d.get("J", 1.0)), float(d["beta"]), int(d["seed"]), int(d["replica"]),
-                                  int(d.get("reserved", 0)))
+                                  int(d.get("rng", 0)))
     return arr
 
 

@@ -26,7 +26,7 @@ __device__ __forceinline__ Key3 key3(const Rep3Dev &d, uint32_t t, uint32_t colo
     K.thr4 = d.thr4;
     K.thr8 = d.thr8;
     K.thr12 = d.thr12;
-    K.always = d.always;
+    K.always = d.flags & k3Always;
     return K;
 }
 
@@ -78,6 +78,45 @@ __device__ __forceinline__ uint32_t flip_mask32_3d(uint32_t s, const uint32_t (&
                                                              0xCA);
             acc = shift_in_carry(acc, __builtin_amdgcn_uicmp(r[j], thr, 36 /* unsigned < */));
         }
+    }
+    return cl.ge3 | acc;
+}
+
+// Sites to flip in a colour-c word under the bit-sliced contract: the word's
+// 32 sites are one group (counters c0 + m, m = 0..7, c0 = 8 x the word's
+// index in its plane), each site's uniform is compared with its threshold
+// (eq2: thr4, eq1: thr8, otherwise thr12) from the top bit down, and words are
+// drawn four at a time until no lane of the wave has an undecided site, so the
+// result equals the full comparison.
+__device__ __forceinline__ uint32_t flip_mask32_3d_bitsliced(uint32_t s, const uint32_t (&n)[6], uint32_t c0,
+                                                             const Key3 &K)
+{
+    if (K.always)
+        return ~0u;
+    const Classes3 cl = classify6(s, n);
+    const uint32_t thr4 = __builtin_amdgcn_readfirstlane(K.thr4), thr8 = __builtin_amdgcn_readfirstlane(K.thr8);
+    const uint32_t thr12 = __builtin_amdgcn_readfirstlane(K.thr12);
+    uint32_t und = ~cl.ge3, acc = 0;
+    if (thr4 == 0u)  // thr12 <= thr8 <= thr4 = 0: no proposal with dE > 0 is accepted
+        return cl.ge3;
+    if (__builtin_amdgcn_ballot_w64(und != 0u) == 0)
+        return cl.ge3;
+    for (int m = 0; m < 8; ++m) {
+        uint32_t w[4];
+        philox4x32_10(c0 + m, K.t, K.replica, K.colour, K.k0, K.k1, w);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * m + j;
+            const uint32_t m4 = 0u - ((thr4 >> (31 - k)) & 1u), m8 = 0u - ((thr8 >> (31 - k)) & 1u);
+            const uint32_t m12 = 0u - ((thr12 >> (31 - k)) & 1u);
+            // threshold bit k of every site: eq2 ? thr4 : eq1 ? thr8 : thr12
+            const uint32_t q = __builtin_amdgcn_bitop3_b32(cl.eq2, m4, __builtin_amdgcn_bitop3_b32(cl.eq1, m8, m12, 0xCA),
+                                                           0xCA);
+            acc |= und & ~w[j] & q;
+            und &= ~(w[j] ^ q);
+        }
+        if (__builtin_amdgcn_ballot_w64(und != 0u) == 0)
+            break;
     }
     return cl.ge3 | acc;
 }

@@ -57,7 +57,7 @@ __device__ __forceinline__ Neigh3 neigh3(const Rep3Dev &d, uint32_t idx, uint32_
 // Update NW words idx0, idx0 + 256, ... of colour c: every neighbour word of
 // all NW words is loaded before the first update (the planes do not alias),
 // so the loads of a thread are in flight together.
-template <int NW>
+template <int NW, bool BITSLICED>
 __device__ __forceinline__ void sweep_words(const uint32_t *__restrict__ src, uint32_t *__restrict__ tgt,
                                             uint32_t idx0, uint32_t colour, uint32_t t, const Rep3Dev &d)
 {
@@ -77,9 +77,15 @@ __device__ __forceinline__ void sweep_words(const uint32_t *__restrict__ src, ui
         const uint32_t row = idx / d.W, w = idx - row * d.W;
         q0[k] = row * (d.Lx >> 3) + 8u * w;  // (row * Lx / 2 + 32 w) / 4
     }
+    const Key3 K = key3(d, t, colour);
 #pragma unroll
-    for (int k = 0; k < NW; ++k)
-        tgt[idx0 + 256u * k] = s[k] ^ flip_mask32_3d(s[k], n[k], q0[k], key3(d, t, colour));
+    for (int k = 0; k < NW; ++k) {
+        const uint32_t idx = idx0 + 256u * k;
+        if constexpr (BITSLICED)
+            tgt[idx] = s[k] ^ flip_mask32_3d_bitsliced(s[k], n[k], 8u * idx, K);
+        else
+            tgt[idx] = s[k] ^ flip_mask32_3d(s[k], n[k], q0[k], K);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -97,12 +103,21 @@ __global__ __launch_bounds__(256) void k3_sweep(Sweep3Args a, uint32_t colour, u
     uint32_t *tgt = d.plane0 + (colour ? (size_t)words : 0);
     const uint32_t *src = d.plane0 + (colour ? 0 : (size_t)words);
     const uint32_t t = d.t + sweep_off;
+    // the contract is uniform per replica, hence per workgroup
+    const bool bitsliced = (d.flags & k3Bitsliced) != 0;
     if (first + k3WordsPerBlock <= words) {
-        sweep_words<NW>(src, tgt, first + threadIdx.x, colour, t, d);
+        if (bitsliced)
+            sweep_words<NW, true>(src, tgt, first + threadIdx.x, colour, t, d);
+        else
+            sweep_words<NW, false>(src, tgt, first + threadIdx.x, colour, t, d);
         return;
     }
-    for (uint32_t idx = first + threadIdx.x; idx < words; idx += 256)  // the last, partial block
-        sweep_words<1>(src, tgt, idx, colour, t, d);
+    for (uint32_t idx = first + threadIdx.x; idx < words; idx += 256) {  // the last, partial block
+        if (bitsliced)
+            sweep_words<1, true>(src, tgt, idx, colour, t, d);
+        else
+            sweep_words<1, false>(src, tgt, idx, colour, t, d);
+    }
 }
 
 // initial states: both colour planes, same block mapping

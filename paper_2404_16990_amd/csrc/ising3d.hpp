@@ -7,12 +7,14 @@
 
 namespace ising {
 
+enum : uint32_t { k3Always = 1u, k3Bitsliced = 2u };
+
 // Per-replica device descriptor (64 bytes); t is advanced on the device.
 struct Rep3Dev {
     uint32_t *plane0;          // colour-0 plane; colour-1 plane = plane0 + Lz * Ly * W
     uint32_t Lx, Ly, Lz, W;    // W = 32-bit words per colour row = Lx / 64
     uint32_t seed_lo, seed_hi, replica;
-    uint32_t always;           // 1 when beta*J == 0
+    uint32_t flags;            // bit 0: beta*J == 0 (every proposal accepted); bit 1: bit-sliced contract
     uint32_t thr4, thr8, thr12;
     uint32_t t;                // sweeps completed
     uint64_t N;                // Lx * Ly * Lz

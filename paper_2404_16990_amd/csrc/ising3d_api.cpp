@@ -51,8 +51,8 @@ int check3(const ising3d_desc &d, int32_t i)
         return fail(ISING_E_INVALID, "beta must be >= 0 (or +inf)" + at);
     if (d.init != ISING_INIT_RANDOM && d.init != ISING_INIT_UP && d.init != ISING_INIT_DOWN)
         return fail(ISING_E_INVALID, "unknown init mode" + at);
-    if (d.reserved != 0)
-        return fail(ISING_E_INVALID, "reserved must be 0" + at);
+    if (d.rng != ISING_RNG_SITE && d.rng != ISING_RNG_BITSLICED)
+        return fail(ISING_E_INVALID, "unknown random-number contract (rng)" + at);
     if (d.Lx <= 0 || d.Lx % 64 != 0)
         return fail(ISING_E_UNSUPPORTED, "Lx must be a positive multiple of 64" + at);
     if (d.Ly < 2 || d.Ly % 2 != 0 || d.Lz < 2 || d.Lz % 2 != 0)
@@ -177,7 +177,7 @@ int ising3d_batch_create(int32_t n, const ising3d_desc *d, void *dev_buf, size_t
         r.seed_hi = (uint32_t)(d[i].seed >> 32);
         r.replica = d[i].replica;
         const double K = d[i].beta * d[i].J;
-        r.always = K == 0.0 ? 1u : 0u;
+        r.flags = (K == 0.0 ? k3Always : 0u) | (d[i].rng == ISING_RNG_BITSLICED ? k3Bitsliced : 0u);
         r.thr4 = prob_threshold(std::exp(-4.0 * K));
         r.thr8 = prob_threshold(std::exp(-8.0 * K));
         r.thr12 = prob_threshold(std::exp(-12.0 * K));

@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int i
 
 // The 3D sweep's per-word arithmetic (six-input classification, Philox,
 // three-threshold acceptance) on register-resident words.
+template <bool BITSLICED>
 __global__ __launch_bounds__(256) void k_mix3(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8,
                                               uint32_t thr12)
 {
@@ -193,7 +194,8 @@ __global__ __launch_bounds__(256) void k_mix3(uint32_t *out, uint32_t seed, int 
                      tid * 0x846CA68Bu};
     for (int i = 0; i < iters; ++i) {
         K.t = (uint32_t)i;
-        s ^= ising::flip_mask32_3d(s, n, (tid + (uint32_t)i * 0x100000u) * 8u, K);
+        const uint32_t c = (tid + (uint32_t)i * 0x100000u) * 8u;
+        s ^= BITSLICED ? ising::flip_mask32_3d_bitsliced(s, n, c, K) : ising::flip_mask32_3d(s, n, c, K);
     }
     out[tid] = s;
 }
@@ -237,18 +239,26 @@ hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
 extern "C" {
 
 /* Measured ALU ceiling of the 3D sweep's per-word arithmetic: k_mix3 over
- * blocks x 256 threads x iters words of 32 sites; *ms = kernel time. */
-int ising_probe_mix3(void *out, int blocks, int iters, unsigned thr4, unsigned thr8, unsigned thr12, float *ms)
+ * blocks x 256 threads x iters words of 32 sites under contract rng (0 site,
+ * 1 bit-sliced); *ms = kernel time. */
+int ising_probe_mix3(void *out, int blocks, int iters, unsigned thr4, unsigned thr8, unsigned thr12, int rng,
+                     float *ms)
 {
-    if (!out || !ms || blocks <= 0 || iters <= 0)
+    if (!out || !ms || blocks <= 0 || iters <= 0 || (rng != 0 && rng != 1))
         return -1;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return -4;
     uint32_t *o = static_cast<uint32_t *>(out);
-    hipLaunchKernelGGL(k_mix3, dim3(blocks), dim3(256), 0, nullptr, o, 777u, iters, thr4, thr8, thr12);
+    auto launch = [&](uint32_t seed) {
+        if (rng)
+            hipLaunchKernelGGL(k_mix3<true>, dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8, thr12);
+        else
+            hipLaunchKernelGGL(k_mix3<false>, dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8, thr12);
+    };
+    launch(777u);
     hipError_t st = hipEventRecord(e0, nullptr);
-    hipLaunchKernelGGL(k_mix3, dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4, thr8, thr12);
+    launch(12345u);
     if (st == hipSuccess)
         st = hipEventRecord(e1, nullptr);
     if (st == hipSuccess)

@@ -66,7 +66,7 @@ def mix_rate(word_bits=64, blocks=256 * 16, iters=64, T=2.269185, rng=0):
     return blocks * 256 * iters * word_bits / (ms.value * 1e-3)
 
 
-def mix3_rate(blocks=256 * 16, iters=64, T=4.5115):
+def mix3_rate(blocks=256 * 16, iters=64, T=4.5115, rng=0):
     """Measured ALU ceiling of the 3D sweep's per-word arithmetic (flip
     attempts per second): k_mix3 runs ising::flip_mask32_3d on
     register-resident words with no memory traffic."""
@@ -74,11 +74,11 @@ def mix3_rate(blocks=256 * 16, iters=64, T=4.5115):
     import torch
     L = _lib()
     L.ising_probe_mix3.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_uint,
-                                   ctypes.c_uint, ctypes.POINTER(ctypes.c_float)]
+                                   ctypes.c_uint, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     thr = [min(int(math.floor(math.ldexp(math.exp(-4.0 * k / T), 32))), 2**32 - 1) for k in (1, 2, 3)]
     out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     ms = ctypes.c_float()
-    if L.ising_probe_mix3(out.data_ptr(), blocks, iters, thr[0], thr[1], thr[2], ctypes.byref(ms)) != 0:
+    if L.ising_probe_mix3(out.data_ptr(), blocks, iters, thr[0], thr[1], thr[2], int(rng), ctypes.byref(ms)) != 0:
         raise RuntimeError("mix3 probe failed")
     return blocks * 256 * iters * 32 / (ms.value * 1e-3)
 

@@ -151,12 +151,13 @@ def test_3d_layout_and_validation():
     assert P.ctypes.sizeof(P.ising3d_desc) == 48  # 4 int32, 3 x 8 bytes, 2 x 4 bytes
     one = P.ising3d_state_bytes([_d3()])
     assert one >= 2 * 64 * 4 * 6 // 8 and one % 256 == 0
-    assert P.ising3d_state_bytes([_d3(), _d3(Lx=128, Lz=2)]) > one
+    assert P.ising3d_state_bytes([_d3(), _d3(Lx=128, Lz=2), _d3(rng=P.ISING_RNG_BITSLICED)]) > one
     for kw, code in [(dict(Lx=96), P.ISING_E_UNSUPPORTED), (dict(Ly=3), P.ISING_E_UNSUPPORTED),
                      (dict(Lz=0), P.ISING_E_UNSUPPORTED), (dict(Lz=5), P.ISING_E_UNSUPPORTED),
                      (dict(Lx=65536, Ly=256, Lz=256), P.ISING_E_UNSUPPORTED),
                      (dict(J=0.0), P.ISING_E_INVALID), (dict(beta=-1.0), P.ISING_E_INVALID),
-                     (dict(init=5), P.ISING_E_INVALID), (dict(reserved=1), P.ISING_E_INVALID)]:
+                     (dict(init=5), P.ISING_E_INVALID), (dict(rng=2), P.ISING_E_INVALID),
+                     (dict(rng=-1), P.ISING_E_INVALID)]:
         with pytest.raises(P.IsingError) as e:
             P.ising3d_state_bytes([_d3(**kw)])
         assert e.value.code == code, kw

@@ -21,10 +21,13 @@ def _P():
     return P
 
 
-def _descs(shapes):
-    g = [dict(Lx=Lx, Ly=Ly, Lz=Lz, J=1.0, beta=beta, seed=seed, replica=i, init=init)
+def _descs(shapes, rng=0):
+    """rng: 0 or 1 for every replica, or None to alternate the two contracts."""
+    pick = (lambda i: i % 2) if rng is None else (lambda i: rng)
+    g = [dict(Lx=Lx, Ly=Ly, Lz=Lz, J=1.0, beta=beta, seed=seed, replica=i, init=init, rng=pick(i))
          for i, (Lx, Ly, Lz, beta, seed, init) in enumerate(shapes)]
-    o = [oracle.desc3(Lx, Ly, Lz, 1.0, beta, seed, i, init) for i, (Lx, Ly, Lz, beta, seed, init) in enumerate(shapes)]
+    o = [oracle.desc3(Lx, Ly, Lz, 1.0, beta, seed, i, init, rng=pick(i))
+         for i, (Lx, Ly, Lz, beta, seed, init) in enumerate(shapes)]
     return g, o
 
 
@@ -50,10 +53,11 @@ def test_initial_states():
     b.close()
 
 
+@pytest.mark.parametrize("rng", [0, 1])
 @pytest.mark.parametrize("beta", [0.1, 0.2216546, 0.3, 0.6])
-def test_shapes_full_trace(beta):
-    print(f"3d beta={beta}", flush=True)
-    g, o = _descs([(Lx, Ly, Lz, beta, 100 + i, 0) for i, (Lx, Ly, Lz) in enumerate(SHAPES)])
+def test_shapes_full_trace(beta, rng):
+    print(f"3d beta={beta} rng={rng}", flush=True)
+    g, o = _descs([(Lx, Ly, Lz, beta, 100 + i, 0) for i, (Lx, Ly, Lz) in enumerate(SHAPES)], rng)
     b = _P().Batch3(g)
     bond, mag = _run(b, 12, 1)
     states = [oracle.init_state3(d) for d in o]
@@ -65,10 +69,11 @@ def test_shapes_full_trace(beta):
     b.close()
 
 
-def test_special_temperatures():
+@pytest.mark.parametrize("rng", [0, 1])
+def test_special_temperatures(rng):
     shapes = [(64, 4, 4, 0.0, 7, 0), (128, 6, 2, math.inf, 8, 0), (64, 8, 8, math.inf, 9, 1),
               (64, 2, 2, math.inf, 10, 2), (64, 2, 2, 0.0, 11, 0)]
-    g, o = _descs(shapes)
+    g, o = _descs(shapes, rng)
     b = _P().Batch3(g)
     bond, mag = _run(b, 7, 1)
     states = [oracle.init_state3(d) for d in o]
@@ -83,7 +88,7 @@ def test_mixed_batch_split_runs_and_set_spins():
     rng = np.random.default_rng(3)
     shapes = [(int(64 * rng.integers(1, 4)), int(2 * rng.integers(1, 12)), int(2 * rng.integers(1, 12)),
                float(1.0 / rng.uniform(3.0, 7.0)), 500 + i, int(rng.integers(0, 3))) for i in range(30)]
-    g, o = _descs(shapes)
+    g, o = _descs(shapes, None)  # the two random-number contracts alternate
     P = _P()
     b = P.Batch3(g)
     states = [oracle.init_state3(d) for d in o]
@@ -105,18 +110,19 @@ def test_mixed_batch_split_runs_and_set_spins():
     b.close()
 
 
-def test_benchmark_batch_sampled():
+@pytest.mark.parametrize("rng", [0, 1])
+def test_benchmark_batch_sampled(rng):
     """The 3D benchmark batch (16 x 256^3, T from 3.5 to 5.5): 4 sweeps of the
     whole batch, three replicas compared in full with the oracle."""
     import workloads
     w = workloads.cubic_16x256()
-    g = [dict(Lx=r.Lx, Ly=r.Ly, Lz=r.Lz, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
+    g = [dict(Lx=r.Lx, Ly=r.Ly, Lz=r.Lz, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init, rng=rng)
          for r in w.replicas]
     b = _P().Batch3(g)
     bond, mag = _run(b, 4, 2)
     pick = [0, 7, 15]
     o = [oracle.desc3(w.replicas[i].Lx, w.replicas[i].Ly, w.replicas[i].Lz, w.replicas[i].J, w.replicas[i].beta,
-                      w.replicas[i].seed, w.replicas[i].replica, w.replicas[i].init) for i in pick]
+                      w.replicas[i].seed, w.replicas[i].replica, w.replicas[i].init, rng=rng) for i in pick]
     states = [oracle.init_state3(d) for d in o]
     ob, om = oracle.run_batch3(o, states, 4, record_every=2)
     np.testing.assert_array_equal(bond[pick], ob)

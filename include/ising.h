@@ -203,6 +203,9 @@ int ising_cluster_ws_bytes(ising_batch *b, size_t *bytes);
  *             other work may use it while the call's kernels run.
  *  record_every, dev_bond_trace, dev_mag_trace  as in ising_batch_run, with
  *             steps in place of sweeps.
+ * Whole chunks of 16 steps are captured once per (algorithm, workspace,
+ * traces) in a hipGraph and replayed; the trace slot of a step is computed on
+ * the device, so results do not depend on how a run is split into calls.
  * Errors: ISING_E_INVALID (NULL handle or workspace, misaligned workspace,
  * unknown algorithm, counter overflow), ISING_E_NOMEM (ws_bytes too small),
  * ISING_E_HIP.

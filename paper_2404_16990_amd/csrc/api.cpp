@@ -871,6 +871,7 @@ int ising_batch_destroy(ising_batch *b)
     if (!b)
         return ISING_OK;
     drop_graphs(b);
+    drop_cluster_graphs(b);
     if (b->ev_fork)
         (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join)

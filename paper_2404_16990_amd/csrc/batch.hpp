@@ -22,6 +22,20 @@ struct Layout {
     size_t total = 0;
 };
 
+// A captured chunk of cluster steps.
+struct ClGraphKey {
+    int32_t algorithm;
+    uint32_t steps;
+    char *ws;
+    int64_t *bond, *mag;
+    uint32_t every, n_rec;
+    bool operator<(const ClGraphKey &o) const
+    {
+        return std::tie(algorithm, steps, ws, bond, mag, every, n_rec) <
+               std::tie(o.algorithm, o.steps, o.ws, o.bond, o.mag, o.every, o.n_rec);
+    }
+};
+
 struct GraphKey {
     uint32_t sweeps;
     int64_t *bond, *mag;
@@ -44,6 +58,8 @@ uint32_t prob_threshold(double p);
 int cluster_setup(ising_batch *b, hipStream_t st);
 // Bond threshold of replica r after its beta changed (upload on st).
 int cluster_set_beta(ising_batch *b, int32_t r, hipStream_t st);
+// Destroy the batch's captured cluster-step chunks.
+void drop_cluster_graphs(ising_batch *b);
 
 }  // namespace ising
 
@@ -76,5 +92,6 @@ struct ising_batch {
     uint64_t cl_tiles = 0;             // tiles of the whole batch
     size_t cl_tb_off = 0;              // workspace offset of the crossing-bond masks
     size_t cl_ws_bytes = 0;            // workspace a cluster step needs
+    std::map<ising::ClGraphKey, hipGraphExec_t> cl_graphs;
 };
 

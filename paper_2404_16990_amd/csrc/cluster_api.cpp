@@ -35,7 +35,64 @@ void set_bond_threshold(ClRep &c, double J, double beta)
     c.thr2 = prob_threshold(std::exp(-2.0 * K));
 }
 
+// Steps per captured chunk: enough to amortise the launches of a step (four
+// cluster kernels and a recording kernel), few enough to keep capture cheap.
+constexpr uint32_t kClChunk = 16;
+
+// n steps (run-local offsets 0 .. n-1 from the device counters), the
+// recording of each, and the counter advance, enqueued on st.
+int enqueue_cluster_chunk(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, const RecArgs &rec,
+                          hipStream_t st)
+{
+    for (uint32_t j = 0; j < n; ++j) {
+        CL_HIP(launch_cluster_step(a, algorithm, j, st));
+        if (rec.every)
+            CL_HIP(launch_observables_rec(b->d_rep, (uint32_t)b->n, b->max_words, rec, j, st));
+    }
+    CL_HIP(launch_advance(b->d_rep, (uint32_t)b->n, n, st));
+    return ISING_OK;
+}
+
+int cluster_graph(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, const RecArgs &rec,
+                  hipGraphExec_t *out)
+{
+    const ClGraphKey key{algorithm, n, a.ws, rec.bond, rec.mag, rec.every, rec.n_rec};
+    auto it = b->cl_graphs.find(key);
+    if (it != b->cl_graphs.end()) {
+        *out = it->second;
+        return ISING_OK;
+    }
+    if (b->cl_graphs.size() >= 16)
+        drop_cluster_graphs(b);
+    CL_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int st = enqueue_cluster_chunk(b, a, algorithm, n, rec, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != ISING_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return fail(ISING_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess)
+        return fail(ISING_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    b->cl_graphs[key] = ex;
+    *out = ex;
+    return ISING_OK;
+}
+
 }  // namespace
+
+void ising::drop_cluster_graphs(ising_batch *b)
+{
+    for (auto &kv : b->cl_graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    b->cl_graphs.clear();
+}
 
 int ising::cluster_setup(ising_batch *b, hipStream_t st)
 {
@@ -107,31 +164,40 @@ int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uin
         if ((uint64_t)b->rep[r].t + n_steps > 0xffffffffull)
             return fail(ISING_E_INVALID, "step counter would reach 2^32");
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    uint32_t n_rec = 0;
+    RecArgs rec{nullptr, nullptr, 0u, 0u};
     if (record_every > 0 && dev_bond_trace && dev_mag_trace && n_steps / record_every > 0) {
-        n_rec = (uint32_t)(n_steps / record_every);
-        const uint64_t slots = (uint64_t)b->n * n_rec;
-        CL_HIP(launch_fill_i64(dev_bond_trace, slots, 0, hs));
-        CL_HIP(launch_fill_i64(dev_mag_trace, slots, 0, hs));
+        rec.bond = dev_bond_trace;
+        rec.mag = dev_mag_trace;
+        rec.every = record_every;
+        rec.n_rec = (uint32_t)(n_steps / record_every);
+        const uint64_t slots = (uint64_t)b->n * rec.n_rec;
+        CL_HIP(launch_fill_i64(rec.bond, slots, 0, hs));
+        CL_HIP(launch_fill_i64(rec.mag, slots, 0, hs));
     }
-    char *ws = static_cast<char *>(dev_ws);
+    CL_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, hs));
     ClArgs a;
     a.reps = b->d_rep;
     a.cl = b->d_cl;
     a.tile_prefix = b->d_tile_prefix;
     a.n = (uint32_t)b->n;
-    a.ws = ws;
-    a.tb = reinterpret_cast<uint4 *>(ws + b->cl_tb_off);
+    a.ws = static_cast<char *>(dev_ws);
+    a.tb = reinterpret_cast<uint4 *>(a.ws + b->cl_tb_off);
     a.tiles = (uint32_t)b->cl_tiles;
-    for (uint64_t i = 0; i < n_steps; ++i) {
-        CL_HIP(launch_cluster_step(a, algorithm, (uint32_t)i, hs));
-        if (n_rec && (i + 1) % record_every == 0) {
-            const uint64_t j = (i + 1) / record_every - 1;
-            CL_HIP(launch_observables(b->d_rep, (uint32_t)b->n, b->max_words, dev_bond_trace + j, dev_mag_trace + j,
-                                      hs, n_rec));
-        }
+    // whole chunks replay one captured graph; the rest is launched directly
+    const uint64_t full = n_steps / kClChunk, rem = n_steps % kClChunk;
+    if (full > 0) {
+        hipGraphExec_t ex = nullptr;
+        const int st = cluster_graph(b, a, algorithm, kClChunk, rec, &ex);
+        if (st != ISING_OK)
+            return st;
+        for (uint64_t i = 0; i < full; ++i)
+            CL_HIP(hipGraphLaunch(ex, hs));
     }
-    CL_HIP(launch_advance(b->d_rep, (uint32_t)b->n, (uint32_t)n_steps, hs));
+    if (rem > 0) {
+        const int st = enqueue_cluster_chunk(b, a, algorithm, (uint32_t)rem, rec, hs);
+        if (st != ISING_OK)
+            return st;
+    }
     for (int32_t r = 0; r < b->n; ++r)
         b->rep[r].t += (uint32_t)n_steps;
     return ISING_OK;

@@ -304,6 +304,50 @@ __global__ __launch_bounds__(256) void k_observables(const RepDev *__restrict__ 
     }
 }
 
+// Observables of the state after the run-local step i_run = t + step - t0 of
+// every replica, added to the trace slot (i_run + 1) / every - 1 when
+// (i_run + 1) % every == 0 (the slot is computed on the device, so a captured
+// chunk of steps records correctly on every replay).
+__global__ __launch_bounds__(256) void k_observables_rec(const RepDev *__restrict__ reps, RecArgs rec, uint32_t step)
+{
+    const uint32_t r = blockIdx.y;
+    const RepDev d = reps[r];
+    const uint32_t i_run = d.t + step - d.t0;
+    if (rec.every == 0u || ((i_run + 1u) % rec.every) != 0u || (i_run + 1u) / rec.every - 1u >= rec.n_rec)
+        return;
+    const uint64_t slot = (uint64_t)r * rec.n_rec + (i_run + 1u) / rec.every - 1u;
+    const uint32_t W = d.W, Ly = d.Ly;
+    const uint32_t *src = d.plane0;
+    const uint32_t *tgt = d.plane0 + Ly * W;
+    uint32_t anti = 0, pop = 0;
+    for (uint32_t idx = blockIdx.x * 256 + threadIdx.x; idx < Ly * W; idx += gridDim.x * 256) {
+        const uint32_t y = idx / W, w = idx - y * W;
+        const NeighIdx n = neigh_idx(y, w, Ly, W, 1u);
+        const uint32_t same = src[n.same];
+        const uint32_t side = side_word<uint32_t>(same, src[n.nb], n.p);
+        const uint32_t s = tgt[idx];
+        anti += anti_bonds<uint32_t>(s, src[n.up], src[n.dn], same, side);
+        pop += (uint32_t)(__popc(s) + __popc(same));
+    }
+    __shared__ int64_t red[2][4];
+    const int64_t a = wave_sum((int64_t)anti), m = wave_sum((int64_t)pop);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a;
+        red[1][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t db = -2 * (red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        int64_t dm = 2 * (red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        if (blockIdx.x == 0) {
+            db += 2 * (int64_t)d.N;
+            dm -= (int64_t)d.N;
+        }
+        atomicAdd(reinterpret_cast<unsigned long long *>(&rec.bond[slot]), (unsigned long long)db);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&rec.mag[slot]), (unsigned long long)dm);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // bookkeeping (graph-safe: plain kernels, no memset nodes)
 // ---------------------------------------------------------------------------
@@ -344,6 +388,14 @@ hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words
 {
     const uint32_t blocks = std::min<uint32_t>((max_words + 255u) / 256u, 2048u);
     hipLaunchKernelGGL(k_observables, dim3(blocks, n), dim3(256), 0, st, reps, bond, mag, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs &rec,
+                                  uint32_t step, hipStream_t st)
+{
+    const uint32_t blocks = std::min<uint32_t>((max_words + 255u) / 256u, 2048u);
+    hipLaunchKernelGGL(k_observables_rec, dim3(blocks, n), dim3(256), 0, st, reps, rec, step);
     return hipGetLastError();
 }
 

@@ -34,6 +34,10 @@ hipError_t launch_init(const RepDev *reps, const int32_t *modes, uint32_t n, uin
 // Adds replica r's (B, M) to bond[r * stride], mag[r * stride].
 hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words, int64_t *bond,
                               int64_t *mag, hipStream_t st, uint32_t stride = 1);
+// Adds replica r's (B, M) after step t + step to its trace slot if the step
+// is a recorded one (slot from the device counters t, t0; see RecArgs).
+hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs &rec,
+                                  uint32_t step, hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st);
 hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st);
 hipError_t launch_advance(RepDev *reps, uint32_t n, uint32_t delta, hipStream_t st);

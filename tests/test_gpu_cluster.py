@@ -258,3 +258,51 @@ def test_largest_lattice_exact_properties():
     b.close()
     del b
     torch.cuda.empty_cache()
+
+
+def test_captured_chunks_record_across_replays():
+    """40 SW steps (two replays of a captured 16-step chunk, then 8 direct
+    steps) recorded every 3 steps, then 20 Wolff steps recorded every 5: the
+    trace slots are computed on the device, so they continue across replays."""
+    shapes = [(128, 66, 0.44, 31, 0), (64, 64, 0.3, 32, 0), (192, 34, 0.7, 33, 1)]
+    g, o = _descs(shapes)
+    P = _P()
+    b = P.Batch(g)
+    states = [oracle.init_state(d) for d in o]
+    bond, mag = _gpu_cluster(b, 40, "sw", 3)
+    ob, om = oracle.run_cluster_batch(o, states, 40, oracle.SWENDSEN_WANG, record_every=3)
+    assert bond.shape == (3, 13)
+    np.testing.assert_array_equal(bond, ob)
+    np.testing.assert_array_equal(mag, om)
+    bond, mag = _gpu_cluster(b, 20, "wolff", 5)
+    ob, om = oracle.run_cluster_batch(o, states, 20, oracle.WOLFF, t0=40, record_every=5)
+    np.testing.assert_array_equal(bond, ob)
+    np.testing.assert_array_equal(mag, om)
+    _check_states(b, states)
+    b.close()
+
+
+def test_graph_replays_between_eager_calls():
+    """A captured chunk replayed several times with direct steps and sweeps
+    in between; every stage against the oracle."""
+    import torch
+    shapes = [(64, 34, 0.44, 41, 0), (128, 8, 0.5, 42, 2)]
+    g, o = _descs(shapes)
+    P = _P()
+    b = P.Batch(g)
+    states = [oracle.init_state(d) for d in o]
+    t = 0
+    for rnd in range(3):
+        _gpu_cluster(b, 16, "sw", 0)
+        oracle.run_cluster_batch(o, states, 16, oracle.SWENDSEN_WANG, t0=t)
+        t += 16
+        _check_states(b, states)
+        _gpu_cluster(b, 5, "sw", 0)
+        oracle.run_cluster_batch(o, states, 5, oracle.SWENDSEN_WANG, t0=t)
+        t += 5
+        b.run(2)
+        torch.cuda.synchronize()
+        oracle.run_batch(o, states, 2, t0=t)
+        t += 2
+        _check_states(b, states)
+    b.close()

@@ -86,18 +86,28 @@ __device__ __forceinline__ uint32_t run_start(uint64_t H, uint32_t j)
 
 // ---- union-find in LDS (tile-local indices r*64 + j) -----------------------
 // Parents only decrease (a root is linked to a smaller index by atomic min),
-// so every path is strictly decreasing and every loop below ends.
-__device__ __forceinline__ uint32_t lds_find(volatile uint32_t *L, uint32_t a)
+// so every path is strictly decreasing and every loop below ends.  The label
+// array is addressed through an LDS-typed pointer and read with relaxed
+// workgroup-scope atomic loads: ds_read, never cached in a register, never the
+// flat path.
+typedef __attribute__((address_space(3))) uint32_t lu32;
+
+__device__ __forceinline__ uint32_t lds_load(lu32 *p)
 {
-    uint32_t p = L[a];
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t lds_find(lu32 *L, uint32_t a)
+{
+    uint32_t p = lds_load(L + a);
     while (p != a) {
         a = p;
-        p = L[a];
+        p = lds_load(L + a);
     }
     return a;
 }
 
-__device__ __forceinline__ void lds_union(uint32_t *L, uint32_t a, uint32_t b)
+__device__ __forceinline__ void lds_union(lu32 *L, uint32_t a, uint32_t b)
 {
     for (;;) {
         a = lds_find(L, a);
@@ -109,7 +119,7 @@ __device__ __forceinline__ void lds_union(uint32_t *L, uint32_t a, uint32_t b)
             a = b;
             b = t;
         }
-        const uint32_t old = atomicMin(&L[b], a);
+        const uint32_t old = __hip_atomic_fetch_min(L + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == b)
             return;
         b = old;  // b was linked meanwhile: unite a with its new parent
@@ -117,12 +127,12 @@ __device__ __forceinline__ void lds_union(uint32_t *L, uint32_t a, uint32_t b)
 }
 
 // ---- union-find in the workspace (site indices of one replica) ------------
-__device__ __forceinline__ uint32_t ws_load(uint32_t *p)
+__device__ __forceinline__ uint32_t ws_load(gu32 *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t ws_find(uint32_t *G, uint32_t a)
+__device__ __forceinline__ uint32_t ws_find(gu32 *G, uint32_t a)
 {
     uint32_t p = ws_load(G + a);
     while (p != a) {
@@ -132,7 +142,7 @@ __device__ __forceinline__ uint32_t ws_find(uint32_t *G, uint32_t a)
     return a;
 }
 
-__device__ __forceinline__ void ws_union(uint32_t *G, uint32_t a, uint32_t b)
+__device__ __forceinline__ void ws_union(gu32 *G, uint32_t a, uint32_t b)
 {
     for (;;) {
         a = ws_find(G, a);
@@ -144,7 +154,7 @@ __device__ __forceinline__ void ws_union(uint32_t *G, uint32_t a, uint32_t b)
             a = b;
             b = t;
         }
-        const uint32_t old = atomicMin(G + b, a);
+        const uint32_t old = __hip_atomic_fetch_min(G + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == b)
             return;
         b = old;
@@ -153,7 +163,7 @@ __device__ __forceinline__ void ws_union(uint32_t *G, uint32_t a, uint32_t b)
 
 // Point every node on the path from p to its root at the root.  Runs when no
 // link changes any more; concurrent walkers only write the same root.
-__device__ __forceinline__ void ws_compress(uint32_t *G, uint32_t p)
+__device__ __forceinline__ void ws_compress(gu32 *G, uint32_t p)
 {
     uint32_t R = p, q = G[R];
     while (q != R) {
@@ -264,11 +274,11 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
     for (uint32_t rl = first; rl < first + kRowsPerWave && rl + 1 < T.rows; ++rl) {
         const uint64_t D = Dm[rl], implied = D & Hm[rl] & Hm[rl + 1];
         if (((D >> lane) & 1u) && !(lane > 0 && ((implied >> (lane - 1)) & 1u)))
-            lds_union(L, rl * 64 + lane, (rl + 1) * 64 + lane);
+            lds_union((lu32 *)L, rl * 64 + lane, (rl + 1) * 64 + lane);
     }
     __syncthreads();
     for (uint32_t rl = first; rl < first + kRowsPerWave && rl < T.rows; ++rl) {
-        const uint32_t root = lds_find(L, rl * 64 + lane);
+        const uint32_t root = lds_find((lu32 *)L, rl * 64 + lane);
         G[(size_t)(T.y0 + rl) * Lx + T.x0 + lane] = (T.y0 + (root >> 6)) * Lx + T.x0 + (root & 63u);
     }
     if (threadIdx.x == 0) {
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(256) void k_cl_cross(ClArgs a, uint32_t base)
     const uint32_t r = tile_owner(a.tile_prefix, a.n, b);
     const RepDev d = a.reps[r];
     const Tile T = locate(a, d, r, b);
-    uint32_t *G = reinterpret_cast<uint32_t *>(a.ws + a.cl[r].g_off);
+    gu32 *G = global_view(reinterpret_cast<uint32_t *>(a.ws + a.cl[r].g_off));
     const uint4 tb = a.tb[b];
     const uint64_t xd = tb.x | ((uint64_t)tb.y << 32);
     const uint64_t xr = tb.z | ((uint64_t)tb.w << 32);

@@ -69,13 +69,6 @@ __device__ __forceinline__ Tile locate(const ClArgs &a, const RepDev &d, uint32_
     return T;
 }
 
-// Spin bit (1 = up) of tile column j (0..63) in row y from that row's two
-// colour words: the site's colour is (j + y) & 1 and its compact bit j >> 1.
-__device__ __forceinline__ uint32_t tile_spin(uint32_t p0, uint32_t p1, uint32_t y, uint32_t j)
-{
-    return ((((j + y) & 1u) ? p1 : p0) >> (j >> 1)) & 1u;
-}
-
 // Position after the last break below column j of a row whose occupied
 // right-bond mask is H: the first column of j's horizontal run.
 __device__ __forceinline__ uint32_t run_start(uint64_t H, uint32_t j)
@@ -216,21 +209,25 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
         word = (plane1 ? P1 : P0)[(size_t)y * W + col];
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the bond draws
-    // Lane j draws the call of column pair j >> 1 in row 2i + (j & 1) of the
-    // wave: its four words are (right, down) of the even and of the odd column.
-    // The two lanes of a pair swap the halves they need.
+    // Lane j draws the call of column pair j & 31 (columns 2(j & 31) and
+    // 2(j & 31) + 1) in row 2i + (j >> 5) of the wave; its four words are the
+    // right and down bonds of the even and of the odd column.  Each of the four
+    // comparisons' ballots is then, in its low and high halves, the two rows'
+    // masks of that kind in compact order (bit k: column 2k, or 2k + 1).
     // Straight-line code (rows past the tile draw for its last rows and are
     // masked) keeps the load above in flight during the draws.
-    uint32_t occ[kRowsPerWave / 2];
+    uint64_t bre[kRowsPerWave / 2], bde[kRowsPerWave / 2], bro[kRowsPerWave / 2], bdo[kRowsPerWave / 2];
 #pragma unroll
     for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
-        const uint32_t row = T.y0 + min(first + 2 * i, T.rows - 2) + (lane & 1u);
-        const uint32_t g = row * Lx + T.x0 + (lane & ~1u);
+        const uint32_t row = T.y0 + min(first + 2 * i, T.rows - 2) + (lane >> 5);
+        const uint32_t g = row * Lx + T.x0 + 2u * (lane & 31u);
         uint32_t w[4];
         philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
-        const uint32_t bits = (uint32_t)(w[0] >= c.thr2) | ((uint32_t)(w[1] >= c.thr2) << 1) |
-                              ((uint32_t)(w[2] >= c.thr2) << 2) | ((uint32_t)(w[3] >= c.thr2) << 3);
-        occ[i] = (2 * i < nr && !c.none) ? bits : 0u;
+        const bool on = 2 * i < nr && !c.none;
+        bre[i] = __ballot(on && w[0] >= c.thr2);
+        bde[i] = __ballot(on && w[1] >= c.thr2);
+        bro[i] = __ballot(on && w[2] >= c.thr2);
+        bdo[i] = __ballot(on && w[3] >= c.thr2);
     }
     __builtin_amdgcn_sched_barrier(0);  // and the first use of its words after them
     uint32_t p0[kRowsPerWave + 1], p1[kRowsPerWave + 1], nxt[kRowsPerWave];
@@ -241,24 +238,35 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
         if (k < kRowsPerWave)
             nxt[k] = __builtin_amdgcn_readlane(word, R2 + k) & 1u;
     }
-    const uint32_t sel = (lane & 1u) * 2u;
+    // column order from a compact pair (odd << 32 | even): column j is bit
+    // (j & 1) * 32 + (j >> 1)
+    const uint32_t csh = ((lane & 1u) << 5) | (lane >> 1);
+    auto column_order = [&](uint32_t even, uint32_t odd) {
+        const uint64_t x = ((uint64_t)odd << 32) | even;
+        return __ballot((x >> csh) & 1u);
+    };
 #pragma unroll
     for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
         if (2 * i >= nr)
             break;
         const uint32_t rl = first + 2 * i, ya = T.y0 + rl;
-        const uint32_t yb = ya + 1, yc = yb + 1 == Ly ? 0u : yb + 1;
-        const uint32_t sa = tile_spin(p0[2 * i], p1[2 * i], ya, lane);
-        const uint32_t sb = tile_spin(p0[2 * i + 1], p1[2 * i + 1], yb, lane);
-        const uint32_t sc = tile_spin(p0[2 * i + 2], p1[2 * i + 2], yc, lane);
-        const uint32_t ra = lane < 63u ? tile_spin(p0[2 * i], p1[2 * i], ya, lane + 1) : nxt[2 * i];
-        const uint32_t rb = lane < 63u ? tile_spin(p0[2 * i + 1], p1[2 * i + 1], yb, lane + 1) : nxt[2 * i + 1];
-        const uint32_t other = (uint32_t)__shfl_xor((int)occ[i], 1, 64);
-        const uint32_t callA = (lane & 1u) ? other : occ[i], callB = (lane & 1u) ? occ[i] : other;
-        const uint64_t HA = __ballot(((callA >> sel) & 1u) && sa == ra);
-        const uint64_t DA = __ballot(((callA >> (sel + 1)) & 1u) && sa == sb);
-        const uint64_t HB = __ballot(((callB >> sel) & 1u) && sb == rb);
-        const uint64_t DB = __ballot(((callB >> (sel + 1)) & 1u) && sb == sc);
+        const uint32_t yb = ya + 1;
+        // a row's even columns have colour y & 1, its odd columns the other
+        const uint32_t ea = (ya & 1u) ? p1[2 * i] : p0[2 * i], oa = (ya & 1u) ? p0[2 * i] : p1[2 * i];
+        const uint32_t eb = (yb & 1u) ? p1[2 * i + 1] : p0[2 * i + 1], ob = (yb & 1u) ? p0[2 * i + 1] : p1[2 * i + 1];
+        // the row below b has the parity of yb + 1 (Ly is even, so also after wrapping)
+        const uint32_t ec = (yb & 1u) ? p0[2 * i + 2] : p1[2 * i + 2], oc = (yb & 1u) ? p1[2 * i + 2] : p0[2 * i + 2];
+        // aligned bonds in compact order: the right neighbour of column 2k is
+        // column 2k + 1 (odd bit k), that of column 2k + 1 is column 2k + 2
+        // (even bit k + 1, the next tile's column 0 for k = 31); the down
+        // neighbour of a column is the same column of the next row
+        const uint32_t hea = ~(ea ^ oa) & (uint32_t)bre[i], hoa = ~(oa ^ ((ea >> 1) | (nxt[2 * i] << 31))) & (uint32_t)bro[i];
+        const uint32_t dea = ~(ea ^ eb) & (uint32_t)bde[i], doa = ~(oa ^ ob) & (uint32_t)bdo[i];
+        const uint32_t heb = ~(eb ^ ob) & (uint32_t)(bre[i] >> 32);
+        const uint32_t hob = ~(ob ^ ((eb >> 1) | (nxt[2 * i + 1] << 31))) & (uint32_t)(bro[i] >> 32);
+        const uint32_t deb = ~(eb ^ ec) & (uint32_t)(bde[i] >> 32), dob = ~(ob ^ oc) & (uint32_t)(bdo[i] >> 32);
+        const uint64_t HA = column_order(hea, hoa), DA = column_order(dea, doa);
+        const uint64_t HB = column_order(heb, hob), DB = column_order(deb, dob);
         if (lane == 0) {
             Hm[rl] = HA;
             Dm[rl] = DA;

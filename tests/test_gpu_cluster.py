@@ -306,3 +306,34 @@ def test_graph_replays_between_eager_calls():
         t += 2
         _check_states(b, states)
     b.close()
+
+
+def test_uneven_512_and_paper_scale_sampled():
+    """Cluster steps of the uneven batch (512 replicas, 128^2 .. 8192^2; the
+    tile lookup crosses replicas of every size) and of the paper-scale batch
+    (754 x 512 x 528 cold starts, whose 528 rows leave a ragged 16-row tile,
+    plus one 16384 x 12288 lattice): one replica of every size compared in full
+    with the oracle, every replica's trace."""
+    import workloads
+    P = _P()
+    for w, algo, n in ((workloads.uneven_512(), "sw", 3), (workloads.paper_scale(), "wolff", 2)):
+        print(f"{w.name} {algo}", flush=True)
+        g = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init) for r in w.replicas]
+        b = P.Batch(g)
+        bond, mag = _gpu_cluster(b, n, algo, 1)
+        seen, idx = set(), []
+        for i, r in enumerate(w.replicas):
+            if (r.Lx, r.Ly) not in seen:
+                seen.add((r.Lx, r.Ly))
+                idx.append(i)
+        idx += [3, 100]  # two more replicas of common sizes
+        o = [oracle.desc(w.replicas[i].Lx, w.replicas[i].Ly, w.replicas[i].J, w.replicas[i].beta,
+                         w.replicas[i].seed, w.replicas[i].replica, w.replicas[i].init) for i in idx]
+        states = [oracle.init_state(d) for d in o]
+        ob, om = oracle.run_cluster_batch(o, states, n, ALGOS[algo], record_every=1)
+        np.testing.assert_array_equal(bond[idx], ob)
+        np.testing.assert_array_equal(mag[idx], om)
+        for k, i in enumerate(idx):
+            assert np.array_equal(b.get_spins(i), states[k]), (i, w.replicas[i].Lx, w.replicas[i].Ly)
+        b.ws = None
+        b.close()

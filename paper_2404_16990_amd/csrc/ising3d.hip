@@ -88,6 +88,72 @@ __device__ __forceinline__ void sweep_words(const uint32_t *__restrict__ src, ui
     }
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
+
+// Global-memory loads and stores at a 32-bit byte offset from a
+// workgroup-uniform base, so the address is the base register pair plus one
+// offset register.
+__device__ __forceinline__ u32x4 load4(const uint32_t *base, uint32_t byte_off)
+{
+    return *(const gu32x4 *)((const gchar *)base + byte_off);
+}
+
+__device__ __forceinline__ uint32_t load1(const uint32_t *base, uint32_t byte_off)
+{
+    return *(const gu32 *)((const gchar *)base + byte_off);
+}
+
+__device__ __forceinline__ void store4(uint32_t *base, uint32_t byte_off, u32x4 v)
+{
+    *(gu32x4 *)((gchar *)base + byte_off) = v;
+}
+
+// Update the four words idx .. idx + 3 of a colour-c row (W a multiple of 4,
+// idx a multiple of 4, so the four words share their row and their y and z
+// neighbour rows): one 16-byte load from each of the five other-colour rows
+// and from the target row, plus the one other-colour word beyond the quad on
+// the side its x neighbours reach out to.  Offsets are in bytes and stay below
+// 2^32 (a plane of N < 2^32 sites holds N / 16 bytes).
+template <bool BITSLICED>
+__device__ __forceinline__ void sweep_quad(const uint32_t *__restrict__ src, uint32_t *__restrict__ tgt, uint32_t idx,
+                                           uint32_t colour, uint32_t t, const Rep3Dev &d)
+{
+    const uint32_t W = d.W, Ly = d.Ly, Lz = d.Lz;
+    const uint32_t row = idx / W, w = idx - row * W;
+    const uint32_t z = row / Ly, y = row - z * Ly;
+    const uint32_t p = (colour + y + z) & 1u;
+    const uint32_t row_b = 4u * W, slab_b = Ly * row_b, off = 4u * idx;
+    const uint32_t off_ym = y == 0 ? off + (Ly - 1) * row_b : off - row_b;
+    const uint32_t off_yp = y + 1 == Ly ? off - (Ly - 1) * row_b : off + row_b;
+    const uint32_t off_zm = z == 0 ? off + (Lz - 1) * slab_b : off - slab_b;
+    const uint32_t off_zp = z + 1 == Lz ? off - (Lz - 1) * slab_b : off + slab_b;
+    // p = 1: the word after the quad (the row's first word after its last);
+    // p = 0: the word before it (the row's last word before its first)
+    const uint32_t off_x = p ? (w + 4 == W ? off + 16u - row_b : off + 16u) : (w == 0 ? off + row_b - 4u : off - 4u);
+    const u32x4 ym = load4(src, off_ym), yp = load4(src, off_yp), zm = load4(src, off_zm), zp = load4(src, off_zp);
+    const u32x4 same = load4(src, off), s = load4(tgt, off);
+    const uint32_t beyond = load1(src, off_x);
+    const Key3 K = key3(d, t, colour);
+    // word k's other x word: same[k + 1] (or beyond) for p = 1, same[k - 1] (or beyond) for p = 0
+    auto update = [&](uint32_t sk, uint32_t ymk, uint32_t ypk, uint32_t zmk, uint32_t zpk, uint32_t samek,
+                      uint32_t otherk, uint32_t k) {
+        const uint32_t n[6] = {ymk, ypk, zmk, zpk, samek, side_word<uint32_t>(samek, otherk, p)};
+        if constexpr (BITSLICED)
+            return sk ^ flip_mask32_3d_bitsliced(sk, n, 8u * (idx + k), K);
+        else
+            return sk ^ flip_mask32_3d(sk, n, 8u * (idx + k), K);
+    };
+    u32x4 out;
+    out.x = update(s.x, ym.x, yp.x, zm.x, zp.x, same.x, p ? same.y : beyond, 0);
+    out.y = update(s.y, ym.y, yp.y, zm.y, zp.y, same.y, p ? same.z : same.x, 1);
+    out.z = update(s.z, ym.z, yp.z, zm.z, zp.z, same.z, p ? same.w : same.y, 2);
+    out.w = update(s.w, ym.w, yp.w, zm.w, zp.w, same.w, p ? beyond : same.z, 3);
+    store4(tgt, off, out);
+}
+
 // ---------------------------------------------------------------------------
 // one colour of one sweep of every replica: grid = blocks of all replicas;
 // workgroup b handles k3WordsPerBlock consecutive words of its replica's
@@ -105,6 +171,19 @@ __global__ __launch_bounds__(256) void k3_sweep(Sweep3Args a, uint32_t colour, u
     const uint32_t t = d.t + sweep_off;
     // the contract is uniform per replica, hence per workgroup
     const bool bitsliced = (d.flags & k3Bitsliced) != 0;
+    if ((d.W & 3u) == 0) {
+        // rows of a multiple of four words: thread i takes the quad at
+        // first + 4 i (words is a multiple of 4, so a quad is whole or absent)
+        static_assert(k3WordsPerBlock == 4 * 256, "one quad per thread");
+        const uint32_t idx = first + 4u * threadIdx.x;
+        if (idx < words) {
+            if (bitsliced)
+                sweep_quad<true>(src, tgt, idx, colour, t, d);
+            else
+                sweep_quad<false>(src, tgt, idx, colour, t, d);
+        }
+        return;
+    }
     if (first + k3WordsPerBlock <= words) {
         if (bitsliced)
             sweep_words<NW, true>(src, tgt, first + threadIdx.x, colour, t, d);

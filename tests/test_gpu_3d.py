@@ -1,7 +1,8 @@
 """Bit-exact parity of the 3D (simple cubic) sweeps of the HIP library,
 through its C ABI, with the CPU oracle: states and (B, M) traces element by
 element for single lattices of many shapes (one and several words per row,
-Ly = 2 and Lz = 2 double bonds), the special temperatures, a batch of mixed
+rows of a multiple of four words through the quad path and the others word
+by word, Ly = 2 and Lz = 2 double bonds), the special temperatures, a batch of mixed
 shapes, split runs, spin round trips, and the full-size benchmark batch on
 sampled replicas; the largest lattice under exact properties."""
 import math
@@ -13,7 +14,11 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(64, 2, 2), (64, 4, 6), (128, 6, 4), (64, 64, 64), (192, 10, 14), (256, 2, 8), (64, 30, 2)]
+# W = Lx / 64 words per row: 1, 2 and 3 take the word-by-word path, multiples
+# of 4 the quad path (Ly = Lz = 2 double bonds, one and many quads per row,
+# a row of one quad, several workgroups with a partial last one)
+SHAPES = [(64, 2, 2), (64, 4, 6), (128, 6, 4), (64, 64, 64), (192, 10, 14), (256, 2, 8), (64, 30, 2),
+          (256, 2, 2), (256, 6, 10), (512, 4, 6), (768, 10, 4), (1024, 2, 2), (256, 64, 34)]
 
 
 def _P():
@@ -72,7 +77,7 @@ def test_shapes_full_trace(beta, rng):
 @pytest.mark.parametrize("rng", [0, 1])
 def test_special_temperatures(rng):
     shapes = [(64, 4, 4, 0.0, 7, 0), (128, 6, 2, math.inf, 8, 0), (64, 8, 8, math.inf, 9, 1),
-              (64, 2, 2, math.inf, 10, 2), (64, 2, 2, 0.0, 11, 0)]
+              (64, 2, 2, math.inf, 10, 2), (64, 2, 2, 0.0, 11, 0), (256, 4, 2, 0.0, 12, 1), (512, 2, 4, math.inf, 13, 0)]
     g, o = _descs(shapes, rng)
     b = _P().Batch3(g)
     bond, mag = _run(b, 7, 1)
@@ -86,7 +91,7 @@ def test_special_temperatures(rng):
 
 def test_mixed_batch_split_runs_and_set_spins():
     rng = np.random.default_rng(3)
-    shapes = [(int(64 * rng.integers(1, 4)), int(2 * rng.integers(1, 12)), int(2 * rng.integers(1, 12)),
+    shapes = [(int(64 * rng.choice([1, 2, 3, 4, 8])), int(2 * rng.integers(1, 12)), int(2 * rng.integers(1, 12)),
                float(1.0 / rng.uniform(3.0, 7.0)), 500 + i, int(rng.integers(0, 3))) for i in range(30)]
     g, o = _descs(shapes, None)  # the two random-number contracts alternate
     P = _P()

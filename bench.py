@@ -44,9 +44,10 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload_name):
+def measured_traffic(kernel, workload_name, sweeps_per_launch):
     """HBM bytes per launch from the committed counter summary, or None when the
-    summary is for another kernel/workload or the kernel sources changed since."""
+    summary is for another kernel/workload/launch length or the kernel sources
+    changed since."""
     path = os.path.join(ROOT, "profiles", "traffic_k_sweep_resident_batch256x1024.json")
     try:
         with open(path) as f:
@@ -57,7 +58,10 @@ def measured_traffic(kernel, workload_name):
         return None, None
     if not d["kernel"].startswith(kernel) or not d["workload"].startswith(workload_name):
         return None, None
-    return d["traffic_bytes_per_launch"], d["algorithmic_bytes_per_launch"]
+    e = d["by_sweeps_per_launch"].get(str(sweeps_per_launch))
+    if e is None:
+        return None, None
+    return e["traffic_bytes_per_launch"], d["algorithmic_bytes_per_launch"]
 
 
 def host_threads():
@@ -367,9 +371,9 @@ def main():
     sched = m["schedule"]
     peak = alu_peak_flips()
     traffic, algo_bytes = (None, None)
-    if rng == 0 and m["kernel"] == "k_sweep_resident" and sched["sweeps_per_launch"] == 50 \
-            and sched["resident_threads"] == 1024 and sched["word_bits"] == 64:
-        traffic, algo_bytes = measured_traffic(m["kernel"], work.name)
+    if rng == 0 and m["kernel"] == "k_sweep_resident" and sched["resident_threads"] == 1024 \
+            and sched["word_bits"] == 64:
+        traffic, algo_bytes = measured_traffic(m["kernel"], work.name, sched["sweeps_per_launch"])
     launch_s = m["launch_s"]
     roofline = {"bound": "alu", "kernel": m["kernel"], "achieved": m["achieved"] / 1e9, "peak": peak / 1e9,
                 "unit": "Gflip/s", "frac": m["achieved"] / peak, "traffic": traffic,

@@ -125,48 +125,100 @@ __device__ __forceinline__ uint32_t ws_load(gu32 *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t ws_find(gu32 *G, uint32_t a)
+// Union-find in the workspace, up to two unions or four path compressions per
+// lane stepped together: each step loads the next node of every walk at once,
+// so a lane waits for its longest walk instead of for the sum of them.
+// Inactive walks load a valid node (index 0 of the replica) and ignore it.
+//
+// ws_union2: unite A[k] and B[k] for every k with act[k]: find both roots,
+// link the larger to the smaller by atomic min; if the larger was linked
+// meanwhile, unite the smaller with its new parent.
+__device__ __forceinline__ void ws_union2(gu32 *G, uint32_t (&A)[2], uint32_t (&B)[2], bool (&act)[2])
 {
-    uint32_t p = ws_load(G + a);
-    while (p != a) {
-        a = p;
-        p = ws_load(G + a);
-    }
-    return a;
-}
-
-__device__ __forceinline__ void ws_union(gu32 *G, uint32_t a, uint32_t b)
-{
-    for (;;) {
-        a = ws_find(G, a);
-        b = ws_find(G, b);
-        if (a == b)
-            return;
-        if (a > b) {
-            const uint32_t t = a;
-            a = b;
-            b = t;
+    while (act[0] || act[1]) {
+        for (;;) {
+            uint32_t qa[2], qb[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                qa[k] = ws_load(G + A[k]);
+                qb[k] = ws_load(G + B[k]);
+            }
+            bool more = false;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (act[k] && qa[k] != A[k]) {
+                    A[k] = qa[k];
+                    more = true;
+                }
+                if (act[k] && qb[k] != B[k]) {
+                    B[k] = qb[k];
+                    more = true;
+                }
+            }
+            if (!more)
+                break;
         }
-        const uint32_t old = __hip_atomic_fetch_min(G + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b)
-            return;
-        b = old;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!act[k])
+                continue;
+            if (A[k] == B[k]) {
+                act[k] = false;
+                continue;
+            }
+            const uint32_t lo = min(A[k], B[k]), hi = max(A[k], B[k]);
+            const uint32_t old = __hip_atomic_fetch_min(G + hi, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old == hi) {
+                act[k] = false;
+            } else {  // hi was linked meanwhile: unite lo with its new parent
+                A[k] = lo;
+                B[k] = old;
+            }
+        }
     }
 }
 
-// Point every node on the path from p to its root at the root.  Runs when no
-// link changes any more; concurrent walkers only write the same root.
-__device__ __forceinline__ void ws_compress(gu32 *G, uint32_t p)
+// ws_compress4: point every node on the path from p[w] to its root at the root,
+// for every w with (mask >> w) & 1.  Runs when no link changes any more;
+// concurrent walkers only write the same root.
+__device__ __forceinline__ void ws_compress4(gu32 *G, uint32_t (&p)[4], uint32_t mask)
 {
-    uint32_t R = p, q = G[R];
-    while (q != R) {
-        R = q;
-        q = G[R];
+    uint32_t R[4];
+    bool go[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        R[w] = p[w];
+        go[w] = (mask >> w) & 1u;
     }
-    while (p != R) {
-        q = G[p];
-        G[p] = R;
-        p = q;
+    while (go[0] || go[1] || go[2] || go[3]) {
+        uint32_t q[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            q[w] = G[R[w]];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (go[w] && q[w] == R[w])
+                go[w] = false;
+            else if (go[w])
+                R[w] = q[w];
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        go[w] = ((mask >> w) & 1u) && p[w] != R[w];
+    while (go[0] || go[1] || go[2] || go[3]) {
+        uint32_t q[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            q[w] = G[p[w]];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (go[w]) {
+                G[p[w]] = R[w];
+                p[w] = q[w];
+                go[w] = p[w] != R[w];
+            }
+        }
     }
 }
 
@@ -338,37 +390,36 @@ __global__ __launch_bounds__(256) void k_cl_cross(ClArgs a, uint32_t base)
     const uint4 tb = a.tb[b];
     const uint64_t xd = tb.x | ((uint64_t)tb.y << 32);
     const uint64_t xr = tb.z | ((uint64_t)tb.w << 32);
+    // lane j: down bond j (edge 0) and right bond j of row j (edge 1)
+    const bool on0 = ((xd >> lane) & 1u) != 0, on1 = lane < T.rows && ((xr >> lane) & 1u);
+    const Crossing e0 = crossing(d, T, lane), e1 = crossing(d, T, 64u + min(lane, T.rows - 1));
     if (COMPRESS) {
-        if ((xd >> lane) & 1u) {
-            const Crossing e = crossing(d, T, lane);
-            ws_compress(G, e.a);
-            ws_compress(G, e.b);
-        }
-        if (lane < T.rows && ((xr >> lane) & 1u)) {
-            const Crossing e = crossing(d, T, 64u + lane);
-            ws_compress(G, e.a);
-            ws_compress(G, e.b);
-        }
+        uint32_t p[4] = {on0 ? e0.a : 0u, on0 ? e0.b : 0u, on1 ? e1.a : 0u, on1 ? e1.b : 0u};
+        ws_compress4(G, p, (on0 ? 3u : 0u) | (on1 ? 12u : 0u));
         return;
     }
     // Uniting the endpoints' current labels unites the endpoints.  Runs of
     // crossing bonds usually join the same two tile-local clusters, so a bond
     // whose label pair equals the previous lane's bond on the same edge is
     // already covered by that lane's union.
+    uint32_t A[2], B[2];
+    bool act[2];
 #pragma unroll
     for (int edge = 0; edge < 2; ++edge) {
-        const bool on = edge == 0 ? ((xd >> lane) & 1u) != 0 : (lane < T.rows && ((xr >> lane) & 1u));
+        const bool on = edge == 0 ? on0 : on1;
+        const Crossing &e = edge == 0 ? e0 : e1;
         uint32_t la = 0xffffffffu, lb = 0xffffffffu;
         if (on) {
-            const Crossing e = crossing(d, T, edge == 0 ? lane : 64u + lane);
             la = ws_load(G + e.a);
             lb = ws_load(G + e.b);
         }
         const uint32_t pa = (uint32_t)__shfl_up((int)la, 1, 64), pb = (uint32_t)__shfl_up((int)lb, 1, 64);
         const bool dup = lane > 0 && pa == la && pb == lb;
-        if (on && !dup)
-            ws_union(G, la, lb);
+        act[edge] = on && !dup;
+        A[edge] = act[edge] ? la : 0u;
+        B[edge] = act[edge] ? lb : 0u;
     }
+    ws_union2(G, A, B, act);
 }
 
 // ---------------------------------------------------------------------------

@@ -337,16 +337,35 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
             lds_union((lu32 *)L, rl * 64 + lane, (rl + 1) * 64 + lane);
     }
     __syncthreads();
-    for (uint32_t rl = first; rl < first + kRowsPerWave && rl < T.rows; ++rl) {
-        const uint32_t root = lds_find((lu32 *)L, rl * 64 + lane);
-        G[(size_t)(T.y0 + rl) * Lx + T.x0 + lane] = (T.y0 + (root >> 6)) * Lx + T.x0 + (root & 63u);
+    // roots of the wave's rows, the finds of all rows stepped together (no
+    // link changes any more; rows past the tile repeat its last row)
+    uint32_t X[kRowsPerWave];
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; ++k)
+        X[k] = (first + min(k, nr > 0 ? nr - 1 : 0u)) * 64 + lane;
+    for (bool more = nr > 0; more;) {
+        uint32_t q[kRowsPerWave];
+#pragma unroll
+        for (uint32_t k = 0; k < kRowsPerWave; ++k)
+            q[k] = L[X[k]];
+        more = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kRowsPerWave; ++k) {
+            more |= q[k] != X[k];
+            X[k] = q[k];
+        }
     }
-    if (threadIdx.x == 0) {
-        uint64_t xr = 0;
-        for (uint32_t rl = 0; rl < T.rows; ++rl)
-            xr |= (Hm[rl] >> 63) << rl;
-        const uint64_t xd = Dm[T.rows - 1];
-        a.tb[tile] = make_uint4((uint32_t)xd, (uint32_t)(xd >> 32), (uint32_t)xr, (uint32_t)(xr >> 32));
+#pragma unroll
+    for (uint32_t k = 0; k < kRowsPerWave; ++k)
+        if (k < nr)
+            G[(size_t)(T.y0 + first + k) * Lx + T.x0 + lane] = (T.y0 + (X[k] >> 6)) * Lx + T.x0 + (X[k] & 63u);
+    if (wv == 0) {
+        // right-edge crossing bonds: bit 63 of each row's horizontal mask
+        const uint64_t xr = __ballot(lane < T.rows && (Hm[lane] >> 63) != 0);
+        if (lane == 0) {
+            const uint64_t xd = Dm[T.rows - 1];
+            a.tb[tile] = make_uint4((uint32_t)xd, (uint32_t)(xd >> 32), (uint32_t)xr, (uint32_t)(xr >> 32));
+        }
     }
 }
 

@@ -480,6 +480,14 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k)
         R[k] = G[R[k]];
+    // Lane 2k + e (k < nr) owns row k's word of the colour its even (e = 0)
+    // or odd (e = 1) columns hold: colour y & 1 for the even columns.  Only
+    // this workgroup touches these words in this launch, so each is read once
+    // here and written once at the end with its row's flips.
+    const uint32_t my_row = lane >> 1, my_y = T.y0 + first + min(my_row, nr - 1);
+    gu32 *my_word = ((((my_y ^ lane) & 1u) != 0) ? P1 : P0) + (size_t)my_y * W + T.tx;
+    const uint32_t spins = lane < 2 * nr ? *my_word : 0u;
+    uint32_t my_flip = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kRowsPerWave; ++k) {
         bool flip;
@@ -493,19 +501,11 @@ __global__ __launch_bounds__(256) void k_cl_flip(ClArgs a, uint32_t step, uint32
             flip = (word >> (R[k] & 31u)) & 1u;
         }
         const uint64_t F = __ballot(flip);
-        if (k >= nr)
-            break;
-        // even columns hold colour y & 1, odd columns the other colour; only
-        // this workgroup touches these two words in this launch
-        const uint32_t y = T.y0 + first + k;
-        const uint32_t lo = (uint32_t)F, hi = (uint32_t)(F >> 32);
-        gu32 *pe = ((y & 1u) ? P1 : P0) + (size_t)y * W + T.tx;
-        gu32 *po = ((y & 1u) ? P0 : P1) + (size_t)y * W + T.tx;
-        if (lane == 0 && lo != 0u)
-            __hip_atomic_fetch_xor(pe, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (lane == 1 && hi != 0u)
-            __hip_atomic_fetch_xor(po, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (my_row == k)
+            my_flip = (lane & 1u) ? (uint32_t)(F >> 32) : (uint32_t)F;
     }
+    if (lane < 2 * nr && my_flip != 0u)
+        *my_word = spins ^ my_flip;
 }
 
 }  // namespace

@@ -261,35 +261,6 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
         word = (plane1 ? P1 : P0)[(size_t)y * W + col];
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the bond draws
-    // Lane j draws the call of column pair j & 31 (columns 2(j & 31) and
-    // 2(j & 31) + 1) in row 2i + (j >> 5) of the wave; its four words are the
-    // right and down bonds of the even and of the odd column.  Each of the four
-    // comparisons' ballots is then, in its low and high halves, the two rows'
-    // masks of that kind in compact order (bit k: column 2k, or 2k + 1).
-    // Straight-line code (rows past the tile draw for its last rows and are
-    // masked) keeps the load above in flight during the draws.
-    uint64_t bre[kRowsPerWave / 2], bde[kRowsPerWave / 2], bro[kRowsPerWave / 2], bdo[kRowsPerWave / 2];
-#pragma unroll
-    for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
-        const uint32_t row = T.y0 + min(first + 2 * i, T.rows - 2) + (lane >> 5);
-        const uint32_t g = row * Lx + T.x0 + 2u * (lane & 31u);
-        uint32_t w[4];
-        philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
-        const bool on = 2 * i < nr && !c.none;
-        bre[i] = __ballot(on && w[0] >= c.thr2);
-        bde[i] = __ballot(on && w[1] >= c.thr2);
-        bro[i] = __ballot(on && w[2] >= c.thr2);
-        bdo[i] = __ballot(on && w[3] >= c.thr2);
-    }
-    __builtin_amdgcn_sched_barrier(0);  // and the first use of its words after them
-    uint32_t p0[kRowsPerWave + 1], p1[kRowsPerWave + 1], nxt[kRowsPerWave];
-#pragma unroll
-    for (uint32_t k = 0; k <= kRowsPerWave; ++k) {
-        p0[k] = __builtin_amdgcn_readlane(word, k);
-        p1[k] = __builtin_amdgcn_readlane(word, R1 + k);
-        if (k < kRowsPerWave)
-            nxt[k] = __builtin_amdgcn_readlane(word, R2 + k) & 1u;
-    }
     // column order from a compact pair (odd << 32 | even): column j is bit
     // (j & 1) * 32 + (j >> 1)
     const uint32_t csh = ((lane & 1u) << 5) | (lane >> 1);
@@ -297,36 +268,76 @@ __global__ __launch_bounds__(256) void k_cl_local(ClArgs a, uint32_t step, uint3
         const uint64_t x = ((uint64_t)odd << 32) | even;
         return __ballot((x >> csh) & 1u);
     };
+    // Lane j draws the call of column pair j & 31 (columns 2(j & 31) and
+    // 2(j & 31) + 1) in row 2i + (j >> 5) of the wave; its four words are the
+    // right and down bonds of the even and of the odd column.  Each of the four
+    // comparisons' ballots is then, in its low and high halves, the two rows'
+    // masks of that kind in compact order (bit k: column 2k, or 2k + 1).
+    // Two halves of four row pairs: all bond draws of a half first (straight
+    // line; rows past the tile draw for its last rows and are masked, and the
+    // first half keeps the load above in flight), then its pairs, each reading
+    // the spin words it needs from the loaded lanes; a half's 16 ballots and a
+    // pair's words stay within the scalar registers (all 32 ballots plus all
+    // 50 words at once spill).
+    constexpr uint32_t HP = kRowsPerWave / 4;
 #pragma unroll
-    for (uint32_t i = 0; i < kRowsPerWave / 2; ++i) {
-        if (2 * i >= nr)
-            break;
-        const uint32_t rl = first + 2 * i, ya = T.y0 + rl;
-        const uint32_t yb = ya + 1;
-        // a row's even columns have colour y & 1, its odd columns the other
-        const uint32_t ea = (ya & 1u) ? p1[2 * i] : p0[2 * i], oa = (ya & 1u) ? p0[2 * i] : p1[2 * i];
-        const uint32_t eb = (yb & 1u) ? p1[2 * i + 1] : p0[2 * i + 1], ob = (yb & 1u) ? p0[2 * i + 1] : p1[2 * i + 1];
-        // the row below b has the parity of yb + 1 (Ly is even, so also after wrapping)
-        const uint32_t ec = (yb & 1u) ? p0[2 * i + 2] : p1[2 * i + 2], oc = (yb & 1u) ? p1[2 * i + 2] : p0[2 * i + 2];
-        // aligned bonds in compact order: the right neighbour of column 2k is
-        // column 2k + 1 (odd bit k), that of column 2k + 1 is column 2k + 2
-        // (even bit k + 1, the next tile's column 0 for k = 31); the down
-        // neighbour of a column is the same column of the next row
-        const uint32_t hea = ~(ea ^ oa) & (uint32_t)bre[i], hoa = ~(oa ^ ((ea >> 1) | (nxt[2 * i] << 31))) & (uint32_t)bro[i];
-        const uint32_t dea = ~(ea ^ eb) & (uint32_t)bde[i], doa = ~(oa ^ ob) & (uint32_t)bdo[i];
-        const uint32_t heb = ~(eb ^ ob) & (uint32_t)(bre[i] >> 32);
-        const uint32_t hob = ~(ob ^ ((eb >> 1) | (nxt[2 * i + 1] << 31))) & (uint32_t)(bro[i] >> 32);
-        const uint32_t deb = ~(eb ^ ec) & (uint32_t)(bde[i] >> 32), dob = ~(ob ^ oc) & (uint32_t)(bdo[i] >> 32);
-        const uint64_t HA = column_order(hea, hoa), DA = column_order(dea, doa);
-        const uint64_t HB = column_order(heb, hob), DB = column_order(deb, dob);
-        if (lane == 0) {
-            Hm[rl] = HA;
-            Dm[rl] = DA;
-            Hm[rl + 1] = HB;
-            Dm[rl + 1] = DB;
+    for (uint32_t h = 0; h < 2; ++h) {
+        uint64_t bre[HP], bde[HP], bro[HP], bdo[HP];
+#pragma unroll
+        for (uint32_t ii = 0; ii < HP; ++ii) {
+            const uint32_t i = h * HP + ii;
+            const uint32_t row = T.y0 + min(first + 2 * i, T.rows - 2) + (lane >> 5);
+            const uint32_t g = row * Lx + T.x0 + 2u * (lane & 31u);
+            uint32_t w[4];
+            philox4x32_10(g >> 1, t, d.replica, 7u, d.seed_lo, d.seed_hi, w);
+            const bool on = 2 * i < nr && !c.none;
+            bre[ii] = __ballot(on && w[0] >= c.thr2);
+            bde[ii] = __ballot(on && w[1] >= c.thr2);
+            bro[ii] = __ballot(on && w[2] >= c.thr2);
+            bdo[ii] = __ballot(on && w[3] >= c.thr2);
         }
-        L[rl * 64 + lane] = rl * 64 + run_start(HA, lane);
-        L[(rl + 1) * 64 + lane] = (rl + 1) * 64 + run_start(HB, lane);
+        __builtin_amdgcn_sched_barrier(0);  // and the first use of the loaded words after them
+#pragma unroll
+        for (uint32_t ii = 0; ii < HP; ++ii) {
+            const uint32_t i = h * HP + ii;
+            if (2 * i >= nr)
+                break;
+            // colour-0 / colour-1 words of rows 2i, 2i + 1, 2i + 2 of the wave
+            // and the column-0 bits of the next tile in rows 2i, 2i + 1
+            const uint32_t p0a = __builtin_amdgcn_readlane(word, 2 * i), p1a = __builtin_amdgcn_readlane(word, R1 + 2 * i);
+            const uint32_t p0b = __builtin_amdgcn_readlane(word, 2 * i + 1);
+            const uint32_t p1b = __builtin_amdgcn_readlane(word, R1 + 2 * i + 1);
+            const uint32_t p0c = __builtin_amdgcn_readlane(word, 2 * i + 2);
+            const uint32_t p1c = __builtin_amdgcn_readlane(word, R1 + 2 * i + 2);
+            const uint32_t nxa = __builtin_amdgcn_readlane(word, R2 + 2 * i) & 1u;
+            const uint32_t nxb = __builtin_amdgcn_readlane(word, R2 + 2 * i + 1) & 1u;
+            const uint32_t rl = first + 2 * i, ya = T.y0 + rl;
+            const uint32_t yb = ya + 1;
+            // a row's even columns have colour y & 1, its odd columns the other
+            const uint32_t ea = (ya & 1u) ? p1a : p0a, oa = (ya & 1u) ? p0a : p1a;
+            const uint32_t eb = (yb & 1u) ? p1b : p0b, ob = (yb & 1u) ? p0b : p1b;
+            // the row below b has the parity of yb + 1 (Ly is even, so also after wrapping)
+            const uint32_t ec = (yb & 1u) ? p0c : p1c, oc = (yb & 1u) ? p1c : p0c;
+            // aligned bonds in compact order: the right neighbour of column 2k is
+            // column 2k + 1 (odd bit k), that of column 2k + 1 is column 2k + 2
+            // (even bit k + 1, the next tile's column 0 for k = 31); the down
+            // neighbour of a column is the same column of the next row
+            const uint32_t hea = ~(ea ^ oa) & (uint32_t)bre[ii], hoa = ~(oa ^ ((ea >> 1) | (nxa << 31))) & (uint32_t)bro[ii];
+            const uint32_t dea = ~(ea ^ eb) & (uint32_t)bde[ii], doa = ~(oa ^ ob) & (uint32_t)bdo[ii];
+            const uint32_t heb = ~(eb ^ ob) & (uint32_t)(bre[ii] >> 32);
+            const uint32_t hob = ~(ob ^ ((eb >> 1) | (nxb << 31))) & (uint32_t)(bro[ii] >> 32);
+            const uint32_t deb = ~(eb ^ ec) & (uint32_t)(bde[ii] >> 32), dob = ~(ob ^ oc) & (uint32_t)(bdo[ii] >> 32);
+            const uint64_t HA = column_order(hea, hoa), DA = column_order(dea, doa);
+            const uint64_t HB = column_order(heb, hob), DB = column_order(deb, dob);
+            if (lane == 0) {
+                Hm[rl] = HA;
+                Dm[rl] = DA;
+                Hm[rl + 1] = HB;
+                Dm[rl + 1] = DB;
+            }
+            L[rl * 64 + lane] = rl * 64 + run_start(HA, lane);
+            L[(rl + 1) * 64 + lane] = (rl + 1) * 64 + run_start(HB, lane);
+        }
     }
     __syncthreads();
     // vertical bonds inside the tile; a bond is skipped when its left

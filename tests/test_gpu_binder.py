@@ -8,7 +8,6 @@ U_64 - U_128 between the grid temperatures around its sign change (measured: T =
 T_c = 2.2692, U = 0.610 there; the bounds below are several times the
 statistical spread).
 """
-import math
 
 import numpy as np
 import pytest

@@ -54,149 +54,178 @@ __device__ __forceinline__ Neigh3 neigh3(const Rep3Dev &d, uint32_t idx, uint32_
     return n;
 }
 
-// Update NW words idx0, idx0 + 256, ... of colour c: every neighbour word of
-// all NW words is loaded before the first update (the planes do not alias),
-// so the loads of a thread are in flight together.
-template <int NW, bool BITSLICED>
-__device__ __forceinline__ void sweep_words(const uint32_t *__restrict__ src, uint32_t *__restrict__ tgt,
-                                            uint32_t idx0, uint32_t colour, uint32_t t, const Rep3Dev &d)
-{
-    uint32_t s[NW], n[NW][6], q0[NW];
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-        const uint32_t idx = idx0 + 256u * k;
-        const Neigh3 nb = neigh3(d, idx, colour);
-        const uint32_t same = src[nb.same];
-        n[k][0] = src[nb.ym];
-        n[k][1] = src[nb.yp];
-        n[k][2] = src[nb.zm];
-        n[k][3] = src[nb.zp];
-        n[k][4] = same;
-        n[k][5] = side_word<uint32_t>(same, src[nb.nb], nb.p);
-        s[k] = tgt[idx];
-        const uint32_t row = idx / d.W, w = idx - row * d.W;
-        q0[k] = row * (d.Lx >> 3) + 8u * w;  // (row * Lx / 2 + 32 w) / 4
-    }
-    const Key3 K = key3(d, t, colour);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-        const uint32_t idx = idx0 + 256u * k;
-        if constexpr (BITSLICED)
-            tgt[idx] = s[k] ^ flip_mask32_3d_bitsliced(s[k], n[k], 8u * idx, K);
-        else
-            tgt[idx] = s[k] ^ flip_mask32_3d(s[k], n[k], q0[k], K);
-    }
-}
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) char gchar;
-typedef __attribute__((address_space(1))) uint32_t gu32;
-typedef __attribute__((address_space(1))) u32x4 gu32x4;
 
-// Global-memory loads and stores at a 32-bit byte offset from a
-// workgroup-uniform base, so the address is the base register pair plus one
-// offset register.
-__device__ __forceinline__ u32x4 load4(const uint32_t *base, uint32_t byte_off)
+template <int NQ>
+struct VecOf;
+template <>
+struct VecOf<1> {
+    typedef uint32_t type;
+};
+template <>
+struct VecOf<2> {
+    typedef uint32_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecOf<4> {
+    typedef uint32_t type __attribute__((ext_vector_type(4)));
+};
+
+// NQ consecutive words loaded / stored as one access at a 32-bit byte offset
+// from a workgroup-uniform base, so the address is the base register pair
+// plus one offset register.
+template <int NQ>
+__device__ __forceinline__ void load_words(const uint32_t *base, uint32_t byte_off, uint32_t (&v)[NQ])
 {
-    return *(const gu32x4 *)((const gchar *)base + byte_off);
+    typedef typename VecOf<NQ>::type V;
+    typedef __attribute__((address_space(1))) V GV;
+    const V x = *(const GV *)((const gchar *)base + byte_off);
+    if constexpr (NQ == 1) {
+        v[0] = x;
+    } else {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            v[k] = x[k];
+    }
 }
 
-__device__ __forceinline__ uint32_t load1(const uint32_t *base, uint32_t byte_off)
+template <int NQ>
+__device__ __forceinline__ void store_words(uint32_t *base, uint32_t byte_off, const uint32_t (&v)[NQ])
 {
-    return *(const gu32 *)((const gchar *)base + byte_off);
+    typedef typename VecOf<NQ>::type V;
+    typedef __attribute__((address_space(1))) V GV;
+    V x;
+    if constexpr (NQ == 1) {
+        x = v[0];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            x[k] = v[k];
+    }
+    *(GV *)((gchar *)base + byte_off) = x;
 }
 
-__device__ __forceinline__ void store4(uint32_t *base, uint32_t byte_off, u32x4 v)
-{
-    *(gu32x4 *)((gchar *)base + byte_off) = v;
-}
+// The NQ words idx .. idx + NQ - 1 of a colour-c row (W a multiple of NQ, idx
+// a multiple of NQ, so the words share their row and their y and z neighbour
+// rows) and their neighbours: one NQ-word load from each of the five
+// other-colour rows and from the target row, plus the one other-colour word
+// beyond the group on the side its x neighbours reach out to.  Offsets are in
+// bytes and stay below 2^32 (a plane of N < 2^32 sites holds N / 16 bytes).
+template <int NQ>
+struct Group {
+    uint32_t ym[NQ], yp[NQ], zm[NQ], zp[NQ], same[NQ], s[NQ];
+    uint32_t beyond, p;
+};
 
-// Update the four words idx .. idx + 3 of a colour-c row (W a multiple of 4,
-// idx a multiple of 4, so the four words share their row and their y and z
-// neighbour rows): one 16-byte load from each of the five other-colour rows
-// and from the target row, plus the one other-colour word beyond the quad on
-// the side its x neighbours reach out to.  Offsets are in bytes and stay below
-// 2^32 (a plane of N < 2^32 sites holds N / 16 bytes).
-template <bool BITSLICED>
-__device__ __forceinline__ void sweep_quad(const uint32_t *__restrict__ src, uint32_t *__restrict__ tgt, uint32_t idx,
-                                           uint32_t colour, uint32_t t, const Rep3Dev &d)
+template <int NQ>
+__device__ __forceinline__ Group<NQ> load_group(const uint32_t *__restrict__ src, const uint32_t *__restrict__ tgt,
+                                                uint32_t idx, uint32_t colour, const Rep3Dev &d)
 {
     const uint32_t W = d.W, Ly = d.Ly, Lz = d.Lz;
     const uint32_t row = idx / W, w = idx - row * W;
     const uint32_t z = row / Ly, y = row - z * Ly;
-    const uint32_t p = (colour + y + z) & 1u;
+    Group<NQ> g;
+    g.p = (colour + y + z) & 1u;
     const uint32_t row_b = 4u * W, slab_b = Ly * row_b, off = 4u * idx;
     const uint32_t off_ym = y == 0 ? off + (Ly - 1) * row_b : off - row_b;
     const uint32_t off_yp = y + 1 == Ly ? off - (Ly - 1) * row_b : off + row_b;
     const uint32_t off_zm = z == 0 ? off + (Lz - 1) * slab_b : off - slab_b;
     const uint32_t off_zp = z + 1 == Lz ? off - (Lz - 1) * slab_b : off + slab_b;
-    // p = 1: the word after the quad (the row's first word after its last);
+    // p = 1: the word after the group (the row's first word after its last);
     // p = 0: the word before it (the row's last word before its first)
-    const uint32_t off_x = p ? (w + 4 == W ? off + 16u - row_b : off + 16u) : (w == 0 ? off + row_b - 4u : off - 4u);
-    const u32x4 ym = load4(src, off_ym), yp = load4(src, off_yp), zm = load4(src, off_zm), zp = load4(src, off_zp);
-    const u32x4 same = load4(src, off), s = load4(tgt, off);
-    const uint32_t beyond = load1(src, off_x);
-    const Key3 K = key3(d, t, colour);
-    // word k's other x word: same[k + 1] (or beyond) for p = 1, same[k - 1] (or beyond) for p = 0
-    auto update = [&](uint32_t sk, uint32_t ymk, uint32_t ypk, uint32_t zmk, uint32_t zpk, uint32_t samek,
-                      uint32_t otherk, uint32_t k) {
-        const uint32_t n[6] = {ymk, ypk, zmk, zpk, samek, side_word<uint32_t>(samek, otherk, p)};
+    const uint32_t off_x = g.p ? (w + NQ == W ? off + 4u * NQ - row_b : off + 4u * NQ)
+                               : (w == 0 ? off + row_b - 4u : off - 4u);
+    load_words<NQ>(src, off_ym, g.ym);
+    load_words<NQ>(src, off_yp, g.yp);
+    load_words<NQ>(src, off_zm, g.zm);
+    load_words<NQ>(src, off_zp, g.zp);
+    load_words<NQ>(src, off, g.same);
+    load_words<NQ>(tgt, off, g.s);
+    uint32_t b[1];
+    load_words<1>(src, off_x, b);
+    g.beyond = b[0];
+    return g;
+}
+
+template <int NQ, bool BITSLICED>
+__device__ __forceinline__ void update_group(const Group<NQ> &g, uint32_t *__restrict__ tgt, uint32_t idx,
+                                             const Key3 &K)
+{
+    uint32_t out[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        // word k's other x word: same[k + 1] (or beyond) for p = 1, same[k - 1] (or beyond) for p = 0
+        const uint32_t after = k + 1 < NQ ? g.same[k + 1 < NQ ? k + 1 : k] : g.beyond;
+        const uint32_t before = k > 0 ? g.same[k > 0 ? k - 1 : 0] : g.beyond;
+        const uint32_t n[6] = {g.ym[k], g.yp[k], g.zm[k], g.zp[k], g.same[k],
+                               side_word<uint32_t>(g.same[k], g.p ? after : before, g.p)};
         if constexpr (BITSLICED)
-            return sk ^ flip_mask32_3d_bitsliced(sk, n, 8u * (idx + k), K);
+            out[k] = g.s[k] ^ flip_mask32_3d_bitsliced(g.s[k], n, 8u * (idx + k), K);
         else
-            return sk ^ flip_mask32_3d(sk, n, 8u * (idx + k), K);
-    };
-    u32x4 out;
-    out.x = update(s.x, ym.x, yp.x, zm.x, zp.x, same.x, p ? same.y : beyond, 0);
-    out.y = update(s.y, ym.y, yp.y, zm.y, zp.y, same.y, p ? same.z : same.x, 1);
-    out.z = update(s.z, ym.z, yp.z, zm.z, zp.z, same.z, p ? same.w : same.y, 2);
-    out.w = update(s.w, ym.w, yp.w, zm.w, zp.w, same.w, p ? beyond : same.z, 3);
-    store4(tgt, off, out);
+            out[k] = g.s[k] ^ flip_mask32_3d(g.s[k], n, 8u * (idx + k), K);
+    }
+    store_words<NQ>(tgt, 4u * idx, out);
+}
+
+// Thread i of a workgroup updates the 4 / NQ groups of NQ words at
+// first + NQ i + 256 NQ j that lie below words (words is a multiple of NQ, so
+// a group is whole or absent): every group's loads are issued before the first
+// update (a group past the plane loads group 0 instead and is not updated).
+template <int NQ, bool BITSLICED>
+__device__ __forceinline__ void sweep_groups(const uint32_t *__restrict__ src, uint32_t *__restrict__ tgt,
+                                             uint32_t first, uint32_t words, uint32_t colour, uint32_t t,
+                                             const Rep3Dev &d)
+{
+    constexpr int NG = 4 / NQ;
+    static_assert(k3WordsPerBlock == 4 * 256, "four words per thread");
+    if constexpr (NG == 1) {
+        const uint32_t idx = first + NQ * threadIdx.x;
+        if (idx < words) {
+            const Group<NQ> g = load_group<NQ>(src, tgt, idx, colour, d);
+            update_group<NQ, BITSLICED>(g, tgt, idx, key3(d, t, colour));
+        }
+        return;
+    }
+    Group<NQ> g[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+        const uint32_t idx = first + NQ * threadIdx.x + 256u * NQ * j;
+        g[j] = load_group<NQ>(src, tgt, idx < words ? idx : 0u, colour, d);
+    }
+    const Key3 K = key3(d, t, colour);
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+        const uint32_t idx = first + NQ * threadIdx.x + 256u * NQ * j;
+        if (idx < words)
+            update_group<NQ, BITSLICED>(g[j], tgt, idx, K);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// one colour of one sweep of every replica: grid = blocks of all replicas;
-// workgroup b handles k3WordsPerBlock consecutive words of its replica's
-// colour-c plane, thread i the words i, i + 256, ...
+// one colour of one sweep of every replica with group width NQ: grid =
+// blocks of all replicas; workgroup b handles k3WordsPerBlock consecutive
+// words of its replica's colour-c plane, each thread four of them in groups of
+// NQ consecutive words
 // ---------------------------------------------------------------------------
+template <int NQ>
 __global__ __launch_bounds__(256) void k3_sweep(Sweep3Args a, uint32_t colour, uint32_t sweep_off)
 {
-    constexpr int NW = k3WordsPerBlock / 256;
     const uint32_t r = block_owner(a.prefix, a.n, blockIdx.x);
     const Rep3Dev d = a.reps[r];
+    // one kernel per group width (each with its own register budget): the
+    // workgroups of replicas with another width leave at once
+    if (group_width(d.W) != NQ)
+        return;
     const uint32_t words = d.Lz * d.Ly * d.W;
     const uint32_t first = (blockIdx.x - a.prefix[r]) * k3WordsPerBlock;
     uint32_t *tgt = d.plane0 + (colour ? (size_t)words : 0);
     const uint32_t *src = d.plane0 + (colour ? 0 : (size_t)words);
     const uint32_t t = d.t + sweep_off;
     // the contract is uniform per replica, hence per workgroup
-    const bool bitsliced = (d.flags & k3Bitsliced) != 0;
-    if ((d.W & 3u) == 0) {
-        // rows of a multiple of four words: thread i takes the quad at
-        // first + 4 i (words is a multiple of 4, so a quad is whole or absent)
-        static_assert(k3WordsPerBlock == 4 * 256, "one quad per thread");
-        const uint32_t idx = first + 4u * threadIdx.x;
-        if (idx < words) {
-            if (bitsliced)
-                sweep_quad<true>(src, tgt, idx, colour, t, d);
-            else
-                sweep_quad<false>(src, tgt, idx, colour, t, d);
-        }
-        return;
-    }
-    if (first + k3WordsPerBlock <= words) {
-        if (bitsliced)
-            sweep_words<NW, true>(src, tgt, first + threadIdx.x, colour, t, d);
-        else
-            sweep_words<NW, false>(src, tgt, first + threadIdx.x, colour, t, d);
-        return;
-    }
-    for (uint32_t idx = first + threadIdx.x; idx < words; idx += 256) {  // the last, partial block
-        if (bitsliced)
-            sweep_words<1, true>(src, tgt, idx, colour, t, d);
-        else
-            sweep_words<1, false>(src, tgt, idx, colour, t, d);
-    }
+    if ((d.flags & k3Bitsliced) != 0)
+        sweep_groups<NQ, true>(src, tgt, first, words, colour, t, d);
+    else
+        sweep_groups<NQ, false>(src, tgt, first, words, colour, t, d);
 }
 
 // initial states: both colour planes, same block mapping
@@ -292,7 +321,12 @@ hipError_t launch3_init(const Sweep3Args &a, const int32_t *modes, hipStream_t s
 
 hipError_t launch3_sweep(const Sweep3Args &a, uint32_t colour, uint32_t sweep_off, hipStream_t st)
 {
-    hipLaunchKernelGGL(k3_sweep, dim3(a.blocks), dim3(256), 0, st, a, colour, sweep_off);
+    if (a.widths & 4u)
+        hipLaunchKernelGGL(k3_sweep<4>, dim3(a.blocks), dim3(256), 0, st, a, colour, sweep_off);
+    if (a.widths & 2u)
+        hipLaunchKernelGGL(k3_sweep<2>, dim3(a.blocks), dim3(256), 0, st, a, colour, sweep_off);
+    if (a.widths & 1u)
+        hipLaunchKernelGGL(k3_sweep<1>, dim3(a.blocks), dim3(256), 0, st, a, colour, sweep_off);
     return hipGetLastError();
 }
 

@@ -24,12 +24,21 @@ static_assert(sizeof(Rep3Dev) == 64, "3D descriptor must stay 64 bytes");
 // Words of one colour handled by one 256-thread workgroup.
 constexpr uint32_t k3WordsPerBlock = 1024;
 
+// Words per group of the sweep for rows of W words: a thread updates groups
+// of 4, 2 or 1 consecutive words of a row.
+__host__ __device__ inline uint32_t group_width(uint32_t W)
+{
+    return (W & 3u) == 0 ? 4u : (W & 1u) == 0 ? 2u : 1u;
+}
+
 // Workgroup b of a launch serves replica r with prefix[r] <= b < prefix[r+1]
-// (prefix: n + 1 entries in device memory).
+// (prefix: n + 1 entries in device memory).  widths: bit k set when some
+// replica's group width is 2^k (one sweep kernel per width present).
 struct Sweep3Args {
     const Rep3Dev *reps;
     const uint32_t *prefix;
     uint32_t n, blocks;
+    uint32_t widths;
 };
 
 hipError_t launch3_init(const Sweep3Args &a, const int32_t *modes, hipStream_t st);

@@ -27,6 +27,7 @@ struct ising3d_batch {
     uint32_t *d_prefix = nullptr;
     int64_t *d_obs = nullptr;
     uint32_t blocks = 0;
+    uint32_t widths = 0;  // bit k: some replica's sweep groups are 2^k words
 };
 
 #define H3_HIP(expr)                                                                            \
@@ -106,6 +107,7 @@ Sweep3Args args_of(const ising3d_batch *b)
     a.prefix = b->d_prefix;
     a.n = (uint32_t)b->n;
     a.blocks = b->blocks;
+    a.widths = b->widths;
     return a;
 }
 
@@ -185,6 +187,7 @@ int ising3d_batch_create(int32_t n, const ising3d_desc *d, void *dev_buf, size_t
         modes[i] = d[i].init;
         b->prefix[i] = (uint32_t)blocks;
         blocks += (words3(d[i]) + k3WordsPerBlock - 1) / k3WordsPerBlock;
+        b->widths |= group_width(r.W);
     }
     if (blocks >= (1ull << 31)) {
         delete b;

@@ -1,8 +1,7 @@
 """Bit-exact parity of the 3D (simple cubic) sweeps of the HIP library,
 through its C ABI, with the CPU oracle: states and (B, M) traces element by
 element for single lattices of many shapes (one and several words per row,
-rows of a multiple of four words through the quad path and the others word
-by word, Ly = 2 and Lz = 2 double bonds), the special temperatures, a batch of mixed
+every group width of the sweep kernel, Ly = 2 and Lz = 2 double bonds), the special temperatures, a batch of mixed
 shapes, split runs, spin round trips, and the full-size benchmark batch on
 sampled replicas; the largest lattice under exact properties."""
 import math
@@ -14,9 +13,9 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-# W = Lx / 64 words per row: 1, 2 and 3 take the word-by-word path, multiples
-# of 4 the quad path (Ly = Lz = 2 double bonds, one and many quads per row,
-# a row of one quad, several workgroups with a partial last one)
+# W = Lx / 64 words per row: odd widths take groups of 1 word, 2 mod 4 groups
+# of 2, multiples of 4 groups of 4 (Ly = Lz = 2 double bonds, one and many
+# groups per row, a row of one group, several workgroups with a partial last one)
 SHAPES = [(64, 2, 2), (64, 4, 6), (128, 6, 4), (64, 64, 64), (192, 10, 14), (256, 2, 8), (64, 30, 2),
           (256, 2, 2), (256, 6, 10), (512, 4, 6), (768, 10, 4), (1024, 2, 2), (256, 64, 34)]
 

@@ -398,7 +398,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32 (1 bit/spin, integer Philox thresholds)",
+        "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": work.name, "replicas": len(work.replicas), "spins": work.spins,
                    "sweeps_per_step": args.sweeps_per_step, "record_every": m["rec_every"],

@@ -1,4 +1,4 @@
-"""Self-consistency of the exact results the oracle is judged by.
+"""Self-consistency of the exact results the oracle is checked against.
 
 Enumeration, the transfer matrix and Kaufman's closed form must agree on small
 tori; Onsager's energy and Yang's magnetisation must hit their known limits;

@@ -479,7 +479,7 @@ def learned_comparison(units, plain_sweeps):
     t_train = time.perf_counter() - t0
     tr_p, e_p, s_p = learned.plain_trace(b, plain_sweeps, 10)
     acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda")
-    tr_l, e_l, s_l = learned.unit_traces(b, units, learned.learned_units(b, net, 0, acc))
+    tr_l, e_l, s_l = learned.unit_traces(b, units, learned.learned_units(b, net, 0, acc), progress=5000)
     plain = learned.summarise(tr_p, s_p, 10, t_c)
     plain["tau_int_sweeps"] = plain["tau_int_points"] * 10
     lrn = learned.summarise(tr_l, s_l, 1, t_c)

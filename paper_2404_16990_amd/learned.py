@@ -4,6 +4,7 @@ the comparison against plain checkerboard sweeps on effective |m| samples.
 Every device step is a library call (see include/ising.h); this module only
 schedules them and analyses the recorded traces on the host.
 """
+import sys
 import time
 
 import numpy as np
@@ -47,9 +48,11 @@ def _per_spin(batch: Batch):
     return n, j
 
 
-def unit_traces(batch: Batch, units: int, unit):
+def unit_traces(batch: Batch, units: int, unit, progress: int = 0):
     """Run `units` units (callable unit(i) returning device traces (B, M) of
-    the unit); returns (|m| trace, e trace) [n_rep, units] and seconds."""
+    the unit); returns (|m| trace, e trace) [n_rep, units] and seconds.  With
+    progress > 0 the device is drained and a line printed to stderr every
+    `progress` units (a long run then reports as it goes)."""
     import torch
     n, j = _per_spin(batch)
     bonds, mags = [], []
@@ -59,6 +62,9 @@ def unit_traces(batch: Batch, units: int, unit):
         b, m = unit(i)
         bonds.append(b)
         mags.append(m)
+        if progress and (i + 1) % progress == 0 and i + 1 < units:
+            torch.cuda.synchronize()
+            print(f"learned units: {i + 1} of {units}, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     B = np.concatenate([t.cpu().numpy() for t in bonds], axis=1).astype(np.float64)

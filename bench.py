@@ -363,11 +363,18 @@ def main():
     from paper_2404_16990_amd import probe
     import workloads
 
+    t_start = time.perf_counter()
+
+    def progress(what):
+        # one line per finished leg on stderr (stdout carries only the JSON line)
+        print(f"bench: {what} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
     work = workloads.ALL[args.workload]()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     rng = RNG_NAMES[args.rng]
     m, batch = run_path(work, rng, args, stream, json.loads(args.schedule) if args.schedule else None)
+    progress("timed steps done")
     sched = m["schedule"]
     peak = alu_peak_flips()
     traffic, algo_bytes = (None, None)
@@ -422,14 +429,17 @@ def main():
             "measured_alu_ceiling": cv / 1e9, "frac_of_measured_ceiling": mv["achieved"] / cv}}
         bv.close()
         del bv
+        progress("variant done")
     if not args.no_cluster:
         torch.cuda.empty_cache()
         out["cluster"] = cluster_leg(work, stream, args.cluster_steps)
+        progress("cluster steps done")
         if not args.no_cpu_baseline:
             out["cluster"]["cpu_baseline"] = cluster_cpu_baseline(work, 3)
         if args.critical_steps > 0:
             out["cluster"]["critical"] = critical_decorrelation(args.critical_steps, args.critical_steps,
                                                                 args.critical_sweeps)
+            progress("critical comparison done")
         torch.cuda.empty_cache()
     if not args.no_3d:
         torch.cuda.empty_cache()
@@ -441,8 +451,10 @@ def main():
         if not args.no_cpu_baseline:
             out["cubic"]["cpu_baseline"] = cubic_cpu_baseline()
         torch.cuda.empty_cache()
+        progress("3D legs done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps, rng)
+        progress("CPU baseline done")
     if args.learned:
         torch.cuda.empty_cache()
         out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps)

@@ -1,13 +1,19 @@
 """Throughput benchmark: aggregate flip attempts per second on one MI355X.
 
-Workload (default): 256 replicas of 1024x1024 periodic lattices, J = 1,
-T_r = 1.5 + 2 r / 255, seed 16990 + r, random start; (B, M) recorded every 100
-sweeps.  One step = 100 checkerboard sweeps of every replica (each sweep
-updates both colours), so the default 100 timed steps are the full 10^4-sweep
-run.  The lattices are resident in HBM before timing starts.
+Headline workload (default): the uneven batch of 512 periodic square
+lattices, sides 2^k with k uniform on {7..13} (128^2 .. 8192^2, 6.9e9 spins in
+all) and T uniform on [2.0, 2.6), both from numpy PCG64(16990); J = 1,
+seed 16990 + r, random start; (B, M) recorded every 100 sweeps.  One step = 100
+checkerboard sweeps of every replica (each sweep updates both colours), so the
+default 20 timed steps are the workload's full 2000-sweep run.  The lattices
+are resident in HBM before timing starts; the schedule comes from the
+library's autotuner.
 
-Prints ONE JSON line with the metric, the roofline of the dominant kernel, and
-the CPU oracle's rate on a bounded sample of the same workload.
+Prints ONE JSON line with the metric, the roofline of the dominant kernel, the
+CPU oracle's rate on a bounded sample of the same workload, the other plain
+configurations (256 x 1024^2; 754 x 512x528 + 16384x12288) timed the same way,
+and the learned-proposal comparison at T_c (effective independent |m| samples
+per second against plain sweeps).
 """
 import argparse
 import json
@@ -18,20 +24,28 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published figures: 256 CUs at 2.4 GHz; the fp32 vector peak of
-# 157.3 TFLOP/s is 128 FMA lanes per CU per clock, i.e. 128 full-rate 32-bit
-# VALU lane-operations per CU per clock.
-CUS, LANE_OPS_PER_CU_CLK, CLOCK_HZ = 256, 128, 2.4e9
-# Full-rate VALU slots of the minimal instruction sequence for one flip
-# attempt: a quarter of one Philox4x32-10 call (20 v_mad_u64_u32 at 1.86 slots
-# each, measured, + 20 v_bitop3_b32 at 1 slot) plus one threshold compare and
-# one bit insert.
-SLOTS_PER_FLIP = (20 * 1.86 + 20 * 1.0) / 4 + 2.0
+# MI355X: 256 CUs at 2.4 GHz.  Each CU has four SIMDs of 16 lanes; a wave64
+# VALU instruction occupies its SIMD for 4 clocks, so plain (non-packed)
+# 32-bit integer instructions issue at 64 lane-operations per CU per clock
+# (the published fp64 vector rate, 78.6 TFLOP/s, is the same 64 FMA lanes per
+# CU per clock; the fp32 figure of 157.3 TFLOP/s counts two packed fp32
+# operations per lane, which integer work cannot use).
+CUS, LANE_OPS_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
+# VALU instructions of the algorithmic work of one flip attempt: a quarter of
+# one Philox4x32-10 call (20 32x32->64 products and 20 three-input XORs per
+# call, i.e. 5 + 5), the acceptance (threshold select, compare, bit insert: 3)
+# and one instruction of neighbour words, classification and flip amortised
+# over the 32 sites of a word.
+OPS_PER_FLIP = 5 + 5 + 3 + 1
 HBM_BYTES_PER_S = 8.0e12
 
 
+def lane_ops_peak():
+    return CUS * LANE_OPS_PER_CU_CLK * CLOCK_HZ
+
+
 def alu_peak_flips():
-    return CUS * LANE_OPS_PER_CU_CLK * CLOCK_HZ / SLOTS_PER_FLIP
+    return lane_ops_peak() / OPS_PER_FLIP
 
 
 def kernel_source_digest():
@@ -44,13 +58,19 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
+TRAFFIC_FILES = {"k_sweep_stream": "traffic_k_sweep_stream_uneven512.json",
+                 "k_sweep_resident": "traffic_k_sweep_resident_batch256x1024.json"}
+
+
 def measured_traffic(kernel, workload_name, sweeps_per_launch):
-    """HBM bytes per launch from the committed counter summary, or None when the
-    summary is for another kernel/workload/launch length or the kernel sources
-    changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_sweep_resident_batch256x1024.json")
+    """HBM bytes per launch from the committed counter summary of `kernel`, or
+    None when the summary is for another workload or launch length or the
+    kernel sources changed since the counters were taken."""
+    name = TRAFFIC_FILES.get(kernel)
+    if name is None:
+        return None, None
     try:
-        with open(path) as f:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
     except OSError:
         return None, None
@@ -61,7 +81,7 @@ def measured_traffic(kernel, workload_name, sweeps_per_launch):
     e = d["by_sweeps_per_launch"].get(str(sweeps_per_launch))
     if e is None:
         return None, None
-    return e["traffic_bytes_per_launch"], d["algorithmic_bytes_per_launch"]
+    return e["traffic_bytes_per_launch"], e.get("algorithmic_bytes_per_launch", d["algorithmic_bytes_per_launch"])
 
 
 def host_threads():
@@ -75,10 +95,14 @@ def host_threads():
 def cpu_baseline(work, sweeps, rng=0):
     """Time the CPU oracle on every replica of the workload for `sweeps` sweeps
     under the measured path's random-number contract."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     descs = [oracle.desc(r.Lx, r.Ly, r.J, r.beta, r.seed, r.replica, r.init, rng=rng) for r in work.replicas]
-    states = [oracle.init_state(d) for d in descs]
     threads = host_threads()
+    # initial states (untimed) on all host threads: the library calls release the GIL
+    with ThreadPoolExecutor(threads) as pool:
+        states = list(pool.map(oracle.init_state, descs))
     t0 = time.perf_counter()
     oracle.run_batch(descs, states, sweeps, threads=threads)
     dt = time.perf_counter() - t0
@@ -137,42 +161,58 @@ def run_path(work, rng, args, stream, schedule=None):
 
     # dominant kernel: all-resident batches launch one k_sweep_resident per
     # sweeps_per_launch sweeps; all-streaming batches one k_sweep_stream per
-    # colour per sweep.  Launches on the stream are back to back, so the mean
-    # launch duration is the timed region over the number of launches (it
-    # includes the one-thread-per-replica counter kernel after each chunk).
+    # colour per sweep and per word-width list present (the 64-bit list holds
+    # every replica with Lx % 128 == 0, the 32-bit list the rest).  Launches on
+    # the stream are back to back, so the mean launch duration is the timed
+    # region over the number of launches (it includes the one-thread-per-replica
+    # counter kernel after each chunk).
     S = sched["sweeps_per_launch"]
+    n_lists = 1
+    if sched["word_bits"] == 64 and any(r.Lx % 128 for r in work.replicas) and \
+            any(r.Lx % 128 == 0 for r in work.replicas):
+        n_lists = 2
     if n_str == 0:
-        kernel, launches, sweeps_per_launch = "k_sweep_resident", args.steps * -(-spw // S), min(spw, S)
+        kernel, launches, flips_per_launch = "k_sweep_resident", args.steps * -(-spw // S) * n_lists, \
+            work.spins * min(spw, S) / n_lists
     elif n_res == 0:
-        kernel, launches, sweeps_per_launch = "k_sweep_stream", args.steps * spw * 2, 0.5
+        kernel, launches, flips_per_launch = "k_sweep_stream", args.steps * spw * 2 * n_lists, \
+            work.spins * 0.5 / n_lists
     else:
-        kernel, launches, sweeps_per_launch = "k_sweep_resident+k_sweep_stream (concurrent)", \
-            args.steps * -(-spw // S), min(spw, S)
+        # mixed: per chunk of S sweeps, 2 S streaming launches back to back on
+        # the stream, the resident replicas' one launch beside them on a second
+        # stream; the chunk (both kernels' work) is the unit timed
+        kernel, launches, flips_per_launch = \
+            f"k_sweep_stream ({2 * min(spw, S)} launches per chunk) + k_sweep_resident (concurrent)", \
+            args.steps * -(-spw // S), work.spins * min(spw, S)
     launch_s = total_s / launches
-    achieved = work.spins * sweeps_per_launch / launch_s
+    achieved = flips_per_launch / launch_s
     return {"value": flips / total_s, "ms_per_step": total_s * 1e3 / args.steps, "schedule": sched,
             "resident_replicas": n_res, "streamed_replicas": n_str, "autotune": tuned, "wall_s": wall,
             "kernel": kernel, "launches": launches, "launch_s": launch_s, "achieved": achieved,
-            "rec_every": rec_every}, batch
+            "flips_per_launch": flips_per_launch, "rec_every": rec_every}, batch
 
 
 RNG_NAMES = {"site": 0, "bitsliced": 1}
 
 # Irreducible work of one Swendsen-Wang step per site under the library's
 # random-number contract: half a Philox4x32-10 call for the two bonds a site
-# owns and one call for its cluster's flip bit; the minimal HBM traffic is a
-# 32-bit label written and read back plus the spin bits read twice and written
-# once (1 bit per site each, 1.5x for the neighbour rows of the bond pass).
-PHILOX_SLOTS = 20 * 1.86 + 20 * 1.0
-SW_SLOTS_PER_SITE = 1.5 * PHILOX_SLOTS
+# owns and one call for its cluster's flip bit (40 VALU instructions per
+# call); the minimal HBM traffic is a 32-bit label written and read back plus
+# the spin bits read twice and written once (1 bit per site each, 1.5x for the
+# neighbour rows of the bond pass).
+PHILOX_OPS = 20 + 20
+SW_OPS_PER_SITE = 1.5 * PHILOX_OPS
 SW_BYTES_PER_SITE = 4.0 + 4.0 + (1.5 + 1.0 + 1.0) / 8.0
+# 3D flip attempt: the 2D count plus one more threshold select (three
+# thresholds for dE = 4J, 8J, 12J).
+OPS_PER_FLIP_3D = OPS_PER_FLIP + 1
 
 
 def cubic_leg(sweeps, warmup=10, rng=0):
     """3D sweeps of the 16 x 256^3 workload: flip attempts per second, the
-    sweep kernel's roofline (the same derived ALU peak per flip attempt as in
-    2D: a quarter Philox call, one compare, one bit insert) and the oracle's
-    rate on a bounded sample."""
+    sweep kernel's roofline (derived ALU peak: the 2D instruction count per
+    flip attempt plus one threshold select) and the oracle's rate on a bounded
+    sample."""
     import torch
 
     import paper_2404_16990_amd as P
@@ -193,13 +233,13 @@ def cubic_leg(sweeps, warmup=10, rng=0):
     ms = e0.elapsed_time(e1) / sweeps
     b.close()
     flips = w.spins / (ms / 1e3)
-    peak = alu_peak_flips()
+    peak = lane_ops_peak() / OPS_PER_FLIP_3D
     # each sweep is two k3_sweep launches (one per colour) of half the sites
     out = {"workload": w.name, "spins": w.spins, "sweeps": sweeps, "rng": [k for k, v in RNG_NAMES.items() if v == rng][0],
            "value": flips, "unit": "flip attempts/s", "ms_per_sweep": ms,
            "roofline": {"bound": "alu", "kernel": "k3_sweep", "achieved": flips / 1e9, "peak": peak / 1e9,
                         "unit": "Gflip/s", "frac": flips / peak, "traffic": None, "launch_ms": ms / 2,
-                        "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt"}}
+                        "per_unit": f"{OPS_PER_FLIP_3D} VALU instructions per flip attempt"}}
     from paper_2404_16990_amd import probe
     ceiling = probe.mix3_rate(rng=rng)
     out["roofline"]["measured_alu_ceiling"] = {
@@ -261,14 +301,14 @@ def cluster_leg(work, stream, steps, warmup=2):
     out["workspace_bytes"] = int(b.ws.numel())
     b.ws = None
     b.close()
-    peak_alu = CUS * LANE_OPS_PER_CU_CLK * CLOCK_HZ / SW_SLOTS_PER_SITE
+    peak_alu = lane_ops_peak() / SW_OPS_PER_SITE
     peak_hbm = HBM_BYTES_PER_S / SW_BYTES_PER_SITE
     achieved = out["sw"]["value"]
     out["roofline"] = {
         "bound": "alu", "kernel": "k_cl_local + k_cl_cross<merge> + k_cl_cross<compress> + k_cl_flip (whole SW step)",
         "achieved": achieved / 1e9, "peak": min(peak_alu, peak_hbm) / 1e9, "unit": "Gsite/s",
         "frac": achieved / min(peak_alu, peak_hbm), "traffic": None,
-        "per_unit": f"{SW_SLOTS_PER_SITE:.1f} full-rate VALU slots (1.5 Philox calls) and "
+        "per_unit": f"{SW_OPS_PER_SITE:.0f} VALU instructions (1.5 Philox calls) and "
                     f"{SW_BYTES_PER_SITE:.2f} HBM bytes per site",
         "alu_peak": peak_alu / 1e9, "hbm_peak": peak_hbm / 1e9}
     return out
@@ -321,27 +361,77 @@ def critical_decorrelation(sw_steps, wolff_steps, plain_sweeps):
     return res
 
 
+def roofline_of(m, work, rng_name):
+    """Roofline object of the dominant kernel of a timed plain-path run."""
+    from paper_2404_16990_amd import probe
+    sched = m["schedule"]
+    peak = alu_peak_flips()
+    traffic, algo_bytes = (None, None)
+    if rng_name == "site":
+        kern = m["kernel"].split(" ")[0]
+        spl = sched["sweeps_per_launch"] if m["kernel"] != "k_sweep_stream" else 0
+        traffic, algo_bytes = measured_traffic(kern, work.name, spl)
+    launch_s = m["launch_s"]
+    roof = {"bound": "alu", "kernel": m["kernel"], "achieved": m["achieved"] / 1e9, "peak": peak / 1e9,
+            "unit": "Gflip/s", "frac": m["achieved"] / peak, "traffic": traffic,
+            "per_unit": f"{OPS_PER_FLIP} VALU instructions per flip attempt",
+            "peak_basis": f"{CUS} CUs x {LANE_OPS_PER_CU_CLK} integer VALU lanes per clock x "
+                          f"{CLOCK_HZ / 1e9:.1f} GHz = {lane_ops_peak():.3g} lane-ops/s / {OPS_PER_FLIP}",
+            "launch_ms": launch_s * 1e3, "launches": m["launches"], "flips_per_launch": m["flips_per_launch"],
+            "hbm_bytes_per_launch_algorithmic": algo_bytes,
+            "hbm_frac_of_8TBps": (traffic / launch_s / HBM_BYTES_PER_S) if traffic else None}
+    # measured ALU ceiling: the same per-word arithmetic with no memory traffic
+    ceiling = probe.mix_rate(sched["word_bits"], rng=RNG_NAMES[rng_name])
+    roof["measured_alu_ceiling"] = {
+        "value": ceiling / 1e9, "unit": "Gflip/s",
+        "frac": m["achieved"] / ceiling if ceiling >= m["achieved"] else None,
+        "valid": bool(ceiling >= m["achieved"]),
+        "kernel": f"k_mix<{sched['word_bits']}-bit, rng={rng_name}> (ising::update_word on two "
+                  f"register-resident words per thread, best shape and launch)"}
+    return roof
+
+
+def config_leg(name, args, stream):
+    """Another plain configuration timed like the headline (autotuned, the
+    same steps and warm-up); returns its measurement and roofline."""
+    import torch
+    import workloads
+    work = workloads.ALL[name]()
+    m, b = run_path(work, 0, args, stream)
+    out = {"workload": work.name, "replicas": len(work.replicas), "spins": work.spins,
+           "value": m["value"], "unit": "flip attempts/s", "ms_per_step": m["ms_per_step"],
+           "sweeps_per_step": args.sweeps_per_step, "steps": args.steps, "schedule": m["schedule"],
+           "resident_replicas": m["resident_replicas"], "streamed_replicas": m["streamed_replicas"],
+           "autotune": m["autotune"], "roofline": roofline_of(m, work, "site")}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--sweeps-per-step", type=int, default=100)
-    ap.add_argument("--workload", default="batch_256x1024")
+    ap.add_argument("--workload", default="uneven_512")
+    ap.add_argument("--configs", default="batch_256x1024,paper_scale",
+                    help="other plain configurations timed the same way (comma list, '' for none)")
     ap.add_argument("--rng", default="site", choices=list(RNG_NAMES),
                     help="random-number contract of the measured path (site: one Philox word per site; "
                          "bitsliced: transposed group words drawn lazily)")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the second measurement under the other random-number contract")
-    ap.add_argument("--cpu-sweeps", type=int, default=40)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="JSON dict overriding the execution schedule")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--learned", action="store_true",
-                    help="also run the learned-proposal comparison (64 x 256^2 near T_c)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal comparison (64 x 256^2 near T_c)")
     ap.add_argument("--learned-units", type=int, default=10000)
     ap.add_argument("--plain-sweeps", type=int, default=500000)
-    ap.add_argument("--tune-sweeps", type=int, default=20)
+    ap.add_argument("--tune-sweeps", type=int, default=100)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D (simple cubic) leg")
     ap.add_argument("--cubic-sweeps", type=int, default=200)
     ap.add_argument("--no-cluster", action="store_true",
@@ -360,7 +450,6 @@ def main():
 
     import torch
 
-    from paper_2404_16990_amd import probe
     import workloads
 
     t_start = time.perf_counter()
@@ -376,23 +465,7 @@ def main():
     m, batch = run_path(work, rng, args, stream, json.loads(args.schedule) if args.schedule else None)
     progress("timed steps done")
     sched = m["schedule"]
-    peak = alu_peak_flips()
-    traffic, algo_bytes = (None, None)
-    if rng == 0 and m["kernel"] == "k_sweep_resident" and sched["resident_threads"] == 1024 \
-            and sched["word_bits"] == 64:
-        traffic, algo_bytes = measured_traffic(m["kernel"], work.name, sched["sweeps_per_launch"])
-    launch_s = m["launch_s"]
-    roofline = {"bound": "alu", "kernel": m["kernel"], "achieved": m["achieved"] / 1e9, "peak": peak / 1e9,
-                "unit": "Gflip/s", "frac": m["achieved"] / peak, "traffic": traffic,
-                "per_unit": f"{SLOTS_PER_FLIP:.2f} full-rate VALU slots per flip attempt",
-                "launch_ms": launch_s * 1e3, "launches": m["launches"],
-                "hbm_bytes_per_launch_algorithmic": algo_bytes,
-                "hbm_frac_of_8TBps": (traffic / launch_s / HBM_BYTES_PER_S) if traffic else None}
-    # measured ALU ceiling: the same per-word arithmetic with no memory traffic
-    ceiling = probe.mix_rate(sched["word_bits"], rng=rng)
-    roofline["measured_alu_ceiling"] = {
-        "value": ceiling / 1e9, "unit": "Gflip/s", "frac": m["achieved"] / ceiling,
-        "kernel": f"k_mix<{sched['word_bits']}-bit, rng={args.rng}> (ising::update_word on register-resident words)"}
+    roofline = roofline_of(m, work, args.rng)
 
     out = {
         "metric": "aggregate flip attempts/s on 1 MI355X",
@@ -416,33 +489,39 @@ def main():
     }
     batch.close()
     del batch
+    torch.cuda.empty_cache()
     if not args.no_variant:
         # the same workload under the other random-number contract (its own
         # oracle and parity tests), scheduled and timed the same way
         other = [k for k in RNG_NAMES if k != args.rng][0]
         mv, bv = run_path(work, RNG_NAMES[other], args, stream, json.loads(args.schedule) if args.schedule else None)
-        cv = probe.mix_rate(mv["schedule"]["word_bits"], rng=RNG_NAMES[other])
+        rv = roofline_of(mv, work, other)
         out["variants"] = {f"rng_{other}": {
             "value": mv["value"], "ms_per_step": mv["ms_per_step"], "launch_ms": mv["launch_s"] * 1e3,
             "schedule": mv["schedule"], "autotune": mv["autotune"],
-            "frac_of_derived_peak": mv["achieved"] / peak,
-            "measured_alu_ceiling": cv / 1e9, "frac_of_measured_ceiling": mv["achieved"] / cv}}
+            "frac_of_derived_peak": rv["frac"], "measured_alu_ceiling": rv["measured_alu_ceiling"]}}
         bv.close()
         del bv
-        progress("variant done")
-    if not args.no_cluster:
         torch.cuda.empty_cache()
-        out["cluster"] = cluster_leg(work, stream, args.cluster_steps)
+        progress("variant done")
+    configs = [c for c in args.configs.split(",") if c]
+    if configs:
+        out["configs"] = {}
+        for name in configs:
+            out["configs"][name] = config_leg(name, args, stream)
+            progress(f"config {name} done")
+    if not args.no_cluster:
+        cw = workloads.batch_256x1024()
+        out["cluster"] = cluster_leg(cw, stream, args.cluster_steps)
         progress("cluster steps done")
         if not args.no_cpu_baseline:
-            out["cluster"]["cpu_baseline"] = cluster_cpu_baseline(work, 3)
+            out["cluster"]["cpu_baseline"] = cluster_cpu_baseline(cw, 3)
         if args.critical_steps > 0:
             out["cluster"]["critical"] = critical_decorrelation(args.critical_steps, args.critical_steps,
                                                                 args.critical_sweeps)
             progress("critical comparison done")
         torch.cuda.empty_cache()
     if not args.no_3d:
-        torch.cuda.empty_cache()
         out["cubic"] = cubic_leg(args.cubic_sweeps)
         vb = cubic_leg(args.cubic_sweeps, rng=RNG_NAMES["bitsliced"])
         out["cubic"]["variants"] = {"rng_bitsliced": {k: vb[k] for k in ("value", "ms_per_sweep")}}
@@ -452,12 +531,13 @@ def main():
             out["cubic"]["cpu_baseline"] = cubic_cpu_baseline()
         torch.cuda.empty_cache()
         progress("3D legs done")
+    if not args.no_learned:
+        out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps)
+        torch.cuda.empty_cache()
+        progress("learned comparison done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(work, args.cpu_sweeps, rng)
         progress("CPU baseline done")
-    if args.learned:
-        torch.cuda.empty_cache()
-        out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps)
     print(json.dumps(out), flush=True)
 
 

@@ -255,6 +255,11 @@ int ising_batch_set_schedule(ising_batch *b, const ising_schedule *s);
  * Candidates are searched one schedule field at a time (word width, resident
  * threshold and workgroup size, streaming workgroup shape, sweeps per launch);
  * a candidate replaces the current best only when it is at least 2 % faster.
+ * Every candidate runs the same number of sweeps: trial_sweeps rounded up to
+ * a multiple of 100 (so every sweeps_per_launch candidate, 10, 25, 50 and
+ * 100, runs whole chunks and the graph replays a timed run uses are the ones
+ * timed and checked); its warm-up pass is one chunk (which also captures the
+ * chunk's graph).
  * Afterwards the saved planes and sweep counters are restored, so tuning
  * leaves the simulation unchanged.  If the environment variable
  * ISING_AUTOTUNE_CACHE names a file, a schedule stored there for the same
@@ -269,6 +274,20 @@ int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *c
 
 /* Number of replicas in each execution mode under the current schedule. */
 int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed);
+
+/*
+ * Captured-graph bookkeeping of batch b (host-only, no device call).
+ * ising_batch_run and ising_batch_cluster replay one captured hipGraph per
+ * chunk length (sweeps_per_launch sweeps, or 16 cluster steps per algorithm,
+ * workspace and recording on/off); the trace pointers and record cadence of a
+ * call are written to device memory before its replays, so calls with other
+ * trace buffers reuse the same graph.  *n_cached (optional) receives the
+ * number of executable graphs held now, *n_captured (optional) the number of
+ * captures since the batch was created.  Executable graphs are destroyed
+ * (schedule change, destroy) only after the replays enqueued by the last
+ * call that launched any have finished.  Errors: ISING_E_INVALID (NULL handle).
+ */
+int ising_batch_graph_stats(ising_batch *b, int32_t *n_cached, int64_t *n_captured);
 
 /* ==========================================================================
  * Learned block proposals.
@@ -381,8 +400,10 @@ int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t
 
 int ising_nn_destroy(ising_nn *m);
 
-/* Free host metadata and cached graphs.  Waits for no device work; the caller
- * must not free dev_buf while work on it is still queued. */
+/* Free host metadata and cached graphs.  Waits only for the graph replays
+ * enqueued by the batch's last call that launched any (so their executable
+ * graphs outlive them); the caller must not free dev_buf while work on it is
+ * still queued. */
 int ising_batch_destroy(ising_batch *b);
 
 #ifdef __cplusplus

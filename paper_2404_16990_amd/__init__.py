@@ -25,7 +25,7 @@ EXPORTED = [
     "ising_batch_run", "ising_batch_observables", "ising_batch_get_spins",
     "ising_batch_set_spins", "ising_batch_get_sweep", "ising_batch_set_sweep",
     "ising_batch_set_beta", "ising_batch_get_schedule", "ising_batch_set_schedule",
-    "ising_batch_mode_counts", "ising_batch_autotune", "ising_batch_destroy",
+    "ising_batch_mode_counts", "ising_batch_graph_stats", "ising_batch_autotune", "ising_batch_destroy",
     "ising_nn_param_count", "ising_nn_state_bytes", "ising_nn_create", "ising_nn_get_params",
     "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_train_step_sampled",
     "ising_nn_score",
@@ -97,6 +97,7 @@ def lib():
         L.ising_batch_get_schedule.argtypes = [vp, P(ising_schedule)]
         L.ising_batch_set_schedule.argtypes = [vp, P(ising_schedule)]
         L.ising_batch_mode_counts.argtypes = [vp, P(i32), P(i32)]
+        L.ising_batch_graph_stats.argtypes = [vp, P(i32), P(ctypes.c_int64)]
         L.ising_batch_autotune.argtypes = [vp, i32, P(ising_schedule), P(i32), vp]
         L.ising_batch_destroy.argtypes = [vp]
         f32 = ctypes.c_float
@@ -219,6 +220,13 @@ def ising_batch_set_schedule(h, sched):
 def ising_batch_mode_counts(h):
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().ising_batch_mode_counts(h, ctypes.byref(a), ctypes.byref(b)), "ising_batch_mode_counts")
+    return int(a.value), int(b.value)
+
+
+def ising_batch_graph_stats(h):
+    """Returns (executable graphs held now, captures since creation)."""
+    a, b = ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().ising_batch_graph_stats(h, ctypes.byref(a), ctypes.byref(b)), "ising_batch_graph_stats")
     return int(a.value), int(b.value)
 
 
@@ -455,6 +463,9 @@ class Batch:
 
     def mode_counts(self):
         return ising_batch_mode_counts(self.h)
+
+    def graph_stats(self):
+        return ising_batch_graph_stats(self.h)
 
     def autotune(self, trial_sweeps=10):
         s, n = ising_batch_autotune(self.h, trial_sweeps, self._s())

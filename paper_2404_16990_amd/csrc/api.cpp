@@ -27,6 +27,17 @@ namespace {
 thread_local std::string g_last_error;
 }  // namespace
 
+int ising::wait_graph_replays(ising_batch *b)
+{
+    if (!b->replay_pending)
+        return ISING_OK;
+    const hipError_t e = hipEventSynchronize(b->ev_replay);
+    if (e != hipSuccess)
+        return fail(ISING_E_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    b->replay_pending = false;
+    return ISING_OK;
+}
+
 int ising::fail(int code, const std::string &msg)
 {
     g_last_error = msg;
@@ -95,8 +106,9 @@ int check_desc(const ising_desc &d, int32_t i)
     return ISING_OK;
 }
 
-// Device buffer: [descriptors | schedule lists | observable scratch | init modes |
-//                 couplings | cluster descriptors | cluster tile prefix | planes...]
+// Device buffer: [descriptors | schedule lists | observable scratch | recording
+//                 arguments | init modes | couplings | cluster descriptors |
+//                 cluster tile prefix | planes...]
 int make_layout(int32_t n, const ising_desc *d, Layout *L)
 {
     if (n <= 0 || !d)
@@ -115,6 +127,8 @@ int make_layout(int32_t n, const ising_desc *d, Layout *L)
     off += align256((size_t)(6 * (size_t)n + 2) * sizeof(uint32_t));
     L->obs = off;
     off += align256((size_t)2 * n * sizeof(int64_t));
+    L->rec = off;
+    off += align256(sizeof(RecArgs));
     L->modes = off;
     off += align256((size_t)n * sizeof(int32_t));
     L->kcoup = off;
@@ -138,6 +152,9 @@ namespace {
 
 void drop_graphs(ising_batch *b)
 {
+    if (b->graphs.empty())
+        return;
+    (void)wait_graph_replays(b);
     for (auto &kv : b->graphs)
         (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
@@ -225,8 +242,9 @@ int apply_schedule(ising_batch *b, hipStream_t st)
 // One chunk of `sweeps` sweeps: resident replicas run all of them in one
 // launch (on the auxiliary stream when streaming work runs beside it);
 // streaming replicas get one launch per colour per sweep; then t += sweeps.
-int enqueue_chunk(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipStream_t st)
+int enqueue_chunk(ising_batch *b, uint32_t sweeps, hipStream_t st)
 {
+    const RecArgs *rec = b->d_rec;
     const ising_schedule &s = b->sched;
     const bool have_res = b->res[0].n + b->res[1].n > 0;
     const bool have_str = b->str[0].n + b->str[1].n > 0;
@@ -251,9 +269,9 @@ int enqueue_chunk(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipStream
     return ISING_OK;
 }
 
-int get_graph(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipGraphExec_t *out)
+int get_graph(ising_batch *b, uint32_t sweeps, hipGraphExec_t *out)
 {
-    GraphKey key{sweeps, rec.bond, rec.mag, rec.every, rec.n_rec};
+    const uint32_t key = sweeps;
     auto it = b->graphs.find(key);
     if (it != b->graphs.end()) {
         *out = it->second;
@@ -262,7 +280,7 @@ int get_graph(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipGraphExec_
     if (b->graphs.size() >= 16)
         drop_graphs(b);
     ISING_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    int st = enqueue_chunk(b, sweeps, rec, b->cap);
+    int st = enqueue_chunk(b, sweeps, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (st != ISING_OK) {
@@ -278,6 +296,7 @@ int get_graph(ising_batch *b, uint32_t sweeps, const RecArgs &rec, hipGraphExec_
     if (e != hipSuccess)
         return fail(ISING_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     b->graphs[key] = ex;
+    b->n_captures += 1;
     *out = ex;
     return ISING_OK;
 }
@@ -361,6 +380,7 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
     b->d_rep = reinterpret_cast<RepDev *>(b->buf + L.reps);
     b->d_lists = reinterpret_cast<uint32_t *>(b->buf + L.lists);
     b->d_obs = reinterpret_cast<int64_t *>(b->buf + L.obs);
+    b->d_rec = reinterpret_cast<RecArgs *>(b->buf + L.rec);
     b->d_kcoup = reinterpret_cast<double *>(b->buf + L.kcoup);
     b->rep.resize(n);
     std::vector<int32_t> modes(n);
@@ -402,6 +422,7 @@ int ising_batch_create(int32_t n, const ising_desc *d, void *dev_buf, size_t byt
     CREATE_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     CREATE_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     CREATE_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    CREATE_HIP(hipEventCreateWithFlags(&b->ev_replay, hipEventDisableTiming));
     CREATE_HIP(hipMemcpyAsync(b->d_rep, b->rep.data(), (size_t)n * sizeof(RepDev), hipMemcpyHostToDevice, hs));
     CREATE_HIP(hipMemcpyAsync(b->d_kcoup, kc.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, hs));
     int32_t *d_modes = reinterpret_cast<int32_t *>(b->buf + L.modes);
@@ -449,27 +470,30 @@ int ising_batch_run(ising_batch *b, uint64_t n_sweeps, uint32_t record_every, in
         ISING_HIP(launch_fill_i64(rec.bond, slots, 0, hs));
         ISING_HIP(launch_fill_i64(rec.mag, slots, 0, hs));
     }
+    ISING_HIP(launch_set_rec(b->d_rec, rec, hs));
     ISING_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, hs));
     const uint64_t S = (uint64_t)b->sched.sweeps_per_launch;
     const uint64_t full = n_sweeps / S, rem = n_sweeps % S;
     if (full > 0) {
         if (b->sched.use_graph) {
             hipGraphExec_t ex = nullptr;
-            st = get_graph(b, (uint32_t)S, rec, &ex);
+            st = get_graph(b, (uint32_t)S, &ex);
             if (st != ISING_OK)
                 return st;
             for (uint64_t i = 0; i < full; ++i)
                 ISING_HIP(hipGraphLaunch(ex, hs));
+            ISING_HIP(hipEventRecord(b->ev_replay, hs));
+            b->replay_pending = true;
         } else {
             for (uint64_t i = 0; i < full; ++i) {
-                st = enqueue_chunk(b, (uint32_t)S, rec, hs);
+                st = enqueue_chunk(b, (uint32_t)S, hs);
                 if (st != ISING_OK)
                     return st;
             }
         }
     }
     if (rem > 0) {
-        st = enqueue_chunk(b, (uint32_t)rem, rec, hs);
+        st = enqueue_chunk(b, (uint32_t)rem, hs);
         if (st != ISING_OK)
             return st;
     }
@@ -764,20 +788,31 @@ int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *c
     ISING_HIP(hipEventCreate(&e1));
     const ising_schedule start = b->sched;
     int tried = 0;
-    // time one candidate: warm-up pass, restore, timed pass, compare planes
+    // Every candidate runs the same sweep count, a multiple of 100, so each
+    // sweeps_per_launch candidate (10, 25, 50, 100) runs whole chunks: the
+    // graph replays a timed run uses are what is timed and checked.
+    const uint64_t trial_len = ((uint64_t)trial_sweeps + 99) / 100 * 100;
+    for (int32_t r = 0; r < b->n; ++r)
+        if ((uint64_t)b->rep[r].t + trial_len > 0xffffffffull) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return fail(ISING_E_INVALID, "sweep counter too close to 2^32 for tuning runs");
+        }
+    // time one candidate: warm-up chunk (captures its graph), restore, timed
+    // pass, compare planes
     auto trial = [&](const ising_schedule &c, float *ms) -> int {
         b->sched = c;
         int s2 = apply_schedule(b, hs);
         if (s2 != ISING_OK)
             return s2;
-        s2 = ising_batch_run(b, (uint64_t)trial_sweeps, 0, nullptr, nullptr, hs);
+        s2 = ising_batch_run(b, (uint64_t)c.sweeps_per_launch, 0, nullptr, nullptr, hs);
         if (s2 != ISING_OK)
             return s2;
         s2 = restore_state(b, saved, t0, hs);
         if (s2 != ISING_OK)
             return s2;
         ISING_HIP(hipEventRecord(e0, hs));
-        s2 = ising_batch_run(b, (uint64_t)trial_sweeps, 0, nullptr, nullptr, hs);
+        s2 = ising_batch_run(b, trial_len, 0, nullptr, nullptr, hs);
         if (s2 != ISING_OK)
             return s2;
         ISING_HIP(hipEventRecord(e1, hs));
@@ -853,6 +888,19 @@ int ising_batch_autotune(ising_batch *b, int32_t trial_sweeps, ising_schedule *c
     return ISING_OK;
 }
 
+int ising_batch_graph_stats(ising_batch *b, int32_t *n_cached, int64_t *n_captured)
+{
+    g_last_error.clear();
+    int st = check_handle(b);
+    if (st != ISING_OK)
+        return st;
+    if (n_cached)
+        *n_cached = (int32_t)(b->graphs.size() + b->cl_graphs.size());
+    if (n_captured)
+        *n_captured = b->n_captures;
+    return ISING_OK;
+}
+
 int ising_batch_mode_counts(ising_batch *b, int32_t *n_resident, int32_t *n_streamed)
 {
     g_last_error.clear();
@@ -876,6 +924,8 @@ int ising_batch_destroy(ising_batch *b)
         (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join)
         (void)hipEventDestroy(b->ev_join);
+    if (b->ev_replay)
+        (void)hipEventDestroy(b->ev_replay);
     if (b->aux)
         (void)hipStreamDestroy(b->aux);
     if (b->cap)

@@ -17,32 +17,22 @@
 namespace ising {
 
 struct Layout {
-    size_t reps = 0, lists = 0, obs = 0, modes = 0, kcoup = 0, cl = 0, clprefix = 0;
+    size_t reps = 0, lists = 0, obs = 0, rec = 0, modes = 0, kcoup = 0, cl = 0, clprefix = 0;
     std::vector<size_t> planes;
     size_t total = 0;
 };
 
-// A captured chunk of cluster steps.
+// A captured chunk of cluster steps.  The trace pointers and cadence are not
+// part of the key (the kernels read them from the batch's device slot); only
+// whether the chunk contains recording kernels at all.
 struct ClGraphKey {
     int32_t algorithm;
     uint32_t steps;
     char *ws;
-    int64_t *bond, *mag;
-    uint32_t every, n_rec;
+    bool recording;
     bool operator<(const ClGraphKey &o) const
     {
-        return std::tie(algorithm, steps, ws, bond, mag, every, n_rec) <
-               std::tie(o.algorithm, o.steps, o.ws, o.bond, o.mag, o.every, o.n_rec);
-    }
-};
-
-struct GraphKey {
-    uint32_t sweeps;
-    int64_t *bond, *mag;
-    uint32_t every, n_rec;
-    bool operator<(const GraphKey &o) const
-    {
-        return std::tie(sweeps, bond, mag, every, n_rec) < std::tie(o.sweeps, o.bond, o.mag, o.every, o.n_rec);
+        return std::tie(algorithm, steps, ws, recording) < std::tie(o.algorithm, o.steps, o.ws, o.recording);
     }
 };
 
@@ -58,8 +48,12 @@ uint32_t prob_threshold(double p);
 int cluster_setup(ising_batch *b, hipStream_t st);
 // Bond threshold of replica r after its beta changed (upload on st).
 int cluster_set_beta(ising_batch *b, int32_t r, hipStream_t st);
-// Destroy the batch's captured cluster-step chunks.
+// Destroy the batch's captured cluster-step chunks (after the last replay
+// enqueued on the batch's streams has finished).
 void drop_cluster_graphs(ising_batch *b);
+// Wait until every graph replay enqueued so far has finished (no-op when
+// none was launched since the last wait).
+int wait_graph_replays(ising_batch *b);
 
 }  // namespace ising
 
@@ -74,6 +68,7 @@ struct ising_batch {
     double *d_kcoup = nullptr;  // K = beta*J per replica (device)
     uint32_t *d_lists = nullptr;
     int64_t *d_obs = nullptr;
+    ising::RecArgs *d_rec = nullptr;  // recording arguments of the run being enqueued
     int device = 0;
     int lds_max = 0;        // LDS per workgroup the device allows (bytes)
     ising_schedule sched{};
@@ -83,7 +78,12 @@ struct ising_batch {
     uint32_t max_words = 0;
     hipStream_t aux = nullptr, cap = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    std::map<ising::GraphKey, hipGraphExec_t> graphs;
+    // Captured sweep chunks by sweep count.  ev_replay is recorded after each
+    // call's replays; executable graphs are destroyed only after it completed.
+    std::map<uint32_t, hipGraphExec_t> graphs;
+    hipEvent_t ev_replay = nullptr;
+    bool replay_pending = false;
+    int64_t n_captures = 0;            // sweep and cluster chunks captured so far
     // cluster steps
     std::vector<ising::ClRep> cl;      // host mirror of the cluster descriptors
     std::vector<uint32_t> tile_prefix; // host mirror of the tile prefix (n + 1 entries)

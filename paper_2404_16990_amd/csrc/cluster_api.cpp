@@ -41,22 +41,23 @@ constexpr uint32_t kClChunk = 16;
 
 // n steps (run-local offsets 0 .. n-1 from the device counters), the
 // recording of each, and the counter advance, enqueued on st.
-int enqueue_cluster_chunk(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, const RecArgs &rec,
+// The recording kernels read the run's arguments from the batch's device slot.
+int enqueue_cluster_chunk(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, bool recording,
                           hipStream_t st)
 {
     for (uint32_t j = 0; j < n; ++j) {
         CL_HIP(launch_cluster_step(a, algorithm, j, st));
-        if (rec.every)
-            CL_HIP(launch_observables_rec(b->d_rep, (uint32_t)b->n, b->max_words, rec, j, st));
+        if (recording)
+            CL_HIP(launch_observables_rec(b->d_rep, (uint32_t)b->n, b->max_words, b->d_rec, j, st));
     }
     CL_HIP(launch_advance(b->d_rep, (uint32_t)b->n, n, st));
     return ISING_OK;
 }
 
-int cluster_graph(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, const RecArgs &rec,
+int cluster_graph(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, bool recording,
                   hipGraphExec_t *out)
 {
-    const ClGraphKey key{algorithm, n, a.ws, rec.bond, rec.mag, rec.every, rec.n_rec};
+    const ClGraphKey key{algorithm, n, a.ws, recording};
     auto it = b->cl_graphs.find(key);
     if (it != b->cl_graphs.end()) {
         *out = it->second;
@@ -65,7 +66,7 @@ int cluster_graph(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, co
     if (b->cl_graphs.size() >= 16)
         drop_cluster_graphs(b);
     CL_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    const int st = enqueue_cluster_chunk(b, a, algorithm, n, rec, b->cap);
+    const int st = enqueue_cluster_chunk(b, a, algorithm, n, recording, b->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (st != ISING_OK) {
@@ -81,6 +82,7 @@ int cluster_graph(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, co
     if (e2 != hipSuccess)
         return fail(ISING_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
     b->cl_graphs[key] = ex;
+    b->n_captures += 1;
     *out = ex;
     return ISING_OK;
 }
@@ -89,6 +91,9 @@ int cluster_graph(ising_batch *b, const ClArgs &a, int algorithm, uint32_t n, co
 
 void ising::drop_cluster_graphs(ising_batch *b)
 {
+    if (b->cl_graphs.empty())
+        return;
+    (void)wait_graph_replays(b);
     for (auto &kv : b->cl_graphs)
         (void)hipGraphExecDestroy(kv.second);
     b->cl_graphs.clear();
@@ -174,7 +179,9 @@ int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uin
         CL_HIP(launch_fill_i64(rec.bond, slots, 0, hs));
         CL_HIP(launch_fill_i64(rec.mag, slots, 0, hs));
     }
+    CL_HIP(launch_set_rec(b->d_rec, rec, hs));
     CL_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, hs));
+    const bool recording = rec.every != 0;
     ClArgs a;
     a.reps = b->d_rep;
     a.cl = b->d_cl;
@@ -187,14 +194,16 @@ int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uin
     const uint64_t full = n_steps / kClChunk, rem = n_steps % kClChunk;
     if (full > 0) {
         hipGraphExec_t ex = nullptr;
-        const int st = cluster_graph(b, a, algorithm, kClChunk, rec, &ex);
+        const int st = cluster_graph(b, a, algorithm, kClChunk, recording, &ex);
         if (st != ISING_OK)
             return st;
         for (uint64_t i = 0; i < full; ++i)
             CL_HIP(hipGraphLaunch(ex, hs));
+        CL_HIP(hipEventRecord(b->ev_replay, hs));
+        b->replay_pending = true;
     }
     if (rem > 0) {
-        const int st = enqueue_cluster_chunk(b, a, algorithm, (uint32_t)rem, rec, hs);
+        const int st = enqueue_cluster_chunk(b, a, algorithm, (uint32_t)rem, recording, hs);
         if (st != ISING_OK)
             return st;
     }

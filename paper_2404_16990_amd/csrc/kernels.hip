@@ -126,9 +126,10 @@ __global__ __launch_bounds__(THREADS) void k_sweep_stream(const RepDev *__restri
                                                           const uint32_t *__restrict__ prefix,
                                                           uint32_t nlist, uint32_t words_per_wg,
                                                           uint32_t colour, uint32_t sweep_off,
-                                                          RecArgs rec)
+                                                          const RecArgs *__restrict__ recp)
 {
     constexpr int PER32 = WordTraits<Word>::PER32;
+    const RecArgs rec = *recp;
     // workgroup -> list entry: largest e with prefix[e] <= blockIdx.x
     uint32_t lo = 0, hi = nlist;
     const uint32_t bid = blockIdx.x;
@@ -201,9 +202,10 @@ template <typename Word, int THREADS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, THREADS / 256 > 0 ? THREADS / 256 : 1)))
 void k_sweep_resident(const RepDev *__restrict__ reps,
                                                             const uint32_t *__restrict__ list,
-                                                            uint32_t n_sweeps, RecArgs rec)
+                                                            uint32_t n_sweeps, const RecArgs *__restrict__ recp)
 {
     constexpr int PER32 = WordTraits<Word>::PER32;
+    const RecArgs rec = *recp;
     extern __shared__ uint4 lds4[];
     const uint32_t r = list[blockIdx.x];
     const RepDev d = reps[r];
@@ -308,8 +310,10 @@ __global__ __launch_bounds__(256) void k_observables(const RepDev *__restrict__ 
 // every replica, added to the trace slot (i_run + 1) / every - 1 when
 // (i_run + 1) % every == 0 (the slot is computed on the device, so a captured
 // chunk of steps records correctly on every replay).
-__global__ __launch_bounds__(256) void k_observables_rec(const RepDev *__restrict__ reps, RecArgs rec, uint32_t step)
+__global__ __launch_bounds__(256) void k_observables_rec(const RepDev *__restrict__ reps,
+                                                         const RecArgs *__restrict__ recp, uint32_t step)
 {
+    const RecArgs rec = *recp;
     const uint32_t r = blockIdx.y;
     const RepDev d = reps[r];
     const uint32_t i_run = d.t + step - d.t0;
@@ -358,6 +362,15 @@ __global__ void k_fill_i64(int64_t *__restrict__ p, uint64_t n, int64_t v)
         p[i] = v;
 }
 
+// The recording arguments of the run about to be enqueued, written on the
+// stream in order, so a captured chunk reads the current run's traces on
+// every replay.
+__global__ void k_set_rec(RecArgs *__restrict__ dst, RecArgs v)
+{
+    if (threadIdx.x == 0)
+        *dst = v;
+}
+
 __global__ void k_begin_run(RepDev *__restrict__ reps, uint32_t n)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -391,7 +404,7 @@ hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words
     return hipGetLastError();
 }
 
-hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs &rec,
+hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs *rec,
                                   uint32_t step, hipStream_t st)
 {
     const uint32_t blocks = std::min<uint32_t>((max_words + 255u) / 256u, 2048u);
@@ -408,6 +421,12 @@ hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_set_rec(RecArgs *dst, const RecArgs &v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_rec, dim3(1), dim3(64), 0, st, dst, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_begin_run, dim3((n + 255) / 256), dim3(256), 0, st, reps, n);
@@ -421,7 +440,7 @@ hipError_t launch_advance(RepDev *reps, uint32_t n, uint32_t delta, hipStream_t 
 }
 
 template <typename Word, int T>
-static hipError_t stream_t(const StreamList &L, uint32_t colour, uint32_t sweep_off, const RecArgs &rec,
+static hipError_t stream_t(const StreamList &L, uint32_t colour, uint32_t sweep_off, const RecArgs *rec,
                            hipStream_t st)
 {
     hipLaunchKernelGGL((k_sweep_stream<Word, T>), dim3(L.n_wg), dim3(T), 0, st, L.reps, L.list,
@@ -430,7 +449,7 @@ static hipError_t stream_t(const StreamList &L, uint32_t colour, uint32_t sweep_
 }
 
 hipError_t launch_sweep_stream(const StreamList &L, int word_bits, int threads, uint32_t colour,
-                               uint32_t sweep_off, const RecArgs &rec, hipStream_t st)
+                               uint32_t sweep_off, const RecArgs *rec, hipStream_t st)
 {
     if (L.n == 0)
         return hipSuccess;
@@ -455,7 +474,7 @@ hipError_t launch_sweep_stream(const StreamList &L, int word_bits, int threads, 
 }
 
 template <typename Word, int T>
-static hipError_t resident_t(const ResidentList &L, uint32_t n_sweeps, const RecArgs &rec, hipStream_t st)
+static hipError_t resident_t(const ResidentList &L, uint32_t n_sweeps, const RecArgs *rec, hipStream_t st)
 {
     hipLaunchKernelGGL((k_sweep_resident<Word, T>), dim3(L.n), dim3(T), L.lds_bytes, st, L.reps, L.list,
                        n_sweeps, rec);
@@ -512,7 +531,7 @@ uint32_t resident_static_lds(int /*threads*/)
 }
 
 hipError_t launch_sweep_resident(const ResidentList &L, int word_bits, int threads, uint32_t n_sweeps,
-                                 const RecArgs &rec, hipStream_t st)
+                                 const RecArgs *rec, hipStream_t st)
 {
     if (L.n == 0)
         return hipSuccess;

@@ -35,16 +35,21 @@ hipError_t launch_init(const RepDev *reps, const int32_t *modes, uint32_t n, uin
 hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words, int64_t *bond,
                               int64_t *mag, hipStream_t st, uint32_t stride = 1);
 // Adds replica r's (B, M) after step t + step to its trace slot if the step
-// is a recorded one (slot from the device counters t, t0; see RecArgs).
-hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs &rec,
+// is a recorded one (slot from the device counters t, t0; see RecArgs).  The
+// recording arguments are read from device memory (rec), where
+// launch_set_rec put the current run's, so captured graphs stay valid.
+hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs *rec,
                                   uint32_t step, hipStream_t st);
+// Write the recording arguments of the next run to device memory (a kernel,
+// ordered on the stream like the work that reads them).
+hipError_t launch_set_rec(RecArgs *dst, const RecArgs &v, hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st);
 hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st);
 hipError_t launch_advance(RepDev *reps, uint32_t n, uint32_t delta, hipStream_t st);
 hipError_t launch_sweep_stream(const StreamList &L, int word_bits, int threads, uint32_t colour,
-                               uint32_t sweep_off, const RecArgs &rec, hipStream_t st);
+                               uint32_t sweep_off, const RecArgs *rec, hipStream_t st);
 hipError_t launch_sweep_resident(const ResidentList &L, int word_bits, int threads, uint32_t n_sweeps,
-                                 const RecArgs &rec, hipStream_t st);
+                                 const RecArgs *rec, hipStream_t st);
 // Raise the dynamic-LDS limit of every resident-kernel instantiation.
 hipError_t prepare_resident_kernels(int max_dynamic_lds);
 // Largest static LDS of the resident kernels in bytes, as the runtime reports it.

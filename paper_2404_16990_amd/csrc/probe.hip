@@ -140,17 +140,20 @@ __global__ __launch_bounds__(256) void k_clock(uint64_t *stamps, uint32_t *out, 
 }
 
 // The sweep's per-word arithmetic with no memory traffic: every thread
-// updates one register-resident word per iteration with ising::update_word
-// (classification, Philox, acceptance) from synthetic neighbour words, the
-// updated word feeding the next iteration, and a fresh counter per iteration.
-// Sites per second of this kernel is the measured ALU ceiling of the sweep's
-// instruction mix (thresholds of T_c; no data-dependent branches).
-template <typename Word, bool BITSLICED>
-__global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4,
-                                             uint32_t thr8)
+// updates two register-resident words per iteration with ising::update_word
+// (classification, Philox, acceptance) from synthetic neighbour words and a
+// fresh counter per word and iteration; the results are XOR-accumulated, so no
+// update waits for the previous one.  THREADS and the occupancy hint match the
+// sweep kernels (256 threads as the streaming kernel; 1024 threads with at most
+// four waves per SIMD as the LDS-resident kernel).  Sites per second of the
+// faster shape is the measured ALU ceiling of the sweep's instruction mix
+// (thresholds of T_c; no data-dependent branches).
+template <typename Word, bool BITSLICED, int THREADS>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, THREADS >= 1024 ? 4 : 8)))
+void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8)
 {
     using ising::SweepKey;
-    const uint32_t tid = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t tid = blockIdx.x * (uint32_t)THREADS + threadIdx.x;
     SweepKey K;
     K.k0 = seed;
     K.k1 = seed * 3u + 1u;
@@ -161,15 +164,20 @@ __global__ __launch_bounds__(256) void k_mix(uint32_t *out, uint32_t seed, int i
     K.thr8 = thr8;
     K.always = 0u;
     K.rng = BITSLICED ? 1u : 0u;
-    Word s = (Word)(tid * 0x9E3779B97F4A7C15ull), up = (Word)(tid * 0xC2B2AE3D27D4EB4Full),
-         dn = (Word)(tid * 0x165667B19E3779F9ull), same = (Word)(tid * 0x27D4EB2F165667C5ull);
+    const Word s0 = (Word)(tid * 0x9E3779B97F4A7C15ull), s1 = (Word)(tid * 0xD6E8FEB86659FD93ull);
+    const Word up = (Word)(tid * 0xC2B2AE3D27D4EB4Full), dn = (Word)(tid * 0x165667B19E3779F9ull);
+    const Word same = (Word)(tid * 0x27D4EB2F165667C5ull);
     const Word side = same ^ up;
     constexpr uint32_t QW = ising::WordTraits<Word>::BITS / 4;
+    Word acc = 0;
     for (int i = 0; i < iters; ++i) {
         K.t = (uint32_t)i;
-        s = ising::update_word<Word, BITSLICED>(s, up, dn, same, side, (tid + (uint32_t)i * 0x100000u) * QW, K);
+        const Word v = (Word)(uint32_t)i * (Word)0x9E3779B9u;
+        const uint32_t q = (2u * tid + (uint32_t)i * 0x200000u) * QW;
+        acc ^= ising::update_word<Word, BITSLICED>(s0 ^ v, up, dn, same, side, q, K);
+        acc ^= ising::update_word<Word, BITSLICED>(s1 ^ v, dn, up, side, same, q + QW, K);
     }
-    out[tid] = (uint32_t)s ^ (uint32_t)((uint64_t)s >> 32);
+    out[tid] = (uint32_t)acc ^ (uint32_t)((uint64_t)acc >> 32);
 }
 
 // The 3D sweep's per-word arithmetic (six-input classification, Philox,
@@ -234,6 +242,39 @@ hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
     return hipGetLastError();
 }
 
+// Shortest of `reps` timed k_mix launches (after one warm-up launch) in each
+// of the two launch shapes.
+template <typename Word, bool BITSLICED>
+hipError_t mix_best(uint32_t *o, int blocks, int iters, unsigned thr4, unsigned thr8, int reps, hipEvent_t e0,
+                    hipEvent_t e1, float *best)
+{
+    hipError_t err = hipSuccess;
+    for (int shape = 0; shape < 2 && err == hipSuccess; ++shape) {
+        for (int rep = 0; rep <= reps && err == hipSuccess; ++rep) {
+            err = hipEventRecord(e0, nullptr);
+            if (err != hipSuccess)
+                break;
+            if (shape == 0)
+                hipLaunchKernelGGL((k_mix<Word, BITSLICED, 256>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u,
+                                   iters, thr4, thr8);
+            else
+                hipLaunchKernelGGL((k_mix<Word, BITSLICED, 1024>), dim3(blocks / 4), dim3(1024), 0, nullptr, o,
+                                   12345u, iters, thr4, thr8);
+            err = hipGetLastError();
+            if (err == hipSuccess)
+                err = hipEventRecord(e1, nullptr);
+            if (err == hipSuccess)
+                err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess)
+                err = hipEventElapsedTime(&ms, e0, e1);
+            if (err == hipSuccess && rep > 0 && (*best <= 0.f || ms < *best))
+                *best = ms;
+        }
+    }
+    return err;
+}
+
 }  // namespace
 
 extern "C" {
@@ -271,45 +312,32 @@ int ising_probe_mix3(void *out, int blocks, int iters, unsigned thr4, unsigned t
 }
 
 /* Measured ALU ceiling of the sweep's per-word arithmetic: k_mix with 32- or
- * 64-bit words on blocks x 256 threads for iters iterations (after a warm-up
- * launch), under the site (rng 0) or bit-sliced (rng 1) random-number
- * contract.  Sites counted: blocks * 256 * iters * word_bits.  Writes the
- * milliseconds of the timed launch to *ms; returns 0, or <0 on error. */
+ * 64-bit words under the site (rng 0) or bit-sliced (rng 1) random-number
+ * contract, in two launch shapes with the same total thread count: blocks x
+ * 256 threads, and blocks / 4 x 1024 threads (blocks must be a multiple of 4).
+ * Each shape runs one warm-up launch, then `reps` timed launches; *ms receives
+ * the shortest timed launch over both shapes.  Sites counted per launch:
+ * blocks * 256 * iters * 2 * word_bits.  Returns 0, or <0 on error. */
 int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned thr4, unsigned thr8, int rng,
-                    float *ms)
+                    int reps, float *ms)
 {
-    if (!out || blocks <= 0 || iters <= 0 || !ms || (word_bits != 32 && word_bits != 64) || (rng != 0 && rng != 1))
+    if (!out || blocks <= 0 || blocks % 4 != 0 || iters <= 0 || reps <= 0 || !ms ||
+        (word_bits != 32 && word_bits != 64) || (rng != 0 && rng != 1))
         return -1;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return -4;
     uint32_t *o = static_cast<uint32_t *>(out);
-    hipError_t err = hipSuccess;
-    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
-        if (rep == 1)
-            err = hipEventRecord(e0, nullptr);
-        if (err != hipSuccess)
-            break;
-        if (word_bits == 32 && rng == 0)
-            hipLaunchKernelGGL((k_mix<uint32_t, false>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
-                               thr8);
-        else if (word_bits == 32)
-            hipLaunchKernelGGL((k_mix<uint32_t, true>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
-                               thr8);
-        else if (rng == 0)
-            hipLaunchKernelGGL((k_mix<uint64_t, false>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
-                               thr8);
-        else
-            hipLaunchKernelGGL((k_mix<uint64_t, true>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u, iters, thr4,
-                               thr8);
-        err = hipGetLastError();
-    }
-    if (err == hipSuccess)
-        err = hipEventRecord(e1, nullptr);
-    if (err == hipSuccess)
-        err = hipEventSynchronize(e1);
-    if (err == hipSuccess)
-        err = hipEventElapsedTime(ms, e0, e1);
+    *ms = 0.f;
+    hipError_t err;
+    if (word_bits == 32 && rng == 0)
+        err = mix_best<uint32_t, false>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+    else if (word_bits == 32)
+        err = mix_best<uint32_t, true>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+    else if (rng == 0)
+        err = mix_best<uint64_t, false>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+    else
+        err = mix_best<uint64_t, true>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return err == hipSuccess ? 0 : -4;

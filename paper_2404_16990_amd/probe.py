@@ -48,22 +48,25 @@ def measure(blocks=256 * 16, iters=4096):
             "philox_lane_cycles_per_call": xor / res["philox4x32_10"]}
 
 
-def mix_rate(word_bits=64, blocks=256 * 16, iters=64, T=2.269185, rng=0):
+def mix_rate(word_bits=64, blocks=256 * 16, iters=128, T=2.269185, rng=0, reps=5):
     """Measured ALU ceiling of the sweep's per-word arithmetic, in site updates
-    (flip attempts) per second: k_mix runs ising::update_word on register-resident
-    words (classification, Philox4x32-10, acceptance) with no memory traffic."""
+    (flip attempts) per second: k_mix runs ising::update_word on two
+    register-resident words per thread (classification, Philox4x32-10,
+    acceptance) with no memory traffic and no dependence between updates, in
+    the streaming and the LDS-resident kernels' launch shapes; the best of
+    `reps` timed launches per shape after a warm-up launch."""
     import math
     import torch
     L = _lib()
     L.ising_probe_mix.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
-                                  ctypes.c_uint, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+                                  ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     thr = [min(int(math.floor(math.ldexp(math.exp(-4.0 * k / T), 32))), 2**32 - 1) for k in (1, 2)]
     out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     ms = ctypes.c_float()
-    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], int(rng),
+    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], int(rng), int(reps),
                          ctypes.byref(ms)) != 0:
         raise RuntimeError("mix probe failed")
-    return blocks * 256 * iters * word_bits / (ms.value * 1e-3)
+    return blocks * 256 * iters * 2 * word_bits / (ms.value * 1e-3)
 
 
 def mix3_rate(blocks=256 * 16, iters=64, T=4.5115, rng=0):

@@ -67,6 +67,9 @@ def lib():
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
                                        ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int32]
+        L.oracle_sweeps_rows.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int32]
         L.oracle_bond_threshold.argtypes = [ctypes.c_double, ctypes.c_double, u32p,
                                             ctypes.POINTER(ctypes.c_int32)]
         L.oracle_cluster_labels.argtypes = [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_uint32,
@@ -162,33 +165,64 @@ def sweeps(d, s, n, t0=0, record_every=0):
     return bond[:n_rec], mag[:n_rec]
 
 
+def sweeps_rows(d, s, n, t0=0, record_every=0, threads=None):
+    """sweeps() on host threads that split the rows of each colour phase
+    (the same result for every thread count)."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape == (d.Ly, d.Lx)
+    n_rec = n // record_every if record_every else 0
+    bond = np.zeros(max(n_rec, 1), dtype=np.int64)
+    mag = np.zeros(max(n_rec, 1), dtype=np.int64)
+    if threads is None:
+        threads = default_threads()
+    st = lib().oracle_sweeps_rows(ctypes.byref(d), s.ctypes.data, int(t0), int(n), int(record_every),
+                                  bond.ctypes.data if n_rec else None,
+                                  mag.ctypes.data if n_rec else None, int(threads))
+    if st != 0:
+        raise ValueError("invalid arguments")
+    return bond[:n_rec], mag[:n_rec]
+
+
 def run_batch(descs, states, n, t0=None, record_every=0, threads=None):
     """Sweep many replicas in place on host threads.
 
     ``states`` is a list of (Ly, Lx) int8 arrays; returns (bond, mag) traces of
-    shape (n_replicas, n // record_every).
+    shape (n_replicas, n // record_every).  A replica larger than an even
+    share of the batch (total spins / threads), or any replica when there are
+    fewer replicas than threads, runs alone on all threads split over its rows
+    (sweeps_rows); the rest run one replica per thread.  Every split gives the
+    same result.
     """
     nrep = len(descs)
-    arr = (Desc * nrep)(*descs)
-    ptrs = (ctypes.c_void_p * nrep)()
     for r, s in enumerate(states):
         assert s.dtype == np.int8 and s.flags.c_contiguous
         assert s.shape == (descs[r].Ly, descs[r].Lx)
-        ptrs[r] = s.ctypes.data
     n_rec = n // record_every if record_every else 0
     bond = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
     mag = np.zeros((nrep, max(n_rec, 1)), dtype=np.int64)
-    t0a = None
-    if t0 is not None:
-        t0a = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.uint64), (nrep,)))
+    t0s = np.broadcast_to(np.asarray(0 if t0 is None else t0, dtype=np.uint64), (nrep,))
     if threads is None:
         threads = default_threads()
-    st = lib().oracle_run_batch(nrep, arr, ptrs, t0a.ctypes.data if t0a is not None else None,
-                                int(n), int(record_every),
-                                bond.ctypes.data if n_rec else None,
-                                mag.ctypes.data if n_rec else None, int(threads))
-    if st != 0:
-        raise ValueError("invalid arguments")
+    sizes = [d.Lx * d.Ly for d in descs]
+    share = sum(sizes) / max(threads, 1)
+    alone = [r for r in range(nrep) if threads > 1 and (nrep < threads or sizes[r] > share)]
+    for r in alone:
+        b, m = sweeps_rows(descs[r], states[r], n, int(t0s[r]), record_every, threads)
+        bond[r, :n_rec], mag[r, :n_rec] = b, m
+    taken = set(alone)
+    rest = [r for r in range(nrep) if r not in taken]
+    if rest:
+        k = len(rest)
+        arr = (Desc * k)(*[descs[r] for r in rest])
+        ptrs = (ctypes.c_void_p * k)(*[states[r].ctypes.data for r in rest])
+        t0a = np.ascontiguousarray(t0s[rest])
+        rb = np.zeros((k, max(n_rec, 1)), dtype=np.int64)
+        rm = np.zeros((k, max(n_rec, 1)), dtype=np.int64)
+        st = lib().oracle_run_batch(k, arr, ptrs, t0a.ctypes.data, int(n), int(record_every),
+                                    rb.ctypes.data if n_rec else None,
+                                    rm.ctypes.data if n_rec else None, int(threads))
+        if st != 0:
+            raise ValueError("invalid arguments")
+        bond[rest], mag[rest] = rb, rm
     return bond[:, :n_rec], mag[:, :n_rec]
 
 

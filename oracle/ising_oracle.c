@@ -49,6 +49,7 @@
  *  - observables: B = sum_{x,y} s(x,y) (s(x+1,y) + s(x,y+1)) (every bond
  *    once), M = sum s, E = -J B.
  */
+#define _POSIX_C_SOURCE 200112L /* pthread barriers */
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
@@ -231,14 +232,17 @@ void oracle_observables(int32_t Lx, int32_t Ly, const int8_t *s, int64_t *bond, 
 
 /* ---- one sweep: red sites, then blue sites (Supplementary algorithm S2) -- */
 
-static void flip_colour(const oracle_desc *d, int8_t *s, uint32_t t, int colour,
-                        uint32_t thr4, uint32_t thr8, int32_t always)
+/* Update the colour-`colour` sites of rows y_begin .. y_end - 1.  They read
+ * only sites of the other colour, so any split of the rows gives the same
+ * result. */
+static void flip_colour_rows(const oracle_desc *d, int8_t *s, uint32_t t, int colour,
+                             uint32_t thr4, uint32_t thr8, int32_t always, int32_t y_begin, int32_t y_end)
 {
     const int32_t Lx = d->Lx, Ly = d->Ly;
     int32_t x, y;
     group_words cache;
     cache.valid = 0;
-    for (y = 0; y < Ly; ++y) {
+    for (y = y_begin; y < y_end; ++y) {
         for (x = 0; x < Lx; ++x) {
             int64_t i = (int64_t)y * Lx + x;
             int32_t sum, dE;
@@ -260,6 +264,12 @@ static void flip_colour(const oracle_desc *d, int8_t *s, uint32_t t, int colour,
                 s[i] = (int8_t)(-s[i]);
         }
     }
+}
+
+static void flip_colour(const oracle_desc *d, int8_t *s, uint32_t t, int colour,
+                        uint32_t thr4, uint32_t thr8, int32_t always)
+{
+    flip_colour_rows(d, s, t, colour, thr4, thr8, always, 0, d->Ly);
 }
 
 /*
@@ -291,7 +301,8 @@ int oracle_sweeps(const oracle_desc *d, int8_t *s, uint64_t t0, uint64_t n,
 /* ---- many independent replicas on host threads -------------------------- */
 
 typedef struct {
-    int32_t n, stride, first;
+    int32_t n;
+    int32_t *next; /* shared: the next replica not yet taken */
     const oracle_desc *d;
     int8_t *const *states;
     const uint64_t *t0;
@@ -306,7 +317,7 @@ static void *batch_worker(void *arg)
 {
     batch_job *job = (batch_job *)arg;
     int32_t r;
-    for (r = job->first; r < job->n; r += job->stride) {
+    while ((r = __atomic_fetch_add(job->next, 1, __ATOMIC_RELAXED)) < job->n) {
         int64_t *b = job->bond ? job->bond + (uint64_t)r * job->n_rec : NULL;
         int64_t *m = job->mag ? job->mag + (uint64_t)r * job->n_rec : NULL;
         int st = oracle_sweeps(&job->d[r], job->states[r], job->t0 ? job->t0[r] : 0,
@@ -317,14 +328,15 @@ static void *batch_worker(void *arg)
     return NULL;
 }
 
-/* Replica r runs on thread r % n_threads; results do not depend on n_threads. */
+/* Threads take replicas one at a time in index order until none is left;
+ * replicas are independent, so results do not depend on n_threads. */
 int oracle_run_batch(int32_t n, const oracle_desc *d, int8_t *const *states, const uint64_t *t0,
                      uint64_t n_sweeps, uint32_t record_every, int64_t *bond, int64_t *mag,
                      int32_t n_threads)
 {
     batch_job *jobs;
     pthread_t *tids;
-    int32_t k, started = 0;
+    int32_t k, started = 0, next = 0;
     int status = OR_OK;
     if (n <= 0)
         return OR_EINVAL;
@@ -341,8 +353,7 @@ int oracle_run_batch(int32_t n, const oracle_desc *d, int8_t *const *states, con
     }
     for (k = 0; k < n_threads; ++k) {
         jobs[k].n = n;
-        jobs[k].stride = n_threads;
-        jobs[k].first = k;
+        jobs[k].next = &next;
         jobs[k].d = d;
         jobs[k].states = states;
         jobs[k].t0 = t0;
@@ -358,10 +369,7 @@ int oracle_run_batch(int32_t n, const oracle_desc *d, int8_t *const *states, con
             break;
         started = k;
     }
-    batch_worker(&jobs[0]);
-    /* any thread that failed to start has its share run here */
-    for (k = started + 1; k < n_threads; ++k)
-        batch_worker(&jobs[k]);
+    batch_worker(&jobs[0]); /* threads that failed to start leave their replicas to the others */
     for (k = 1; k <= started; ++k)
         pthread_join(tids[k], NULL);
     for (k = 0; k < n_threads; ++k)
@@ -370,4 +378,123 @@ int oracle_run_batch(int32_t n, const oracle_desc *d, int8_t *const *states, con
     free(jobs);
     free(tids);
     return status;
+}
+
+/* ---- one lattice on host threads: the rows of a colour split between them -- */
+
+typedef struct {
+    const oracle_desc *d;
+    int8_t *s;
+    uint64_t t0, n;
+    uint32_t record_every;
+    int64_t *bond, *mag;
+    uint32_t thr4, thr8;
+    int32_t always;
+    int32_t index;
+    /* shared */
+    pthread_mutex_t *lock;
+    pthread_cond_t *gate;
+    int32_t *n_workers; /* -1 until every thread that will take part has started */
+    pthread_barrier_t *bar;
+} rows_job;
+
+static void *rows_worker(void *arg)
+{
+    rows_job *j = (rows_job *)arg;
+    int32_t nw, y0, y1;
+    uint64_t i;
+    pthread_mutex_lock(j->lock);
+    while (*j->n_workers < 0)
+        pthread_cond_wait(j->gate, j->lock);
+    nw = *j->n_workers;
+    pthread_mutex_unlock(j->lock);
+    y0 = (int32_t)((int64_t)j->index * j->d->Ly / nw);
+    y1 = (int32_t)((int64_t)(j->index + 1) * j->d->Ly / nw);
+    for (i = 0; i < j->n; ++i) {
+        uint32_t t = (uint32_t)(j->t0 + i);
+        int colour;
+        for (colour = 0; colour < 2; ++colour) {
+            flip_colour_rows(j->d, j->s, t, colour, j->thr4, j->thr8, j->always, y0, y1);
+            pthread_barrier_wait(j->bar);
+        }
+        if (j->record_every && j->bond && j->mag && (i + 1) % j->record_every == 0) {
+            if (j->index == 0) {
+                uint64_t k = (i + 1) / j->record_every - 1;
+                oracle_observables(j->d->Lx, j->d->Ly, j->s, &j->bond[k], &j->mag[k]);
+            }
+            pthread_barrier_wait(j->bar);
+        }
+    }
+    return NULL;
+}
+
+/*
+ * oracle_sweeps for one lattice on up to n_threads host threads (at most one
+ * per row): in each colour phase thread k updates rows Ly*k/m .. Ly*(k+1)/m - 1
+ * of the m threads that started, then all wait for each other.  Sites of one
+ * colour only read the other colour and every uniform is a function of
+ * (seed, replica, sweep, colour, site), so the result equals oracle_sweeps
+ * for every thread count.
+ */
+int oracle_sweeps_rows(const oracle_desc *d, int8_t *s, uint64_t t0, uint64_t n, uint32_t record_every,
+                       int64_t *bond, int64_t *mag, int32_t n_threads)
+{
+    uint32_t thr4, thr8;
+    int32_t always, k, started = 0, n_workers = -1;
+    rows_job *jobs;
+    pthread_t *tids;
+    pthread_mutex_t lock = PTHREAD_MUTEX_INITIALIZER;
+    pthread_cond_t gate = PTHREAD_COND_INITIALIZER;
+    pthread_barrier_t bar;
+    if (!desc_ok(d) || t0 + n > 0x100000000ull)
+        return OR_EINVAL;
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > d->Ly)
+        n_threads = d->Ly;
+    if (n_threads == 1)
+        return oracle_sweeps(d, s, t0, n, record_every, bond, mag);
+    oracle_thresholds(d->J, d->beta, &thr4, &thr8, &always);
+    jobs = (rows_job *)calloc((size_t)n_threads, sizeof(rows_job));
+    tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !tids) {
+        free(jobs);
+        free(tids);
+        return OR_ENOMEM;
+    }
+    for (k = 0; k < n_threads; ++k) {
+        jobs[k].d = d;
+        jobs[k].s = s;
+        jobs[k].t0 = t0;
+        jobs[k].n = n;
+        jobs[k].record_every = record_every;
+        jobs[k].bond = bond;
+        jobs[k].mag = mag;
+        jobs[k].thr4 = thr4;
+        jobs[k].thr8 = thr8;
+        jobs[k].always = always;
+        jobs[k].index = k;
+        jobs[k].lock = &lock;
+        jobs[k].gate = &gate;
+        jobs[k].n_workers = &n_workers;
+        jobs[k].bar = &bar;
+    }
+    /* threads 1.. wait at the gate until the number of participants is known */
+    for (k = 1; k < n_threads; ++k) {
+        if (pthread_create(&tids[k], NULL, rows_worker, &jobs[k]) != 0)
+            break;
+        started = k;
+    }
+    pthread_barrier_init(&bar, NULL, (unsigned)(started + 1));
+    pthread_mutex_lock(&lock);
+    n_workers = started + 1;
+    pthread_cond_broadcast(&gate);
+    pthread_mutex_unlock(&lock);
+    rows_worker(&jobs[0]);
+    for (k = 1; k <= started; ++k)
+        pthread_join(tids[k], NULL);
+    pthread_barrier_destroy(&bar);
+    free(jobs);
+    free(tids);
+    return OR_OK;
 }

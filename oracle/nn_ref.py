@@ -134,9 +134,18 @@ def nll(logits, x):
     return float(np.mean(np.logaddexp(0.0, z)))
 
 
-def loss_and_grad(theta, C, x, bnd, beta):
-    """Mean per-site negative log-likelihood and its gradient (flat, float64)."""
-    logits, cache = forward(theta, C, x, bnd, beta)
+def loss_and_grad(theta, C, x, bnd, beta, bf16=False):
+    """Mean per-site negative log-likelihood and its gradient (flat, float64).
+
+    With bf16=True the gradient is evaluated at the rounding points of the
+    matrix-core layers: the forward is forward(..., bf16=True), and in the
+    backward the gradient of each layer-2..4 pre-activation is rounded to
+    bfloat16 before it enters the two products of that layer (its weight
+    gradient against the bfloat16 inputs, and the gradient passed to the
+    layer below through the bfloat16 weights).  Bias and layer-1 gradients
+    use the unrounded values; the loss is always the exact one.
+    """
+    logits, cache = forward(theta, C, x, bnd, beta, bf16=bf16)
     x = np.asarray(x, dtype=np.float64)
     n = x.size
     loss = nll(logits, x)
@@ -151,7 +160,9 @@ def loss_and_grad(theta, C, x, bnd, beta):
     for l in (4, 3, 2):
         dpre = dh * (1.0 - hs[l - 1] ** 2)
         G[f"b{l}"] = dpre.sum(axis=(0, 1, 2))
-        hin = hs[l - 2]
+        hin = bf16_round(hs[l - 2]) if bf16 else hs[l - 2]
+        if bf16:
+            dpre = bf16_round(dpre)
         dh = np.zeros_like(hin)
         for t, (di, dj) in enumerate(TAPS_B):
             G[f"W{l}"][t] = np.einsum("nijc,nijd->cd", _shift(hin, di, dj), dpre)
@@ -193,3 +204,53 @@ def sample(theta, C, bnd, beta, uniforms):
         logits, _ = forward(theta, C, x[None], np.asarray(bnd)[None], np.asarray([beta]))
         x[i, j] = 1.0 if uniforms[k] < threshold(logits[0, i, j]) else -1.0
     return x
+
+
+def adam_step(theta, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One step of Adam (Kingma and Ba, 2015, Algorithm 1) in float64.
+
+    t is the 1-based step number; m, v the first and second moment estimates
+    before the step (zeros before the first).  Returns (theta', m', v'):
+      m' = b1 m + (1 - b1) g,   v' = b2 v + (1 - b2) g^2,
+      theta' = theta - lr (m' / (1 - b1^t)) / (sqrt(v' / (1 - b2^t)) + eps).
+    """
+    g = np.asarray(grad, dtype=np.float64)
+    m2 = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v2 = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    mhat = m2 / (1.0 - b1 ** t)
+    vhat = v2 / (1.0 - b2 ** t)
+    return np.asarray(theta, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m2, v2
+
+
+def thresholds(logits):
+    """Vectorised threshold() over an array of logits (uint64 values)."""
+    p = 1.0 / (1.0 + np.exp(-np.asarray(logits, dtype=np.float64)))
+    return np.clip(np.floor(p * 4294967296.0), 1, 4294967295).astype(np.uint64)
+
+
+def sample_batch(theta, C, bnd, beta, uniforms, bf16=False):
+    """sample() for N blocks at once: uniforms (N, Bs*Bs) uint32; site k of
+    every block is drawn from the logits of the blocks drawn so far.
+    Returns (x (N, Bs, Bs) of +-1, thresholds (N, Bs*Bs) used at each site)."""
+    u = np.asarray(uniforms, dtype=np.uint64)
+    N, BB = u.shape
+    Bs = int(round(math.sqrt(BB)))
+    x = np.zeros((N, Bs, Bs))
+    thr = np.zeros((N, BB), dtype=np.uint64)
+    beta = np.asarray(beta, dtype=np.float64)
+    for k in range(BB):
+        i, j = divmod(k, Bs)
+        logits, _ = forward(theta, C, x, bnd, beta, bf16=bf16)
+        thr[:, k] = thresholds(logits[:, i, j])
+        x[:, i, j] = np.where(u[:, k] < thr[:, k], 1.0, -1.0)
+    return x, thr
+
+
+def log_q_batch(theta, C, x, bnd, beta, bf16=False):
+    """log_q() for N blocks at once: x (N, Bs, Bs) of +-1.  Returns (log q (N,),
+    per-site logits (N, Bs, Bs))."""
+    x = np.asarray(x, dtype=np.float64)
+    logits, _ = forward(theta, C, x, bnd, beta, bf16=bf16)
+    thr = thresholds(logits).astype(np.float64)
+    chosen = np.where(x > 0, thr, 4294967296.0 - thr)
+    return (np.log(chosen) - 32 * math.log(2.0)).sum(axis=(1, 2)), logits

@@ -245,6 +245,31 @@ def test_record_every_and_threads_do_not_change_results():
         assert np.array_equal(b, b1[r]) and np.array_equal(s, st1[r])
 
 
+@pytest.mark.parametrize("rng", [0, 1])
+def test_row_split_threads_do_not_change_results(rng):
+    """One lattice whose colour phases are split over its rows on 2..64 threads
+    (row counts that do not divide, one thread per row, more threads than rows)
+    equals the single-thread sweep, traces included; run_batch's mix of
+    row-split replicas and one-replica-per-thread replicas does too."""
+    for Lx, Ly in ((24, 14), (64, 6), (10, 2)):
+        d = oracle.desc(Lx, Ly, beta=1 / 2.4, seed=77, replica=3, rng=rng)
+        ref = oracle.init_state(d)
+        b0, m0 = oracle.sweeps(d, ref, 30, t0=5, record_every=3)
+        for th in (2, 3, 5, 7, 64):
+            s = oracle.init_state(d)
+            b, m = oracle.sweeps_rows(d, s, 30, t0=5, record_every=3, threads=th)
+            assert np.array_equal(s, ref) and np.array_equal(b, b0) and np.array_equal(m, m0), (Lx, Ly, th)
+    descs = [oracle.desc(64, 64, beta=0.4, seed=5, replica=0, rng=rng)] + \
+            [oracle.desc(8, 4, beta=0.5, seed=6 + r, replica=1 + r, rng=rng) for r in range(5)]
+    for th in (4, 16):   # the 64 x 64 replica alone on all threads; then every replica row-split
+        st1 = [oracle.init_state(d) for d in descs]
+        st2 = [s.copy() for s in st1]
+        b1, m1 = oracle.run_batch(descs, st1, 12, t0=[3, 0, 1, 2, 3, 4], record_every=4, threads=1)
+        b2, m2 = oracle.run_batch(descs, st2, 12, t0=[3, 0, 1, 2, 3, 4], record_every=4, threads=th)
+        assert all(np.array_equal(x, y) for x, y in zip(st1, st2))
+        assert np.array_equal(b1, b2) and np.array_equal(m1, m2)
+
+
 @pytest.mark.parametrize("rng,name", [(0, "oracle_single64.json"), (1, "oracle_single64_bitsliced.json")])
 def test_oracle_golden_trace_single_64(rng, name):
     """Regression pin: the stored trace was written by a script that calls only the oracle."""

@@ -77,3 +77,16 @@ def equilibration(x, candidates=100):
         if ne > best[2]:
             best = (t0, g, ne)
     return best
+
+
+def batch_means_error(x, n_bins=10):
+    """Mean of a correlated series and the standard error of the mean of n_bins
+    consecutive equal bins (the tail beyond a whole number of bins dropped).
+    Independent of any autocorrelation estimate; unbiased once a bin is much
+    longer than the series' autocorrelation time."""
+    x = np.asarray(x, dtype=np.float64)
+    m = x.size // n_bins
+    if m < 1 or n_bins < 2:
+        return float(x.mean()), float("nan")
+    b = x[:m * n_bins].reshape(n_bins, m).mean(axis=1)
+    return float(x.mean()), float(b.std(ddof=1) / np.sqrt(n_bins))

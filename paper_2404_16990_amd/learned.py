@@ -108,13 +108,26 @@ def summarise(trace, seconds, units_per_trace_point, replica):
             "run_over_tau": trace.shape[1] / tau}
 
 
-def agreement(tr_a, tr_b):
-    """Per replica z of <|m|> between two traces with tau-corrected errors."""
+def agreement(tr_a, tr_b, n_bins=0):
+    """Per replica z of the mean of two traces: errors from Sokal's windowed
+    tau_int (n_bins = 0) or from batch means over n_bins bins."""
     zs = []
     for r in range(tr_a.shape[0]):
-        ta, _ = analysis.tau_int(tr_a[r])
-        tb, _ = analysis.tau_int(tr_b[r])
-        ma, ea = analysis.mean_and_error(tr_a[r], ta)
-        mb, eb = analysis.mean_and_error(tr_b[r], tb)
+        if n_bins:
+            ma, ea = analysis.batch_means_error(tr_a[r], n_bins)
+            mb, eb = analysis.batch_means_error(tr_b[r], n_bins)
+        else:
+            ta, _ = analysis.tau_int(tr_a[r])
+            tb, _ = analysis.tau_int(tr_b[r])
+            ma, ea = analysis.mean_and_error(tr_a[r], ta)
+            mb, eb = analysis.mean_and_error(tr_b[r], tb)
         zs.append((ma - mb) / np.sqrt(ea * ea + eb * eb) if ea + eb > 0 else 0.0)
     return np.array(zs)
+
+
+def agreement_summary(z):
+    """Fraction of |z| < 2 (0.954 for correct Gaussian errors), max |z| and
+    chi^2 per degree of freedom, mean(z^2) (1 for correct errors)."""
+    z = np.asarray(z, dtype=np.float64)
+    return {"within_2sigma": float(np.mean(np.abs(z) < 2)), "max_abs_z": float(np.max(np.abs(z))),
+            "chi2_per_dof": float(np.mean(z * z))}

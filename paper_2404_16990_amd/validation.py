@@ -16,6 +16,7 @@ analyses the recorded traces on the host.
 import argparse
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -54,10 +55,13 @@ def expected_m(T, L, J=1.0):
     return spontaneous_m(T, J) if T < T_C * J else finite_size_m(T, L, J)
 
 
-def run_size(L, temps, sweeps, every, rng, seed0=16990, chunks=10, log=print, cluster_burnin=0):
+def run_size(L, temps, sweeps, every, rng, seed0=16990, chunks=10, log=print, cluster_burnin=0,
+             keep_traces=False):
     """One size of the campaign.  With cluster_burnin > 0 the random starts
     are first equilibrated by that many Swendsen-Wang steps (same batch, same
-    step counter); the measured trace is always Metropolis sweeps."""
+    step counter); the measured trace is always Metropolis sweeps.  With
+    keep_traces the result also holds the recorded magnetisations M (int64,
+    replicas x sweeps // every) under "mag"."""
     import torch
     descs = [dict(Lx=L, Ly=L, J=1.0, beta=1.0 / T, seed=seed0 + i, replica=i, init=0, rng=rng)
              for i, T in enumerate(temps)]
@@ -78,12 +82,25 @@ def run_size(L, temps, sweeps, every, rng, seed0=16990, chunks=10, log=print, cl
     t0 = time.perf_counter()
     for c in range(chunks):
         _, mag = b.run(per, every)
-        traces.append(np.abs(mag.cpu().numpy().astype(np.float64)) / n)
+        traces.append(mag.cpu().numpy())
         log(f"L={L}: {(c + 1) * per} of {sweeps} sweeps, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     b.close()
-    m = np.concatenate(traces, axis=1)
+    mag = np.concatenate(traces, axis=1)
+    rows = analyse(mag, temps, L, every)
+    out = {"L": L, "sweeps": sweeps, "every": every, "seconds": seconds, "cluster_burnin": cluster_burnin,
+           "cluster_burnin_s": burnin_s, "flips_per_s": len(temps) * n * sweeps / seconds, "rows": rows}
+    if keep_traces:
+        out["mag"] = mag
+    return out
+
+
+def analyse(mag, temps, L, every):
+    """Per temperature: the equilibration point of the |m| trace (Chodera's
+    automatic detection), <|m|> after it with its tau-corrected error, and
+    the comparison values."""
+    m = np.abs(np.asarray(mag, dtype=np.float64)) / float(L * L)
     rows = []
     for i, T in enumerate(temps):
         t_eq, g, n_eff = analysis.equilibration(m[i])
@@ -93,8 +110,7 @@ def run_size(L, temps, sweeps, every, rng, seed0=16990, chunks=10, log=print, cl
         rows.append({"T": round(float(T), 6), "m": mean, "err": err, "exact": spontaneous_m(T),
                      "expected": expected_m(float(T), L),
                      "t_eq_sweeps": int(t_eq * every), "n_eff": float(n_eff)})
-    return {"L": L, "sweeps": sweeps, "every": every, "seconds": seconds, "cluster_burnin": cluster_burnin,
-            "cluster_burnin_s": burnin_s, "flips_per_s": len(temps) * n * sweeps / seconds, "rows": rows}
+    return rows
 
 
 def summarise(res, band=0.05):
@@ -124,7 +140,9 @@ def main():
     ap.add_argument("--rng", default="bitsliced", choices=["site", "bitsliced"])
     ap.add_argument("--cluster-burnin", type=int, default=0,
                     help="Swendsen-Wang steps before the Metropolis sweeps (0: none, as in the paper)")
-    ap.add_argument("--out", default="")
+    ap.add_argument("--out", default="", help="JSON file for every row of every size")
+    ap.add_argument("--summary", default="",
+                    help="JSON file for the agreement summary of each size, its timing and the command line")
     args = ap.parse_args()
     temps = np.round(np.arange(args.t_min, args.t_max + 0.5 * args.dt, args.dt), 6)
     rng = 1 if args.rng == "bitsliced" else 0
@@ -137,6 +155,17 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             json.dump({"rng": args.rng, "results": results}, f)
+    if args.summary:
+        sizes = []
+        for res in results:
+            keep = ("L", "sweeps", "every", "seconds", "cluster_burnin", "cluster_burnin_s", "flips_per_s")
+            e = {k: res[k] for k in keep}
+            e["summary"] = summarise(res)
+            e["rows_every_0.25"] = [r for r in res["rows"] if abs(round(r["T"] / 0.25) * 0.25 - r["T"]) < 1e-9]
+            sizes.append(e)
+        with open(args.summary, "w") as f:
+            json.dump({"command": "python -m paper_2404_16990_amd.validation " + " ".join(sys.argv[1:]),
+                       "rng": args.rng, "temperatures": len(temps), "sizes": sizes}, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -42,3 +42,20 @@ def test_equilibration_keeps_a_stationary_series():
 def test_equilibration_of_a_constant_series():
     t0, g, ne = analysis.equilibration(np.ones(100))
     assert t0 == 0 and g == 1.0
+
+
+def test_batch_means_error_of_ar1():
+    """For AR(1) with coefficient phi the error of the mean of n samples is
+    sqrt(var * 2 tau / n), tau = (1 + phi) / (2 (1 - phi)); with bins much
+    longer than tau the batch-means estimate agrees with it (mean over many
+    independent series, so the check is sharp)."""
+    rng = np.random.default_rng(5)
+    phi, n, bins = 0.9, 40000, 10
+    tau = (1 + phi) / (2 * (1 - phi))
+    var = 1.0 / (1 - phi * phi)
+    want = np.sqrt(var * 2 * tau / n)
+    errs = [analysis.batch_means_error(_ar1(rng, n, phi), bins)[1] for _ in range(40)]
+    assert abs(np.mean(errs) / want - 1) < 0.1, (np.mean(errs), want)
+    # uncorrelated samples: the plain standard error
+    x = rng.normal(size=n)
+    assert abs(analysis.batch_means_error(x, 20)[1] / (1 / np.sqrt(n)) - 1) < 0.45

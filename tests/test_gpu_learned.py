@@ -1,13 +1,19 @@
 """Learned block proposals on the GPU, through the C ABI.
 
 - the BF16 matrix-core lane layout the kernels assume;
-- forward logits against the float64 reference evaluated at the same BF16
-  rounding points; gradients against the exact float64 backward;
-- the incremental pass: causal, sum_x q(x) = 1, scoring reproduces the
-  sampler's own log q bit for bit, sampler frequencies match q;
+- forward logits and gradients, element by element, against the float64
+  reference evaluated at the same BF16 rounding points;
+- Adam steps against a float64 Adam step fed the GPU's own gradient;
+- training blocks extracted from the lattice against their definition (Philox
+  positions, periodic boundary strips), bit for bit;
+- the incremental pass at block sizes 8 and 4: log q and the sampled sites
+  against the float64 network, causal, sum_x q(x) = 1, scoring reproduces
+  the sampler's own log q bit for bit, sampler frequencies match q;
 - Metropolis-Hastings block rounds keep the Boltzmann distribution: mean
   energy against the exact transfer-matrix / Kaufman values, with untrained
-  and trained networks, alone and interleaved with checkerboard sweeps;
+  and trained networks, alone and interleaved with checkerboard sweeps, and
+  at the benchmark's shape (256^2, 8 x 8 blocks, trained network) against
+  Kaufman's 256^2 energy with independent-replica errors;
 - training lowers the loss and raises the block acceptance rate.
 """
 import itertools
@@ -74,7 +80,15 @@ def test_forward_matches_reference_at_bf16_points(Bs):
     assert abs(float(loss.cpu()) - nn_ref.nll(exact_ref, x.reshape(-1, Bs, Bs))) < 5e-3
 
 
-def test_gradient_matches_float64_backward():
+def test_gradient_matches_float64_backward_at_bf16_points():
+    """Gradient element by element against the float64 backward evaluated at the
+    kernels' bfloat16 rounding points (weights and inputs of the layer-2..4
+    products, and the pre-activation gradients entering the backward
+    products).  Only fp32 arithmetic differs, so the bound is cosine >= 0.9999
+    and max |error| <= 1e-2 of the largest gradient, in every parameter group;
+    per element, |error| <= 2e-2 |g| + 1e-3 of the group's largest entry (one
+    bfloat16 rounding flip, 2^-8 relative, moves a product's contribution by
+    less than that)."""
     import torch
     P = _P()
     rng = np.random.default_rng(3)
@@ -85,17 +99,144 @@ def test_gradient_matches_float64_backward():
     _, grad, _ = net.forward_backward(_dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32))
     torch.cuda.synchronize()
     gg = grad.cpu().numpy().astype(np.float64)
-    _, ref = nn_ref.loss_and_grad(theta.astype(np.float64), C, x.reshape(-1, Bs, Bs).astype(np.float64), bnd, kc)
+    xb = x.reshape(-1, Bs, Bs).astype(np.float64)
+    _, ref = nn_ref.loss_and_grad(theta.astype(np.float64), C, xb, bnd, kc, bf16=True)
     cos = float(gg @ ref / (np.linalg.norm(gg) * np.linalg.norm(ref)))
-    rel = float(np.linalg.norm(gg - ref) / np.linalg.norm(ref))
-    # BF16 operands (8 significant bits) in the forward and backward GEMMs
-    assert cos > 0.999 and rel < 0.05, (cos, rel)
-    # every parameter group gets a gradient of the right size
+    nmax = float(np.abs(gg - ref).max() / np.abs(ref).max())
+    print(f"gradient vs bf16-point reference: cos {cos:.8f}, normalised max error {nmax:.2e}")
+    assert cos >= 0.9999 and nmax <= 1e-2, (cos, nmax)
     Pg, Pr = nn_ref.unpack(gg, C), nn_ref.unpack(ref, C)
     for k in Pr:
-        nr = np.linalg.norm(Pr[k])
-        if nr > 1e-8:
-            assert np.linalg.norm(Pg[k] - Pr[k]) / nr < 0.1, k
+        scale = np.abs(Pr[k]).max()
+        if scale < 1e-12:
+            continue
+        err = np.abs(Pg[k] - Pr[k])
+        assert err.max() <= 1e-2 * scale, (k, err.max() / scale)
+        bad = err > 2e-2 * np.abs(Pr[k]) + 1e-3 * scale
+        assert not bad.any(), (k, int(bad.sum()), float((err / scale).max()))
+    # the exact float64 backward is close as well (BF16 operands: 8 significant bits)
+    _, exact_ref = nn_ref.loss_and_grad(theta.astype(np.float64), C, xb, bnd, kc)
+    cos_e = float(gg @ exact_ref / (np.linalg.norm(gg) * np.linalg.norm(exact_ref)))
+    assert cos_e > 0.999, cos_e
+
+
+def test_adam_steps_match_float64_adam():
+    """Four training steps: each step's parameters equal one float64 Adam step
+    (Kingma and Ba, 2015; beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected)
+    applied to the previous reference parameters with the gradient the GPU
+    computed for that step, to fp32 rounding (a few ulps of the parameter plus
+    1e-5 of the step size per step)."""
+    import torch
+    P = _P()
+    rng = np.random.default_rng(31)
+    Bs, lr = 8, 2e-3
+    theta0 = _params(1.0)
+    net = P.Net(theta0, block=Bs, max_batch=64, max_seq=64)
+    th = theta0.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for t in range(1, 5):
+        x, bnd, kc = _rand_blocks(rng, 40, Bs)
+        X, BN, K = _dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32)
+        _, grad, _ = net.forward_backward(X, BN, K)
+        g = grad.cpu().numpy().astype(np.float64)   # the gradient the step itself recomputes (deterministic)
+        net.train_step(X, BN, K, lr)
+        torch.cuda.synchronize()
+        th, m, v = nn_ref.adam_step(th, g, m, v, t, lr)
+        got = net.params.astype(np.float64)
+        tol = t * (4 * np.spacing(np.abs(th).astype(np.float32)).astype(np.float64) + 1e-5 * lr)
+        err = np.abs(got - th)
+        assert np.all(err <= tol), (t, int((err > tol).sum()), float((err / tol).max()))
+        # the step really moved every parameter with a nonzero gradient by ~lr
+        moved = np.abs(got - theta0.astype(np.float64)) if t == 1 else None
+        if t == 1:
+            nz = np.abs(g) > 1e-6
+            assert np.all(moved[nz] > 0.5 * lr), float(moved[nz].min())
+
+
+def test_extract_blocks_follow_their_definition():
+    """Training blocks: sample i of replica r sits at bx = w0 mod Lx/Bs,
+    by = w1 mod Ly/Bs with (w0, w1, ...) = Philox(ctr = {i, draw, replica, 5},
+    key = seed); block spins, the four boundary strips and K = beta*J are read
+    from the lattice itself (get_spins), with periodic wrap."""
+    import torch
+    from oracle import philox
+    P = _P()
+    Lx, Ly, R = 128, 48, 3
+    descs = [dict(Lx=Lx, Ly=Ly, J=1.0 + 0.25 * r, beta=0.41 + 0.02 * r, seed=0xFEED0000 + 977 * r, replica=5 + r,
+                  init=0) for r in range(R)]
+    b = P.Batch(descs)
+    b.run(7)
+    spins = [b.get_spins(r).astype(np.int8) for r in range(R)]
+    for Bs, per, draw in ((8, 60, 3), (4, 50, 0xFFFFFFFF), (2, 40, 17)):
+        blocks, bnd, coup = b.extract_blocks(Bs, per, draw)
+        torch.cuda.synchronize()
+        blocks, bnd, coup = blocks.cpu().numpy(), bnd.cpu().numpy(), coup.cpu().numpy()
+        edges = set()
+        for q in range(R * per):
+            r, i = divmod(q, per)
+            d = descs[r]
+            o = philox.philox4x32_10((i, draw, d["replica"], 5), philox.seed_key(d["seed"]))
+            bx, by = o[0] % (Lx // Bs), o[1] % (Ly // Bs)
+            x0, y0 = bx * Bs, by * Bs
+            s = spins[r]
+            assert np.array_equal(blocks[q], s[y0:y0 + Bs, x0:x0 + Bs].ravel()), (Bs, q)
+            expect = np.concatenate([s[(y0 - 1) % Ly, x0:x0 + Bs], s[(y0 + Bs) % Ly, x0:x0 + Bs],
+                                     s[y0:y0 + Bs, (x0 - 1) % Lx], s[y0:y0 + Bs, (x0 + Bs) % Lx]])
+            assert np.array_equal(bnd[q], expect), (Bs, q)
+            assert coup[q] == np.float32(d["beta"] * d["J"]), (Bs, q)
+            edges.add((bx == 0, by == 0, bx == Lx // Bs - 1, by == Ly // Bs - 1))
+        assert len(edges) > 2  # wrapped boundaries were among the draws
+
+
+@pytest.mark.parametrize("Bs", [8, 4])
+def test_sampler_and_scorer_match_the_float64_network(Bs):
+    """The incremental kernels at the production block sizes against the float64
+    network at the same bfloat16 rounding points.  log q is a sum of Bs^2 terms
+    log sigmoid(+-logit), each moving by at most |d logit| (slope <= 1), so the
+    forward bound on logits (5e-3 max, 3e-4 mean) gives |d log q| <= Bs^2 * 5e-3
+    and a mean <= Bs^2 * 3e-4.  The sampler, fed the uniforms of its definition,
+    draws the reference's sites until the first site whose uniform lies within
+    2^32 * sigmoid' * 5e-3 <= 2^32 * 1.25e-3 of the reference threshold."""
+    import torch
+    from oracle import philox
+    P = _P()
+    rng = np.random.default_rng(40 + Bs)
+    theta = _params(1.5, seed=41)
+    th64 = theta.astype(np.float64)
+    n, BB = 64, Bs * Bs
+    _, bnd, kc = _rand_blocks(rng, n, Bs)
+    net = P.Net(theta, block=Bs, max_batch=16, max_seq=n)
+    dbnd, dkc = _dev(bnd, torch.int8), _dev(kc, torch.float32)
+    seed, replica, round_, blk0 = 0xABCDEF012345, 7, 11, 300
+    xs, lq = net.sample(dbnd, dkc, seed=seed, replica=replica, round_=round_, blk0=blk0)
+    xr = np.where(rng.random((n, BB)) < 0.5, 1, -1).astype(np.int8)
+    lq_r = net.score(_dev(xr, torch.int8), dbnd, dkc)
+    torch.cuda.synchronize()
+    xs, lq, lq_r = xs.cpu().numpy(), lq.cpu().numpy(), lq_r.cpu().numpy()
+    # log q of the sampled blocks and of random blocks
+    for blocks, got in ((xs, lq), (xr, lq_r)):
+        ref, _ = nn_ref.log_q_batch(th64, C, blocks.reshape(n, Bs, Bs).astype(np.float64), bnd, kc, bf16=True)
+        d = np.abs(got - ref)
+        assert d.max() <= BB * 5e-3 and d.mean() <= BB * 3e-4, (d.max(), d.mean())
+    # sampled sites against the reference sampler with the same uniforms
+    key = philox.seed_key(seed)
+    u = np.zeros((n, BB), dtype=np.uint64)
+    for i in range(n):
+        for k in range(BB):
+            s = (blk0 + i) * BB + k
+            u[i, k] = philox.philox4x32_10((s >> 2, round_, replica, 3), key)[s & 3]
+    rx, rthr = nn_ref.sample_batch(th64, C, bnd, kc, u, bf16=True)
+    margin = 2.0 ** 32 * 1.25e-3
+    identical = 0
+    for i in range(n):
+        diff = np.nonzero(xs[i] != rx[i].ravel())[0]
+        if len(diff) == 0:
+            identical += 1
+            continue
+        k = diff[0]
+        assert abs(float(u[i, k]) - float(rthr[i, k])) < margin, (i, k, int(u[i, k]), int(rthr[i, k]))
+    assert identical >= n // 2, identical
 
 
 def test_q_sums_to_one_and_is_causal():
@@ -263,3 +404,36 @@ def test_sampled_minibatch_rows_follow_the_philox_definition():
         b.train_step(_dev(x[rows], torch.int8), _dev(bnd[rows], torch.int8), _dev(kc[rows], torch.float32), 1e-3)
         torch.cuda.synchronize()
         assert np.array_equal(a.params, b.params), k
+
+
+def test_block_moves_exact_at_the_production_shape():
+    """The benchmark's learned path on 256^2 lattices with 8 x 8 blocks and a
+    network trained on the plain sampler's blocks: 48 independent replicas at
+    T = 2.3 (distinct seeds), equilibrated by Swendsen-Wang steps, then units
+    of one block round (both block colours) and one checkerboard sweep.  The
+    mean energy per spin over the replicas' run means must equal Kaufman's
+    exact value for the 256 x 256 torus within 4 standard errors of the
+    spread between independent replicas (an error estimate that needs no
+    autocorrelation time), and the blocks must really move."""
+    import torch
+    from paper_2404_16990_amd import learned
+    P = _P()
+    R, L, T = 48, 256, 2.3
+    descs = [dict(Lx=L, Ly=L, J=1.0, beta=1.0 / T, seed=31000 + r, replica=r, init=0) for r in range(R)]
+    b = P.Batch(descs)
+    b.cluster(150, "sw")
+    b.run(200)
+    X, BN, K = learned.collect_blocks(b, 8, 16, 24, 25)
+    net = P.Net(workloads.nn_initial_params(C), block=8, max_batch=512, max_seq=65536)
+    hist = learned.train(net, X, BN, K, 400, 512, 2e-3, seed=3, log_every=100)
+    assert hist[-1][1] < 0.8 * hist[0][1], hist
+    acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+    _, e, _ = learned.unit_traces(b, 400, learned.learned_units(b, net, 0, acc))
+    rate = float(acc.sum().cpu()) / (400 * R * (L // 8) ** 2)
+    assert rate > 0.2, rate
+    means = e[:, 50:].mean(axis=1)
+    exact_e = exact.kaufman_energy(L, L, T)
+    z = (means.mean() - exact_e) / (means.std(ddof=1) / math.sqrt(R))
+    print(f"256^2 learned chain at T = {T}: <e> = {means.mean():.6f} +- {means.std(ddof=1) / math.sqrt(R):.6f}, "
+          f"exact {exact_e:.6f}, z = {z:.2f}, block acceptance {rate:.3f}")
+    assert abs(z) < 4, (means.mean(), exact_e, z)

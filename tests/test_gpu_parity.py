@@ -263,20 +263,6 @@ def test_batch_256x1024_all_replicas_20_sweeps():
     assert_states(b, w.replicas, states, which=range(0, 256, 17))
 
 
-def test_batch_256x1024_sampled_replicas_1000_sweeps():
-    """The whole batch for 1000 sweeps at the benchmark's cadence (record every
-    100) in its launch configuration; four replicas across the temperature
-    range against the oracle, traces and final states."""
-    w = workloads.batch_256x1024()
-    b = gpu_batch(w.replicas)
-    gb, gm = gpu_run(b, 1000, w.record_every)
-    idx = [0, 85, 170, 255]
-    states, ob, om = oracle_run([w.replicas[i] for i in idx], 1000, w.record_every)
-    assert np.array_equal(gb[idx], ob) and np.array_equal(gm[idx], om)
-    for k, i in enumerate(idx):
-        assert np.array_equal(b.get_spins(i), states[k]), i
-
-
 # ---- autotuner: state untouched, self-checked candidates, cache ---------------------
 
 def test_autotune_leaves_state_and_keeps_parity(tmp_path, monkeypatch):
@@ -301,49 +287,7 @@ def test_autotune_leaves_state_and_keeps_parity(tmp_path, monkeypatch):
     assert n2 == 0 and sched2 == sched
 
 
-# ---- full-size uneven and paper-scale batches, sampled replicas -----------------------
-
-def _sample_by_size(reps, per_size=1):
-    seen = {}
-    for i, r in enumerate(reps):
-        seen.setdefault((r.Lx, r.Ly), [])
-        if len(seen[(r.Lx, r.Ly)]) < per_size:
-            seen[(r.Lx, r.Ly)].append(i)
-    return sorted(i for v in seen.values() for i in v)
-
-
-def test_uneven_512_sampled():
-    w = workloads.uneven_512()
-    b = gpu_batch(w.replicas)
-    n_res, n_str = b.mode_counts()
-    assert n_res > 0 and n_str > 0  # both execution modes run side by side
-    gb, gm = gpu_run(b, 4, 2)
-    idx = _sample_by_size(w.replicas)
-    sub = [w.replicas[i] for i in idx]
-    states, ob, om = oracle_run(sub, 4, 2)
-    assert np.array_equal(gb[idx], ob) and np.array_equal(gm[idx], om)
-    for k, i in enumerate(idx):
-        assert np.array_equal(b.get_spins(i), states[k]), (i, w.replicas[i].Lx)
-
-
-def test_paper_scale_sampled():
-    w = workloads.paper_scale()
-    b = gpu_batch(w.replicas)
-    gb, gm = gpu_run(b, 2, 1)
-    big = len(w.replicas) - 1
-    small = list(range(0, big, 63))
-    idx = small + [big]
-    sub = [w.replicas[i] for i in idx]
-    states, ob, om = oracle_run(sub, 2, 1)
-    assert np.array_equal(gb[idx], ob) and np.array_equal(gm[idx], om)
-    assert np.array_equal(b.get_spins(big), states[-1])
-    # 18 more sweeps: the small replicas against the oracle continued from its states
-    gb, gm = gpu_run(b, 18, 18)
-    ssub = sub[:-1]
-    sb, sm = oracle.run_batch([odesc(r) for r in ssub], states[:-1], 18, t0=2, record_every=18)
-    assert np.array_equal(gb[small], sb) and np.array_equal(gm[small], sm)
-    for k, i in enumerate(small):
-        assert np.array_equal(b.get_spins(i), states[k])
+# (the uneven 512-replica and paper-scale batches at full size: test_gpu_parity_scale.py)
 
 
 # ---- hipGraph replays interleaved with eager work --------------------------------------

@@ -474,6 +474,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal comparison (64 x 256^2 near T_c)")
     ap.add_argument("--learned-units", type=int, default=10000)
+    ap.add_argument("--learned-train-steps", type=int, default=2000,
+                    help="Adam steps of the learned leg's training (fewer only to profile it)")
     ap.add_argument("--plain-sweeps", type=int, default=500000)
     ap.add_argument("--tune-sweeps", type=int, default=100)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D (simple cubic) leg")
@@ -554,7 +556,7 @@ def main():
         torch.cuda.empty_cache()
         progress("3D legs done")
     if not args.no_learned:
-        out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps)
+        out["learned"] = learned_comparison(args.learned_units, args.plain_sweeps, args.learned_train_steps)
         torch.cuda.empty_cache()
         progress("learned comparison done")
     if not args.no_cpu_baseline:
@@ -563,7 +565,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def learned_comparison(units, plain_sweeps):
+def learned_comparison(units, plain_sweeps, train_steps=2000):
     """Effective independent |m| samples per second at T_c: plain checkerboard
     sweeps against learned 8x8 block proposals (1 block round : 1 sweep).
 
@@ -588,7 +590,7 @@ def learned_comparison(units, plain_sweeps):
     X, BN, K = learned.collect_blocks(b, 8, 16, 98, 100)
     net = P.Net(workloads.nn_initial_params(64), block=8, max_batch=512, max_seq=65536)
     t0 = time.perf_counter()
-    hist = learned.train(net, X, BN, K, 2000, 512, 2e-3, log_every=500)
+    hist = learned.train(net, X, BN, K, train_steps, 512, 2e-3, log_every=500)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     tr_p, e_p, s_p = learned.plain_trace(b, plain_sweeps, 10)
@@ -613,7 +615,7 @@ def learned_comparison(units, plain_sweeps):
     return {
         "metric": "effective independent |m| samples/s at T_c (one replica, whole-batch time)",
         "workload": w.name, "replica_at_tc": t_c, "T": w.replicas[t_c].T,
-        "training": {"blocks": int(X.shape[0]), "steps": 2000, "batch": 512, "lr": 2e-3,
+        "training": {"blocks": int(X.shape[0]), "steps": train_steps, "batch": 512, "lr": 2e-3,
                      "loss": hist, "seconds": t_train},
         "plain": plain, "learned": lrn,
         "block_acceptance": float(acc.cpu().sum()) / (units * len(descs) * 1024),
@@ -621,7 +623,7 @@ def learned_comparison(units, plain_sweeps):
                      "achieved": flop_unit * units / s_l / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": flop_unit * units / s_l / 2.5e15, "traffic": None,
                      "per_unit": f"{flop_unit / 1e9:.1f} GFLOP of BF16 MFMA per unit"},
-        "training_tflops": flop_train_step * 2000 / t_train / 1e12,
+        "training_tflops": flop_train_step * train_steps / t_train / 1e12,
         "learned_over_plain": lrn["effective_samples_per_s"] / plain["effective_samples_per_s"],
         "energy_agreement": dict(learned.agreement_summary(ze), z=[round(float(v), 3) for v in ze],
                                  batch_means=learned.agreement_summary(zeb)),

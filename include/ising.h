@@ -342,8 +342,14 @@ int ising_nn_forward_backward(ising_nn *m, const int8_t *dev_blocks, const int8_
                               const float *dev_coupling, int32_t batch, float *dev_logits, float *dev_grad,
                               float *dev_loss, void *stream);
 
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on `batch` blocks; the loss
- * before the step goes to dev_loss.  Asynchronous. */
+/* One Adam step (Kingma and Ba's Algorithm 1: beta1 0.9, beta2 0.999, eps
+ * 1e-8, bias corrections 1 - beta^t with t the step number since the
+ * parameters were last set, kept on the device) on `batch` blocks; the loss
+ * before the step goes to dev_loss.  The whole step (forward, backward,
+ * Adam, BF16 weight copies) is captured into a hipGraph the first time it is
+ * called with a given set of arguments and replayed afterwards; at most 8
+ * argument sets are kept (the oldest are destroyed once their replays have
+ * finished).  Asynchronous. */
 int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd, const float *dev_coupling,
                         int32_t batch, float lr, float *dev_loss, void *stream);
 
@@ -398,6 +404,11 @@ int ising_batch_extract_blocks(ising_batch *b, int32_t block, int32_t per_replic
  * with Lx and Ly multiples of 2*Bs.  Asynchronous. */
 int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t *dev_accepts, void *stream);
 
+/* Captured training steps held now (*n_cached) and captured since creation
+ * (*n_captured); either may be NULL.  Host-only. */
+int ising_nn_graph_stats(ising_nn *m, int32_t *n_cached, int64_t *n_captured);
+
+/* Free host metadata and captured graphs (after their replays finished). */
 int ising_nn_destroy(ising_nn *m);
 
 /* Free host metadata and cached graphs.  Waits only for the graph replays

@@ -29,7 +29,8 @@ EXPORTED = [
     "ising_nn_param_count", "ising_nn_state_bytes", "ising_nn_create", "ising_nn_get_params",
     "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_train_step_sampled",
     "ising_nn_score",
-    "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_destroy",
+    "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_graph_stats",
+    "ising_nn_destroy",
     "ising_cluster_ws_bytes", "ising_batch_cluster",
     "ising3d_state_bytes", "ising3d_batch_create", "ising3d_batch_run", "ising3d_batch_observables",
     "ising3d_batch_get_spins", "ising3d_batch_set_spins", "ising3d_batch_get_sweep", "ising3d_batch_destroy",
@@ -113,6 +114,7 @@ def lib():
         L.ising_nn_sample.argtypes = [vp, i32, vp, vp, u64, u32, u32, u32, vp, vp, vp]
         L.ising_batch_extract_blocks.argtypes = [vp, i32, i32, u32, vp, vp, vp, vp]
         L.ising_batch_block_round.argtypes = [vp, vp, u32, vp, vp]
+        L.ising_nn_graph_stats.argtypes = [vp, P(i32), P(ctypes.c_int64)]
         L.ising_nn_destroy.argtypes = [vp]
         L.ising_cluster_ws_bytes.argtypes = [vp, P(ctypes.c_size_t)]
         L.ising_batch_cluster.argtypes = [vp, i32, u64, u32, vp, ctypes.c_size_t, vp, vp, vp]
@@ -367,6 +369,13 @@ def ising_batch_block_round(b, m, round_, accepts=None, stream=None):
     _check(lib().ising_batch_block_round(b, m, int(round_), accepts, stream), "ising_batch_block_round")
 
 
+def ising_nn_graph_stats(m):
+    n = ctypes.c_int32()
+    c = ctypes.c_int64()
+    _check(lib().ising_nn_graph_stats(m, ctypes.byref(n), ctypes.byref(c)), "ising_nn_graph_stats")
+    return int(n.value), int(c.value)
+
+
 def ising_nn_destroy(m):
     _check(lib().ising_nn_destroy(m), "ising_nn_destroy")
 
@@ -554,6 +563,10 @@ class Net:
         ising_nn_sample(self.h, n, bnd.data_ptr(), coupling.data_ptr(), seed, replica, round_, blk0,
                         out.data_ptr(), logq.data_ptr(), self._s())
         return out, logq
+
+    def graph_stats(self):
+        """(captured training steps held, captured since creation)."""
+        return ising_nn_graph_stats(self.h)
 
     def close(self):
         if getattr(self, "h", None) is not None:

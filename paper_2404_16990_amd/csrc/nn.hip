@@ -18,12 +18,11 @@ namespace nn {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// float -> bfloat16 bits, round to nearest even (inputs are finite)
+// float -> bfloat16 bits, round to nearest even (inputs are finite): one
+// v_cvt_pk_bf16_f32 on gfx950
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 // tanh from the hardware exp2 and reciprocal: tanh|x| = (1 - e)/(1 + e), e = exp(-2|x|).
@@ -54,57 +53,78 @@ __device__ __forceinline__ bf16x8 zero_bf16x8()
 }
 
 // ---------------------------------------------------------------------------
-// parameters -> BF16 GEMM operands
+// parameters -> BF16 matrix-core operands
 // ---------------------------------------------------------------------------
 __global__ void k_cast_weights(const float *__restrict__ params, uint16_t *__restrict__ wt,
-                               uint16_t *__restrict__ wtt)
+                               uint16_t *__restrict__ wtd)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over 3 * C * KB
     if (idx >= 3 * C * KB)
         return;
     const int l = idx / (C * KB), r = idx - l * C * KB;
     const int c = r / KB, k = r - c * KB;          // output channel, K index t*C + c'
-    const float w = params[off_w(l + 2) + k * C + c];  // W_l[t][c'][c]
-    const uint16_t b = f2bf(w);
+    const int t = k / C, ci = k - t * C;
+    const uint16_t b = f2bf(params[off_w(l + 2) + k * C + c]);  // W_l[t][c'][c]
     wt[(l * C + c) * KB + k] = b;
-    wtt[(l * KB + k) * C + c] = b;
+    wtd[(l * C + ci) * KB + t * C + c] = b;
 }
 
 // ---------------------------------------------------------------------------
-// generic C[M][N] = sum_k A[m][k] * Bt[n][k]   (BF16 in, FP32 out)
-// 256 threads, 64x64 tile, each wave a 32x32 quarter of 2x2 MFMA 16x16x32.
-// Requires K % 32 == 0 and 16-byte aligned rows (lda, ldb multiples of 8).
+// Masked 3x3 convolution of a layer as an implicit GEMM on the matrix cores
+// (BF16 operands, FP32 accumulation).  K = 5 taps x 64 channels in the order
+// t*C + c; a row's A is read straight from the activation rows at the tap
+// offsets (zero where the tap leaves the block), so no unfolded copy exists.
+//  forward (BWD = false), rows p, columns c:
+//    pre[p][c] = sum_t sum_c' in[p + off(t)][c'] W_t[c'][c]   (B = wt)
+//    out = tanh(pre + bias) and its BF16 copy (rows past Pvalid: 0)
+//  data gradient (BWD = true), rows q, columns c':
+//    dh[q][c'] = sum_t sum_c in[q - off(t)][c] W_t[c'][c]     (B = wtd)
+//    out = dh (1 - hprev^2) and its BF16 copy
+// 256 threads per 64 rows x 64 columns; each wave a 32 x 32 quarter of 2 x 2
+// MFMA 16x16x32 tiles.
 // ---------------------------------------------------------------------------
-// blockIdx.z = s sums k in [s kchunk, min(K, (s + 1) kchunk)) into the slice
-// Cm + s M ldc (split-K partials; one slice when gridDim.z = 1).
-__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
-                                                 const uint16_t *__restrict__ Bt, int ldb,
-                                                 float *__restrict__ Cm, int ldc, int M, int N, int K, int kchunk)
+template <bool BWD>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Bt,
+                                              const float *__restrict__ bias, const float *__restrict__ hprev,
+                                              int Pvalid, int Bs, float *__restrict__ out,
+                                              uint16_t *__restrict__ outb)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-    Cm += (size_t)blockIdx.z * M * ldc;
-    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-    const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int m0 = blockIdx.x * 64 + (wave >> 1) * 32, n0 = (wave & 1) * 32;
     const int r = lane & 15, kq = (lane >> 4) * 8;
+    const int BB = Bs * Bs;
+    int base[2], ri[2], rj[2];
+    bool live[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int p = m0 + a * 16 + r;
+        live[a] = p < Pvalid;
+        const int n = p / BB, k = p - n * BB;
+        base[a] = n * BB;
+        ri[a] = k / Bs;
+        rj[a] = k - ri[a] * Bs;
+    }
     floatx4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
             acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k = kb; k < ke; k += 32) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const int t = q >> 1, half = q & 1;
+        const int di = BWD ? -tap_di(t) : tap_di(t), dj = BWD ? -tap_dj(t) : tap_dj(t);
         bf16x8 av[2], bv[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int row = m0 + a * 16 + r;
-            av[a] = row < M ? load_bf16x8(A + (size_t)row * lda + k + kq) : zero_bf16x8();
+            const int ii = ri[a] + di, jj = rj[a] + dj;
+            av[a] = (live[a] && ii >= 0 && ii < Bs && jj >= 0 && jj < Bs)
+                        ? load_bf16x8(in + (size_t)(base[a] + ii * Bs + jj) * C + half * 32 + kq)
+                        : zero_bf16x8();
         }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int col = n0 + b * 16 + r;
-            bv[b] = col < N ? load_bf16x8(Bt + (size_t)col * ldb + k + kq) : zero_bf16x8();
-        }
+        for (int b = 0; b < 2; ++b)
+            bv[b] = load_bf16x8(Bt + (size_t)(n0 + b * 16 + r) * KB + q * 32 + kq);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -117,23 +137,102 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int row = m0 + a * 16 + 4 * (lane >> 4) + i;
-                const int col = n0 + b * 16 + r;
-                if (row < M && col < N)
-                    Cm[(size_t)row * ldc + col] = acc[a][b][i];
+                const int p = m0 + a * 16 + 4 * (lane >> 4) + i, c = n0 + b * 16 + r;
+                const size_t idx = (size_t)p * C + c;
+                float v;
+                if (BWD) {
+                    const float hv = hprev[idx];
+                    v = acc[a][b][i] * (1.f - hv * hv);
+                } else {
+                    v = p < Pvalid ? net_tanh(acc[a][b][i] + bias[c]) : 0.f;
+                }
+                out[idx] = v;
+                if (outb)
+                    outb[idx] = f2bf(v);
             }
 }
 
-// C[i] = sum over s = 0..S-1 of part[s][i], in that order
-__global__ void k_sum_splits(const float *__restrict__ part, int S, int n, float *__restrict__ Cm)
+// ---------------------------------------------------------------------------
+// Weight gradient of a layer, split over positions (the K of the product):
+//   part[s][c][t*C + c'] = sum over the positions p of split s of
+//                          dpreb[p][c] in[p + off(t)][c']   (0 where the tap leaves the block)
+// Each step stages 32 positions of both operands in LDS, transposed, so a
+// matrix-core operand (8 consecutive positions of one channel) is one 16-byte
+// read.  Grid: 5 taps x splits; each wave a 32 x 32 quarter of the 64 x 64 tile.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dpreb, const uint16_t *__restrict__ in,
+                                               int Pvalid, int Bs, float *__restrict__ part)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
+    constexpr int ROW = 40;  // 32 positions + padding (bf16 elements; rows stay 16-byte aligned)
+    __shared__ __attribute__((aligned(16))) uint16_t at[C][ROW];
+    __shared__ __attribute__((aligned(16))) uint16_t bt[C][ROW];
+    const int t = blockIdx.x, s = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = (wave >> 1) * 32, n0 = (wave & 1) * 32;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    const int pl = tid >> 3, c8 = (tid & 7) * 8;  // staging: position in step, channel chunk
+    const int BB = Bs * Bs;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int p_begin = s * WGRAD_CHUNK, p_end = min(p_begin + WGRAD_CHUNK, Pvalid);
+    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
+        const int p = p0 + pl;
+        uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = va;
+        if (p < p_end) {
+            va = *reinterpret_cast<const uint4 *>(dpreb + (size_t)p * C + c8);
+            const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
+            const int ii = i + tap_di(t), jj = j + tap_dj(t);
+            if (ii >= 0 && jj >= 0 && jj < Bs)
+                vb = *reinterpret_cast<const uint4 *>(in + (size_t)(n * BB + ii * Bs + jj) * C + c8);
+        }
+        const uint16_t *ea = reinterpret_cast<const uint16_t *>(&va);
+        const uint16_t *eb = reinterpret_cast<const uint16_t *>(&vb);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            at[c8 + q][pl] = ea[q];
+            bt[c8 + q][pl] = eb[q];
+        }
+        __syncthreads();
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            av[a] = load_bf16x8(&at[m0 + a * 16 + r][kq]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            bv[b] = load_bf16x8(&bt[n0 + b * 16 + r][kq]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = m0 + a * 16 + 4 * (lane >> 4) + i, ci = n0 + b * 16 + r;
+                part[((size_t)s * C + c) * KB + t * C + ci] = acc[a][b][i];
+            }
+}
+
+// grad W_l[t][c'][c] = sum over splits s (in order) of part[s][c][t*C + c']
+__global__ void k_wgrad_sum(const float *__restrict__ part, int S, int l, float *__restrict__ grad)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= C * KB)
         return;
+    const int c = idx / KB, k = idx - c * KB;
     float v = 0.f;
     for (int s = 0; s < S; ++s)
-        v += part[(size_t)s * n + i];
-    Cm[i] = v;
+        v += part[(size_t)s * C * KB + idx];
+    grad[off_w(l) + k * C + c] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -179,44 +278,6 @@ __global__ void k_layer1(const float *__restrict__ params, const int8_t *__restr
     }
     h[idx] = v;
     hb[idx] = f2bf(v);
-}
-
-// xcol[p][t*C + c'] = hb[p + tap t][c'] inside the block, else 0; also transposed
-__global__ void k_im2col(const uint16_t *__restrict__ hb, int nblk, int Bs, int Ppad,
-                         uint16_t *__restrict__ xcol, uint16_t *__restrict__ xcolt)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over Ppad * 5 * (C / 8)
-    if (idx >= Ppad * 5 * (C / 8))
-        return;
-    const int p = idx / (5 * (C / 8));
-    const int r = idx - p * 5 * (C / 8);
-    const int t = r / (C / 8), c8 = (r - t * (C / 8)) * 8;
-    const int BB = Bs * Bs;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (p < nblk * BB) {
-        const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
-        const int ii = i + tap_di(t), jj = j + tap_dj(t);
-        if (ii >= 0 && jj >= 0 && jj < Bs)
-            v = *reinterpret_cast<const uint4 *>(hb + (size_t)(n * BB + ii * Bs + jj) * C + c8);
-    }
-    *reinterpret_cast<uint4 *>(xcol + (size_t)p * KB + t * C + c8) = v;
-    const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        xcolt[(size_t)(t * C + c8 + q) * Ppad + p] = e[q];
-}
-
-__global__ void k_bias_tanh(const float *__restrict__ pre, const float *__restrict__ bias, int Pvalid,
-                            int Ppad, float *__restrict__ h, uint16_t *__restrict__ hb)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Ppad * C)
-        return;
-    const int p = idx / C, c = idx - p * C;
-    const float v = p < Pvalid ? net_tanh(pre[idx] + bias[c]) : 0.f;
-    h[idx] = v;
-    if (hb)
-        hb[idx] = f2bf(v);
 }
 
 __global__ void k_head(const float *__restrict__ h4, const float *__restrict__ params, int Pvalid,
@@ -281,10 +342,10 @@ __global__ __launch_bounds__(256) void k_sum(const float *__restrict__ partial, 
 // ---------------------------------------------------------------------------
 // training backward
 // ---------------------------------------------------------------------------
-// dpre4 = dlogit * wo * (1 - h4^2), in fp32, bf16 and transposed bf16
+// dpre4 = dlogit * wo * (1 - h4^2), in fp32 and bf16
 __global__ void k_dpre_head(const float *__restrict__ h4, const float *__restrict__ dlogit,
                             const float *__restrict__ params, int Ppad, float *__restrict__ dpre,
-                            uint16_t *__restrict__ dpreb, uint16_t *__restrict__ dpret)
+                            uint16_t *__restrict__ dpreb)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= Ppad * C)
@@ -293,9 +354,7 @@ __global__ void k_dpre_head(const float *__restrict__ h4, const float *__restric
     const float hv = h4[idx];
     const float d = dlogit[p] * params[OFF_WO + c] * (1.f - hv * hv);
     dpre[idx] = d;
-    const uint16_t b = f2bf(d);
-    dpreb[idx] = b;
-    dpret[(size_t)c * Ppad + p] = b;
+    dpreb[idx] = f2bf(d);
 }
 
 // partial column sums: partial[blk][c] = sum over this block's rows of A[p][c] * (w ? w[p] : 1)
@@ -326,45 +385,6 @@ __global__ void k_reduce_cols(const float *__restrict__ partial, int nb, int wid
     for (int b = 0; b < nb; ++b)
         s += partial[(size_t)b * width + j];
     out[j] = s;
-}
-
-// grad[W_l][t][c'][c] = wgrad[c][t*C + c']
-__global__ void k_scatter_wgrad(const float *__restrict__ wgrad, int l, float *__restrict__ grad)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= C * KB)
-        return;
-    const int c = idx / KB, k = idx - c * KB;
-    grad[off_w(l) + k * C + c] = wgrad[idx];
-}
-
-// dh[q][c'] = sum_t dxcol[q - tap t][t*C + c'];  dpre = dh (1 - h^2)
-__global__ void k_col2im(const float *__restrict__ dxcol, const float *__restrict__ hprev, int nblk, int Bs,
-                         int Ppad, float *__restrict__ dpre, uint16_t *__restrict__ dpreb,
-                         uint16_t *__restrict__ dpret)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Ppad * C)
-        return;
-    const int q = idx / C, c = idx - q * C;
-    const int BB = Bs * Bs;
-    float dh = 0.f;
-    if (q < nblk * BB) {
-        const int n = q / BB, k = q - n * BB, i = k / Bs, j = k - i * Bs;
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            // source position p with p + tap t = q
-            const int ii = i - tap_di(t), jj = j - tap_dj(t);
-            if (ii < Bs && jj >= 0 && jj < Bs)
-                dh += dxcol[(size_t)(n * BB + ii * Bs + jj) * KB + t * C + c];
-        }
-    }
-    const float hv = hprev[idx];
-    const float d = dh * (1.f - hv * hv);
-    dpre[idx] = d;
-    const uint16_t b = f2bf(d);
-    dpreb[idx] = b;
-    dpret[(size_t)c * Ppad + q] = b;
 }
 
 // layer-1 gradients: 10 rows (W1 taps 0..3, U1 f 0..3, v1, b1) x C, partial over positions
@@ -410,12 +430,18 @@ __global__ __launch_bounds__(256) void k_layer1_grad(const float *__restrict__ d
             partial[(size_t)blockIdx.x * 10 * C + q * C + c] = red[0][q][c] + red[1][q][c] + red[2][q][c] + red[3][q][c];
 }
 
+// Adam step number t = (steps taken) + 1 from the device counter, so a
+// captured training step stays valid for every replay; the bias corrections
+// 1 - beta^t are formed in FP64 from the exact decimal betas.
 __global__ void k_adam(float *__restrict__ params, const float *__restrict__ grad, float *__restrict__ m,
-                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2)
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       const uint32_t *__restrict__ steps_taken)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    const double t = (double)*steps_taken + 1.0;
+    const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
     const float g = grad[i];
     const float mi = b1 * m[i] + (1.f - b1) * g;
     const float vi = b2 * v[i] + (1.f - b2) * g * g;
@@ -427,17 +453,18 @@ __global__ void k_adam(float *__restrict__ params, const float *__restrict__ gra
 // ---------------------------------------------------------------------------
 // Autoregressive passes.  Both evaluate the conditional of every site k of a
 // block given the sites before it and the boundary with one per-site
-// arithmetic: layer 1 on the VALU (layer1_site), layers 2..4 as MFMA tiles
-// whose 16 rows are 16 sequences at one site and whose K runs over the taps
-// in a fixed order, the logit head summed in a fixed tree, and the uint32
-// threshold (site_threshold).  A matrix-core product row depends only on its
-// own A row, so a block scored by k_nn_score gets bit for bit the log q that
-// k_nn_sample assigned when it drew it.
+// arithmetic: every layer as matrix-core tiles of 16 rows (layer 1 in FP32,
+// layer1_tile; layers 2..4 in BF16 with K running over the taps in a fixed
+// order), the logit head summed in a fixed tree, and the uint32 threshold
+// (site_threshold).  A matrix-core product row depends only on its own A
+// row, so a block scored by
+// k_nn_score gets bit for bit the log q that k_nn_sample assigned when it
+// drew it.
 //  - k_nn_sample: 16 sequences per workgroup, one site per step (a site
-//    depends on the one drawn just before it);
-//  - k_nn_score: 16 given blocks per workgroup, one block row per step (a
-//    site only looks at the row above and at sites to its left, all known),
-//    so each wave runs Bs independent MFMA chains per layer.
+//    depends on the one drawn just before it); a tile's rows are the 16
+//    sequences at one site;
+//  - k_nn_score: every site of its blocks at once, one layer at a time (all
+//    spins are given); a tile's rows are 16 (block, site) pairs.
 // Each wave owns 16 output channels of layers 2..4, whose BF16 weights it
 // keeps in registers for the whole pass.
 // ---------------------------------------------------------------------------
@@ -447,7 +474,7 @@ constexpr int RING_ROW = C + 8;  // padded row (bf16 elements) against LDS bank 
 struct ArWeights {
     bf16x8 w[3][10];  // layers 2..4: this lane's B-operand slices (output channel cw)
     float bias[3], wo_c, bo;
-    float w1[4], u1[4], v1, b1;  // layer 1 of channel tid & 63
+    float l1w[3];     // layer 1: this lane's B operands (channel cw, input k = lane >> 4 of each group)
 };
 
 __device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int lane, ArWeights &p)
@@ -464,34 +491,54 @@ __device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int
         p.bias[l] = P[off_b(l + 2) + cw];
     p.wo_c = P[OFF_WO + cw];
     p.bo = P[OFF_BO];
-    const int c1 = lane;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        p.w1[t] = P[OFF_W1 + t * C + c1];
-        p.u1[t] = P[OFF_U1 + t * C + c1];
-    }
-    p.v1 = P[OFF_V1 + c1];
-    p.b1 = P[OFF_B1 + c1];
+    const int k = lane >> 4;
+    p.l1w[0] = P[OFF_W1 + k * C + cw];
+    p.l1w[1] = P[OFF_U1 + k * C + cw];
+    p.l1w[2] = k == 0 ? P[OFF_V1 + cw] : (k == 1 ? P[OFF_B1 + cw] : 0.f);
 }
 
-// Layer-1 output (BF16) of channel lane at site (i, j) of one sequence: x
-// holds the sequence's known sites; the site at position ov_pos (if any)
-// is taken from ov_val instead.
-template <int BS>
-__device__ __forceinline__ uint16_t layer1_site(const int8_t *x, int ov_pos, float ov_val, const int8_t *bnd,
-                                                float kc, int i, int j, const ArWeights &p)
+// Layer 1 of a tile of 16 rows on the matrix cores (FP32 operands,
+// v_mfma_f32_16x16x4_f32, three K groups of 4): a row's inputs are its four
+// spin taps (0 outside the block), its four boundary features (the boundary
+// spin beside the site on that edge: top, bottom, left, right; else 0), then
+// K and 1; the B operands are W1, U1 and (v1, b1) of this wave's 16 channels.
+// Lane (row lane & 15, input k = lane >> 4) passes its three inputs; the
+// result holds pre1 of rows 4 (lane >> 4) + r, channel cw.
+__device__ __forceinline__ floatx4 layer1_tile(float in_tap, float in_bnd, float in_k, const ArWeights &p)
 {
-    float pre = __builtin_fmaf(kc, p.v1, p.b1);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int ii = i + tap_di(t), jj = j + tap_dj(t);
-        if (ii >= 0 && jj >= 0 && jj < BS) {
-            const int pos = ii * BS + jj;
-            pre = __builtin_fmaf(pos == ov_pos ? ov_val : (float)x[pos], p.w1[t], pre);
-        }
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in_tap, p.l1w[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in_bnd, p.l1w[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in_k, p.l1w[2], acc, 0, 0, 0);
+    return acc;
+}
+
+// The three layer-1 inputs number k (0..3) of site (i, j) of a block: x holds
+// the block's known sites (the one at position ov_pos, if any, is ov_val
+// instead), bnd its boundary (top row, bottom row, left column, right column).
+template <int BS>
+__device__ __forceinline__ void layer1_inputs(const int8_t *x, int ov_pos, float ov_val, const int8_t *bnd,
+                                              float kc, int i, int j, int k, float *in_tap, float *in_bnd,
+                                              float *in_k)
+{
+    const int ii = i + tap_di(k), jj = j + tap_dj(k);
+    float v = 0.f;
+    if (ii >= 0 && jj >= 0 && jj < BS) {
+        const int pos = ii * BS + jj;
+        v = pos == ov_pos ? ov_val : (float)x[pos];
     }
-    pre += boundary_field(bnd, BS, i, j, p.u1);
-    return f2bf(net_tanh(pre));
+    *in_tap = v;
+    float b = 0.f;
+    if (k == 0 && i == 0)
+        b = (float)bnd[j];
+    else if (k == 1 && i == BS - 1)
+        b = (float)bnd[BS + j];
+    else if (k == 2 && j == 0)
+        b = (float)bnd[2 * BS + i];
+    else if (k == 3 && j == BS - 1)
+        b = (float)bnd[3 * BS + i];
+    *in_bnd = b;
+    *in_k = k == 0 ? kc : (k == 1 ? 1.f : 0.f);
 }
 
 // uint32 threshold of a site from its logit: clamp(floor(sigmoid * 2^32), 1,
@@ -504,18 +551,31 @@ __device__ __forceinline__ uint32_t site_threshold(float logit)
     return t > 1u ? t : 1u;
 }
 
+// v + the value of the lane selected by a DPP control (in-register cross-lane
+// read; out-of-row sources read 0)
+template <int CTRL>
+__device__ __forceinline__ float add_dpp(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
 // Sum of the logit head over this wave's 16 channels for the 4 rows this
-// lane holds (fixed butterfly over the 16 lanes of a row group); lane 0 of
-// each group writes out[row].
+// lane holds: within each row of 16 lanes, pairs, then quads (quad
+// permutations), then lane + 4 and lane + 8 (row shifts), so lane 0 of the
+// row holds ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)) + (the same
+// for lanes 8..15), a fixed order; it writes out[row].
 __device__ __forceinline__ void head_rows(const floatx4 &acc, const ArWeights &p, int lane, float *out)
 {
+    // the product is rounded before the sums in every kernel that inlines
+    // this (no contraction into fused multiply-adds)
+#pragma clang fp contract(off)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         float v = net_tanh(acc[r] + p.bias[2]) * p.wo_c;
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 8, 64);
+        v = add_dpp<0xb1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+        v = add_dpp<0x4e>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+        v = add_dpp<0x104>(v);  // row_shl 4: lane + 4
+        v = add_dpp<0x108>(v);  // row_shl 8: lane + 8
         if ((lane & 15) == 0)
             out[4 * (lane >> 4) + r] = v;
     }
@@ -591,26 +651,36 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
     const int cw = 16 * wave + (lane & 15);
     __syncthreads();
 
+    // every lane draws for the sequence of its tile row; the threshold of the
+    // site drawn in one step is recorded (over its uniform) in the next step,
+    // after every wave has read that uniform
+    const int srow = lane & 15, kin = lane >> 4;
+    uint32_t thr_prev = 0u;
     for (int k = 0; k <= BB; ++k) {
         const int i = k / BS, j = k - i * BS, slot = k % RING;
-        // draw site k - 1 of this wave's sequences (every lane of the wave
-        // evaluates the same decision; lane 0 records it), then layer 1 of site k
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int s = wave + 4 * q;
-            float xprev = 0.f;
-            if (k > 0) {
-                const uint32_t thr = site_threshold(
-                    head_logit(head_part[0], head_part[1], head_part[2], head_part[3], s, p.bo));
-                const int8_t xv = ut[s][k - 1] < thr ? (int8_t)1 : (int8_t)-1;
-                xprev = (float)xv;
-                if (lane == 0) {
-                    xs[s][k - 1] = xv;
-                    ut[s][k - 1] = thr;
-                }
+        // draw site k - 1 (every wave, every lane of a row the same decision;
+        // wave 0 records it), then layer 1 of site k for the wave's channels
+        float xprev = 0.f;
+        if (k > 0) {
+            const uint32_t thr = site_threshold(
+                head_logit(head_part[0], head_part[1], head_part[2], head_part[3], srow, p.bo));
+            const int8_t xv = ut[srow][k - 1] < thr ? (int8_t)1 : (int8_t)-1;
+            xprev = (float)xv;
+            if (wave == 0 && kin == 0) {
+                xs[srow][k - 1] = xv;
+                if (k > 1)
+                    ut[srow][k - 2] = thr_prev;
             }
-            if (k < BB)
-                ring[0][slot][s][lane] = layer1_site<BS>(&xs[s][0], k - 1, xprev, &bs[s][0], ks[s], i, j, p);
+            thr_prev = thr;
+        }
+        if (k < BB) {
+            float in_tap, in_bnd, in_k;
+            layer1_inputs<BS>(&xs[srow][0], k - 1, xprev, &bs[srow][0], ks[srow], i, j, kin, &in_tap, &in_bnd,
+                              &in_k);
+            const floatx4 pre = layer1_tile(in_tap, in_bnd, in_k, p);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                ring[0][slot][4 * kin + r][cw] = f2bf(net_tanh(pre[r]));
         }
         __syncthreads();
         if (k == BB)
@@ -640,6 +710,9 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
             __syncthreads();
         }
     }
+    if (wave == 0 && kin == 0)
+        ut[srow][BB - 1] = thr_prev;
+    __syncthreads();
     logq_parts(xs, ut, BB, tid, lq_part);
     __syncthreads();
     for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
@@ -651,94 +724,123 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
         seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
 }
 
-// 512 threads: wave w computes output channels 16 (w & 3) .. +15 for the
-// sites j of a row with j / (BS / 2) == w >> 2 (half the row's tiles).
+// Scoring has no site-to-site dependency (every spin is given), so a
+// workgroup holds all SCORE_POS positions of its blocks in LDS and runs the
+// network one layer at a time: layer 1 for every position on the VALU, then
+// for layers 2..4 wave w (output channels 16w .. 16w+15, weights in
+// registers) walks the position tiles of 16 rows, four independent MFMA
+// chains at a time.  A row of a tile is one (block, site) pair; its A row is
+// the previous layer at the site's five taps (zero outside the block), its B
+// operands and K order are the sampler's, and a matrix-core product row
+// depends only on its own A row, so every site gets the sampler's logit and
+// threshold bit for bit.
+constexpr int SCORE_POS = 256;  // positions per workgroup (a multiple of 64)
+constexpr int SCORE_TILES = 4;  // MFMA chains a wave runs together
+
 template <int BS>
-__global__ __launch_bounds__(512) void k_nn_score(NetDev net, SeqDev seq, int n_seq)
+__global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_seq)
 {
-    constexpr int BB = BS * BS, HT = BS / 2;  // tiles per wave
-    // layer outputs of the current and the previous block row: [layer][row & 1][site j][sequence][channel]
-    __shared__ __attribute__((aligned(16))) uint16_t rows[3][2][BS][SEQ_PER_WG][RING_ROW];
-    __shared__ float head_part[4][BS][SEQ_PER_WG];
-    __shared__ int8_t xs[SEQ_PER_WG][64];
-    __shared__ int8_t bs[SEQ_PER_WG][32];
-    __shared__ uint32_t thr_s[SEQ_PER_WG][64];
-    __shared__ float ks[SEQ_PER_WG];
-    __shared__ double lq_part[SEQ_PER_WG][16];
+    constexpr int BB = BS * BS;
+    constexpr int G = SCORE_POS / BB < 16 ? SCORE_POS / BB : 16;  // blocks per workgroup
+    constexpr int P = G * BB;                                      // positions (a multiple of 64)
+    constexpr int MT = P / 16;                                     // tiles of 16 positions
+    static_assert(P % 64 == 0 && MT % SCORE_TILES == 0, "whole tile groups");
+    // activations of the layer being read and the layer being written (ping-pong);
+    // after layer 4 the first holds the head partials, the thresholds and the log-q parts
+    __shared__ __attribute__((aligned(16))) uint16_t hbuf[2][P][RING_ROW];
+    __shared__ int8_t xs[G][64];
+    __shared__ int8_t bs[G][32];
+    __shared__ float ks[G];
+    float(*head_part)[P] = reinterpret_cast<float(*)[P]>(&hbuf[1][0][0]);              // [4][P]
+    uint32_t(*thr_s)[64] = reinterpret_cast<uint32_t(*)[64]>(&hbuf[0][0][0]);         // [G][64]
+    double(*lq_part)[16] = reinterpret_cast<double(*)[16]>(&hbuf[0][0][0] + G * 64 * 2);  // [G][16]
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nsl = wave & 3, j0 = (wave >> 2) * HT;
-    const int s0 = blockIdx.x * SEQ_PER_WG;
+    const int s0 = blockIdx.x * G;
 
-    for (int i = tid; i < SEQ_PER_WG * 64; i += 512) {
+    for (int i = tid; i < G * 64; i += 256) {
         const int s = i >> 6, k = i & 63;
         xs[s][k] = (s0 + s < n_seq && k < BB) ? seq.x[(size_t)(s0 + s) * BB + k] : (int8_t)0;
     }
-    for (int i = tid; i < SEQ_PER_WG * 32; i += 512) {
+    for (int i = tid; i < G * 32; i += 256) {
         const int s = i >> 5, k = i & 31;
         bs[s][k] = (s0 + s < n_seq && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
     }
-    if (tid < SEQ_PER_WG)
+    if (tid < G)
         ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
     ArWeights p;
-    load_ar_weights(net, nsl, lane, p);
-    const int cw = 16 * nsl + (lane & 15);
+    load_ar_weights(net, wave, lane, p);
+    const int cw = 16 * wave + (lane & 15);
     __syncthreads();
 
-    for (int i = 0; i < BS; ++i) {
-        const int par = i & 1;
-        // layer 1 of row i: channel lane, sequences wave and wave + 8, every site
+    // layer 1: this wave's 16 channels for every tile of 16 positions
+    for (int m = 0; m < MT; ++m) {
+        const int pos = 16 * m + (lane & 15);  // this lane's row
+        const int s = pos / BB, k = pos - s * BB, i = k / BS, j = k - i * BS;
+        float in_tap, in_bnd, in_k;
+        layer1_inputs<BS>(&xs[s][0], -1, 0.f, &bs[s][0], ks[s], i, j, lane >> 4, &in_tap, &in_bnd, &in_k);
+        const floatx4 pre = layer1_tile(in_tap, in_bnd, in_k, p);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int s = wave + 8 * q;
+        for (int r = 0; r < 4; ++r)
+            hbuf[0][16 * m + 4 * (lane >> 4) + r][cw] = f2bf(net_tanh(pre[r]));
+    }
+    __syncthreads();
+
+    // layers 2..4: this wave's 16 output channels for every position
 #pragma unroll
-            for (int j = 0; j < BS; ++j)
-                rows[0][par][j][s][lane] = layer1_site<BS>(&xs[s][0], -1, 0.f, &bs[s][0], ks[s], i, j, p);
-        }
-        __syncthreads();
+    for (int l = 0; l < 3; ++l) {
+        const uint16_t(*hin)[RING_ROW] = hbuf[l & 1];
+        uint16_t(*hout)[RING_ROW] = hbuf[(l + 1) & 1];
+        for (int m0 = 0; m0 < MT; m0 += SCORE_TILES) {
+            floatx4 acc[SCORE_TILES];
+            int src[SCORE_TILES], si[SCORE_TILES], sj[SCORE_TILES];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            floatx4 acc[HT];
-#pragma unroll
-            for (int jt = 0; jt < HT; ++jt)
-                acc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int u = 0; u < SCORE_TILES; ++u) {
+                acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+                const int pos = 16 * (m0 + u) + (lane & 15);  // this lane's A row
+                const int s = pos / BB, k = pos - s * BB;
+                si[u] = k / BS;
+                sj[u] = k - si[u] * BS;
+                src[u] = s * BB;
+            }
 #pragma unroll
             for (int q = 0; q < 10; ++q) {
                 const int t = q >> 1, half = q & 1;
-                const int ii = i + tap_di(t);
 #pragma unroll
-                for (int jt = 0; jt < HT; ++jt) {
-                    const int jj = j0 + jt + tap_dj(t);
+                for (int u = 0; u < SCORE_TILES; ++u) {
+                    const int ii = si[u] + tap_di(t), jj = sj[u] + tap_dj(t);
                     bf16x8 a = zero_bf16x8();
                     if (ii >= 0 && jj >= 0 && jj < BS)
-                        a = load_bf16x8(&rows[l][ii & 1][jj][lane & 15][half * 32 + 8 * (lane >> 4)]);
-                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, p.w[l][q], acc[jt], 0, 0, 0);
+                        a = load_bf16x8(&hin[src[u] + ii * BS + jj][half * 32 + 8 * (lane >> 4)]);
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, p.w[l][q], acc[u], 0, 0, 0);
                 }
             }
 #pragma unroll
-            for (int jt = 0; jt < HT; ++jt) {
+            for (int u = 0; u < SCORE_TILES; ++u) {
+                const int row0 = 16 * (m0 + u) + 4 * (lane >> 4);
                 if (l < 2) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        rows[l + 1][par][j0 + jt][4 * (lane >> 4) + r][cw] =
-                            f2bf(net_tanh(acc[jt][r] + p.bias[l]));
+                        hout[row0 + r][cw] = f2bf(net_tanh(acc[u][r] + p.bias[l]));
                 } else {
-                    head_rows(acc[jt], p, lane, head_part[nsl][j0 + jt]);
+                    // hout is the other buffer, free now: head partials of this wave
+                    head_rows(acc[u], p, lane, &head_part[wave][16 * (m0 + u)]);
                 }
             }
-            __syncthreads();
         }
-        if (tid < SEQ_PER_WG * BS) {
-            const int s = tid / BS, j = tid - s * BS;
-            thr_s[s][i * BS + j] = site_threshold(
-                head_logit(head_part[0][j], head_part[1][j], head_part[2][j], head_part[3][j], s, p.bo));
-        }
+        __syncthreads();
+    }
+
+    // thresholds (position pos = s * BB + k) and log q, in the sampler's order
+    for (int pos = tid; pos < P; pos += 256) {
+        const int s = pos / BB, k = pos - s * BB;
+        thr_s[s][k] = site_threshold(head_logit(head_part[0], head_part[1], head_part[2], head_part[3], pos, p.bo));
     }
     __syncthreads();
-    if (tid < 256)
-        logq_parts(xs, thr_s, BB, tid, lq_part);
+    for (int idx = tid; idx < G * 16; idx += 256)
+        logq_parts(xs, thr_s, BB, idx, lq_part);
     __syncthreads();
-    if (tid < SEQ_PER_WG && s0 + tid < n_seq)
+    if (tid < G && s0 + tid < n_seq)
         seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
 }
 
@@ -919,11 +1021,11 @@ __global__ void k_extract(const RepDev *__restrict__ reps, const double *__restr
 // key = seed); one workgroup of 64 threads copies one row.
 __global__ __launch_bounds__(64) void k_gather_rows(const int8_t *__restrict__ x, const int8_t *__restrict__ bnd,
                                                     const float *__restrict__ kc, uint32_t n_rows, int BB, int NB,
-                                                    uint32_t step, uint32_t seed_lo, uint32_t seed_hi,
-                                                    int8_t *__restrict__ tx, int8_t *__restrict__ tb,
-                                                    float *__restrict__ tk)
+                                                    const uint32_t *__restrict__ steps_taken, uint32_t seed_lo,
+                                                    uint32_t seed_hi, int8_t *__restrict__ tx,
+                                                    int8_t *__restrict__ tb, float *__restrict__ tk)
 {
-    const uint32_t i = blockIdx.x;
+    const uint32_t i = blockIdx.x, step = *steps_taken;
     uint32_t o[4];
     philox4x32_10(i, step, 0u, 6u, seed_lo, seed_hi, o);
     const size_t row = (size_t)(((uint64_t)o[0] * n_rows) >> 32);
@@ -933,6 +1035,13 @@ __global__ __launch_bounds__(64) void k_gather_rows(const int8_t *__restrict__ x
         tb[(size_t)i * NB + j] = bnd[row * NB + j];
     if (threadIdx.x == 0)
         tk[i] = kc[row];
+}
+
+// one training step taken (after its Adam update)
+__global__ void k_step_advance(uint32_t *steps_taken)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *steps_taken += 1u;
 }
 
 // standalone sampled sequences: Philox key and block id of sequence i
@@ -957,34 +1066,10 @@ static inline unsigned blocks_for(long n, int t) { return (unsigned)((n + t - 1)
 hipError_t cast_weights(const NetDev &net, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cast_weights, dim3(blocks_for(3L * C * KB, 256)), dim3(256), 0, st, net.params, net.wt,
-                       net.wtt);
+                       net.wtd);
     return hipGetLastError();
 }
 
-hipError_t gemm_nt(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *Cm, int ldc, int M, int N,
-                   int K, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_gemm_nt, dim3(blocks_for(N, 64), blocks_for(M, 64), 1), dim3(256), 0, st, A, lda, Bt, ldb,
-                       Cm, ldc, M, N, K, K);
-    return hipGetLastError();
-}
-
-// Split-K product for a small output and a long K (the weight gradients):
-// partials of kchunk-long K ranges go to part[S][M][N], then a fixed-order sum.
-static hipError_t gemm_nt_splitk(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float *part, float *Cm,
-                                 int M, int N, int K, int kchunk, hipStream_t st)
-{
-    const int S = (K + kchunk - 1) / kchunk;
-    hipLaunchKernelGGL(k_gemm_nt, dim3(blocks_for(N, 64), blocks_for(M, 64), S), dim3(256), 0, st, A, lda, Bt, ldb,
-                       part, N, M, N, K, kchunk);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for((long)M * N, 256)), dim3(256), 0, st, part, S, M * N, Cm);
-    return hipGetLastError();
-}
-
-// forward of nblk blocks; logits[P]; returns the padded position count in *ppad
 hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
                    int nblk, int Bs, hipStream_t st)
 {
@@ -993,13 +1078,9 @@ hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const 
                        nblk, Bs, Pp, ws.h[0], ws.hb[0]);
     for (int l = 2; l <= 4; ++l) {
         const int li = l - 2;
-        hipLaunchKernelGGL(k_im2col, dim3(blocks_for((long)Pp * 5 * (C / 8), 256)), dim3(256), 0, st,
-                           ws.hb[li], nblk, Bs, Pp, ws.xcol[li], ws.xcolt[li]);
-        hipError_t e = gemm_nt(ws.xcol[li], KB, net.wt + (size_t)li * C * KB, KB, ws.pre, C, Pp, C, KB, st);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_bias_tanh, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.pre,
-                           net.params + off_b(l), Pv, Pp, ws.h[l - 1], l < 4 ? ws.hb[l - 1] : (uint16_t *)nullptr);
+        hipLaunchKernelGGL(k_conv<false>, dim3(Pp / 64), dim3(256), 0, st, ws.hb[li], net.wt + (size_t)li * C * KB,
+                           net.params + off_b(l), (const float *)nullptr, Pv, Bs, ws.h[l - 1],
+                           l < 4 ? ws.hb[l - 1] : (uint16_t *)nullptr);
     }
     hipLaunchKernelGGL(k_head, dim3(blocks_for(Pv, 256)), dim3(256), 0, st, ws.h[3], net.params, Pv, ws.logits);
     const int nb = blocks_for(Pp, 256);
@@ -1014,33 +1095,29 @@ hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const
     const int Pv = nblk * Bs * Bs, Pp = (Pv + 63) / 64 * 64;
     const int rows_per_blk = 256;
     const int nbr = blocks_for(Pp, rows_per_blk);
+    const int splits = (Pv + WGRAD_CHUNK - 1) / WGRAD_CHUNK;
     // head: dwo = sum_p h4[p] dlogit[p]; dbo = sum_p dlogit[p]
     hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.h[3], ws.dlogit, Pp, rows_per_blk, ws.partial);
     hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + OFF_WO);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, ws.dlogit, Pp, 1.f, net.grad + OFF_BO);
     hipLaunchKernelGGL(k_dpre_head, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.h[3], ws.dlogit,
-                       net.params, Pp, ws.dpre, ws.dpreb, ws.dpret);
+                       net.params, Pp, ws.dpre[0], ws.dpreb[0]);
     for (int l = 4; l >= 2; --l) {
-        const int li = l - 2;
-        hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.dpre, (const float *)nullptr, Pp, rows_per_blk,
-                           ws.partial);
+        const int li = l - 2, cur = l & 1, nxt = cur ^ 1;  // layer 4 reads buffer 0
+        hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.dpre[cur], (const float *)nullptr, Pp,
+                           rows_per_blk, ws.partial);
         hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + off_b(l));
-        // weight gradient [C][KB] = dpre^T (C x P) . xcol (P x KB), split over P in
-        // chunks of 512 positions; the partials use ws.pre, which is free here
-        // (S C KB <= Pp KB floats)
-        hipError_t e = gemm_nt_splitk(ws.dpret, Pp, ws.xcolt[li], Pp, ws.pre, ws.wgrad, C, KB, Pp, 512, st);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_scatter_wgrad, dim3(blocks_for((long)C * KB, 256)), dim3(256), 0, st, ws.wgrad, l,
+        // weight gradient against this layer's input (BF16 activations of layer l - 1)
+        hipLaunchKernelGGL(k_wgrad, dim3(5, splits), dim3(256), 0, st, ws.dpreb[cur], ws.hb[li], Pv, Bs, ws.wpart);
+        hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks_for((long)C * KB, 256)), dim3(256), 0, st, ws.wpart, splits, l,
                            net.grad);
-        // data gradient [P][KB] = dpre (P x C) . W (C x KB)
-        e = gemm_nt(ws.dpreb, C, net.wtt + (size_t)li * KB * C, C, ws.pre, KB, Pp, KB, C, st);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_col2im, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.pre, ws.h[l - 2],
-                           nblk, Bs, Pp, ws.dpre, ws.dpreb, ws.dpret);
+        // gradient of layer l - 1's pre-activation
+        hipLaunchKernelGGL(k_conv<true>, dim3(Pp / 64), dim3(256), 0, st, ws.dpreb[cur],
+                           net.wtd + (size_t)li * C * KB, (const float *)nullptr, ws.h[l - 2], Pv, Bs, ws.dpre[nxt],
+                           ws.dpreb[nxt]);
     }
-    hipLaunchKernelGGL(k_layer1_grad, dim3(nbr), dim3(256), 0, st, ws.dpre, x, bnd, kc, nblk, Bs, rows_per_blk,
+    // layer 2 wrote dpre1 into buffer 1
+    hipLaunchKernelGGL(k_layer1_grad, dim3(nbr), dim3(256), 0, st, ws.dpre[1], x, bnd, kc, nblk, Bs, rows_per_blk,
                        ws.partial);
     // rows: W1 taps (4), U1 (4), v1, b1 -> contiguous in the flat vector starting at OFF_W1
     hipLaunchKernelGGL(k_reduce_cols, dim3(blocks_for(10 * C, 256)), dim3(256), 0, st, ws.partial, nbr, 10 * C,
@@ -1048,12 +1125,15 @@ hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const
     return hipGetLastError();
 }
 
-hipError_t adam(const NetDev &net, float lr, int step, hipStream_t st)
+hipError_t adam(const NetDev &net, float lr, hipStream_t st)
 {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(N_PARAMS, 256)), dim3(256), 0, st, net.params, net.grad, net.adam_m,
-                       net.adam_v, N_PARAMS, lr, b1, b2, eps, c1, c2);
+                       net.adam_v, N_PARAMS, lr, b1, b2, eps, (const uint32_t *)net.step);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, net.step);
     return hipGetLastError();
 }
 
@@ -1061,8 +1141,8 @@ template <int BS>
 static hipError_t ar_pass_bs(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, hipStream_t st)
 {
     if (n_score > 0) {
-        hipLaunchKernelGGL(k_nn_score<BS>, dim3(blocks_for(n_score, SEQ_PER_WG)), dim3(512), 0, st, net, seq,
-                           n_score);
+        constexpr int G = SCORE_POS / (BS * BS) < 16 ? SCORE_POS / (BS * BS) : 16;
+        hipLaunchKernelGGL(k_nn_score<BS>, dim3(blocks_for(n_score, G)), dim3(256), 0, st, net, seq, n_score);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -1110,10 +1190,11 @@ hipError_t seq_setup(const SeqDev &seq, int n, uint64_t seed, uint32_t replica, 
     return hipGetLastError();
 }
 
-hipError_t gather_rows(const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc, uint32_t n_rows,
-                       int batch, int Bs, uint32_t step, uint64_t seed, hipStream_t st)
+hipError_t gather_rows(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                       uint32_t n_rows, int batch, int Bs, uint64_t seed, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather_rows, dim3(batch), dim3(64), 0, st, x, bnd, kc, n_rows, Bs * Bs, 4 * Bs, step,
+    hipLaunchKernelGGL(k_gather_rows, dim3(batch), dim3(64), 0, st, x, bnd, kc, n_rows, Bs * Bs, 4 * Bs,
+                       (const uint32_t *)net.step,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ws.tx, ws.tbnd, ws.tcoup);
     return hipGetLastError();
 }

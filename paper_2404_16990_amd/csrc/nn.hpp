@@ -40,8 +40,9 @@ __host__ __device__ constexpr int tap_dj(int t) { return t < 3 ? t - 1 : (t == 3
 // Device pointers of one network: parameters, Adam moments, BF16 copies.
 struct NetDev {
     float *params, *adam_m, *adam_v, *grad;
-    uint16_t *wt;   // [3][C][KB]  Wt[l][c][t*C + c'] = W_l[t][c'][c]   (bf16)
-    uint16_t *wtt;  // [3][KB][C]  transposed copy for the data gradient
+    uint16_t *wt;   // [3][C][KB]  wt[l][c][t*C + c'] = W_l[t][c'][c]   (bf16, forward B operand)
+    uint16_t *wtd;  // [3][C][KB]  wtd[l][c'][t*C + c] = W_l[t][c'][c]  (bf16, data-gradient B operand)
+    uint32_t *step; // training steps taken since the parameters were set (device counter)
 };
 
 // Sequences for the incremental (autoregressive) pass.
@@ -54,19 +55,18 @@ struct SeqDev {
     double *logq;     // [n]
 };
 
+// Positions per split of the weight-gradient product (its K).
+constexpr int WGRAD_CHUNK = 512;
+
 // Training workspace (positions padded to a multiple of 64).
 struct TrainWs {
     float *h[4];        // [P][C] fp32 activations
-    uint16_t *hb[3];    // [P][C] bf16 activations of layers 1..3 (GEMM inputs)
-    uint16_t *xcol[3];  // [P][KB] im2col of layer l+2's input
-    uint16_t *xcolt[3]; // [KB][P]
-    float *pre;         // [P][KB] scratch: GEMM outputs (P x C) and data gradients (P x KB)
-    float *dpre;        // [P][C]
-    uint16_t *dpreb;    // [P][C]
-    uint16_t *dpret;    // [C][P]
+    uint16_t *hb[3];    // [P][C] bf16 activations of layers 1..3 (inputs of layers 2..4)
+    float *dpre[2];     // [P][C] pre-activation gradients (ping-pong between layers)
+    uint16_t *dpreb[2]; // [P][C] their bf16 copies
     float *logits, *dlogit;  // [P]
     float *partial;     // reduction partials
-    float *wgrad;       // [C][KB]
+    float *wpart;       // [splits][C][KB] weight-gradient partials
     float *loss;        // [1] scratch
     int8_t *tx, *tbnd;  // [max_batch][Bs*Bs], [max_batch][4 Bs]: minibatch drawn on the device
     float *tcoup;       // [max_batch]

@@ -6,7 +6,9 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ising.h"
@@ -29,8 +31,8 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct NNLayout {
-    size_t params, adam_m, adam_v, grad, wt, wtt;
-    size_t h[4], hb[3], xcol[3], xcolt[3], pre, dpre, dpreb, dpret, logits, dlogit, partial, wgrad, loss;
+    size_t params, adam_m, adam_v, grad, wt, wtd, step;
+    size_t h[4], hb[3], dpre[2], dpreb[2], logits, dlogit, partial, wpart, loss;
     size_t tx, tbnd, tcoup;
     size_t sx, sbnd, scoup, skey, sblk, slogq;
     size_t total;
@@ -66,22 +68,20 @@ NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
     L.adam_v = take(N_PARAMS * 4);
     L.grad = take(N_PARAMS * 4);
     L.wt = take((size_t)3 * C * KB * 2);
-    L.wtt = take((size_t)3 * KB * C * 2);
+    L.wtd = take((size_t)3 * C * KB * 2);
+    L.step = take(4);
     for (int l = 0; l < 4; ++l)
         L.h[l] = take((size_t)Pp * C * 4);
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < 3; ++l)
         L.hb[l] = take((size_t)Pp * C * 2);
-        L.xcol[l] = take((size_t)Pp * KB * 2);
-        L.xcolt[l] = take((size_t)Pp * KB * 2);
+    for (int b = 0; b < 2; ++b) {
+        L.dpre[b] = take((size_t)Pp * C * 4);
+        L.dpreb[b] = take((size_t)Pp * C * 2);
     }
-    L.pre = take((size_t)Pp * KB * 4);
-    L.dpre = take((size_t)Pp * C * 4);
-    L.dpreb = take((size_t)Pp * C * 2);
-    L.dpret = take((size_t)Pp * C * 2);
     L.logits = take((size_t)Pp * 4);
     L.dlogit = take((size_t)Pp * 4);
     L.partial = take((size_t)(Pp / 256 + 2) * 10 * C * 4);
-    L.wgrad = take((size_t)C * KB * 4);
+    L.wpart = take((size_t)((Pp + WGRAD_CHUNK - 1) / WGRAD_CHUNK) * C * KB * 4);
     L.loss = take(4);
     L.tx = take((size_t)max_batch * block * block);
     L.tbnd = take((size_t)max_batch * 4 * block);
@@ -98,6 +98,23 @@ NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
 
 }  // namespace
 
+// A captured training step: everything its kernels take as arguments (the
+// step number is read from the device counter).
+struct TrainKey {
+    bool sampled;
+    const void *blocks, *bnd, *coupling;
+    int64_t n_rows;
+    int32_t batch;
+    uint32_t lr_bits;
+    uint64_t seed;
+    float *loss;
+    bool operator<(const TrainKey &o) const
+    {
+        return std::tie(sampled, blocks, bnd, coupling, n_rows, batch, lr_bits, seed, loss) <
+               std::tie(o.sampled, o.blocks, o.bnd, o.coupling, o.n_rows, o.batch, o.lr_bits, o.seed, o.loss);
+    }
+};
+
 struct ising_nn {
     int32_t Bs = 0, max_batch = 0, max_seq = 0;
     char *buf = nullptr;
@@ -105,7 +122,14 @@ struct ising_nn {
     NetDev net{};
     TrainWs ws{};
     SeqDev seq{};
-    int step = 0;
+    // captured training steps, replayed on the caller's stream; ev_replay is
+    // recorded after each call's replay, and executable graphs are destroyed
+    // only after it completed
+    hipStream_t cap = nullptr;
+    hipEvent_t ev_replay = nullptr;
+    bool replay_pending = false;
+    std::map<TrainKey, hipGraphExec_t> graphs;
+    int64_t captures = 0;
 };
 
 namespace {
@@ -122,9 +146,81 @@ int upload_params(ising_nn *m, const float *host, hipStream_t st)
     NN_HIP(hipMemcpyAsync(m->net.params, host, N_PARAMS * sizeof(float), hipMemcpyHostToDevice, st));
     NN_HIP(hipMemsetAsync(m->net.adam_m, 0, N_PARAMS * sizeof(float), st));
     NN_HIP(hipMemsetAsync(m->net.adam_v, 0, N_PARAMS * sizeof(float), st));
+    NN_HIP(hipMemsetAsync(m->net.step, 0, sizeof(uint32_t), st));
     NN_HIP(cast_weights(m->net, st));
     NN_HIP(hipStreamSynchronize(st));
-    m->step = 0;
+    return ISING_OK;
+}
+
+int wait_replays(ising_nn *m)
+{
+    if (m->replay_pending) {
+        NN_HIP(hipEventSynchronize(m->ev_replay));
+        m->replay_pending = false;
+    }
+    return ISING_OK;
+}
+
+void drop_graphs(ising_nn *m)
+{
+    (void)wait_replays(m);
+    for (auto &kv : m->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    m->graphs.clear();
+}
+
+// One training step (minibatch gather if sampled, forward, backward, Adam,
+// counter advance, BF16 weight copies, loss copy) enqueued on st.
+int enqueue_train(ising_nn *m, const TrainKey &k, float lr, hipStream_t st)
+{
+    const int8_t *x = static_cast<const int8_t *>(k.blocks), *bnd = static_cast<const int8_t *>(k.bnd);
+    const float *kc = static_cast<const float *>(k.coupling);
+    if (k.sampled) {
+        NN_HIP(gather_rows(m->net, m->ws, x, bnd, kc, (uint32_t)k.n_rows, k.batch, m->Bs, k.seed, st));
+        x = m->ws.tx;
+        bnd = m->ws.tbnd;
+        kc = m->ws.tcoup;
+    }
+    NN_HIP(forward(m->net, m->ws, x, bnd, kc, k.batch, m->Bs, st));
+    NN_HIP(backward(m->net, m->ws, x, bnd, kc, k.batch, m->Bs, st));
+    NN_HIP(adam(m->net, lr, st));
+    NN_HIP(cast_weights(m->net, st));
+    if (k.loss)
+        NN_HIP(hipMemcpyAsync(k.loss, m->ws.loss, 4, hipMemcpyDeviceToDevice, st));
+    return ISING_OK;
+}
+
+// Replay the captured step for these arguments (capturing it on first use).
+int train(ising_nn *m, const TrainKey &k, float lr, hipStream_t st)
+{
+    auto it = m->graphs.find(k);
+    hipGraphExec_t ex = nullptr;
+    if (it != m->graphs.end()) {
+        ex = it->second;
+    } else {
+        if (m->graphs.size() >= 8)
+            drop_graphs(m);
+        NN_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_train(m, k, lr, m->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(m->cap, &g);
+        if (rc != ISING_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return fail(ISING_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess)
+            return fail(ISING_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+        m->graphs[k] = ex;
+        m->captures += 1;
+    }
+    NN_HIP(hipGraphLaunch(ex, st));
+    NN_HIP(hipEventRecord(m->ev_replay, st));
+    m->replay_pending = true;
     return ISING_OK;
 }
 
@@ -199,22 +295,20 @@ int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t 
     m->net.adam_v = reinterpret_cast<float *>(B + L.adam_v);
     m->net.grad = reinterpret_cast<float *>(B + L.grad);
     m->net.wt = reinterpret_cast<uint16_t *>(B + L.wt);
-    m->net.wtt = reinterpret_cast<uint16_t *>(B + L.wtt);
+    m->net.wtd = reinterpret_cast<uint16_t *>(B + L.wtd);
+    m->net.step = reinterpret_cast<uint32_t *>(B + L.step);
     for (int l = 0; l < 4; ++l)
         m->ws.h[l] = reinterpret_cast<float *>(B + L.h[l]);
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < 3; ++l)
         m->ws.hb[l] = reinterpret_cast<uint16_t *>(B + L.hb[l]);
-        m->ws.xcol[l] = reinterpret_cast<uint16_t *>(B + L.xcol[l]);
-        m->ws.xcolt[l] = reinterpret_cast<uint16_t *>(B + L.xcolt[l]);
+    for (int b = 0; b < 2; ++b) {
+        m->ws.dpre[b] = reinterpret_cast<float *>(B + L.dpre[b]);
+        m->ws.dpreb[b] = reinterpret_cast<uint16_t *>(B + L.dpreb[b]);
     }
-    m->ws.pre = reinterpret_cast<float *>(B + L.pre);
-    m->ws.dpre = reinterpret_cast<float *>(B + L.dpre);
-    m->ws.dpreb = reinterpret_cast<uint16_t *>(B + L.dpreb);
-    m->ws.dpret = reinterpret_cast<uint16_t *>(B + L.dpret);
     m->ws.logits = reinterpret_cast<float *>(B + L.logits);
     m->ws.dlogit = reinterpret_cast<float *>(B + L.dlogit);
     m->ws.partial = reinterpret_cast<float *>(B + L.partial);
-    m->ws.wgrad = reinterpret_cast<float *>(B + L.wgrad);
+    m->ws.wpart = reinterpret_cast<float *>(B + L.wpart);
     m->ws.loss = reinterpret_cast<float *>(B + L.loss);
     m->ws.tx = reinterpret_cast<int8_t *>(B + L.tx);
     m->ws.tbnd = reinterpret_cast<int8_t *>(B + L.tbnd);
@@ -226,7 +320,15 @@ int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t 
     m->seq.blk = reinterpret_cast<uint32_t *>(B + L.sblk);
     m->seq.logq = reinterpret_cast<double *>(B + L.slogq);
     st = upload_params(m, host_params, reinterpret_cast<hipStream_t>(stream));
+    if (st == ISING_OK) {
+        const hipError_t e1 = hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking);
+        const hipError_t e2 = e1 == hipSuccess ? hipEventCreateWithFlags(&m->ev_replay, hipEventDisableTiming) : e1;
+        if (e2 != hipSuccess)
+            st = fail(ISING_E_HIP, std::string("stream/event creation: ") + hipGetErrorString(e2));
+    }
     if (st != ISING_OK) {
+        if (m->cap)
+            (void)hipStreamDestroy(m->cap);
         delete m;
         return st;
     }
@@ -257,6 +359,19 @@ int ising_nn_set_params(ising_nn *m, const float *host_params, void *stream)
     if (!host_params)
         return fail(ISING_E_INVALID, "host_params must not be NULL");
     return upload_params(m, host_params, reinterpret_cast<hipStream_t>(stream));
+}
+
+int ising_nn_graph_stats(ising_nn *m, int32_t *n_cached, int64_t *n_captured)
+{
+    clear_error();
+    int st = check_nn(m);
+    if (st != ISING_OK)
+        return st;
+    if (n_cached)
+        *n_cached = (int32_t)m->graphs.size();
+    if (n_captured)
+        *n_captured = m->captures;
+    return ISING_OK;
 }
 
 int ising_nn_forward_backward(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
@@ -297,15 +412,10 @@ int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev
         return fail(ISING_E_INVALID, "block arrays must not be NULL");
     if (!(lr > 0.0f))
         return fail(ISING_E_INVALID, "lr must be > 0");
-    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    NN_HIP(forward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
-    NN_HIP(backward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
-    m->step += 1;
-    NN_HIP(adam(m->net, lr, m->step, hs));
-    NN_HIP(cast_weights(m->net, hs));
-    if (dev_loss)
-        NN_HIP(hipMemcpyAsync(dev_loss, m->ws.loss, 4, hipMemcpyDeviceToDevice, hs));
-    return ISING_OK;
+    uint32_t lr_bits;
+    std::memcpy(&lr_bits, &lr, 4);
+    const TrainKey k{false, dev_blocks, dev_bnd, dev_coupling, 0, batch, lr_bits, 0, dev_loss};
+    return train(m, k, lr, reinterpret_cast<hipStream_t>(stream));
 }
 
 int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
@@ -324,10 +434,10 @@ int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int
         return fail(ISING_E_INVALID, "block arrays must not be NULL");
     if (!(lr > 0.0f))
         return fail(ISING_E_INVALID, "lr must be > 0");
-    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    NN_HIP(gather_rows(m->ws, dev_blocks, dev_bnd, dev_coupling, (uint32_t)n_rows, batch, m->Bs, (uint32_t)m->step,
-                       seed, hs));
-    return ising_nn_train_step(m, m->ws.tx, m->ws.tbnd, m->ws.tcoup, batch, lr, dev_loss, stream);
+    uint32_t lr_bits;
+    std::memcpy(&lr_bits, &lr, 4);
+    const TrainKey k{true, dev_blocks, dev_bnd, dev_coupling, n_rows, batch, lr_bits, seed, dev_loss};
+    return train(m, k, lr, reinterpret_cast<hipStream_t>(stream));
 }
 
 int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_t *dev_bnd,
@@ -426,6 +536,13 @@ int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t
 
 int ising_nn_destroy(ising_nn *m)
 {
+    if (m) {
+        drop_graphs(m);
+        if (m->ev_replay)
+            (void)hipEventDestroy(m->ev_replay);
+        if (m->cap)
+            (void)hipStreamDestroy(m->cap);
+    }
     delete m;
     return ISING_OK;
 }

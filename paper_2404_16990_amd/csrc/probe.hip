@@ -235,6 +235,18 @@ __global__ __launch_bounds__(64) void k_mfma_layout(const uint16_t *a, const uin
         out[l * 4 + i] = c[i];
 }
 
+// One v_mfma_f32_16x16x4_f32 with per-lane operands as given (a, b: one float
+// per lane; out: 64 lanes x 4 floats).
+__global__ __launch_bounds__(64) void k_mfma_layout_f32(const float *a, const float *b, float *out)
+{
+    const int l = threadIdx.x;
+    probe_floatx4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[l], b[l], c, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        out[l * 4 + i] = c[i];
+}
+
 template <int W>
 hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
 {
@@ -440,6 +452,17 @@ int ising_probe_mfma_layout(const void *a, const void *b, void *out)
         return -1;
     hipLaunchKernelGGL(k_mfma_layout, dim3(1), dim3(64), 0, nullptr, static_cast<const uint16_t *>(a),
                        static_cast<const uint16_t *>(b), static_cast<float *>(out));
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return -4;
+    return 0;
+}
+
+int ising_probe_mfma_layout_f32(const void *a, const void *b, void *out)
+{
+    if (!a || !b || !out)
+        return -1;
+    hipLaunchKernelGGL(k_mfma_layout_f32, dim3(1), dim3(64), 0, nullptr, static_cast<const float *>(a),
+                       static_cast<const float *>(b), static_cast<float *>(out));
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return -4;
     return 0;

@@ -190,3 +190,28 @@ def mfma_layout():
         for i in range(4):
             got[4 * (l // 16) + i, l % 16] = o[l, i]
     return bool(np.array_equal(got, Cm))
+
+
+def mfma_layout_f32():
+    """Check the lane layout of v_mfma_f32_16x16x4_f32 (the network's layer 1):
+    A (16x4) lane l holds A[l%16][l//16]; B (4x16) lane l holds B[l//16][l%16];
+    C as for the BF16 product.  Returns True if it holds."""
+    import numpy as np
+    import torch
+    L = _lib()
+    L.ising_probe_mfma_layout_f32.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rng = np.random.default_rng(1)
+    A = rng.integers(-8, 9, size=(16, 4)).astype(np.float32)
+    B = rng.integers(-8, 9, size=(4, 16)).astype(np.float32)
+    a = np.array([A[l % 16, l // 16] for l in range(64)], np.float32)
+    b = np.array([B[l // 16, l % 16] for l in range(64)], np.float32)
+    da, db = torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")
+    out = torch.zeros(64 * 4, dtype=torch.float32, device="cuda")
+    if L.ising_probe_mfma_layout_f32(da.data_ptr(), db.data_ptr(), out.data_ptr()) != 0:
+        raise RuntimeError("mfma probe failed")
+    o = out.cpu().numpy().reshape(64, 4)
+    got = np.zeros((16, 16), np.float32)
+    for l in range(64):
+        for i in range(4):
+            got[4 * (l // 16) + i, l % 16] = o[l, i]
+    return bool(np.array_equal(got, A @ B))

@@ -54,6 +54,7 @@ def _params(scale=1.0, seed=16990):
 def test_mfma_lane_layout():
     from paper_2404_16990_amd import probe
     assert probe.mfma_layout()
+    assert probe.mfma_layout_f32()
 
 
 @pytest.mark.parametrize("Bs", [8, 4, 2])
@@ -437,3 +438,31 @@ def test_block_moves_exact_at_the_production_shape():
     print(f"256^2 learned chain at T = {T}: <e> = {means.mean():.6f} +- {means.std(ddof=1) / math.sqrt(R):.6f}, "
           f"exact {exact_e:.6f}, z = {z:.2f}, block acceptance {rate:.3f}")
     assert abs(z) < 4, (means.mean(), exact_e, z)
+
+
+def test_training_steps_replay_one_captured_graph():
+    """40 sampled training steps with the same arguments replay one captured
+    step (its step number lives on the device); setting the parameters
+    restarts the count, so the same 40 steps again give the same parameters
+    bit for bit."""
+    import torch
+    P = _P()
+    rng = np.random.default_rng(12)
+    Bs, batch = 4, 128
+    x, bnd, kc = _rand_blocks(rng, 2000, Bs)
+    X, BN, K = _dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32)
+    theta0 = _params(1.0)
+    net = P.Net(theta0, block=Bs, max_batch=batch, max_seq=64)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(40):
+        net.train_step_sampled(X, BN, K, batch, 1e-3, 7, loss)
+    torch.cuda.synchronize()
+    a = net.params
+    assert net.graph_stats() == (1, 1)
+    assert not np.array_equal(a, theta0)
+    net.set_params(theta0)
+    for _ in range(40):
+        net.train_step_sampled(X, BN, K, batch, 1e-3, 7, loss)
+    torch.cuda.synchronize()
+    assert np.array_equal(net.params, a)
+    assert net.graph_stats() == (1, 1)

@@ -215,6 +215,27 @@ int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uin
                         void *stream);
 
 /*
+ * ising_batch_cluster without a caller workspace, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is the library's own:
+ * ISING_CLUSTER_STATIC_WS_BYTES bytes of device memory in the loaded code
+ * object, one copy per device, held until the process ends; its address on a
+ * device is looked up on the first call with that device current.  Steps are
+ * launched directly (no graph is captured), and nothing is allocated.  Every
+ * call on one device shares that workspace: calls whose work overlaps on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller.  The workspace holds nothing between calls (each step rewrites all
+ * of it that it reads), so results equal ising_batch_cluster's bit for bit.
+ * The current device must be the batch's device.
+ * Errors: ISING_E_INVALID (as ising_batch_cluster; current device is not the
+ * batch's), ISING_E_NOMEM (ising_cluster_ws_bytes() of the batch exceeds
+ * ISING_CLUSTER_STATIC_WS_BYTES; the detail gives both sizes), ISING_E_HIP.
+ */
+#define ISING_CLUSTER_STATIC_WS_BYTES ((size_t)64 << 20)
+int ising_batch_cluster_static(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t record_every,
+                               int64_t *dev_bond_trace, int64_t *dev_mag_trace, void *stream);
+
+/*
  * Execution schedule (what the autotuner chooses; every schedule gives
  * bit-identical results).
  *  word_bits        32 or 64: bits per machine word a thread updates

@@ -31,7 +31,7 @@ EXPORTED = [
     "ising_nn_score",
     "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_graph_stats",
     "ising_nn_destroy",
-    "ising_cluster_ws_bytes", "ising_batch_cluster",
+    "ising_cluster_ws_bytes", "ising_batch_cluster", "ising_batch_cluster_static",
     "ising3d_state_bytes", "ising3d_batch_create", "ising3d_batch_run", "ising3d_batch_observables",
     "ising3d_batch_get_spins", "ising3d_batch_set_spins", "ising3d_batch_get_sweep", "ising3d_batch_destroy",
 ]
@@ -118,6 +118,7 @@ def lib():
         L.ising_nn_destroy.argtypes = [vp]
         L.ising_cluster_ws_bytes.argtypes = [vp, P(ctypes.c_size_t)]
         L.ising_batch_cluster.argtypes = [vp, i32, u64, u32, vp, ctypes.c_size_t, vp, vp, vp]
+        L.ising_batch_cluster_static.argtypes = [vp, i32, u64, u32, vp, vp, vp]
         L.ising3d_state_bytes.argtypes = [i32, P(ising3d_desc), P(ctypes.c_size_t)]
         L.ising3d_batch_create.argtypes = [i32, P(ising3d_desc), vp, ctypes.c_size_t, vp, P(vp)]
         L.ising3d_batch_run.argtypes = [vp, u64, u32, vp, vp, vp]
@@ -308,6 +309,14 @@ def ising_batch_cluster(h, algorithm, n_steps, record_every, dev_ws, ws_bytes, d
                                      stream), "ising_batch_cluster")
 
 
+ISING_CLUSTER_STATIC_WS_BYTES = 64 << 20
+
+
+def ising_batch_cluster_static(h, algorithm, n_steps, record_every, dev_bond=None, dev_mag=None, stream=None):
+    _check(lib().ising_batch_cluster_static(h, algorithm, n_steps, record_every, dev_bond, dev_mag, stream),
+           "ising_batch_cluster_static")
+
+
 def ising_nn_param_count(channels=64):
     n = ctypes.c_int32()
     _check(lib().ising_nn_param_count(int(channels), ctypes.byref(n)), "ising_nn_param_count")
@@ -432,6 +441,22 @@ class Batch:
             return bond, mag
         ising_batch_cluster(self.h, algo, n_steps, 0, self.ws.data_ptr(), self.ws.numel(), None, None, self._s())
         return None
+
+    def cluster_static(self, n_steps, algorithm="sw", bond=None, mag=None, record_every=0):
+        """cluster() on the library's own workspace (ising_batch_cluster_static):
+        the call allocates nothing; traces, if wanted, are caller tensors of
+        shape (n, n_steps // record_every), int64."""
+        algo = {"sw": ISING_CLUSTER_SWENDSEN_WANG, "wolff": ISING_CLUSTER_WOLFF}[algorithm]
+        if record_every:
+            n_rec = n_steps // record_every
+            for t in (bond, mag):
+                if t is None or tuple(t.shape) != (self.n, n_rec) or t.dtype != self.torch.int64 \
+                        or not t.is_contiguous():
+                    raise ValueError("bond and mag must be contiguous int64 tensors of shape (n, n_steps // every)")
+            ising_batch_cluster_static(self.h, algo, n_steps, record_every, bond.data_ptr(), mag.data_ptr(),
+                                       self._s())
+        else:
+            ising_batch_cluster_static(self.h, algo, n_steps, 0, None, None, self._s())
 
     def observables(self):
         import numpy as np

@@ -13,6 +13,8 @@
 // The root of a cluster is its smallest site index.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "cluster.hpp"
 
 namespace ising {
@@ -545,6 +547,30 @@ hipError_t launch_cluster_step(const ClArgs &a, int algorithm, uint32_t step, hi
             hipLaunchKernelGGL(k_cl_flip<kClSwendsenWang>, dim3(cnt), dim3(256), 0, st, a, step, base);
     }
     return hipGetLastError();
+}
+
+// Workspace of the allocation-free cluster entry point.  In host code this
+// name only stands for the symbol; its device address comes from
+// hipGetSymbolAddress, separately for every device.
+static __device__ __align__(256) unsigned char scratch[kClStaticWsBytes];
+
+hipError_t static_cluster_ws(int device, char **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static char *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[device] = static_cast<char *>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace ising

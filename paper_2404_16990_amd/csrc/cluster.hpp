@@ -60,4 +60,11 @@ enum { kClSwendsenWang = 0, kClWolff = 1 };
 // Enqueue one cluster step (counter t + step for every replica) on st.
 hipError_t launch_cluster_step(const ClArgs &a, int algorithm, uint32_t step, hipStream_t st);
 
+// Bytes of the library's own cluster workspace (one copy per device, part of
+// the loaded code object, held until the process ends).
+constexpr size_t kClStaticWsBytes = size_t(64) << 20;
+// Device address of that workspace on `device`, which must be the current
+// device; looked up once per device and kept.
+hipError_t static_cluster_ws(int device, char **ptr);
+
 }  // namespace ising

@@ -3,6 +3,7 @@
 // is a kernel in cluster.hip or kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -149,26 +150,21 @@ int ising_cluster_ws_bytes(ising_batch *b, size_t *bytes)
     return ISING_OK;
 }
 
-int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t record_every, void *dev_ws,
-                        size_t ws_bytes, int64_t *dev_bond_trace, int64_t *dev_mag_trace, void *stream)
+}  // extern "C"
+
+namespace {
+
+// The body of both cluster entry points once the workspace is known.  With
+// graphs, whole chunks replay one captured graph and the rest is launched
+// directly; without, every step is launched directly (nothing is allocated).
+int run_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t record_every, char *ws,
+                int64_t *dev_bond_trace, int64_t *dev_mag_trace, hipStream_t hs, bool graphs)
 {
-    clear_error();
-    if (!b)
-        return fail(ISING_E_INVALID, "NULL batch handle");
-    if (algorithm != ISING_CLUSTER_SWENDSEN_WANG && algorithm != ISING_CLUSTER_WOLFF)
-        return fail(ISING_E_INVALID, "unknown cluster algorithm");
-    if (!dev_ws)
-        return fail(ISING_E_INVALID, "dev_ws must not be NULL");
-    if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0)
-        return fail(ISING_E_INVALID, "dev_ws must be 256-byte aligned");
-    if (ws_bytes < b->cl_ws_bytes)
-        return fail(ISING_E_NOMEM, "dev_ws is smaller than ising_cluster_ws_bytes()");
     if (n_steps == 0)
         return ISING_OK;
     for (int32_t r = 0; r < b->n; ++r)
         if ((uint64_t)b->rep[r].t + n_steps > 0xffffffffull)
             return fail(ISING_E_INVALID, "step counter would reach 2^32");
-    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     RecArgs rec{nullptr, nullptr, 0u, 0u};
     if (record_every > 0 && dev_bond_trace && dev_mag_trace && n_steps / record_every > 0) {
         rec.bond = dev_bond_trace;
@@ -187,11 +183,10 @@ int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uin
     a.cl = b->d_cl;
     a.tile_prefix = b->d_tile_prefix;
     a.n = (uint32_t)b->n;
-    a.ws = static_cast<char *>(dev_ws);
+    a.ws = ws;
     a.tb = reinterpret_cast<uint4 *>(a.ws + b->cl_tb_off);
     a.tiles = (uint32_t)b->cl_tiles;
-    // whole chunks replay one captured graph; the rest is launched directly
-    const uint64_t full = n_steps / kClChunk, rem = n_steps % kClChunk;
+    const uint64_t full = graphs ? n_steps / kClChunk : 0, rem = n_steps - full * kClChunk;
     if (full > 0) {
         hipGraphExec_t ex = nullptr;
         const int st = cluster_graph(b, a, algorithm, kClChunk, recording, &ex);
@@ -202,14 +197,67 @@ int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uin
         CL_HIP(hipEventRecord(b->ev_replay, hs));
         b->replay_pending = true;
     }
-    if (rem > 0) {
-        const int st = enqueue_cluster_chunk(b, a, algorithm, (uint32_t)rem, recording, hs);
+    for (uint64_t done = 0; done < rem;) {
+        const uint32_t n = (uint32_t)std::min<uint64_t>(rem - done, 1u << 20);
+        const int st = enqueue_cluster_chunk(b, a, algorithm, n, recording, hs);
         if (st != ISING_OK)
             return st;
+        done += n;
     }
     for (int32_t r = 0; r < b->n; ++r)
         b->rep[r].t += (uint32_t)n_steps;
     return ISING_OK;
+}
+
+int check_cluster_args(ising_batch *b, int32_t algorithm)
+{
+    if (!b)
+        return fail(ISING_E_INVALID, "NULL batch handle");
+    if (algorithm != ISING_CLUSTER_SWENDSEN_WANG && algorithm != ISING_CLUSTER_WOLFF)
+        return fail(ISING_E_INVALID, "unknown cluster algorithm");
+    return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ising_batch_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t record_every, void *dev_ws,
+                        size_t ws_bytes, int64_t *dev_bond_trace, int64_t *dev_mag_trace, void *stream)
+{
+    clear_error();
+    int st = check_cluster_args(b, algorithm);
+    if (st != ISING_OK)
+        return st;
+    if (!dev_ws)
+        return fail(ISING_E_INVALID, "dev_ws must not be NULL");
+    if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0)
+        return fail(ISING_E_INVALID, "dev_ws must be 256-byte aligned");
+    if (ws_bytes < b->cl_ws_bytes)
+        return fail(ISING_E_NOMEM, "dev_ws is smaller than ising_cluster_ws_bytes()");
+    return run_cluster(b, algorithm, n_steps, record_every, static_cast<char *>(dev_ws), dev_bond_trace,
+                       dev_mag_trace, reinterpret_cast<hipStream_t>(stream), true);
+}
+
+int ising_batch_cluster_static(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t record_every,
+                               int64_t *dev_bond_trace, int64_t *dev_mag_trace, void *stream)
+{
+    clear_error();
+    int st = check_cluster_args(b, algorithm);
+    if (st != ISING_OK)
+        return st;
+    if (b->cl_ws_bytes > kClStaticWsBytes)
+        return fail(ISING_E_NOMEM, "the batch needs " + std::to_string(b->cl_ws_bytes) +
+                                       " bytes of cluster workspace; the static workspace holds " +
+                                       std::to_string(kClStaticWsBytes) + " (use ising_batch_cluster)");
+    int cur = -1;
+    CL_HIP(hipGetDevice(&cur));
+    if (cur != b->device)
+        return fail(ISING_E_INVALID, "the current device is not the batch's device");
+    char *ws = nullptr;
+    CL_HIP(static_cluster_ws(cur, &ws));
+    return run_cluster(b, algorithm, n_steps, record_every, ws, dev_bond_trace, dev_mag_trace,
+                       reinterpret_cast<hipStream_t>(stream), false);
 }
 
 }  // extern "C"

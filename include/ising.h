@@ -379,13 +379,24 @@ int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev
  * dev_coupling [n_rows], same layouts as above): row i of the k-th training
  * step since the parameters were last set is floor(u * n_rows / 2^32), u the
  * first word of Philox4x32-10(counter (i, k, 0, 6), key seed), i < batch.
- * The rows are copied into the network's workspace by a kernel, so the
- * training set stays where it is and the host takes no part in sampling.
+ * The training kernels read the drawn rows straight from the training set,
+ * so it stays where it is and the host takes no part in sampling.
  * Errors: ISING_E_INVALID for batch outside [1, max_batch], n_rows outside
  * [1, 2^32 - 1], NULL arrays or lr <= 0.  Asynchronous. */
 int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
                                 const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
                                 float *dev_loss, void *stream);
+
+/* n_steps >= 1 consecutive ising_nn_train_step_sampled steps in one call
+ * (the same rows, parameters and results as n_steps single calls; dev_loss,
+ * if not NULL, holds the last step's loss).  The steps run as replays of
+ * graphs of up to 16 captured steps each, so consecutive steps follow each
+ * other on the GPU without a launch between them.  Errors: those of
+ * ising_nn_train_step_sampled, and ISING_E_INVALID for n_steps < 1.
+ * Asynchronous. */
+int ising_nn_train_steps_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                                 const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
+                                 int64_t n_steps, float *dev_loss, void *stream);
 
 /* Autoregressive passes on n <= max_seq sequences.  Site k = i*Bs + j of a
  * block has P(x_k = +1 | x_<k, boundary, K) = sigmoid(logit_k) and the uint32

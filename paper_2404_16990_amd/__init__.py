@@ -28,7 +28,7 @@ EXPORTED = [
     "ising_batch_mode_counts", "ising_batch_graph_stats", "ising_batch_autotune", "ising_batch_destroy",
     "ising_nn_param_count", "ising_nn_state_bytes", "ising_nn_create", "ising_nn_get_params",
     "ising_nn_set_params", "ising_nn_forward_backward", "ising_nn_train_step", "ising_nn_train_step_sampled",
-    "ising_nn_score",
+    "ising_nn_train_steps_sampled", "ising_nn_score",
     "ising_nn_sample", "ising_batch_extract_blocks", "ising_batch_block_round", "ising_nn_graph_stats",
     "ising_nn_destroy",
     "ising_cluster_ws_bytes", "ising_batch_cluster", "ising_batch_cluster_static",
@@ -110,6 +110,8 @@ def lib():
         L.ising_nn_forward_backward.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
         L.ising_nn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, vp, vp]
         L.ising_nn_train_step_sampled.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, f32, u64, vp, vp]
+        L.ising_nn_train_steps_sampled.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, f32, u64, ctypes.c_int64,
+                                                   vp, vp]
         L.ising_nn_score.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ising_nn_sample.argtypes = [vp, i32, vp, vp, u64, u32, u32, u32, vp, vp, vp]
         L.ising_batch_extract_blocks.argtypes = [vp, i32, i32, u32, vp, vp, vp, vp]
@@ -360,6 +362,12 @@ def ising_nn_train_step_sampled(m, blocks, bnd, coupling, n_rows, batch, lr, see
                                              int(seed), loss, stream), "ising_nn_train_step_sampled")
 
 
+def ising_nn_train_steps_sampled(m, blocks, bnd, coupling, n_rows, batch, lr, seed, n_steps, loss, stream=None):
+    _check(lib().ising_nn_train_steps_sampled(m, blocks, bnd, coupling, int(n_rows), int(batch), float(lr),
+                                              int(seed), int(n_steps), loss, stream),
+           "ising_nn_train_steps_sampled")
+
+
 def ising_nn_score(m, n, blocks, bnd, coupling, logq, stream=None):
     _check(lib().ising_nn_score(m, int(n), blocks, bnd, coupling, logq, stream), "ising_nn_score")
 
@@ -571,6 +579,13 @@ class Net:
         ising_nn_train_step_sampled(self.h, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(),
                                     blocks.shape[0], batch, lr, seed,
                                     loss.data_ptr() if loss is not None else None, self._s())
+
+    def train_steps_sampled(self, blocks, bnd, coupling, batch, lr, seed, n_steps, loss=None):
+        """n_steps consecutive train_step_sampled steps in one call (replays of
+        graphs of up to 16 captured steps); loss receives the last step's."""
+        ising_nn_train_steps_sampled(self.h, blocks.data_ptr(), bnd.data_ptr(), coupling.data_ptr(),
+                                     blocks.shape[0], batch, lr, seed, n_steps,
+                                     loss.data_ptr() if loss is not None else None, self._s())
 
     def score(self, blocks, bnd, coupling):
         torch = self.torch

@@ -25,14 +25,18 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
-// tanh from the hardware exp2 and reciprocal: tanh|x| = (1 - e)/(1 + e), e = exp(-2|x|).
-// Every kernel of the network uses this one definition, so training, scoring
-// and sampling evaluate the same function.
+// tanh from the hardware exp2 and reciprocal: tanh x = 1 - 2 / (1 + e^{2x}).
+// exp2 overflows to +inf (reciprocal 0) or underflows to 0 far from the
+// origin, so the ends are exactly +1 and -1; near 0 the error is absolute,
+// about one ulp of 1.  Three vector operations and two transcendentals: the
+// activations of every layer go through it, and it is the largest share of
+// the vector-unit work of the network kernels.  Every kernel of the network
+// uses this one definition, so training, scoring and sampling evaluate the
+// same function.
 __device__ __forceinline__ float net_tanh(float x)
 {
-    const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * fabsf(x));  // 2 log2(e)
-    const float t = (1.f - e) * __builtin_amdgcn_rcpf(1.f + e);
-    return copysignf(t, x);
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // e^{2x}; 2.885... = 2 log2(e)
+    return fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + e), 1.f);
 }
 
 __device__ __forceinline__ float net_sigmoid(float x)
@@ -70,41 +74,62 @@ __global__ void k_cast_weights(const float *__restrict__ params, uint16_t *__res
 }
 
 // ---------------------------------------------------------------------------
-// Masked 3x3 convolution of a layer as an implicit GEMM on the matrix cores
-// (BF16 operands, FP32 accumulation).  K = 5 taps x 64 channels in the order
-// t*C + c; a row's A is read straight from the activation rows at the tap
-// offsets (zero where the tap leaves the block), so no unfolded copy exists.
-//  forward (BWD = false), rows p, columns c:
-//    pre[p][c] = sum_t sum_c' in[p + off(t)][c'] W_t[c'][c]   (B = wt)
-//    out = tanh(pre + bias) and its BF16 copy (rows past Pvalid: 0)
-//  data gradient (BWD = true), rows q, columns c':
-//    dh[q][c'] = sum_t sum_c in[q - off(t)][c] W_t[c'][c]     (B = wtd)
-//    out = dh (1 - hprev^2) and its BF16 copy
-// 256 threads per 64 rows x 64 columns; each wave a 32 x 32 quarter of 2 x 2
-// MFMA 16x16x32 tiles.
+// Training step, fused per tile of 64 positions.  Blocks of 2x2, 4x4 and 8x8
+// sites hold 4, 16 and 64 positions, so a tile holds whole blocks and every
+// tap of the masked convolutions stays inside it: one workgroup runs the
+// whole forward and backward of its tile.  The BF16 activations (or
+// pre-activation gradients) a product reads sit in LDS; every FP32 activation
+// stays in the registers of the lane that produced it, because the data
+// gradient puts a layer's pre-activation gradient at the same (position,
+// channel) places of the result tiles as the forward put the activation, so
+// each tanh derivative is where it is needed.
+//  layers 2..4 and their data gradients are implicit GEMMs on the matrix
+//  cores (BF16 operands, FP32 accumulation), K = 5 taps x 64 channels in the
+//  order t*C + c; a row's A operand is the row at the tap offset inside its
+//  block, or an all-zero LDS row where the tap leaves the block (so operand
+//  reads never branch):
+//    forward, rows p, columns c:        pre[p][c] = sum_t sum_c' h[p + off(t)][c'] W_t[c'][c]
+//    data gradient, rows q, columns c': dh[q][c'] = sum_t sum_c d[q - off(t)][c] W_t[c'][c]
+//  each wave a 32 x 32 quarter of the 64 x 64 result (2 x 2 MFMA 16x16x32
+//  tiles); half of the next product's B operands load while the current one
+//  finishes.
+// A tile writes the BF16 operands of the weight gradient (inputs and
+// pre-activation gradients of layers 2..4), its logits, and one row of
+// partial sums: layer-1, bias and head gradients and the loss (nn.hpp).
 // ---------------------------------------------------------------------------
-template <bool BWD>
-__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Bt,
-                                              const float *__restrict__ bias, const float *__restrict__ hprev,
-                                              int Pvalid, int Bs, float *__restrict__ out,
-                                              uint16_t *__restrict__ outb)
+constexpr int ACT_ROW = C + 8;  // padded LDS row (bf16 elements; rows stay 16-byte aligned)
+
+// v + the value of the lane selected by a DPP control (in-register cross-lane
+// read; out-of-row sources read 0)
+template <int CTRL>
+__device__ __forceinline__ float add_dpp(float v)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = blockIdx.x * 64 + (wave >> 1) * 32, n0 = (wave & 1) * 32;
-    const int r = lane & 15, kq = (lane >> 4) * 8;
-    const int BB = Bs * Bs;
-    int base[2], ri[2], rj[2];
-    bool live[2];
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+// this lane's B operands of a product, K slices Q0..Q1-1: output column
+// n0 + 16 b + r, K indices q*32 + kq .. q*32 + kq + 7
+template <int Q0, int Q1>
+__device__ __forceinline__ void load_b(const uint16_t *__restrict__ Bt, int n0, int r, int kq, bf16x8 (&bv)[10][2])
+{
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int p = m0 + a * 16 + r;
-        live[a] = p < Pvalid;
-        const int n = p / BB, k = p - n * BB;
-        base[a] = n * BB;
-        ri[a] = k / Bs;
-        rj[a] = k - ri[a] * Bs;
-    }
-    floatx4 acc[2][2];
+    for (int q = Q0; q < Q1; ++q)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            bv[q][b] = load_bf16x8(Bt + (size_t)(n0 + b * 16 + r) * KB + q * 32 + kq);
+}
+
+// rows arow[a] (this lane's A rows, at (ai, aj) of their block) times the
+// columns n0.. of this wave: forward taps (BWD = false) or mirrored taps
+// (true); row TILE of src is zero.  The caller loaded K slices 0..4 of the B
+// operands in advance; slices 5..9 load here, under the first products.
+template <bool BWD>
+__device__ __forceinline__ void tile_conv(const uint16_t (*src)[ACT_ROW], const uint16_t *__restrict__ Bt,
+                                          bf16x8 (&bv)[10][2], const int (&arow)[2], const int (&ai)[2],
+                                          const int (&aj)[2], const bool (&alive)[2], int Bs, int n0, int r,
+                                          int kq, floatx4 (&acc)[2][2])
+{
+    load_b<5, 10>(Bt, n0, r, kq, bv);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -114,63 +139,377 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ in, c
     for (int q = 0; q < 10; ++q) {
         const int t = q >> 1, half = q & 1;
         const int di = BWD ? -tap_di(t) : tap_di(t), dj = BWD ? -tap_dj(t) : tap_dj(t);
-        bf16x8 av[2], bv[2];
+        bf16x8 av[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int ii = ri[a] + di, jj = rj[a] + dj;
-            av[a] = (live[a] && ii >= 0 && ii < Bs && jj >= 0 && jj < Bs)
-                        ? load_bf16x8(in + (size_t)(base[a] + ii * Bs + jj) * C + half * 32 + kq)
-                        : zero_bf16x8();
+            const int ii = ai[a] + di, jj = aj[a] + dj;
+            const bool ok = alive[a] & (ii >= 0) & (ii < Bs) & (jj >= 0) & (jj < Bs);
+            av[a] = load_bf16x8(&src[ok ? arow[a] + di * Bs + dj : TILE][half * 32 + kq]);
         }
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-            bv[b] = load_bf16x8(Bt + (size_t)(n0 + b * 16 + r) * KB + q * 32 + kq);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[q][b], acc[a][b], 0, 0, 0);
     }
+}
+
+// the tile's 64 LDS rows to a [64][C] BF16 array in global memory (32 bytes a thread)
+__device__ __forceinline__ void store_tile(const uint16_t (*src)[ACT_ROW], uint16_t *__restrict__ dst, int tid)
+{
+    const int row = tid >> 2, col = (tid & 3) * 16;
+    const uint4 *s = reinterpret_cast<const uint4 *>(&src[row][col]);
+    uint4 *d = reinterpret_cast<uint4 *>(dst + (size_t)row * C + col);
+    d[0] = s[0];
+    d[1] = s[1];
+}
+
+// Where a tile's blocks come from: block i of the batch is row i of (x, bnd,
+// kc), or, with a step counter, row floor(u * n_rows / 2^32) with u the first
+// word of Philox(ctr = (i, step, 0, 6), key = seed): a minibatch drawn on the
+// device.
+struct BatchSrc {
+    const int8_t *x, *bnd;
+    const float *kc;
+    const uint32_t *step;  // null: rows in order
+    uint32_t n_rows, seed_lo, seed_hi;
+};
+
+// per-lane column sums of one partial-sum row q, written for the fixed-order
+// sum over the eight row groups at the end of the tile
+__device__ __forceinline__ void put_cols(float (*colpart)[14][C], int grp, int q, const int (&cb)[2], float t0,
+                                         float t1)
+{
+    colpart[grp][q][cb[0]] = t0;
+    colpart[grp][q][cb[1]] = t1;
+}
+
+template <int BS>
+__global__ __launch_bounds__(256, 2) void k_train_tile(NetDev net, TrainWs ws, BatchSrc src, int nblk)
+{
+    constexpr int Bs = BS;
+    constexpr int BND_ZERO = 128;  // index of the zero entry of bs
+    __shared__ __attribute__((aligned(16))) uint16_t act[2][TILE + 1][ACT_ROW];  // row TILE: zeros
+    __shared__ float colpart[8][14][C];  // [row group][partial-sum row q][channel]
+    __shared__ float h1s[TILE][C];        // FP32 layer-1 activations (needed last)
+    __shared__ float rowred[2][TILE];
+    __shared__ float dls[TILE];
+    __shared__ float lrow[TILE];
+    __shared__ float ks[16];
+    __shared__ uint32_t rows[16];
+    __shared__ int8_t xs[TILE + 1];      // entry TILE: 0
+    __shared__ int8_t bs[BND_ZERO + 1];  // entry BND_ZERO: 0
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = (wave >> 1) * 32, n0 = (wave & 1) * 32;
+    const int r = lane & 15, g4 = lane >> 4, kq = g4 * 8, grp = (wave >> 1) * 4 + g4;
+    const int BB = Bs * Bs, NB = 4 * Bs, Pvalid = nblk * BB;
+    const int p0 = blockIdx.x * TILE, nb0 = p0 / BB;
+    const int nbl = min(TILE / BB, nblk - nb0);
+    const float *P = net.params;
+
+    bf16x8 bv[10][2];
+    load_b<0, 5>(net.wt, n0, r, kq, bv);  // layer 2's first half, in flight during the set-up and layer 1
+
+    if (tid < nbl) {
+        uint32_t row = (uint32_t)(nb0 + tid);
+        if (src.step) {
+            uint32_t o[4];
+            philox4x32_10(row, *src.step, 0u, 6u, src.seed_lo, src.seed_hi, o);
+            row = (uint32_t)(((uint64_t)o[0] * src.n_rows) >> 32);
+        }
+        rows[tid] = row;
+        ks[tid] = src.kc[row];
+    }
+    if (tid < 18) {  // the two zero rows, 9 x 16 bytes each
+        uint4 *z = reinterpret_cast<uint4 *>(&act[tid / 9][TILE][0]);
+        z[tid % 9] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    if (tid == 0) {
+        xs[TILE] = 0;
+        bs[BND_ZERO] = 0;
+    }
+    __syncthreads();
+    if (tid < TILE) {
+        const int nl = tid / BB;
+        xs[tid] = p0 + tid < Pvalid ? src.x[(size_t)rows[nl] * BB + tid - nl * BB] : (int8_t)0;
+    }
+    for (int e = tid; e < nbl * NB; e += 256) {
+        const int nl = e / NB;
+        bs[e] = src.bnd[(size_t)rows[nl] * NB + e - nl * NB];
+    }
+    int arow[2], ai[2], aj[2];
+    bool alive[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        arow[a] = m0 + a * 16 + r;
+        alive[a] = p0 + arow[a] < Pvalid;
+        const int k = arow[a] % BB;
+        ai[a] = k / Bs;
+        aj[a] = k - ai[a] * Bs;
+    }
+    const int cb[2] = {n0 + r, n0 + 16 + r};
+    __syncthreads();
+
+    // result place (a, b, i): row m0 + 16 a + 4 g4 + i, column cb[b]; the FP32
+    // activations of layers 2..4 stay in registers, layer 1's in LDS
+    float h[4][2][2][4];
+    // layer 1 (FP32 on the vector units): taps, boundary features, K and bias
+    {
+        float w1[4][2], u1[4][2], v1[2], b1[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                w1[t][b] = P[OFF_W1 + t * C + cb[b]];
+                u1[t][b] = P[OFF_U1 + t * C + cb[b]];
+            }
+            v1[b] = P[OFF_V1 + cb[b]];
+            b1[b] = P[OFF_B1 + cb[b]];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = m0 + a * 16 + 4 * g4 + i;
+                const int nl = p / BB, k = p - nl * BB, pi = k / Bs, pj = k - pi * Bs;
+                float xt[4], bf[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int ii = pi + tap_di(t), jj = pj + tap_dj(t);
+                    xt[t] = (float)xs[(ii >= 0 && jj >= 0 && jj < Bs) ? nl * BB + ii * Bs + jj : TILE];
+                }
+                const int nbase = nl * NB;
+                bf[0] = (float)bs[pi == 0 ? nbase + pj : BND_ZERO];
+                bf[1] = (float)bs[pi == Bs - 1 ? nbase + Bs + pj : BND_ZERO];
+                bf[2] = (float)bs[pj == 0 ? nbase + 2 * Bs + pi : BND_ZERO];
+                bf[3] = (float)bs[pj == Bs - 1 ? nbase + 3 * Bs + pi : BND_ZERO];
+                const bool valid = p0 + p < Pvalid;
+                const float kv = ks[nl];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    float pre = kv * v1[b] + b1[b];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        pre += xt[t] * w1[t][b];
+                    float f = 0.f;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        f += bf[t] * u1[t][b];
+                    pre += f;
+                    const float v = valid ? net_tanh(pre) : 0.f;
+                    h1s[p][cb[b]] = v;
+                    act[0][p][cb[b]] = f2bf(v);
+                }
+            }
+    }
+    __syncthreads();
+    store_tile(act[0], ws.hb[0] + (size_t)p0 * C, tid);
+
+    // layers 2..4: act[(l - 2) & 1] holds the BF16 input
+#pragma unroll
+    for (int l = 2; l <= 4; ++l) {
+        const int cur = (l - 2) & 1;
+        floatx4 acc[2][2];
+        tile_conv<false>(act[cur], net.wt + (size_t)(l - 2) * C * KB, bv, arow, ai, aj, alive, Bs, n0, r, kq, acc);
+        // the next product's first B slices: layer l + 1, or the first data gradient (layer 4's)
+        load_b<0, 5>(l < 4 ? net.wt + (size_t)(l - 1) * C * KB : net.wtd + (size_t)2 * C * KB, n0, r, kq, bv);
+        const float bias[2] = {P[off_b(l) + cb[0]], P[off_b(l) + cb[1]]};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int p = m0 + a * 16 + 4 * g4 + i;
+                    // rows past the batch read only zero rows: a finite tanh(bias), masked
+                    const float v = net_tanh(acc[a][b][i] + bias[b]) * (p0 + p < Pvalid ? 1.f : 0.f);
+                    h[l - 1][a][b][i] = v;
+                    if (l < 4)
+                        act[cur ^ 1][p][cb[b]] = f2bf(v);
+                }
+        if (l < 4) {
+            __syncthreads();
+            store_tile(act[cur ^ 1], ws.hb[l - 1] + (size_t)p0 * C, tid);
+        }
+    }
+
+    // head: logit[p] = bo + sum_c h4[p][c] wo[c] (a fixed DPP tree over the 16
+    // lanes of a row, then the two column halves), the loss softplus(-x logit)
+    // and dlogit = -x sigmoid(-x logit) / P
+    const float wo[2] = {P[OFF_WO + cb[0]], P[OFF_WO + cb[1]]};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < 4; ++i) {
+            float s = h[3][a][0][i] * wo[0] + h[3][a][1][i] * wo[1];
+            s = add_dpp<0xb1>(s);   // lane ^ 1
+            s = add_dpp<0x4e>(s);   // lane ^ 2
+            s = add_dpp<0x104>(s);  // lane + 4
+            s = add_dpp<0x108>(s);  // lane + 8
+            if (r == 0)
+                rowred[wave & 1][m0 + a * 16 + 4 * g4 + i] = s;
+        }
+    __syncthreads();
+    if (tid < TILE) {
+        float l = 0.f, d = 0.f;
+        if (p0 + tid < Pvalid) {
+            const float logit = (P[OFF_BO] + rowred[0][tid]) + rowred[1][tid];
+            ws.logits[p0 + tid] = logit;
+            const float xv = (float)xs[tid];
+            const float z = -xv * logit;
+            l = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+            d = -xv / (1.f + expf(-z)) / (float)Pvalid;
+        }
+        dls[tid] = d;
+        lrow[tid] = l;
+    }
+    __syncthreads();
+
+    // head backward: dpre4 = dlogit wo (1 - h4^2); wo and b4 gradient partials
+    float d[2][2][4];
+    {
+        float swo[2] = {0.f, 0.f}, sb4[2] = {0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int p = m0 + a * 16 + 4 * (lane >> 4) + i, c = n0 + b * 16 + r;
-                const size_t idx = (size_t)p * C + c;
-                float v;
-                if (BWD) {
-                    const float hv = hprev[idx];
-                    v = acc[a][b][i] * (1.f - hv * hv);
-                } else {
-                    v = p < Pvalid ? net_tanh(acc[a][b][i] + bias[c]) : 0.f;
+                const int p = m0 + a * 16 + 4 * g4 + i;
+                const float dl = dls[p];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const float hv = h[3][a][b][i];
+                    const float dv = dl * wo[b] * (1.f - hv * hv);
+                    d[a][b][i] = dv;
+                    act[1][p][cb[b]] = f2bf(dv);
+                    swo[b] += hv * dl;
+                    sb4[b] += dv;
                 }
-                out[idx] = v;
-                if (outb)
-                    outb[idx] = f2bf(v);
             }
+        put_cols(colpart, grp, 13, cb, swo[0], swo[1]);
+        put_cols(colpart, grp, 12, cb, sb4[0], sb4[1]);
+    }
+    __syncthreads();
+    store_tile(act[1], ws.db[2] + (size_t)p0 * C, tid);
+
+    // data gradients: layer l's BF16 pre-activation gradient in act[(l + 1) & 1]
+    // -> layer l-1's, times its tanh derivative
+#pragma unroll
+    for (int l = 4; l >= 2; --l) {
+        const int srcb = (l + 1) & 1;
+        floatx4 acc[2][2];
+        tile_conv<true>(act[srcb], net.wtd + (size_t)(l - 2) * C * KB, bv, arow, ai, aj, alive, Bs, n0, r, kq,
+                        acc);
+        if (l > 2)
+            load_b<0, 5>(net.wtd + (size_t)(l - 3) * C * KB, n0, r, kq, bv);
+        float sb[2] = {0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float hv = l > 2 ? h[l - 2][a][b][i] : h1s[m0 + a * 16 + 4 * g4 + i][cb[b]];
+                    const float v = acc[a][b][i] * (1.f - hv * hv);
+                    d[a][b][i] = v;
+                    if (l > 2) {
+                        act[srcb ^ 1][m0 + a * 16 + 4 * g4 + i][cb[b]] = f2bf(v);
+                        sb[b] += v;
+                    }
+                }
+        if (l > 2) {
+            put_cols(colpart, grp, 10 + (l - 3), cb, sb[0], sb[1]);
+            __syncthreads();
+            store_tile(act[srcb ^ 1], ws.db[l - 3] + (size_t)p0 * C, tid);
+        }
+    }
+
+    // layer-1 gradients from dpre1: taps (W1), boundary features (U1), K (v1), 1 (b1)
+    {
+        float g1[10][2];
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            g1[q][0] = g1[q][1] = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = m0 + a * 16 + 4 * g4 + i;
+                const int nl = p / BB, k = p - nl * BB, pi = k / Bs, pj = k - pi * Bs;
+                const int nbase = nl * NB;
+                float in[10];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int ii = pi + tap_di(t), jj = pj + tap_dj(t);
+                    in[t] = (float)xs[(ii >= 0 && jj >= 0 && jj < Bs) ? nl * BB + ii * Bs + jj : TILE];
+                }
+                in[4] = (float)bs[pi == 0 ? nbase + pj : BND_ZERO];
+                in[5] = (float)bs[pi == Bs - 1 ? nbase + Bs + pj : BND_ZERO];
+                in[6] = (float)bs[pj == 0 ? nbase + 2 * Bs + pi : BND_ZERO];
+                in[7] = (float)bs[pj == Bs - 1 ? nbase + 3 * Bs + pi : BND_ZERO];
+                in[8] = ks[nl];
+                in[9] = 1.f;
+                const bool valid = p0 + p < Pvalid;  // d is 0 past the batch; ks there is unset
+#pragma unroll
+                for (int q = 0; q < 10; ++q)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        g1[q][b] += valid ? in[q] * d[a][b][i] : 0.f;
+            }
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            put_cols(colpart, grp, q, cb, g1[q][0], g1[q][1]);
+    }
+    __syncthreads();
+    float *part = ws.partial + (size_t)blockIdx.x * PART_ROW;
+    for (int e = tid; e < 14 * C; e += 256) {
+        const int q = e / C, c = e - q * C;
+        float s = 0.f;
+#pragma unroll
+        for (int g = 0; g < 8; ++g)
+            s += colpart[g][q][c];
+        part[e] = s;
+    }
+    if (tid >= 254) {  // the loss and the head-bias gradient over the tile's rows
+        const float *v = tid == 254 ? lrow : dls;
+        float s = 0.f;
+        for (int p = 0; p < TILE; ++p)
+            s += v[p];
+        part[tid == 254 ? PART_LOSS : PART_BO] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient of a layer, split over positions (the K of the product):
-//   part[s][c][t*C + c'] = sum over the positions p of split s of
-//                          dpreb[p][c] in[p + off(t)][c']   (0 where the tap leaves the block)
-// Each step stages 32 positions of both operands in LDS, transposed, so a
-// matrix-core operand (8 consecutive positions of one channel) is one 16-byte
-// read.  Grid: 5 taps x splits; each wave a 32 x 32 quarter of the 64 x 64 tile.
+// Weight gradients of layers 2..4, split over positions (the K of the product):
+//   wpart[z][s][t*C + c'][c] = sum over the positions p of split s of
+//                              in_z[p + off(t)][c'] d_z[p][c]
+// (in_z: BF16 input of layer z + 2, d_z: its BF16 pre-activation gradient; 0
+// where the tap leaves the block), so a split's rows t*C + c' are laid out
+// like the parameter vector.  Each step stages 64 positions of both operands
+// in LDS transposed, a channel's positions pairwise in 32-bit words whose
+// index is XOR-swizzled by the channel's group of 8 (the staging writes of a
+// wave then hit 64 distinct banks); a matrix-core operand (8 consecutive
+// positions of one channel) stays one 16-byte read.  Grid: 5 taps x splits x
+// 3 layers; each wave a 32 x 32 quarter of the 64 x 64 tile.  advance (if not
+// null): the training-step counter, counted here because no other workgroup
+// of this kernel reads it (the tile kernel before it drew its minibatch with
+// the old count, the Adam update after it uses the new one).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dpreb, const uint16_t *__restrict__ in,
-                                               int Pvalid, int Bs, float *__restrict__ part)
+template <int BS>
+__global__ __launch_bounds__(256) void k_wgrad(TrainWs ws, int Pvalid, int splits, uint32_t *advance)
 {
-    constexpr int ROW = 40;  // 32 positions + padding (bf16 elements; rows stay 16-byte aligned)
-    __shared__ __attribute__((aligned(16))) uint16_t at[C][ROW];
-    __shared__ __attribute__((aligned(16))) uint16_t bt[C][ROW];
-    const int t = blockIdx.x, s = blockIdx.y;
+    constexpr int Bs = BS;
+    constexpr int WROW = 36;  // words per staged channel row: 32 used, rows 16-byte aligned
+    __shared__ __attribute__((aligned(16))) uint32_t sd[C][WROW];  // pre-activation gradient
+    __shared__ __attribute__((aligned(16))) uint32_t si[C][WROW];  // tap-shifted input
+    const int t = blockIdx.x, s = blockIdx.y, z = blockIdx.z;
+    if (advance && t == 0 && s == 0 && z == 0 && threadIdx.x == 0)
+        *advance += 1u;
+    const uint16_t *__restrict__ dpre = ws.db[z];
+    const uint16_t *__restrict__ in = ws.hb[z];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = (wave >> 1) * 32, n0 = (wave & 1) * 32;
-    const int r = lane & 15, kq = (lane >> 4) * 8;
-    const int pl = tid >> 3, c8 = (tid & 7) * 8;  // staging: position in step, channel chunk
+    const int r = lane & 15, g4 = lane >> 4;
+    const int pp = tid >> 3, cg = tid & 7;  // staging: position pair, group of 8 channels
     const int BB = Bs * Bs;
     floatx4 acc[2][2];
 #pragma unroll
@@ -179,275 +518,170 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ dpre
         for (int b = 0; b < 2; ++b)
             acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int p_begin = s * WGRAD_CHUNK, p_end = min(p_begin + WGRAD_CHUNK, Pvalid);
-    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
-        const int p = p0 + pl;
-        uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = va;
+    // channels 8 cg .. 8 cg + 7 of position p of both operands (0 past the split or outside the block)
+    auto fetch = [&](int p, uint4 &vd, uint4 &vi) {
+        vd = make_uint4(0u, 0u, 0u, 0u);
+        vi = vd;
         if (p < p_end) {
-            va = *reinterpret_cast<const uint4 *>(dpreb + (size_t)p * C + c8);
+            vd = *reinterpret_cast<const uint4 *>(dpre + (size_t)p * C + 8 * cg);
             const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
             const int ii = i + tap_di(t), jj = j + tap_dj(t);
             if (ii >= 0 && jj >= 0 && jj < Bs)
-                vb = *reinterpret_cast<const uint4 *>(in + (size_t)(n * BB + ii * Bs + jj) * C + c8);
+                vi = *reinterpret_cast<const uint4 *>(in + (size_t)(n * BB + ii * Bs + jj) * C + 8 * cg);
         }
-        const uint16_t *ea = reinterpret_cast<const uint16_t *>(&va);
-        const uint16_t *eb = reinterpret_cast<const uint16_t *>(&vb);
+    };
+    uint4 d0, d1, i0, i1;
+    fetch(p_begin + 2 * pp, d0, i0);
+    fetch(p_begin + 2 * pp + 1, d1, i1);
+    for (int p0 = p_begin; p0 < p_end; p0 += 64) {
+        const uint16_t *ed0 = reinterpret_cast<const uint16_t *>(&d0), *ed1 = reinterpret_cast<const uint16_t *>(&d1);
+        const uint16_t *ei0 = reinterpret_cast<const uint16_t *>(&i0), *ei1 = reinterpret_cast<const uint16_t *>(&i1);
+        const int w = pp ^ (cg << 2);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            at[c8 + q][pl] = ea[q];
-            bt[c8 + q][pl] = eb[q];
+            sd[8 * cg + q][w] = (uint32_t)ed0[q] | ((uint32_t)ed1[q] << 16);
+            si[8 * cg + q][w] = (uint32_t)ei0[q] | ((uint32_t)ei1[q] << 16);
         }
         __syncthreads();
-        bf16x8 av[2], bv[2];
+        fetch(p0 + 64 + 2 * pp, d0, i0);  // the next step's operands load while this one multiplies
+        fetch(p0 + 64 + 2 * pp + 1, d1, i1);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-            av[a] = load_bf16x8(&at[m0 + a * 16 + r][kq]);
+        for (int kst = 0; kst < 2; ++kst) {
+            bf16x8 av[2], bv[2];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-            bv[b] = load_bf16x8(&bt[n0 + b * 16 + r][kq]);
+            for (int a = 0; a < 2; ++a) {
+                const int row = m0 + a * 16 + r;
+                av[a] = load_bf16x8(reinterpret_cast<const uint16_t *>(
+                    &si[row][(16 * kst + 4 * g4) ^ (((row >> 3) & 7) << 2)]));
+            }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const int row = n0 + b * 16 + r;
+                bv[b] = load_bf16x8(reinterpret_cast<const uint16_t *>(
+                    &sd[row][(16 * kst + 4 * g4) ^ (((row >> 3) & 7) << 2)]));
+            }
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
         __syncthreads();
     }
+    float *__restrict__ part = ws.wpart + ((size_t)z * splits + s) * KB * C;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int c = m0 + a * 16 + 4 * (lane >> 4) + i, ci = n0 + b * 16 + r;
-                part[((size_t)s * C + c) * KB + t * C + ci] = acc[a][b][i];
+                const int k = t * C + m0 + a * 16 + 4 * g4 + i, c = n0 + b * 16 + r;
+                part[(size_t)k * C + c] = acc[a][b][i];
             }
 }
 
-// grad W_l[t][c'][c] = sum over splits s (in order) of part[s][c][t*C + c']
-__global__ void k_wgrad_sum(const float *__restrict__ part, int S, int l, float *__restrict__ grad)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= C * KB)
-        return;
-    const int c = idx / KB, k = idx - c * KB;
-    float v = 0.f;
-    for (int s = 0; s < S; ++s)
-        v += part[(size_t)s * C * KB + idx];
-    grad[off_w(l) + k * C + c] = v;
-}
-
 // ---------------------------------------------------------------------------
-// training forward
+// End of a training step: the gradient from the partial sums (weight entries
+// over the position splits in 4 groups, the other entries over the tiles in
+// 16 groups, each combined in a fixed order), the loss, and with ADAM the Adam
+// update (the step number t is the device counter, already advanced by the
+// weight-gradient kernel; the bias corrections 1 - beta^t are formed in FP64 from the
+// exact decimal betas) and the BF16 copies of the updated weights.
+// Workgroups [0, FIN_W_BLOCKS) take 64 weight entries each, the rest 16
+// partial-sum columns each.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float boundary_field(const int8_t *bnd, int Bs, int i, int j, const float *u)
+constexpr int FIN_W_BLOCKS = 3 * C * KB / 64;
+constexpr int FIN_S_BLOCKS = (PART_USED + 15) / 16;
+
+__device__ __forceinline__ float adam_update(const NetDev &net, int i, float g, float lr, float c1, float c2)
 {
-    float f = 0.f;
-    if (i == 0)
-        f += (float)bnd[j] * u[0];
-    if (i == Bs - 1)
-        f += (float)bnd[Bs + j] * u[1];
-    if (j == 0)
-        f += (float)bnd[2 * Bs + i] * u[2];
-    if (j == Bs - 1)
-        f += (float)bnd[3 * Bs + i] * u[3];
-    return f;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mi = b1 * net.adam_m[i] + (1.f - b1) * g;
+    const float vi = b2 * net.adam_v[i] + (1.f - b2) * g * g;
+    net.adam_m[i] = mi;
+    net.adam_v[i] = vi;
+    const float w = net.params[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    net.params[i] = w;
+    return w;
 }
 
-__global__ void k_layer1(const float *__restrict__ params, const int8_t *__restrict__ x,
-                         const int8_t *__restrict__ bnd, const float *__restrict__ kc, int nblk, int Bs,
-                         int Ppad, float *__restrict__ h, uint16_t *__restrict__ hb)
+// parameter index of partial-sum column j (j != PART_LOSS)
+__device__ __forceinline__ int part_param(int j)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Ppad * C)
-        return;
-    const int p = idx / C, c = idx - p * C;
-    const int BB = Bs * Bs;
-    float v = 0.f;
-    if (p < nblk * BB) {
-        const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
-        float pre = kc[n] * params[OFF_V1 + c] + params[OFF_B1 + c];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int ii = i + tap_di(t), jj = j + tap_dj(t);
-            if (ii >= 0 && jj >= 0 && jj < Bs)
-                pre += (float)x[n * BB + ii * Bs + jj] * params[OFF_W1 + t * C + c];
-        }
-        const float u[4] = {params[OFF_U1 + c], params[OFF_U1 + C + c], params[OFF_U1 + 2 * C + c],
-                            params[OFF_U1 + 3 * C + c]};
-        pre += boundary_field(bnd + n * 4 * Bs, Bs, i, j, u);
-        v = net_tanh(pre);
+    if (j < PART_B2)
+        return OFF_W1 + j;
+    if (j < PART_B3)
+        return off_b(2) + j - PART_B2;
+    if (j < PART_B4)
+        return off_b(3) + j - PART_B3;
+    if (j < PART_WO)
+        return off_b(4) + j - PART_B4;
+    if (j < PART_BO)
+        return OFF_WO + j - PART_WO;
+    return OFF_BO;
+}
+
+template <bool ADAM>
+__global__ __launch_bounds__(256) void k_finish(NetDev net, TrainWs ws, int n_tiles, int splits, int Pvalid, float lr,
+                                                float *loss_out)
+{
+    __shared__ float red[16][64];
+    const int tid = threadIdx.x;
+    float c1 = 1.f, c2 = 1.f;
+    if (ADAM) {
+        const double t = (double)*net.step;
+        c1 = (float)(1.0 - pow(0.9, t));
+        c2 = (float)(1.0 - pow(0.999, t));
     }
-    h[idx] = v;
-    hb[idx] = f2bf(v);
-}
-
-__global__ void k_head(const float *__restrict__ h4, const float *__restrict__ params, int Pvalid,
-                       float *__restrict__ logits)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= Pvalid)
-        return;
-    float s = params[OFF_BO];
-    for (int c = 0; c < C; ++c)
-        s = fmaf(h4[(size_t)p * C + c], params[OFF_WO + c], s);
-    logits[p] = s;
-}
-
-// per-position loss softplus(-x l) into partial sums; dlogit = -x sigmoid(-x l) / P
-__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ logits, const int8_t *__restrict__ x,
-                                              int Pvalid, int Ppad, float *__restrict__ dlogit,
-                                              float *__restrict__ partial)
-{
-    __shared__ float red[256];
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    float l = 0.f;
-    if (p < Ppad) {
-        float d = 0.f;
-        if (p < Pvalid) {
-            const float xv = (float)x[p];
-            const float z = -xv * logits[p];
-            l = z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
-            d = -xv / (1.f + expf(-z)) / (float)Pvalid;  // -x sigmoid(z)
-        }
-        dlogit[p] = d;
-    }
-    red[threadIdx.x] = l;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-            red[threadIdx.x] += red[threadIdx.x + s];
+    if (blockIdx.x < FIN_W_BLOCKS) {
+        const int z = blockIdx.x / (C * KB / 64), el = tid & 63, g = tid >> 6;
+        const int e = (blockIdx.x - z * (C * KB / 64)) * 64 + el;  // k * C + c, k = t*C + c'
+        const float *wp = ws.wpart + (size_t)z * splits * KB * C + e;
+        float v = 0.f;
+#pragma unroll 8
+        for (int s = g; s < splits; s += 4)
+            v += wp[(size_t)s * KB * C];
+        red[g][el] = v;
         __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        partial[blockIdx.x] = red[0];
-}
-
-__global__ __launch_bounds__(256) void k_sum(const float *__restrict__ partial, int n, float scale,
-                                             float *__restrict__ out)
-{
-    __shared__ float red[256];
-    float s = 0.f;
-    for (int i = threadIdx.x; i < n; i += 256)
-        s += partial[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k)
-            red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        out[0] = red[0] * scale;
-}
-
-// ---------------------------------------------------------------------------
-// training backward
-// ---------------------------------------------------------------------------
-// dpre4 = dlogit * wo * (1 - h4^2), in fp32 and bf16
-__global__ void k_dpre_head(const float *__restrict__ h4, const float *__restrict__ dlogit,
-                            const float *__restrict__ params, int Ppad, float *__restrict__ dpre,
-                            uint16_t *__restrict__ dpreb)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Ppad * C)
-        return;
-    const int p = idx / C, c = idx - p * C;
-    const float hv = h4[idx];
-    const float d = dlogit[p] * params[OFF_WO + c] * (1.f - hv * hv);
-    dpre[idx] = d;
-    dpreb[idx] = f2bf(d);
-}
-
-// partial column sums: partial[blk][c] = sum over this block's rows of A[p][c] * (w ? w[p] : 1)
-__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ A, const float *__restrict__ w,
-                                                int rows, int rows_per_blk, float *__restrict__ partial)
-{
-    // 256 threads = 4 row groups x 64 columns
-    __shared__ float red[4][C];
-    const int c = threadIdx.x & (C - 1), g = threadIdx.x >> 6;
-    const int r0 = blockIdx.x * rows_per_blk;
-    const int r1 = min(r0 + rows_per_blk, rows);
-    float s = 0.f;
-    for (int r = r0 + g; r < r1; r += 4)
-        s += A[(size_t)r * C + c] * (w ? w[r] : 1.f);
-    red[g][c] = s;
-    __syncthreads();
-    if (g == 0)
-        partial[blockIdx.x * C + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-}
-
-// out[j] (+)= sum_b partial[b][j], j < width; fixed order
-__global__ void k_reduce_cols(const float *__restrict__ partial, int nb, int width, float *__restrict__ out)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= width)
-        return;
-    float s = 0.f;
-    for (int b = 0; b < nb; ++b)
-        s += partial[(size_t)b * width + j];
-    out[j] = s;
-}
-
-// layer-1 gradients: 10 rows (W1 taps 0..3, U1 f 0..3, v1, b1) x C, partial over positions
-__global__ __launch_bounds__(256) void k_layer1_grad(const float *__restrict__ dpre1, const int8_t *__restrict__ x,
-                                                     const int8_t *__restrict__ bnd, const float *__restrict__ kc,
-                                                     int nblk, int Bs, int rows_per_blk, float *__restrict__ partial)
-{
-    __shared__ float red[4][10][C];
-    const int c = threadIdx.x & (C - 1), g = threadIdx.x >> 6;
-    const int BB = Bs * Bs, P = nblk * BB;
-    const int r0 = blockIdx.x * rows_per_blk, r1 = min(r0 + rows_per_blk, P);
-    float acc[10];
-#pragma unroll
-    for (int q = 0; q < 10; ++q)
-        acc[q] = 0.f;
-    for (int p = r0 + g; p < r1; p += 4) {
-        const int n = p / BB, k = p - n * BB, i = k / Bs, j = k - i * Bs;
-        const float d = dpre1[(size_t)p * C + c];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int ii = i + tap_di(t), jj = j + tap_dj(t);
-            if (ii >= 0 && jj >= 0 && jj < Bs)
-                acc[t] += (float)x[n * BB + ii * Bs + jj] * d;
+        if (g == 0) {
+            const float gr = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+            const int i = off_w(z + 2) + e;
+            net.grad[i] = gr;
+            if (ADAM) {
+                const uint16_t wb = f2bf(adam_update(net, i, gr, lr, c1, c2));
+                const int k = e / C, c = e - k * C, t = k / C, ci = k - t * C;
+                net.wt[((size_t)z * C + c) * KB + k] = wb;
+                net.wtd[((size_t)z * C + ci) * KB + t * C + c] = wb;
+            }
         }
-        const int8_t *bn = bnd + n * 4 * Bs;
-        if (i == 0)
-            acc[4] += (float)bn[j] * d;
-        if (i == Bs - 1)
-            acc[5] += (float)bn[Bs + j] * d;
-        if (j == 0)
-            acc[6] += (float)bn[2 * Bs + i] * d;
-        if (j == Bs - 1)
-            acc[7] += (float)bn[3 * Bs + i] * d;
-        acc[8] += kc[n] * d;
-        acc[9] += d;
-    }
+    } else {
+        const int jl = tid & 15, g = tid >> 4;
+        const int j = (blockIdx.x - FIN_W_BLOCKS) * 16 + jl;
+        float v = 0.f;
+        if (j < PART_USED)
+#pragma unroll 8
+            for (int b = g; b < n_tiles; b += 16)
+                v += ws.partial[(size_t)b * PART_ROW + j];
+        red[g][jl] = v;
+        __syncthreads();
+        if (g == 0 && j < PART_USED) {
+            float gr = 0.f;
 #pragma unroll
-    for (int q = 0; q < 10; ++q)
-        red[g][q][c] = acc[q];
-    __syncthreads();
-    if (g == 0)
-        for (int q = 0; q < 10; ++q)
-            partial[(size_t)blockIdx.x * 10 * C + q * C + c] = red[0][q][c] + red[1][q][c] + red[2][q][c] + red[3][q][c];
-}
-
-// Adam step number t = (steps taken) + 1 from the device counter, so a
-// captured training step stays valid for every replay; the bias corrections
-// 1 - beta^t are formed in FP64 from the exact decimal betas.
-__global__ void k_adam(float *__restrict__ params, const float *__restrict__ grad, float *__restrict__ m,
-                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
-                       const uint32_t *__restrict__ steps_taken)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    const double t = (double)*steps_taken + 1.0;
-    const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
-    const float g = grad[i];
-    const float mi = b1 * m[i] + (1.f - b1) * g;
-    const float vi = b2 * v[i] + (1.f - b2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
-    params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+            for (int k = 0; k < 16; ++k)
+                gr += red[k][jl];
+            if (j == PART_LOSS) {
+                const float loss = gr * (1.f / (float)Pvalid);
+                ws.loss[0] = loss;
+                if (loss_out)
+                    *loss_out = loss;
+            } else {
+                const int i = part_param(j);
+                net.grad[i] = gr;
+                if (ADAM)
+                    (void)adam_update(net, i, gr, lr, c1, c2);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -551,14 +785,6 @@ __device__ __forceinline__ uint32_t site_threshold(float logit)
     return t > 1u ? t : 1u;
 }
 
-// v + the value of the lane selected by a DPP control (in-register cross-lane
-// read; out-of-row sources read 0)
-template <int CTRL>
-__device__ __forceinline__ float add_dpp(float v)
-{
-    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
-}
-
 // Sum of the logit head over this wave's 16 channels for the 4 rows this
 // lane holds: within each row of 16 lanes, pairs, then quads (quad
 // permutations), then lane + 4 and lane + 8 (row shifts), so lane 0 of the
@@ -589,7 +815,8 @@ __device__ __forceinline__ float head_logit(const float *h0, const float *h1, co
 
 // log q = sum_k log(thr_k or 2^32 - thr_k) - BB * 32 ln 2 in FP64, summed in a
 // fixed order: 16 parts of 4 consecutive sites, then the parts in order.
-__device__ __forceinline__ void logq_parts(const int8_t (*xs)[64], const uint32_t (*thr)[64], int BB, int tid,
+template <int XS, int TS>
+__device__ __forceinline__ void logq_parts(const int8_t (*xs)[XS], const uint32_t (*thr)[TS], int BB, int tid,
                                            double (*part)[16])
 {
     const int s = tid >> 4, pt = tid & 15;
@@ -615,9 +842,10 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
     constexpr int BB = BS * BS;
     __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][RING_ROW];
     __shared__ float head_part[4][SEQ_PER_WG];
-    __shared__ int8_t xs[SEQ_PER_WG][64];
-    __shared__ int8_t bs[SEQ_PER_WG][32];
-    __shared__ uint32_t ut[SEQ_PER_WG][64];  // site uniform; replaced by the site's threshold once drawn
+    // per-sequence rows padded so the 16 rows of a tile fall in different LDS banks
+    __shared__ int8_t xs[SEQ_PER_WG][68];
+    __shared__ int8_t bs[SEQ_PER_WG][36];
+    __shared__ uint32_t ut[SEQ_PER_WG][65];  // site uniform; replaced by the site's threshold once drawn
     __shared__ float ks[SEQ_PER_WG];
     __shared__ double lq_part[SEQ_PER_WG][16];
 
@@ -1016,34 +1244,6 @@ __global__ void k_extract(const RepDev *__restrict__ reps, const double *__restr
     kout[q] = (float)kcoup[r];
 }
 
-// Minibatch drawn on the device: row i of training step k is
-// floor(u * n_rows / 2^32) with u the first word of Philox(ctr = (i, k, 0, 6),
-// key = seed); one workgroup of 64 threads copies one row.
-__global__ __launch_bounds__(64) void k_gather_rows(const int8_t *__restrict__ x, const int8_t *__restrict__ bnd,
-                                                    const float *__restrict__ kc, uint32_t n_rows, int BB, int NB,
-                                                    const uint32_t *__restrict__ steps_taken, uint32_t seed_lo,
-                                                    uint32_t seed_hi, int8_t *__restrict__ tx,
-                                                    int8_t *__restrict__ tb, float *__restrict__ tk)
-{
-    const uint32_t i = blockIdx.x, step = *steps_taken;
-    uint32_t o[4];
-    philox4x32_10(i, step, 0u, 6u, seed_lo, seed_hi, o);
-    const size_t row = (size_t)(((uint64_t)o[0] * n_rows) >> 32);
-    for (int j = threadIdx.x; j < BB; j += 64)
-        tx[(size_t)i * BB + j] = x[row * BB + j];
-    for (int j = threadIdx.x; j < NB; j += 64)
-        tb[(size_t)i * NB + j] = bnd[row * NB + j];
-    if (threadIdx.x == 0)
-        tk[i] = kc[row];
-}
-
-// one training step taken (after its Adam update)
-__global__ void k_step_advance(uint32_t *steps_taken)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *steps_taken += 1u;
-}
-
 // standalone sampled sequences: Philox key and block id of sequence i
 __global__ void k_seq_setup(SeqDev seq, int n, uint32_t seed_lo, uint32_t seed_hi, uint32_t replica, uint32_t round,
                             uint32_t blk0)
@@ -1070,70 +1270,44 @@ hipError_t cast_weights(const NetDev &net, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
-                   int nblk, int Bs, hipStream_t st)
+hipError_t train_tiles(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                       int nblk, int Bs, bool sampled, uint32_t n_rows, uint64_t seed, bool advance, hipStream_t st)
 {
-    const int Pv = nblk * Bs * Bs, Pp = (Pv + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_layer1, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, net.params, x, bnd, kc,
-                       nblk, Bs, Pp, ws.h[0], ws.hb[0]);
-    for (int l = 2; l <= 4; ++l) {
-        const int li = l - 2;
-        hipLaunchKernelGGL(k_conv<false>, dim3(Pp / 64), dim3(256), 0, st, ws.hb[li], net.wt + (size_t)li * C * KB,
-                           net.params + off_b(l), (const float *)nullptr, Pv, Bs, ws.h[l - 1],
-                           l < 4 ? ws.hb[l - 1] : (uint16_t *)nullptr);
-    }
-    hipLaunchKernelGGL(k_head, dim3(blocks_for(Pv, 256)), dim3(256), 0, st, ws.h[3], net.params, Pv, ws.logits);
-    const int nb = blocks_for(Pp, 256);
-    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, st, ws.logits, x, Pv, Pp, ws.dlogit, ws.partial);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, ws.partial, nb, 1.f / (float)Pv, ws.loss);
-    return hipGetLastError();
-}
-
-hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
-                    int nblk, int Bs, hipStream_t st)
-{
-    const int Pv = nblk * Bs * Bs, Pp = (Pv + 63) / 64 * 64;
-    const int rows_per_blk = 256;
-    const int nbr = blocks_for(Pp, rows_per_blk);
+    const int Pv = nblk * Bs * Bs, n_tiles = (Pv + TILE - 1) / TILE;
     const int splits = (Pv + WGRAD_CHUNK - 1) / WGRAD_CHUNK;
-    // head: dwo = sum_p h4[p] dlogit[p]; dbo = sum_p dlogit[p]
-    hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.h[3], ws.dlogit, Pp, rows_per_blk, ws.partial);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + OFF_WO);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, ws.dlogit, Pp, 1.f, net.grad + OFF_BO);
-    hipLaunchKernelGGL(k_dpre_head, dim3(blocks_for((long)Pp * C, 256)), dim3(256), 0, st, ws.h[3], ws.dlogit,
-                       net.params, Pp, ws.dpre[0], ws.dpreb[0]);
-    for (int l = 4; l >= 2; --l) {
-        const int li = l - 2, cur = l & 1, nxt = cur ^ 1;  // layer 4 reads buffer 0
-        hipLaunchKernelGGL(k_colsum, dim3(nbr), dim3(256), 0, st, ws.dpre[cur], (const float *)nullptr, Pp,
-                           rows_per_blk, ws.partial);
-        hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(C), 0, st, ws.partial, nbr, C, net.grad + off_b(l));
-        // weight gradient against this layer's input (BF16 activations of layer l - 1)
-        hipLaunchKernelGGL(k_wgrad, dim3(5, splits), dim3(256), 0, st, ws.dpreb[cur], ws.hb[li], Pv, Bs, ws.wpart);
-        hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks_for((long)C * KB, 256)), dim3(256), 0, st, ws.wpart, splits, l,
-                           net.grad);
-        // gradient of layer l - 1's pre-activation
-        hipLaunchKernelGGL(k_conv<true>, dim3(Pp / 64), dim3(256), 0, st, ws.dpreb[cur],
-                           net.wtd + (size_t)li * C * KB, (const float *)nullptr, ws.h[l - 2], Pv, Bs, ws.dpre[nxt],
-                           ws.dpreb[nxt]);
+    const BatchSrc srcb{x, bnd, kc, sampled ? (const uint32_t *)net.step : nullptr, n_rows, (uint32_t)seed,
+                        (uint32_t)(seed >> 32)};
+    uint32_t *adv = advance ? net.step : (uint32_t *)nullptr;
+    const dim3 tg(n_tiles), wg(5, splits, 3), blk(256);
+    switch (Bs) {
+    case 2:
+        hipLaunchKernelGGL(k_train_tile<2>, tg, blk, 0, st, net, ws, srcb, nblk);
+        hipLaunchKernelGGL(k_wgrad<2>, wg, blk, 0, st, ws, Pv, splits, adv);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_train_tile<4>, tg, blk, 0, st, net, ws, srcb, nblk);
+        hipLaunchKernelGGL(k_wgrad<4>, wg, blk, 0, st, ws, Pv, splits, adv);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_train_tile<8>, tg, blk, 0, st, net, ws, srcb, nblk);
+        hipLaunchKernelGGL(k_wgrad<8>, wg, blk, 0, st, ws, Pv, splits, adv);
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
-    // layer 2 wrote dpre1 into buffer 1
-    hipLaunchKernelGGL(k_layer1_grad, dim3(nbr), dim3(256), 0, st, ws.dpre[1], x, bnd, kc, nblk, Bs, rows_per_blk,
-                       ws.partial);
-    // rows: W1 taps (4), U1 (4), v1, b1 -> contiguous in the flat vector starting at OFF_W1
-    hipLaunchKernelGGL(k_reduce_cols, dim3(blocks_for(10 * C, 256)), dim3(256), 0, st, ws.partial, nbr, 10 * C,
-                       net.grad + OFF_W1);
     return hipGetLastError();
 }
 
-hipError_t adam(const NetDev &net, float lr, hipStream_t st)
+hipError_t finish_step(const NetDev &net, const TrainWs &ws, int nblk, int Bs, bool adam, float lr,
+                       float *loss_out, hipStream_t st)
 {
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    hipLaunchKernelGGL(k_adam, dim3(blocks_for(N_PARAMS, 256)), dim3(256), 0, st, net.params, net.grad, net.adam_m,
-                       net.adam_v, N_PARAMS, lr, b1, b2, eps, (const uint32_t *)net.step);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, net.step);
+    const int Pv = nblk * Bs * Bs, n_tiles = (Pv + TILE - 1) / TILE;
+    const int splits = (Pv + WGRAD_CHUNK - 1) / WGRAD_CHUNK;
+    const dim3 grid(FIN_W_BLOCKS + FIN_S_BLOCKS);
+    if (adam)
+        hipLaunchKernelGGL(k_finish<true>, grid, dim3(256), 0, st, net, ws, n_tiles, splits, Pv, lr, loss_out);
+    else
+        hipLaunchKernelGGL(k_finish<false>, grid, dim3(256), 0, st, net, ws, n_tiles, splits, Pv, lr, loss_out);
     return hipGetLastError();
 }
 
@@ -1187,15 +1361,6 @@ hipError_t seq_setup(const SeqDev &seq, int n, uint64_t seed, uint32_t replica, 
 {
     hipLaunchKernelGGL(k_seq_setup, dim3(blocks_for(n, 256)), dim3(256), 0, st, seq, n,
                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), replica, round, blk0);
-    return hipGetLastError();
-}
-
-hipError_t gather_rows(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
-                       uint32_t n_rows, int batch, int Bs, uint64_t seed, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_gather_rows, dim3(batch), dim3(64), 0, st, x, bnd, kc, n_rows, Bs * Bs, 4 * Bs,
-                       (const uint32_t *)net.step,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), ws.tx, ws.tbnd, ws.tcoup);
     return hipGetLastError();
 }
 

@@ -55,21 +55,26 @@ struct SeqDev {
     double *logq;     // [n]
 };
 
-// Positions per split of the weight-gradient product (its K).
+// Positions per split of the weight-gradient product (its K; a multiple of 64).
 constexpr int WGRAD_CHUNK = 512;
 
-// Training workspace (positions padded to a multiple of 64).
+// Positions per training tile: whole blocks of every supported size (2, 4, 8).
+constexpr int TILE = 64;
+
+// A tile's row of partial sums (PART_ROW floats): the layer-1 gradients (W1,
+// U1, v1, b1: 10 C, in parameter order), the bias gradients of layers 2, 3, 4
+// and the head weights (C each), the head bias, the loss.
+constexpr int PART_L1 = 0, PART_B2 = 10 * C, PART_B3 = 11 * C, PART_B4 = 12 * C, PART_WO = 13 * C;
+constexpr int PART_BO = 14 * C, PART_LOSS = 14 * C + 1, PART_USED = 14 * C + 2, PART_ROW = 15 * C;
+
+// Training workspace (positions padded to a multiple of TILE).
 struct TrainWs {
-    float *h[4];        // [P][C] fp32 activations
-    uint16_t *hb[3];    // [P][C] bf16 activations of layers 1..3 (inputs of layers 2..4)
-    float *dpre[2];     // [P][C] pre-activation gradients (ping-pong between layers)
-    uint16_t *dpreb[2]; // [P][C] their bf16 copies
-    float *logits, *dlogit;  // [P]
-    float *partial;     // reduction partials
-    float *wpart;       // [splits][C][KB] weight-gradient partials
-    float *loss;        // [1] scratch
-    int8_t *tx, *tbnd;  // [max_batch][Bs*Bs], [max_batch][4 Bs]: minibatch drawn on the device
-    float *tcoup;       // [max_batch]
+    uint16_t *hb[3];    // [P][C] bf16 inputs of layers 2..4 (activations of layers 1..3)
+    uint16_t *db[3];    // [P][C] bf16 pre-activation gradients of layers 2..4
+    float *logits;      // [P]
+    float *partial;     // [tiles][PART_ROW]
+    float *wpart;       // [3][splits][KB][C] weight-gradient partials
+    float *loss;        // [1]
 };
 
 }  // namespace nn

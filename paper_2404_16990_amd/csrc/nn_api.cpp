@@ -32,8 +32,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct NNLayout {
     size_t params, adam_m, adam_v, grad, wt, wtd, step;
-    size_t h[4], hb[3], dpre[2], dpreb[2], logits, dlogit, partial, wpart, loss;
-    size_t tx, tbnd, tcoup;
+    size_t hb[3], db[3], logits, partial, wpart, loss;
     size_t sx, sbnd, scoup, skey, sblk, slogq;
     size_t total;
     int Pp;
@@ -61,7 +60,7 @@ NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
         off += align256(bytes);
         return o;
     };
-    const int Pp = (max_batch * block * block + 63) / 64 * 64;
+    const int Pp = (max_batch * block * block + TILE - 1) / TILE * TILE;
     L.Pp = Pp;
     L.params = take(N_PARAMS * 4);
     L.adam_m = take(N_PARAMS * 4);
@@ -70,22 +69,14 @@ NNLayout make_nn_layout(int32_t block, int32_t max_batch, int32_t max_seq)
     L.wt = take((size_t)3 * C * KB * 2);
     L.wtd = take((size_t)3 * C * KB * 2);
     L.step = take(4);
-    for (int l = 0; l < 4; ++l)
-        L.h[l] = take((size_t)Pp * C * 4);
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < 3; ++l) {
         L.hb[l] = take((size_t)Pp * C * 2);
-    for (int b = 0; b < 2; ++b) {
-        L.dpre[b] = take((size_t)Pp * C * 4);
-        L.dpreb[b] = take((size_t)Pp * C * 2);
+        L.db[l] = take((size_t)Pp * C * 2);
     }
     L.logits = take((size_t)Pp * 4);
-    L.dlogit = take((size_t)Pp * 4);
-    L.partial = take((size_t)(Pp / 256 + 2) * 10 * C * 4);
-    L.wpart = take((size_t)((Pp + WGRAD_CHUNK - 1) / WGRAD_CHUNK) * C * KB * 4);
+    L.partial = take((size_t)(Pp / TILE) * PART_ROW * 4);
+    L.wpart = take((size_t)3 * ((Pp + WGRAD_CHUNK - 1) / WGRAD_CHUNK) * KB * C * 4);
     L.loss = take(4);
-    L.tx = take((size_t)max_batch * block * block);
-    L.tbnd = take((size_t)max_batch * 4 * block);
-    L.tcoup = take((size_t)max_batch * 4);
     L.sx = take((size_t)max_seq * block * block);
     L.sbnd = take((size_t)max_seq * 4 * block);
     L.scoup = take((size_t)max_seq * 4);
@@ -108,10 +99,12 @@ struct TrainKey {
     uint32_t lr_bits;
     uint64_t seed;
     float *loss;
+    int32_t steps;  // training steps in one graph
     bool operator<(const TrainKey &o) const
     {
-        return std::tie(sampled, blocks, bnd, coupling, n_rows, batch, lr_bits, seed, loss) <
-               std::tie(o.sampled, o.blocks, o.bnd, o.coupling, o.n_rows, o.batch, o.lr_bits, o.seed, o.loss);
+        return std::tie(sampled, blocks, bnd, coupling, n_rows, batch, lr_bits, seed, loss, steps) <
+               std::tie(o.sampled, o.blocks, o.bnd, o.coupling, o.n_rows, o.batch, o.lr_bits, o.seed, o.loss,
+                        o.steps);
     }
 };
 
@@ -169,29 +162,25 @@ void drop_graphs(ising_nn *m)
     m->graphs.clear();
 }
 
-// One training step (minibatch gather if sampled, forward, backward, Adam,
-// counter advance, BF16 weight copies, loss copy) enqueued on st.
+// k.steps training steps enqueued on st, each the fused forward and backward
+// of every tile (drawing its minibatch rows if sampled), the weight-gradient
+// products (which count the step on the device), and the gradient reduction
+// with the Adam update, the BF16 weight copies and the loss.
 int enqueue_train(ising_nn *m, const TrainKey &k, float lr, hipStream_t st)
 {
     const int8_t *x = static_cast<const int8_t *>(k.blocks), *bnd = static_cast<const int8_t *>(k.bnd);
     const float *kc = static_cast<const float *>(k.coupling);
-    if (k.sampled) {
-        NN_HIP(gather_rows(m->net, m->ws, x, bnd, kc, (uint32_t)k.n_rows, k.batch, m->Bs, k.seed, st));
-        x = m->ws.tx;
-        bnd = m->ws.tbnd;
-        kc = m->ws.tcoup;
+    for (int32_t i = 0; i < k.steps; ++i) {
+        NN_HIP(train_tiles(m->net, m->ws, x, bnd, kc, k.batch, m->Bs, k.sampled, (uint32_t)k.n_rows, k.seed, true,
+                           st));
+        NN_HIP(finish_step(m->net, m->ws, k.batch, m->Bs, true, lr, k.loss, st));
     }
-    NN_HIP(forward(m->net, m->ws, x, bnd, kc, k.batch, m->Bs, st));
-    NN_HIP(backward(m->net, m->ws, x, bnd, kc, k.batch, m->Bs, st));
-    NN_HIP(adam(m->net, lr, st));
-    NN_HIP(cast_weights(m->net, st));
-    if (k.loss)
-        NN_HIP(hipMemcpyAsync(k.loss, m->ws.loss, 4, hipMemcpyDeviceToDevice, st));
     return ISING_OK;
 }
 
-// Replay the captured step for these arguments (capturing it on first use).
-int train(ising_nn *m, const TrainKey &k, float lr, hipStream_t st)
+// Replay the captured steps for these arguments `replays` times (capturing
+// them on first use).
+int train(ising_nn *m, const TrainKey &k, float lr, hipStream_t st, int64_t replays = 1)
 {
     auto it = m->graphs.find(k);
     hipGraphExec_t ex = nullptr;
@@ -218,7 +207,8 @@ int train(ising_nn *m, const TrainKey &k, float lr, hipStream_t st)
         m->graphs[k] = ex;
         m->captures += 1;
     }
-    NN_HIP(hipGraphLaunch(ex, st));
+    for (int64_t i = 0; i < replays; ++i)
+        NN_HIP(hipGraphLaunch(ex, st));
     NN_HIP(hipEventRecord(m->ev_replay, st));
     m->replay_pending = true;
     return ISING_OK;
@@ -297,22 +287,14 @@ int ising_nn_create(int32_t block, int32_t channels, int32_t max_batch, int32_t 
     m->net.wt = reinterpret_cast<uint16_t *>(B + L.wt);
     m->net.wtd = reinterpret_cast<uint16_t *>(B + L.wtd);
     m->net.step = reinterpret_cast<uint32_t *>(B + L.step);
-    for (int l = 0; l < 4; ++l)
-        m->ws.h[l] = reinterpret_cast<float *>(B + L.h[l]);
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < 3; ++l) {
         m->ws.hb[l] = reinterpret_cast<uint16_t *>(B + L.hb[l]);
-    for (int b = 0; b < 2; ++b) {
-        m->ws.dpre[b] = reinterpret_cast<float *>(B + L.dpre[b]);
-        m->ws.dpreb[b] = reinterpret_cast<uint16_t *>(B + L.dpreb[b]);
+        m->ws.db[l] = reinterpret_cast<uint16_t *>(B + L.db[l]);
     }
     m->ws.logits = reinterpret_cast<float *>(B + L.logits);
-    m->ws.dlogit = reinterpret_cast<float *>(B + L.dlogit);
     m->ws.partial = reinterpret_cast<float *>(B + L.partial);
     m->ws.wpart = reinterpret_cast<float *>(B + L.wpart);
     m->ws.loss = reinterpret_cast<float *>(B + L.loss);
-    m->ws.tx = reinterpret_cast<int8_t *>(B + L.tx);
-    m->ws.tbnd = reinterpret_cast<int8_t *>(B + L.tbnd);
-    m->ws.tcoup = reinterpret_cast<float *>(B + L.tcoup);
     m->seq.x = reinterpret_cast<int8_t *>(B + L.sx);
     m->seq.bnd = reinterpret_cast<int8_t *>(B + L.sbnd);
     m->seq.coupling = reinterpret_cast<float *>(B + L.scoup);
@@ -387,8 +369,8 @@ int ising_nn_forward_backward(ising_nn *m, const int8_t *dev_blocks, const int8_
     if (!dev_blocks || !dev_bnd || !dev_coupling)
         return fail(ISING_E_INVALID, "block arrays must not be NULL");
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    NN_HIP(forward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
-    NN_HIP(backward(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, hs));
+    NN_HIP(train_tiles(m->net, m->ws, dev_blocks, dev_bnd, dev_coupling, batch, m->Bs, false, 0u, 0u, false, hs));
+    NN_HIP(finish_step(m->net, m->ws, batch, m->Bs, false, 0.f, nullptr, hs));
     const size_t P = (size_t)batch * m->Bs * m->Bs;
     if (dev_logits)
         NN_HIP(hipMemcpyAsync(dev_logits, m->ws.logits, P * 4, hipMemcpyDeviceToDevice, hs));
@@ -414,13 +396,21 @@ int ising_nn_train_step(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev
         return fail(ISING_E_INVALID, "lr must be > 0");
     uint32_t lr_bits;
     std::memcpy(&lr_bits, &lr, 4);
-    const TrainKey k{false, dev_blocks, dev_bnd, dev_coupling, 0, batch, lr_bits, 0, dev_loss};
+    const TrainKey k{false, dev_blocks, dev_bnd, dev_coupling, 0, batch, lr_bits, 0, dev_loss, 1};
     return train(m, k, lr, reinterpret_cast<hipStream_t>(stream));
 }
 
 int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
                                 const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
                                 float *dev_loss, void *stream)
+{
+    return ising_nn_train_steps_sampled(m, dev_blocks, dev_bnd, dev_coupling, n_rows, batch, lr, seed, 1, dev_loss,
+                                        stream);
+}
+
+int ising_nn_train_steps_sampled(ising_nn *m, const int8_t *dev_blocks, const int8_t *dev_bnd,
+                                 const float *dev_coupling, int64_t n_rows, int32_t batch, float lr, uint64_t seed,
+                                 int64_t n_steps, float *dev_loss, void *stream)
 {
     clear_error();
     int st = check_nn(m);
@@ -436,8 +426,24 @@ int ising_nn_train_step_sampled(ising_nn *m, const int8_t *dev_blocks, const int
         return fail(ISING_E_INVALID, "lr must be > 0");
     uint32_t lr_bits;
     std::memcpy(&lr_bits, &lr, 4);
-    const TrainKey k{true, dev_blocks, dev_bnd, dev_coupling, n_rows, batch, lr_bits, seed, dev_loss};
-    return train(m, k, lr, reinterpret_cast<hipStream_t>(stream));
+    if (n_steps < 1)
+        return fail(ISING_E_INVALID, "n_steps must be >= 1");
+    // graphs of up to 16 steps: back-to-back steps without a launch between them
+    constexpr int32_t G = 16;
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const int64_t full = n_steps / G;
+    const int32_t rest = (int32_t)(n_steps % G);
+    if (full > 0) {
+        const TrainKey k{true, dev_blocks, dev_bnd, dev_coupling, n_rows, batch, lr_bits, seed, dev_loss, G};
+        st = train(m, k, lr, hs, full);
+        if (st != ISING_OK)
+            return st;
+    }
+    if (rest > 0) {
+        const TrainKey k{true, dev_blocks, dev_bnd, dev_coupling, n_rows, batch, lr_bits, seed, dev_loss, rest};
+        return train(m, k, lr, hs);
+    }
+    return ISING_OK;
 }
 
 int ising_nn_score(ising_nn *m, int32_t n, const int8_t *dev_blocks, const int8_t *dev_bnd,

@@ -11,15 +11,16 @@ namespace ising {
 namespace nn {
 
 hipError_t cast_weights(const NetDev &net, hipStream_t st);
-hipError_t forward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
-                   int nblk, int Bs, hipStream_t st);
-hipError_t backward(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
-                    int nblk, int Bs, hipStream_t st);
-// Adam update with the step number from the device counter, then the counter advanced.
-hipError_t adam(const NetDev &net, float lr, hipStream_t st);
-// minibatch rows of the training step numbered by the device counter
-hipError_t gather_rows(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
-                       uint32_t n_rows, int batch, int Bs, uint64_t seed, hipStream_t st);
+// Forward and backward of a batch of nblk blocks: rows 0..nblk-1 of (x, bnd,
+// kc), or with sampled a minibatch of nblk rows drawn from the n_rows rows
+// with the step counter and seed; writes the logits, the tile partial sums and
+// the weight-gradient partials; advance: count one training step on the device.
+hipError_t train_tiles(const NetDev &net, const TrainWs &ws, const int8_t *x, const int8_t *bnd, const float *kc,
+                       int nblk, int Bs, bool sampled, uint32_t n_rows, uint64_t seed, bool advance, hipStream_t st);
+// Gradient and loss from the partials (loss also to loss_out if not null);
+// adam: the Adam update with the step number of the device counter.
+hipError_t finish_step(const NetDev &net, const TrainWs &ws, int nblk, int Bs, bool adam, float lr,
+                       float *loss_out, hipStream_t st);
 // sequences [0, n_score) are scored, [n_score, n_score + n_sample) sampled
 hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, int Bs, hipStream_t st);
 hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,

@@ -35,10 +35,12 @@ def train(net: Net, X, BN, K, steps: int, batch_size: int, lr: float, seed: int 
     import torch
     loss = torch.zeros(1, dtype=torch.float32, device=X.device)
     out = []
-    for s in range(steps):
-        net.train_step_sampled(X, BN, K, batch_size, lr, seed, loss)
-        if s % log_every == 0 or s == steps - 1:
-            out.append((s, float(loss.cpu())))
+    marks = sorted(set(list(range(0, steps, log_every)) + [steps - 1]))
+    done = 0
+    for s in marks:  # steps done .. s in one call, then the loss of step s
+        net.train_steps_sampled(X, BN, K, batch_size, lr, seed, s + 1 - done, loss)
+        done = s + 1
+        out.append((s, float(loss.cpu())))
     return out
 
 

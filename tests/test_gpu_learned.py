@@ -81,7 +81,8 @@ def test_forward_matches_reference_at_bf16_points(Bs):
     assert abs(float(loss.cpu()) - nn_ref.nll(exact_ref, x.reshape(-1, Bs, Bs))) < 5e-3
 
 
-def test_gradient_matches_float64_backward_at_bf16_points():
+@pytest.mark.parametrize("Bs,n", [(8, 48), (4, 23), (2, 47)])
+def test_gradient_matches_float64_backward_at_bf16_points(Bs, n):
     """Gradient element by element against the float64 backward evaluated at the
     kernels' bfloat16 rounding points (weights and inputs of the layer-2..4
     products, and the pre-activation gradients entering the backward
@@ -89,13 +90,13 @@ def test_gradient_matches_float64_backward_at_bf16_points():
     and max |error| <= 1e-2 of the largest gradient, in every parameter group;
     per element, |error| <= 2e-2 |g| + 1e-3 of the group's largest entry (one
     bfloat16 rounding flip, 2^-8 relative, moves a product's contribution by
-    less than that)."""
+    less than that).  A 64-position tile holds 1, 4 or 16 blocks; 23 and 47
+    blocks leave the last tile partly empty."""
     import torch
     P = _P()
-    rng = np.random.default_rng(3)
-    Bs = 8
+    rng = np.random.default_rng(3 + Bs)
     theta = _params(1.2)
-    x, bnd, kc = _rand_blocks(rng, 48, Bs)
+    x, bnd, kc = _rand_blocks(rng, n, Bs)
     net = P.Net(theta, block=Bs, max_batch=64, max_seq=64)
     _, grad, _ = net.forward_backward(_dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32))
     torch.cuda.synchronize()
@@ -466,3 +467,29 @@ def test_training_steps_replay_one_captured_graph():
     torch.cuda.synchronize()
     assert np.array_equal(net.params, a)
     assert net.graph_stats() == (1, 1)
+
+
+def test_multi_step_training_equals_single_steps():
+    """train_steps_sampled(n) is n single sampled steps: 37 steps in one call
+    (two replays of a captured 16-step graph, then a 5-step graph) leave the
+    parameters and the last loss bit for bit where 37 single calls leave
+    them."""
+    import torch
+    P = _P()
+    rng = np.random.default_rng(13)
+    Bs, batch = 8, 96
+    x, bnd, kc = _rand_blocks(rng, 700, Bs)
+    X, BN, K = _dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32)
+    theta0 = _params(1.0)
+    a = P.Net(theta0, block=Bs, max_batch=batch, max_seq=64)
+    b = P.Net(theta0, block=Bs, max_batch=batch, max_seq=64)
+    la = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lb = torch.zeros(1, dtype=torch.float32, device="cuda")
+    a.train_steps_sampled(X, BN, K, batch, 2e-3, 5, 37, la)
+    for _ in range(37):
+        b.train_step_sampled(X, BN, K, batch, 2e-3, 5, lb)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.params, b.params)
+    assert float(la.cpu()) == float(lb.cpu())
+    assert a.graph_stats() == (2, 2)
+    assert not np.array_equal(a.params, theta0)

@@ -327,9 +327,10 @@ def cluster_leg(work, stream, steps, warmup=2):
 
 def critical_decorrelation(sw_steps, wolff_steps, plain_sweeps):
     """tau_int(|m|) and effective independent samples per second at T_c for
-    Swendsen-Wang steps, Wolff steps and checkerboard Metropolis sweeps, on 64
-    replicas of 256^2 at T = linspace(2.20, 2.35, 64) (replica 29 is at T_c),
-    equilibrated first by 2000 SW steps."""
+    Swendsen-Wang steps, Wolff steps and checkerboard Metropolis sweeps, on the
+    64 replicas of 256^2 of the block-proposal workload (8 independent replicas
+    at each of 8 temperatures; tau averaged over the 8 at T_c), equilibrated
+    first by 2000 SW steps."""
     import numpy as np
     import torch
 
@@ -341,16 +342,18 @@ def critical_decorrelation(sw_steps, wolff_steps, plain_sweeps):
     descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
              for r in w.replicas]
     b = P.Batch(descs)
-    t_c = min(range(len(w.replicas)), key=lambda r: abs(w.replicas[r].T - workloads.T_CRITICAL_PRINTED))
+    tc_group = [r for r in range(len(w.replicas)) if w.replicas[r].T == workloads.T_CRITICAL_PRINTED]
     b.cluster(2000, "sw")
     n = float(256 * 256)
-    res = {"workload": w.name, "replica_at_tc": t_c, "T": w.replicas[t_c].T}
+    res = {"workload": w.name, "replicas_at_tc": tc_group, "T": workloads.T_CRITICAL_PRINTED}
 
     def summary(trace, seconds, units, unit_name):
-        tau, win = analysis.tau_int(trace[t_c])
+        taus = np.array([analysis.tau_int(trace[r])[0] for r in tc_group])
+        tau = float(taus.mean())
         rate = analysis.effective_rate(units / seconds, tau)
-        return {f"tau_int_{unit_name}": tau, "window": win, unit_name: units, "seconds": seconds,
-                "effective_samples_per_s": rate, "mean_abs_m": float(trace[t_c].mean())}
+        return {f"tau_int_{unit_name}": tau, f"tau_int_{unit_name}_error": float(taus.std(ddof=1) / np.sqrt(len(taus))),
+                unit_name: units, "seconds": seconds, "effective_samples_per_s": rate,
+                "mean_abs_m": float(trace[tc_group].mean())}
 
     for algo, steps in (("sw", sw_steps), ("wolff", wolff_steps)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -569,10 +572,13 @@ def learned_comparison(units, plain_sweeps, train_steps=2000):
     """Effective independent |m| samples per second at T_c: plain checkerboard
     sweeps against learned 8x8 block proposals (1 block round : 1 sweep).
 
-    64 replicas of 256^2 at T = linspace(2.20, 2.35, 64); replica 29
-    (T = 2.26905) is the one at T_c.  10^5 sweeps of burn-in, 98 x 16 x 64 =
-    100,352 training blocks taken 100 sweeps apart, 2000 Adam steps of 512
-    blocks; then a plain run and a learned run from the equilibrated state.
+    64 replicas of 256^2: 8 independent replicas at each of 8 temperatures in
+    [2.20, 2.35], one of them T_c; tau_int at T_c is the mean over its 8
+    replicas.  10^5 sweeps of burn-in, 98 x 16 x 64 = 100,352 training blocks
+    taken 100 sweeps apart, 2000 Adam steps of 512 blocks; then a plain run
+    and a learned run from the equilibrated state.  The two samplers'
+    observables are compared per temperature with errors from the spread
+    between the independent replicas.
     """
     import numpy as np
     import torch
@@ -585,7 +591,8 @@ def learned_comparison(units, plain_sweeps, train_steps=2000):
     descs = [dict(Lx=r.Lx, Ly=r.Ly, J=r.J, beta=r.beta, seed=r.seed, replica=r.replica, init=r.init)
              for r in w.replicas]
     b = P.Batch(descs)
-    t_c = min(range(len(w.replicas)), key=lambda r: abs(w.replicas[r].T - workloads.T_CRITICAL_PRINTED))
+    groups = [[r for r in range(len(w.replicas)) if w.replicas[r].T == T] for T in workloads.LEARNED_TEMPS]
+    tc_group = groups[workloads.LEARNED_TEMPS.index(workloads.T_CRITICAL_PRINTED)]
     b.run(100000)
     X, BN, K = learned.collect_blocks(b, 8, 16, 98, 100)
     net = P.Net(workloads.nn_initial_params(64), block=8, max_batch=512, max_seq=65536)
@@ -596,25 +603,26 @@ def learned_comparison(units, plain_sweeps, train_steps=2000):
     tr_p, e_p, s_p = learned.plain_trace(b, plain_sweeps, 10)
     acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda")
     tr_l, e_l, s_l = learned.unit_traces(b, units, learned.learned_units(b, net, 0, acc), progress=5000)
-    plain = learned.summarise(tr_p, s_p, 10, t_c)
+    plain = learned.summarise(tr_p, s_p, 10, tc_group)
     plain["tau_int_sweeps"] = plain["tau_int_points"] * 10
-    lrn = learned.summarise(tr_l, s_l, 1, t_c)
-    z = learned.agreement(tr_p, tr_l)
-    ze = learned.agreement(e_p, e_l)
-    # the same comparison with batch-means errors (10 bins per chain), which
-    # need no autocorrelation estimate
-    zb = learned.agreement(tr_p, tr_l, n_bins=10)
-    zeb = learned.agreement(e_p, e_l, n_bins=10)
+    lrn = learned.summarise(tr_l, s_l, 1, tc_group)
+    # per temperature, errors from the spread between independent replicas
+    z = learned.replica_agreement(tr_p, tr_l, groups)
+    ze = learned.replica_agreement(e_p, e_l, groups)
+    # per replica with Sokal-window errors: a diagnostic, reliable only where
+    # the run is many tau long
+    zs = learned.agreement(tr_p, tr_l)
+    zes = learned.agreement(e_p, e_l)
     # matrix-core work: per sequence and site, 3 layers x 10 K-steps x 4 channel
     # slices of a 16x16x32 BF16 tile shared by 16 sequences; per unit, a scored
     # and a sampled sequence for every block of the batch
     blocks = len(descs) * (256 // 8) * (256 // 8)
     flop_unit = 2 * blocks * 64 * (3 * 10 * 4 * 16 * 16 * 32 * 2 / 16)
     flop_train_step = 9 * 2.0 * 512 * 64 * 64 * 320
-    temps = [w.replicas[r].T for r in range(len(w.replicas))]
     return {
-        "metric": "effective independent |m| samples/s at T_c (one replica, whole-batch time)",
-        "workload": w.name, "replica_at_tc": t_c, "T": w.replicas[t_c].T,
+        "metric": "effective independent |m| samples/s at T_c (per replica, tau the mean over the 8 replicas "
+                  "at T_c, whole-batch time)",
+        "workload": w.name, "replicas_at_tc": tc_group, "T": workloads.T_CRITICAL_PRINTED,
         "training": {"blocks": int(X.shape[0]), "steps": train_steps, "batch": 512, "lr": 2e-3,
                      "loss": hist, "seconds": t_train},
         "plain": plain, "learned": lrn,
@@ -625,11 +633,13 @@ def learned_comparison(units, plain_sweeps, train_steps=2000):
                      "per_unit": f"{flop_unit / 1e9:.1f} GFLOP of BF16 MFMA per unit"},
         "training_tflops": flop_train_step * train_steps / t_train / 1e12,
         "learned_over_plain": lrn["effective_samples_per_s"] / plain["effective_samples_per_s"],
+        "agreement_errors": "per temperature, spread of the 8 independent replicas' run means (Student t, "
+                            "about 14 degrees of freedom: 93.5 % of |z| < 2 expected)",
+        "temperatures": list(workloads.LEARNED_TEMPS),
         "energy_agreement": dict(learned.agreement_summary(ze), z=[round(float(v), 3) for v in ze],
-                                 batch_means=learned.agreement_summary(zeb)),
-        "temperatures": [round(t, 6) for t in temps],
-        "abs_m_z": [round(float(v), 3) for v in z],
-        "abs_m_agreement": dict(learned.agreement_summary(z), batch_means=learned.agreement_summary(zb)),
+                                 per_replica_sokal=learned.agreement_summary(zes)),
+        "abs_m_agreement": dict(learned.agreement_summary(z), z=[round(float(v), 3) for v in z],
+                                per_replica_sokal=learned.agreement_summary(zs)),
         "run_over_tau": {"plain": plain["run_over_tau"], "learned": lrn["run_over_tau"]},
     }
 

@@ -705,21 +705,20 @@ __global__ __launch_bounds__(256) void k_finish(NetDev net, TrainWs ws, int n_ti
 constexpr int SEQ_PER_WG = 16;
 constexpr int RING_ROW = C + 8;  // padded row (bf16 elements) against LDS bank conflicts
 
-struct ArWeights {
-    bf16x8 w[3][10];  // layers 2..4: this lane's B-operand slices (output channel cw)
+// the FP32 parameters a lane of the incremental passes uses (output channel cw)
+struct ArScalars {
     float bias[3], wo_c, bo;
-    float l1w[3];     // layer 1: this lane's B operands (channel cw, input k = lane >> 4 of each group)
+    float l1w[3];  // layer 1: this lane's B operands (channel cw, input k = lane >> 4 of each group)
 };
 
-__device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int lane, ArWeights &p)
+struct ArWeights : ArScalars {
+    bf16x8 w[3][10];  // layers 2..4: this lane's B-operand slices (output channel cw)
+};
+
+__device__ __forceinline__ void load_ar_scalars(const NetDev &net, int wave, int lane, ArScalars &p)
 {
     const float *P = net.params;
     const int cw = 16 * wave + (lane & 15);
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int q = 0; q < 10; ++q)
-            p.w[l][q] = load_bf16x8(net.wt + ((size_t)l * C + cw) * KB + q * 32 + 8 * (lane >> 4));
 #pragma unroll
     for (int l = 0; l < 3; ++l)
         p.bias[l] = P[off_b(l + 2) + cw];
@@ -731,6 +730,23 @@ __device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int
     p.l1w[2] = k == 0 ? P[OFF_V1 + cw] : (k == 1 ? P[OFF_B1 + cw] : 0.f);
 }
 
+// this lane's B-operand slices of layer l + 2 (output channel cw)
+__device__ __forceinline__ void load_ar_layer(const NetDev &net, int l, int wave, int lane, bf16x8 (&w)[10])
+{
+    const int cw = 16 * wave + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        w[q] = load_bf16x8(net.wt + ((size_t)l * C + cw) * KB + q * 32 + 8 * (lane >> 4));
+}
+
+__device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int lane, ArWeights &p)
+{
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+        load_ar_layer(net, l, wave, lane, p.w[l]);
+    load_ar_scalars(net, wave, lane, p);
+}
+
 // Layer 1 of a tile of 16 rows on the matrix cores (FP32 operands,
 // v_mfma_f32_16x16x4_f32, three K groups of 4): a row's inputs are its four
 // spin taps (0 outside the block), its four boundary features (the boundary
@@ -738,7 +754,7 @@ __device__ __forceinline__ void load_ar_weights(const NetDev &net, int wave, int
 // K and 1; the B operands are W1, U1 and (v1, b1) of this wave's 16 channels.
 // Lane (row lane & 15, input k = lane >> 4) passes its three inputs; the
 // result holds pre1 of rows 4 (lane >> 4) + r, channel cw.
-__device__ __forceinline__ floatx4 layer1_tile(float in_tap, float in_bnd, float in_k, const ArWeights &p)
+__device__ __forceinline__ floatx4 layer1_tile(float in_tap, float in_bnd, float in_k, const ArScalars &p)
 {
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in_tap, p.l1w[0], acc, 0, 0, 0);
@@ -790,7 +806,7 @@ __device__ __forceinline__ uint32_t site_threshold(float logit)
 // permutations), then lane + 4 and lane + 8 (row shifts), so lane 0 of the
 // row holds ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)) + (the same
 // for lanes 8..15), a fixed order; it writes out[row].
-__device__ __forceinline__ void head_rows(const floatx4 &acc, const ArWeights &p, int lane, float *out)
+__device__ __forceinline__ void head_rows(const floatx4 &acc, const ArScalars &p, int lane, float *out)
 {
     // the product is rounded before the sums in every kernel that inlines
     // this (no contraction into fused multiply-adds)
@@ -922,7 +938,7 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
                 const int t = q >> 1, half = q & 1;
                 const int ii = i + tap_di(t), jj = j + tap_dj(t);
                 bf16x8 a = zero_bf16x8();
-                if (ii >= 0 && jj >= 0 && jj < BS) {
+                if (ii >= 0 && jj >= 0 && jj < BS) {  // the same for the whole workgroup
                     const int pslot = (k + tap_di(t) * BS + tap_dj(t) + RING) % RING;
                     a = load_bf16x8(&ring[l][pslot][lane & 15][half * 32 + 8 * (lane >> 4)]);
                 }
@@ -954,15 +970,17 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
 
 // Scoring has no site-to-site dependency (every spin is given), so a
 // workgroup holds all SCORE_POS positions of its blocks in LDS and runs the
-// network one layer at a time: layer 1 for every position on the VALU, then
-// for layers 2..4 wave w (output channels 16w .. 16w+15, weights in
-// registers) walks the position tiles of 16 rows, four independent MFMA
-// chains at a time.  A row of a tile is one (block, site) pair; its A row is
-// the previous layer at the site's five taps (zero outside the block), its B
+// network one layer at a time: layer 1 for every position, then for layers
+// 2..4 wave w (output channels 16w .. 16w+15) walks the position tiles of 16
+// rows, four independent MFMA chains at a time.  A row of a tile is one
+// (block, site) pair; its A row is the previous layer at the site's five taps
+// (an all-zero LDS row outside the block, so the reads never branch), its B
 // operands and K order are the sampler's, and a matrix-core product row
 // depends only on its own A row, so every site gets the sampler's logit and
-// threshold bit for bit.
-constexpr int SCORE_POS = 256;  // positions per workgroup (a multiple of 64)
+// threshold bit for bit.  A wave holds one layer's weights at a time (the
+// next layer's load during the barrier), which with 128 positions per
+// workgroup leaves room for four workgroups per CU.
+constexpr int SCORE_POS = 128;  // positions per workgroup (a multiple of 64)
 constexpr int SCORE_TILES = 4;  // MFMA chains a wave runs together
 
 template <int BS>
@@ -973,9 +991,10 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     constexpr int P = G * BB;                                      // positions (a multiple of 64)
     constexpr int MT = P / 16;                                     // tiles of 16 positions
     static_assert(P % 64 == 0 && MT % SCORE_TILES == 0, "whole tile groups");
-    // activations of the layer being read and the layer being written (ping-pong);
-    // after layer 4 the first holds the head partials, the thresholds and the log-q parts
-    __shared__ __attribute__((aligned(16))) uint16_t hbuf[2][P][RING_ROW];
+    // activations of the layer being read and the layer being written
+    // (ping-pong; row P of each is zero); after layer 4 the first holds the
+    // head partials, the thresholds and the log-q parts
+    __shared__ __attribute__((aligned(16))) uint16_t hbuf[2][P + 1][RING_ROW];
     __shared__ int8_t xs[G][64];
     __shared__ int8_t bs[G][32];
     __shared__ float ks[G];
@@ -986,6 +1005,8 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int s0 = blockIdx.x * G;
 
+    bf16x8 w[10];
+    load_ar_layer(net, 0, wave, lane, w);  // layer 2's, in flight under the set-up and layer 1
     for (int i = tid; i < G * 64; i += 256) {
         const int s = i >> 6, k = i & 63;
         xs[s][k] = (s0 + s < n_seq && k < BB) ? seq.x[(size_t)(s0 + s) * BB + k] : (int8_t)0;
@@ -996,8 +1017,12 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     }
     if (tid < G)
         ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
-    ArWeights p;
-    load_ar_weights(net, wave, lane, p);
+    if (tid < 18) {  // the two zero rows, 9 x 16 bytes each
+        uint4 *z = reinterpret_cast<uint4 *>(&hbuf[tid / 9][P][0]);
+        z[tid % 9] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    ArScalars p;
+    load_ar_scalars(net, wave, lane, p);
     const int cw = 16 * wave + (lane & 15);
     __syncthreads();
 
@@ -1014,22 +1039,24 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     }
     __syncthreads();
 
-    // layers 2..4: this wave's 16 output channels for every position
+    // layers 2..4: this wave's 16 output channels for every position; a lane's
+    // A row sits at the same place (site k, column j) of every tile whose
+    // block row is the same, so the column taps' validity is fixed per lane
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const uint16_t(*hin)[RING_ROW] = hbuf[l & 1];
         uint16_t(*hout)[RING_ROW] = hbuf[(l + 1) & 1];
         for (int m0 = 0; m0 < MT; m0 += SCORE_TILES) {
             floatx4 acc[SCORE_TILES];
-            int src[SCORE_TILES], si[SCORE_TILES], sj[SCORE_TILES];
+            int si[SCORE_TILES], sj[SCORE_TILES], row[SCORE_TILES];
 #pragma unroll
             for (int u = 0; u < SCORE_TILES; ++u) {
                 acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
-                const int pos = 16 * (m0 + u) + (lane & 15);  // this lane's A row
-                const int s = pos / BB, k = pos - s * BB;
+                row[u] = 16 * (m0 + u) + r16;  // this lane's A row
+                const int k = row[u] % BB;
                 si[u] = k / BS;
                 sj[u] = k - si[u] * BS;
-                src[u] = s * BB;
             }
 #pragma unroll
             for (int q = 0; q < 10; ++q) {
@@ -1037,10 +1064,10 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
 #pragma unroll
                 for (int u = 0; u < SCORE_TILES; ++u) {
                     const int ii = si[u] + tap_di(t), jj = sj[u] + tap_dj(t);
-                    bf16x8 a = zero_bf16x8();
-                    if (ii >= 0 && jj >= 0 && jj < BS)
-                        a = load_bf16x8(&hin[src[u] + ii * BS + jj][half * 32 + 8 * (lane >> 4)]);
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, p.w[l][q], acc[u], 0, 0, 0);
+                    const bool ok = (ii >= 0) & (jj >= 0) & (jj < BS);
+                    const bf16x8 a =
+                        load_bf16x8(&hin[ok ? row[u] + tap_di(t) * BS + tap_dj(t) : P][half * 32 + kq]);
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[q], acc[u], 0, 0, 0);
                 }
             }
 #pragma unroll
@@ -1056,6 +1083,8 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
                 }
             }
         }
+        if (l < 2)
+            load_ar_layer(net, l + 1, wave, lane, w);
         __syncthreads();
     }
 

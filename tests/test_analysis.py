@@ -59,3 +59,29 @@ def test_batch_means_error_of_ar1():
     # uncorrelated samples: the plain standard error
     x = rng.normal(size=n)
     assert abs(analysis.batch_means_error(x, 20)[1] / (1 / np.sqrt(n)) - 1) < 0.45
+
+
+def test_replica_agreement_z_follows_its_reference_distribution():
+    """Two samplers of the same AR(1) process (tau ~ 50 steps, runs only ~10 tau
+    long, where per-chain tau estimates are poor): z from the spread of 8
+    independent replicas per group has the spread of Student's t with ~14
+    degrees of freedom (variance 14/12), and a shifted sampler is caught."""
+    from paper_2404_16990_amd import learned
+    rng = np.random.default_rng(2024)
+    n_groups, per, n = 400, 8, 500
+    phi = 0.96
+
+    def chains(shift):
+        x = np.zeros((n_groups * per, n))
+        e = rng.standard_normal((n_groups * per, n))
+        x[:, 0] = e[:, 0] / np.sqrt(1 - phi * phi)
+        for t in range(1, n):
+            x[:, t] = phi * x[:, t - 1] + e[:, t]
+        return x + shift
+
+    groups = [list(range(g * per, (g + 1) * per)) for g in range(n_groups)]
+    z = learned.replica_agreement(chains(0.0), chains(0.0), groups)
+    assert 0.85 < np.var(z) < 1.5, np.var(z)
+    assert 0.9 < np.mean(np.abs(z) < 2) < 0.97, np.mean(np.abs(z) < 2)
+    z_shift = learned.replica_agreement(chains(0.0), chains(3.0), groups)
+    assert np.mean(np.abs(z_shift) > 2) > 0.9

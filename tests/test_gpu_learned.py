@@ -493,3 +493,89 @@ def test_multi_step_training_equals_single_steps():
     assert float(la.cpu()) == float(lb.cpu())
     assert a.graph_stats() == (2, 2)
     assert not np.array_equal(a.params, theta0)
+
+
+def _host_block_round(net, spins, descs, Bs, round_):
+    """One block round computed on the host from its definition, with the
+    library's standalone passes supplying the proposals and log q: colour 0
+    (bx + by even) then colour 1 on the lattice colour 0 left; per block the
+    current spins and boundary from the host lattice, the proposal from the
+    sampler with the block's id and the round, log q of the current spins
+    from the scorer, dB exactly, log A = K dB + log q(s) - log q(s'), and the
+    53-bit uniform of Philox(counter (block id, round, replica, 4), key seed).
+    Returns the new lattices, accepts per replica and the smallest
+    |u - exp(log A)| met (a decision closer than FP64 rounding is undecided)."""
+    import torch
+    from oracle import philox
+    out = [s.copy() for s in spins]
+    acc = np.zeros(len(descs), dtype=np.int64)
+    closest = 1.0
+    for r, d in enumerate(descs):
+        s = out[r]
+        Ly, Lx = s.shape
+        nbx, nby = Lx // Bs, Ly // Bs
+        K = d["beta"] * d["J"]
+        for colour in (0, 1):
+            for by in range(nby):
+                for bx in range(nbx):
+                    if (bx + by) % 2 != colour:
+                        continue
+                    y0, x0 = by * Bs, bx * Bs
+                    cur = s[y0:y0 + Bs, x0:x0 + Bs].copy()
+                    bnd = np.concatenate([s[(y0 - 1) % Ly, x0:x0 + Bs], s[(y0 + Bs) % Ly, x0:x0 + Bs],
+                                          s[y0:y0 + Bs, (x0 - 1) % Lx], s[y0:y0 + Bs, (x0 + Bs) % Lx]])
+                    blk = by * nbx + bx
+                    kc = np.array([K], dtype=np.float32)
+                    prop, lq_p = net.sample(_dev(bnd[None], torch.int8), _dev(kc, torch.float32), d["seed"],
+                                            d["replica"], round_, blk)
+                    lq_c = net.score(_dev(cur.reshape(1, -1), torch.int8), _dev(bnd[None], torch.int8),
+                                     _dev(kc, torch.float32))
+                    prop = prop.cpu().numpy().reshape(Bs, Bs).astype(np.int64)
+                    lq_p, lq_c = float(lq_p.cpu()[0]), float(lq_c.cpu()[0])
+
+                    def bonds(x):
+                        x = x.astype(np.int64)
+                        inner = (x[:, :-1] * x[:, 1:]).sum() + (x[:-1, :] * x[1:, :]).sum()
+                        edge = (x[0] * bnd[:Bs]).sum() + (x[-1] * bnd[Bs:2 * Bs]).sum() \
+                            + (x[:, 0] * bnd[2 * Bs:3 * Bs]).sum() + (x[:, -1] * bnd[3 * Bs:]).sum()
+                        return int(inner + edge)
+
+                    log_a = K * (bonds(prop) - bonds(cur)) + lq_c - lq_p
+                    o = philox.philox4x32_10((blk, round_, d["replica"], 4), philox.seed_key(d["seed"]))
+                    u = float((int(o[0]) << 21) | (int(o[1]) >> 11)) * 2.0 ** -53
+                    if log_a < 0:
+                        closest = min(closest, abs(u - math.exp(log_a)))
+                    if log_a >= 0 or u < math.exp(log_a):
+                        s[y0:y0 + Bs, x0:x0 + Bs] = prop
+                        acc[r] += 1
+    return out, acc, closest
+
+
+@pytest.mark.parametrize("Bs", [8, 4])
+def test_block_round_follows_its_definition(Bs):
+    """Two block rounds of a batch (replicas at K = 0.02, 0.15 and 0.45, so
+    proposals are both accepted and rejected) against the round computed on the
+    host from its definition: the lattices and per-replica accept counts agree
+    bit for bit."""
+    import torch
+    P = _P()
+    Lx, Ly = 64, 16
+    descs = [dict(Lx=Lx, Ly=Ly, J=1.0, beta=beta, seed=0x5EED0000 + 31 * r, replica=3 + r, init=0)
+             for r, beta in enumerate((0.02, 0.15, 0.45))]
+    b = P.Batch(descs)
+    b.run(30)
+    net = P.Net(_params(1.0), block=Bs, max_batch=16, max_seq=256)
+    acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda")
+    total = np.zeros(len(descs), dtype=np.int64)
+    for round_ in (7, 8):
+        before = [b.get_spins(r).astype(np.int64) for r in range(len(descs))]
+        want, a, closest = _host_block_round(net, before, descs, Bs, round_)
+        assert closest > 1e-12, closest
+        b.block_round(net, round_, acc)
+        torch.cuda.synchronize()
+        total += a
+        for r in range(len(descs)):
+            assert np.array_equal(b.get_spins(r).astype(np.int64), want[r]), (Bs, round_, r)
+        assert np.array_equal(acc.cpu().numpy(), total), (acc.cpu().numpy(), total)
+    n_blocks = 2 * len(descs) * (Lx // Bs) * (Ly // Bs)
+    assert 0 < total.sum() < n_blocks, total

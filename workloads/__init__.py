@@ -94,11 +94,21 @@ def paper_scale() -> Workload:
     return Workload("paper-scale-754x512x528+16384x12288", reps, sweeps=1000, record_every=100)
 
 
+# temperatures of the block-proposal workload: eight in [2.20, 2.35], one of
+# them the printed critical temperature
+LEARNED_TEMPS = (2.20, 2.22, 2.24, T_CRITICAL_PRINTED, 2.29, 2.31, 2.33, 2.35)
+LEARNED_PER_T = 8
+
+
 def learned_64x256() -> Workload:
-    """64 replicas of 256x256 at T = linspace(2.20, 2.35, 64) for the block-proposal path."""
-    Ts = np.linspace(2.20, 2.35, 64)
+    """64 replicas of 256x256 for the block-proposal path: 8 independent
+    replicas (distinct seeds) at each temperature of LEARNED_TEMPS, replica
+    r at LEARNED_TEMPS[r // 8], so an observable can be compared between two
+    samplers with errors from the spread between independent replicas, and
+    tau at T_c averaged over 8 chains."""
+    Ts = [T for T in LEARNED_TEMPS for _ in range(LEARNED_PER_T)]
     reps = [Replica(256, 256, float(T), BASE_SEED + r, r) for r, T in enumerate(Ts)]
-    return Workload("learned-64x256^2-T2.20..2.35", reps, sweeps=1000, record_every=1)
+    return Workload("learned-64x256^2-8T-in-2.20..2.35-x8", reps, sweeps=1000, record_every=1)
 
 
 @dataclass

@@ -685,6 +685,82 @@ __global__ __launch_bounds__(256) void k_finish(NetDev net, TrainWs ws, int n_ti
 }
 
 // ---------------------------------------------------------------------------
+// lattice <-> blocks
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int spin_at(const RepDev &d, uint32_t x, uint32_t y)
+{
+    const uint32_t c = (x + y) & 1u, k = x >> 1;
+    const uint32_t w = d.plane0[c * d.Ly * d.W + y * d.W + (k >> 5)];
+    return ((w >> (k & 31)) & 1u) ? 1 : -1;
+}
+
+// block (bx, by) of a replica -> its spins and boundary
+__device__ void read_block(const RepDev &d, int Bs, uint32_t bx, uint32_t by, int8_t *x, int8_t *bnd)
+{
+    const uint32_t x0 = bx * Bs, y0 = by * Bs;
+    for (int i = 0; i < Bs; ++i)
+        for (int j = 0; j < Bs; ++j)
+            x[i * Bs + j] = (int8_t)spin_at(d, x0 + j, y0 + i);
+    const uint32_t yu = y0 == 0 ? d.Ly - 1 : y0 - 1, yd = (y0 + Bs) % d.Ly;
+    const uint32_t xl = x0 == 0 ? d.Lx - 1 : x0 - 1, xr = (x0 + Bs) % d.Lx;
+    for (int j = 0; j < Bs; ++j) {
+        bnd[j] = (int8_t)spin_at(d, x0 + j, yu);
+        bnd[Bs + j] = (int8_t)spin_at(d, x0 + j, yd);
+    }
+    for (int i = 0; i < Bs; ++i) {
+        bnd[2 * Bs + i] = (int8_t)spin_at(d, xl, y0 + i);
+        bnd[3 * Bs + i] = (int8_t)spin_at(d, xr, y0 + i);
+    }
+}
+
+// colour-`colour` block number idx of a replica -> (bx, by); blocks alternate in colour
+__device__ __forceinline__ void block_coords(uint32_t idx, uint32_t nbx, uint32_t colour, uint32_t *bx, uint32_t *by)
+{
+    const uint32_t half = nbx / 2;
+    *by = idx / half;
+    *bx = 2 * (idx - *by * half) + ((*by + colour) & 1u);
+}
+
+// Boundary spin q of block (bx, by): top row, bottom row, left column, right
+// column, Bs each, periodic.
+__device__ __forceinline__ int8_t boundary_spin(const RepDev &d, int Bs, uint32_t bx, uint32_t by, int q)
+{
+    const uint32_t x0 = bx * Bs, y0 = by * Bs;
+    const int side = q / Bs, m = q - side * Bs;
+    uint32_t x, y;
+    if (side < 2) {
+        x = x0 + m;
+        y = side == 0 ? (y0 == 0 ? d.Ly - 1 : y0 - 1) : (y0 + Bs) % d.Ly;
+    } else {
+        y = y0 + m;
+        x = side == 2 ? (x0 == 0 ? d.Lx - 1 : x0 - 1) : (x0 + Bs) % d.Lx;
+    }
+    return (int8_t)spin_at(d, x, y);
+}
+
+// A block round's sequences: number b (< count) is block first + b of the
+// round's colour, counted replica by replica (per_rep blocks of that colour
+// each).  The scorer reads the current blocks from the packed lattice, the
+// sampler draws the proposals and applies the Metropolis-Hastings decision.
+struct RoundArgs {
+    const RepDev *reps;
+    const double *kcoup;           // K = beta*J per replica (FP64)
+    unsigned long long *accepts;   // accepted blocks per replica
+    uint32_t colour, round, first, count, per_rep;
+};
+
+// replica r, block position (bx, by) and blocks per row nbx of round sequence b
+template <int BS>
+__device__ __forceinline__ void round_block(const RoundArgs &ra, uint32_t b, uint32_t &r, uint32_t &bx, uint32_t &by,
+                                            uint32_t &nbx)
+{
+    const uint32_t g = ra.first + b;
+    r = g / ra.per_rep;
+    nbx = ra.reps[r].Lx / BS;
+    block_coords(g - r * ra.per_rep, nbx, ra.colour, &bx, &by);
+}
+
+// ---------------------------------------------------------------------------
 // Autoregressive passes.  Both evaluate the conditional of every site k of a
 // block given the sites before it and the boundary with one per-site
 // arithmetic: every layer as matrix-core tiles of 16 rows (layer 1 in FP32,
@@ -852,8 +928,21 @@ __device__ __forceinline__ double logq_total(const double *part, int BB)
     return sum - (double)BB * 32.0 * 0.69314718055994530942;
 }
 
-template <int BS>
-__global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int first, int n_seq)
+// ROUND: the sequences are a block round's proposals (sequence first + b for
+// round block b): the scorer of the round has gathered each block's current
+// spins (seq.x[b]) and boundary (seq.bnd[first + b]) from the lattice and
+// written log q of the current block (seq.logq[b]); K and the Philox key come
+// from the replica descriptors, and after the draw the workgroup applies the
+// Metropolis-Hastings decision to its 16 blocks (the scorer has written
+// log q of the current blocks to seq.logq[b]): lanes 16 s .. 16 s + 15 add
+// the change dB of the bonds of four sites each (the site's right and lower
+// neighbours inside the block and its boundary neighbours), log A =
+// K dB + log q(s) - log q(s') in FP64 against the 53-bit uniform of
+// Philox(counter (block id, round, replica, 4)), and an accepted proposal is
+// XORed into the packed planes (same-colour blocks share no bond, so the
+// workgroups of a round do not interact).
+template <int BS, bool ROUND>
+__global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int first, int n_seq, RoundArgs ra)
 {
     constexpr int BB = BS * BS;
     __shared__ __attribute__((aligned(16))) uint16_t ring[3][RING][SEQ_PER_WG][RING_ROW];
@@ -864,34 +953,89 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
     __shared__ uint32_t ut[SEQ_PER_WG][65];  // site uniform; replaced by the site's threshold once drawn
     __shared__ float ks[SEQ_PER_WG];
     __shared__ double lq_part[SEQ_PER_WG][16];
+    // ROUND: each sequence's replica, block position and blocks per row; the
+    // current spins of its block; the proposal's log q
+    __shared__ uint32_t sref[ROUND ? SEQ_PER_WG : 1][4];
+    __shared__ int8_t cs[ROUND ? SEQ_PER_WG : 1][68];
+    // ROUND: the proposal's log q, the current block's, K in FP64 and the MH uniform
+    __shared__ double lqs[ROUND ? SEQ_PER_WG : 1][4];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int s0 = first + blockIdx.x * SEQ_PER_WG, end = first + n_seq;
 
+    ArWeights p;
+    load_ar_weights(net, wave & 3, lane, p);  // in flight during the set-up
     for (int i = tid; i < SEQ_PER_WG * 64; i += 256)
         xs[i >> 6][i & 63] = 0;
-    for (int i = tid; i < SEQ_PER_WG * 32; i += 256) {
-        const int s = i >> 5, k = i & 31;
-        bs[s][k] = (s0 + s < end && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
+    if (ROUND) {
+        if (tid < SEQ_PER_WG) {
+            float kc = 0.f;
+            if (s0 + tid < end) {
+                const uint32_t b = (uint32_t)(s0 + tid - first);
+                uint32_t r, bx, by, nbx;
+                round_block<BS>(ra, b, r, bx, by, nbx);
+                sref[tid][0] = r;
+                sref[tid][1] = bx;
+                sref[tid][2] = by;
+                sref[tid][3] = nbx;
+                const double K = ra.kcoup[r];
+                kc = (float)K;
+                const RepDev &d = ra.reps[r];
+                uint32_t o[4];
+                philox4x32_10(by * nbx + bx, ra.round, d.replica, 4u, d.seed_lo, d.seed_hi, o);
+                lqs[tid][1] = seq.logq[b];  // the scorer's log q of the current block
+                lqs[tid][2] = K;
+                lqs[tid][3] = (double)(((uint64_t)o[0] << 21) | (o[1] >> 11)) * 1.1102230246251565404e-16;  // 2^-53
+            }
+            ks[tid] = kc;
+        }
+        // the current spins and the boundary, gathered from the lattice by the scorer
+        for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
+            const int s = i >> 6, k = i & 63;
+            const bool live = s0 + s < end;
+            if (live && k < BB)
+                cs[s][k] = seq.x[(size_t)(s0 + s - first) * BB + k];
+            if (k < 32)
+                bs[s][k] = (live && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
+        }
+        __syncthreads();  // sref, read by the uniforms below
+    } else {
+        for (int i = tid; i < SEQ_PER_WG * 32; i += 256) {
+            const int s = i >> 5, k = i & 31;
+            bs[s][k] = (s0 + s < end && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
+        }
+        if (tid < SEQ_PER_WG)
+            ks[tid] = s0 + tid < end ? seq.coupling[s0 + tid] : 0.f;
     }
-    if (tid < SEQ_PER_WG)
-        ks[tid] = s0 + tid < end ? seq.coupling[s0 + tid] : 0.f;
     // site uniforms: word site & 3 of Philox(ctr = (site >> 2, round, replica, 3)),
     // site = blk * BB + k; BB is a multiple of 4, so one call serves sites 4m..4m+3
     for (int i = tid; i < SEQ_PER_WG * 16; i += 256) {
         const int s = i >> 4, m = i & 15;
         if (s0 + s < end && 4 * m < BB) {
-            const uint32_t *kk = seq.key + 4 * (size_t)(s0 + s);
-            const uint32_t site0 = seq.blk[s0 + s] * (uint32_t)BB + 4u * m;
+            uint32_t key_lo, key_hi, replica, round, blk;
+            if (ROUND) {
+                const RepDev &d = ra.reps[sref[s][0]];
+                key_lo = d.seed_lo;
+                key_hi = d.seed_hi;
+                replica = d.replica;
+                round = ra.round;
+                blk = sref[s][2] * sref[s][3] + sref[s][1];
+            } else {
+                const uint32_t *kk = seq.key + 4 * (size_t)(s0 + s);
+                key_lo = kk[0];
+                key_hi = kk[1];
+                replica = kk[2];
+                round = kk[3];
+                blk = seq.blk[s0 + s];
+            }
+            const uint32_t site0 = blk * (uint32_t)BB + 4u * m;
             uint32_t o[4];
-            philox4x32_10(site0 >> 2, kk[3], kk[2], 3u, kk[0], kk[1], o);
+            philox4x32_10(site0 >> 2, round, replica, 3u, key_lo, key_hi, o);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 ut[s][4 * m + r] = o[r];
         }
     }
-    ArWeights p;
-    load_ar_weights(net, wave & 3, lane, p);
     const int cw = 16 * wave + (lane & 15);
     __syncthreads();
 
@@ -959,13 +1103,80 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
     __syncthreads();
     logq_parts(xs, ut, BB, tid, lq_part);
     __syncthreads();
-    for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
-        const int s = i >> 6, k = i & 63;
-        if (s0 + s < end && k < BB)
-            seq.x[(size_t)(s0 + s) * BB + k] = xs[s][k];
+    if (!ROUND) {
+        for (int i = tid; i < SEQ_PER_WG * 64; i += 256) {
+            const int s = i >> 6, k = i & 63;
+            if (s0 + s < end && k < BB)
+                seq.x[(size_t)(s0 + s) * BB + k] = xs[s][k];
+        }
+        if (tid < SEQ_PER_WG && s0 + tid < end)
+            seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
+        return;
     }
-    if (tid < SEQ_PER_WG && s0 + tid < end)
-        seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
+    if (tid < SEQ_PER_WG)
+        lqs[tid][0] = logq_total(lq_part[tid], BB);
+    __syncthreads();
+    // Metropolis-Hastings: 16 lanes per block, four sites a lane
+    const int sl = tid >> 4, part = tid & 15;
+    const bool live = s0 + sl < end;  // the same for the 16 lanes of a block
+    int dB = 0;
+    uint32_t changed = 0u;
+    if (live) {
+        const int8_t *bn = bs[sl];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * part + e;
+            if (k < BB) {
+                const int i = k / BS, j = k - i * BS;
+                const int a = cs[sl][k], ap = xs[sl][k];
+                changed |= (uint32_t)(a != ap) << e;
+                if (j + 1 < BS)
+                    dB += ap * xs[sl][k + 1] - a * cs[sl][k + 1];
+                if (i + 1 < BS)
+                    dB += ap * xs[sl][k + BS] - a * cs[sl][k + BS];
+                if (i == 0)
+                    dB += (ap - a) * bn[j];
+                if (i == BS - 1)
+                    dB += (ap - a) * bn[BS + j];
+                if (j == 0)
+                    dB += (ap - a) * bn[2 * BS + i];
+                if (j == BS - 1)
+                    dB += (ap - a) * bn[3 * BS + i];
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1)
+        dB += __shfl_xor(dB, m, 16);
+    if (!live)
+        return;
+    const uint32_t r = sref[sl][0], bx = sref[sl][1], by = sref[sl][2];
+    const RepDev &d = ra.reps[r];
+    // log of pi(s') q(s) / (pi(s) q(s')), pi ~ exp(K B)
+    const double logA = lqs[sl][2] * (double)dB + lqs[sl][1] - lqs[sl][0];
+    if (!(logA >= 0.0 || lqs[sl][3] < exp(logA)))
+        return;
+    if (part == 0)
+        atomicAdd(&ra.accepts[r], 1ull);
+    // a lane's four sites lie in one block row (BS >= 4) or two (BS = 2) and
+    // their bits of one colour in one plane word: one XOR per (row, colour)
+    uint32_t mask[2][2] = {{0u, 0u}, {0u, 0u}};  // [row of the lane's sites][colour]
+    uint32_t word[2][2] = {{0u, 0u}, {0u, 0u}};
+    const int k0 = 4 * part, i0 = k0 / BS;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if ((changed >> e) & 1u) {
+            const int k = k0 + e, i = k / BS, j = k - i * BS;
+            const uint32_t x = bx * BS + j, y = by * BS + i, c = (x + y) & 1u, kk = x >> 1;
+            mask[i - i0][c] |= 1u << (kk & 31);
+            word[i - i0][c] = c * d.Ly * d.W + y * d.W + (kk >> 5);
+        }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (mask[q][c])
+                atomicXor(&d.plane0[word[q][c]], mask[q][c]);
 }
 
 // Scoring has no site-to-site dependency (every spin is given), so a
@@ -983,8 +1194,11 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
 constexpr int SCORE_POS = 128;  // positions per workgroup (a multiple of 64)
 constexpr int SCORE_TILES = 4;  // MFMA chains a wave runs together
 
-template <int BS>
-__global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_seq)
+// ROUND: the sequences are a block round's current blocks, read from the
+// packed lattice with their boundaries and K; the spins go to seq.x[b] and
+// the boundary to seq.bnd[n_seq + b] for the round's sampler.
+template <int BS, bool ROUND>
+__global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_seq, RoundArgs ra)
 {
     constexpr int BB = BS * BS;
     constexpr int G = SCORE_POS / BB < 16 ? SCORE_POS / BB : 16;  // blocks per workgroup
@@ -1007,16 +1221,55 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
 
     bf16x8 w[10];
     load_ar_layer(net, 0, wave, lane, w);  // layer 2's, in flight under the set-up and layer 1
-    for (int i = tid; i < G * 64; i += 256) {
-        const int s = i >> 6, k = i & 63;
-        xs[s][k] = (s0 + s < n_seq && k < BB) ? seq.x[(size_t)(s0 + s) * BB + k] : (int8_t)0;
+    if (ROUND) {
+        __shared__ uint32_t sref[G][3];  // replica, bx, by of each block
+        if (tid < G) {
+            float kc = 0.f;
+            if (s0 + tid < n_seq) {
+                uint32_t r, bx, by, nbx;
+                round_block<BS>(ra, (uint32_t)(s0 + tid), r, bx, by, nbx);
+                sref[tid][0] = r;
+                sref[tid][1] = bx;
+                sref[tid][2] = by;
+                kc = (float)ra.kcoup[r];
+            }
+            ks[tid] = kc;
+        }
+        __syncthreads();
+        for (int i = tid; i < G * 64; i += 256) {
+            const int s = i >> 6, k = i & 63;
+            const bool live = s0 + s < n_seq;
+            int8_t v = 0, bv = 0;
+            if (live) {
+                const RepDev &d = ra.reps[sref[s][0]];
+                const uint32_t bx = sref[s][1], by = sref[s][2];
+                if (k < BB)
+                    v = (int8_t)spin_at(d, bx * BS + k % BS, by * BS + k / BS);
+                if (k < 4 * BS)
+                    bv = boundary_spin(d, BS, bx, by, k);
+            }
+            xs[s][k] = v;
+            if (k < 32)
+                bs[s][k] = bv;
+            // for the sampler of this round: the current spins (its MH) and the
+            // boundary of the proposal, sequence n_seq + b
+            if (live && k < BB)
+                seq.x[(size_t)(s0 + s) * BB + k] = v;
+            if (live && k < 4 * BS)
+                seq.bnd[(size_t)(n_seq + s0 + s) * 4 * BS + k] = bv;
+        }
+    } else {
+        for (int i = tid; i < G * 64; i += 256) {
+            const int s = i >> 6, k = i & 63;
+            xs[s][k] = (s0 + s < n_seq && k < BB) ? seq.x[(size_t)(s0 + s) * BB + k] : (int8_t)0;
+        }
+        for (int i = tid; i < G * 32; i += 256) {
+            const int s = i >> 5, k = i & 31;
+            bs[s][k] = (s0 + s < n_seq && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
+        }
+        if (tid < G)
+            ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
     }
-    for (int i = tid; i < G * 32; i += 256) {
-        const int s = i >> 5, k = i & 31;
-        bs[s][k] = (s0 + s < n_seq && k < 4 * BS) ? seq.bnd[(size_t)(s0 + s) * 4 * BS + k] : (int8_t)0;
-    }
-    if (tid < G)
-        ks[tid] = s0 + tid < n_seq ? seq.coupling[s0 + tid] : 0.f;
     if (tid < 18) {  // the two zero rows, 9 x 16 bytes each
         uint4 *z = reinterpret_cast<uint4 *>(&hbuf[tid / 9][P][0]);
         z[tid % 9] = make_uint4(0u, 0u, 0u, 0u);
@@ -1099,160 +1352,6 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     __syncthreads();
     if (tid < G && s0 + tid < n_seq)
         seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);
-}
-
-// ---------------------------------------------------------------------------
-// lattice <-> blocks
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int spin_at(const RepDev &d, uint32_t x, uint32_t y)
-{
-    const uint32_t c = (x + y) & 1u, k = x >> 1;
-    const uint32_t w = d.plane0[c * d.Ly * d.W + y * d.W + (k >> 5)];
-    return ((w >> (k & 31)) & 1u) ? 1 : -1;
-}
-
-// block (bx, by) of a replica -> its spins and boundary
-__device__ void read_block(const RepDev &d, int Bs, uint32_t bx, uint32_t by, int8_t *x, int8_t *bnd)
-{
-    const uint32_t x0 = bx * Bs, y0 = by * Bs;
-    for (int i = 0; i < Bs; ++i)
-        for (int j = 0; j < Bs; ++j)
-            x[i * Bs + j] = (int8_t)spin_at(d, x0 + j, y0 + i);
-    const uint32_t yu = y0 == 0 ? d.Ly - 1 : y0 - 1, yd = (y0 + Bs) % d.Ly;
-    const uint32_t xl = x0 == 0 ? d.Lx - 1 : x0 - 1, xr = (x0 + Bs) % d.Lx;
-    for (int j = 0; j < Bs; ++j) {
-        bnd[j] = (int8_t)spin_at(d, x0 + j, yu);
-        bnd[Bs + j] = (int8_t)spin_at(d, x0 + j, yd);
-    }
-    for (int i = 0; i < Bs; ++i) {
-        bnd[2 * Bs + i] = (int8_t)spin_at(d, xl, y0 + i);
-        bnd[3 * Bs + i] = (int8_t)spin_at(d, xr, y0 + i);
-    }
-}
-
-// colour-`colour` block number idx of a replica -> (bx, by); blocks alternate in colour
-__device__ __forceinline__ void block_coords(uint32_t idx, uint32_t nbx, uint32_t colour, uint32_t *bx, uint32_t *by)
-{
-    const uint32_t half = nbx / 2;
-    *by = idx / half;
-    *bx = 2 * (idx - *by * half) + ((*by + colour) & 1u);
-}
-
-// Boundary spin q of block (bx, by): top row, bottom row, left column, right
-// column, Bs each, periodic.
-__device__ __forceinline__ int8_t boundary_spin(const RepDev &d, int Bs, uint32_t bx, uint32_t by, int q)
-{
-    const uint32_t x0 = bx * Bs, y0 = by * Bs;
-    const int side = q / Bs, m = q - side * Bs;
-    uint32_t x, y;
-    if (side < 2) {
-        x = x0 + m;
-        y = side == 0 ? (y0 == 0 ? d.Ly - 1 : y0 - 1) : (y0 + Bs) % d.Ly;
-    } else {
-        y = y0 + m;
-        x = side == 2 ? (x0 == 0 ? d.Lx - 1 : x0 - 1) : (x0 + Bs) % d.Lx;
-    }
-    return (int8_t)spin_at(d, x, y);
-}
-
-// One wave per block of the round: sequence b scores the current block,
-// sequence count + b draws the proposal with the same boundary.  Lane k reads
-// site k and boundary spin k.
-__global__ __launch_bounds__(256) void k_block_gather(const RepDev *__restrict__ reps, const double *__restrict__ kcoup,
-                                                      int Bs, uint32_t colour, uint32_t round, uint32_t first,
-                                                      uint32_t count, uint32_t per_rep, SeqDev seq)
-{
-    const uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (b >= count)
-        return;
-    const uint32_t g = first + b, r = g / per_rep, idx = g - r * per_rep;
-    const RepDev d = reps[r];
-    const uint32_t nbx = d.Lx / Bs;
-    uint32_t bx, by;
-    block_coords(idx, nbx, colour, &bx, &by);
-    const int BB = Bs * Bs;
-    if (lane < BB) {
-        const int i = lane / Bs, j = lane - i * Bs;
-        seq.x[(size_t)b * BB + lane] = (int8_t)spin_at(d, bx * Bs + j, by * Bs + i);
-    }
-    if (lane < 4 * Bs) {
-        const int8_t v = boundary_spin(d, Bs, bx, by, lane);
-        seq.bnd[(size_t)b * 4 * Bs + lane] = v;
-        seq.bnd[(size_t)(count + b) * 4 * Bs + lane] = v;
-    }
-    if (lane < 2) {
-        const size_t s = b + (size_t)lane * count;
-        seq.coupling[s] = (float)kcoup[r];
-        seq.key[4 * s + 0] = d.seed_lo;
-        seq.key[4 * s + 1] = d.seed_hi;
-        seq.key[4 * s + 2] = d.replica;
-        seq.key[4 * s + 3] = round;
-        seq.blk[s] = by * nbx + bx;
-    }
-}
-
-// Metropolis-Hastings for each gathered block, one wave per block: lane k
-// adds the change of the bonds of site k to its right and lower neighbours
-// inside the block and to the boundary; the exact integer sum decides with
-// log A = K dB + log q(current) - log q(proposal) against a 53-bit uniform.
-// Accepted proposals are XORed into the packed planes (only this block's
-// bits; same-colour blocks never share a bond, so concurrent blocks do not
-// interact).
-__global__ __launch_bounds__(256) void k_block_mh(const RepDev *__restrict__ reps, const double *__restrict__ kcoup,
-                                                  int Bs, uint32_t colour, uint32_t round, uint32_t first,
-                                                  uint32_t count, uint32_t per_rep, SeqDev seq,
-                                                  unsigned long long *__restrict__ accepts)
-{
-    const uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (b >= count)
-        return;
-    const uint32_t g = first + b, r = g / per_rep, idx = g - r * per_rep;
-    const RepDev d = reps[r];
-    const uint32_t nbx = d.Lx / Bs;
-    uint32_t bx, by;
-    block_coords(idx, nbx, colour, &bx, &by);
-    const int BB = Bs * Bs;
-    const int8_t *s = seq.x + (size_t)b * BB;
-    const int8_t *sp = seq.x + (size_t)(count + b) * BB;
-    const int8_t *bn = seq.bnd + (size_t)b * 4 * Bs;
-    int dB = 0, changed = 0;
-    if (lane < BB) {
-        const int i = lane / Bs, j = lane - i * Bs, k = lane;
-        const int a = s[k], ap = sp[k];
-        changed = a != ap;
-        if (j + 1 < Bs)
-            dB += ap * sp[k + 1] - a * s[k + 1];
-        if (i + 1 < Bs)
-            dB += ap * sp[k + Bs] - a * s[k + Bs];
-        if (i == 0)
-            dB += (ap - a) * bn[j];
-        if (i == Bs - 1)
-            dB += (ap - a) * bn[Bs + j];
-        if (j == 0)
-            dB += (ap - a) * bn[2 * Bs + i];
-        if (j == Bs - 1)
-            dB += (ap - a) * bn[3 * Bs + i];
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        dB += __shfl_xor(dB, m, 64);
-    // log of pi(s') q(s) / (pi(s) q(s')), pi ~ exp(K B)
-    const double logA = kcoup[r] * (double)dB + seq.logq[b] - seq.logq[count + b];
-    uint32_t o[4];
-    philox4x32_10(by * nbx + bx, round, d.replica, 4u, d.seed_lo, d.seed_hi, o);
-    const double u = (double)(((uint64_t)o[0] << 21) | (o[1] >> 11)) * 1.1102230246251565404e-16;  // 2^-53
-    const bool accept = logA >= 0.0 || u < exp(logA);
-    if (!accept)
-        return;
-    if (lane == 0)
-        atomicAdd(&accepts[r], 1ull);
-    if (changed) {
-        const int i = lane / Bs, j = lane - i * Bs;
-        const uint32_t x = bx * Bs + j, y = by * Bs + i, c = (x + y) & 1u, kk = x >> 1;
-        atomicXor(&d.plane0[c * d.Ly * d.W + y * d.W + (kk >> 5)], 1u << (kk & 31));
-    }
 }
 
 // training samples: block position of sample i of replica r drawn from
@@ -1340,19 +1439,21 @@ hipError_t finish_step(const NetDev &net, const TrainWs &ws, int nblk, int Bs, b
     return hipGetLastError();
 }
 
-template <int BS>
-static hipError_t ar_pass_bs(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, hipStream_t st)
+template <int BS, bool ROUND>
+static hipError_t ar_pass_bs(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, const RoundArgs &ra,
+                             hipStream_t st)
 {
     if (n_score > 0) {
         constexpr int G = SCORE_POS / (BS * BS) < 16 ? SCORE_POS / (BS * BS) : 16;
-        hipLaunchKernelGGL(k_nn_score<BS>, dim3(blocks_for(n_score, G)), dim3(256), 0, st, net, seq, n_score);
+        hipLaunchKernelGGL((k_nn_score<BS, ROUND>), dim3(blocks_for(n_score, G)), dim3(256), 0, st, net, seq,
+                           n_score, ra);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     if (n_sample > 0) {
-        hipLaunchKernelGGL(k_nn_sample<BS>, dim3(blocks_for(n_sample, SEQ_PER_WG)), dim3(256), 0, st, net, seq,
-                           n_score, n_sample);
+        hipLaunchKernelGGL((k_nn_sample<BS, ROUND>), dim3(blocks_for(n_sample, SEQ_PER_WG)), dim3(256), 0, st, net,
+                           seq, n_score, n_sample, ra);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -1360,29 +1461,27 @@ static hipError_t ar_pass_bs(const NetDev &net, const SeqDev &seq, int n_score, 
 
 hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, int Bs, hipStream_t st)
 {
+    const RoundArgs none{};
     switch (Bs) {
-    case 2: return ar_pass_bs<2>(net, seq, n_score, n_sample, st);
-    case 4: return ar_pass_bs<4>(net, seq, n_score, n_sample, st);
-    case 8: return ar_pass_bs<8>(net, seq, n_score, n_sample, st);
+    case 2: return ar_pass_bs<2, false>(net, seq, n_score, n_sample, none, st);
+    case 4: return ar_pass_bs<4, false>(net, seq, n_score, n_sample, none, st);
+    case 8: return ar_pass_bs<8, false>(net, seq, n_score, n_sample, none, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
-                        uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, hipStream_t st)
+hipError_t block_round_pass(const NetDev &net, const SeqDev &seq, const RepDev *reps, const double *kcoup, int Bs,
+                            uint32_t colour, uint32_t round, uint32_t first, uint32_t count, uint32_t per_rep,
+                            int64_t *accepts, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_block_gather, dim3(blocks_for(count, 4)), dim3(256), 0, st, reps, kcoup, Bs, colour,
-                       round, first, count, per_rep, seq);
-    return hipGetLastError();
-}
-
-hipError_t block_mh(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
-                    uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, int64_t *accepts,
-                    hipStream_t st)
-{
-    hipLaunchKernelGGL(k_block_mh, dim3(blocks_for(count, 4)), dim3(256), 0, st, reps, kcoup, Bs, colour, round,
-                       first, count, per_rep, seq, reinterpret_cast<unsigned long long *>(accepts));
-    return hipGetLastError();
+    const RoundArgs ra{reps, kcoup, reinterpret_cast<unsigned long long *>(accepts), colour, round, first, count,
+                       per_rep};
+    switch (Bs) {
+    case 2: return ar_pass_bs<2, true>(net, seq, (int)count, (int)count, ra, st);
+    case 4: return ar_pass_bs<4, true>(net, seq, (int)count, (int)count, ra, st);
+    case 8: return ar_pass_bs<8, true>(net, seq, (int)count, (int)count, ra, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t seq_setup(const SeqDev &seq, int n, uint64_t seed, uint32_t replica, uint32_t round, uint32_t blk0,

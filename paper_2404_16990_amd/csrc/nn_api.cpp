@@ -533,9 +533,8 @@ int ising_batch_block_round(ising_batch *b, ising_nn *m, uint32_t round, int64_t
     for (uint32_t colour = 0; colour < 2; ++colour)
         for (uint32_t first = 0; first < total; first += chunk) {
             const uint32_t count = std::min(chunk, total - first);
-            NN_HIP(block_gather(b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count, per_rep, m->seq, hs));
-            NN_HIP(ar_pass(m->net, m->seq, (int)count, (int)count, m->Bs, hs));
-            NN_HIP(block_mh(b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count, per_rep, m->seq, acc, hs));
+            NN_HIP(block_round_pass(m->net, m->seq, b->d_rep, b->d_kcoup, m->Bs, colour, round, first, count,
+                                    per_rep, acc, hs));
         }
     return ISING_OK;
 }

@@ -23,11 +23,12 @@ hipError_t finish_step(const NetDev &net, const TrainWs &ws, int nblk, int Bs, b
                        float *loss_out, hipStream_t st);
 // sequences [0, n_score) are scored, [n_score, n_score + n_sample) sampled
 hipError_t ar_pass(const NetDev &net, const SeqDev &seq, int n_score, int n_sample, int Bs, hipStream_t st);
-hipError_t block_gather(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
-                        uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, hipStream_t st);
-hipError_t block_mh(const RepDev *reps, const double *kcoup, int Bs, uint32_t colour, uint32_t round,
-                    uint32_t first, uint32_t count, uint32_t per_rep, const SeqDev &seq, int64_t *accepts,
-                    hipStream_t st);
+// One colour of a block round for round blocks [first, first + count):
+// scores the current blocks (read from the lattice), samples the proposals
+// and applies the Metropolis-Hastings decisions to the packed planes.
+hipError_t block_round_pass(const NetDev &net, const SeqDev &seq, const RepDev *reps, const double *kcoup, int Bs,
+                            uint32_t colour, uint32_t round, uint32_t first, uint32_t count, uint32_t per_rep,
+                            int64_t *accepts, hipStream_t st);
 hipError_t seq_setup(const SeqDev &seq, int n, uint64_t seed, uint32_t replica, uint32_t round, uint32_t blk0,
                      hipStream_t st);
 hipError_t extract(const RepDev *reps, const double *kcoup, int Bs, uint32_t per_rep, uint32_t count,

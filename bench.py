@@ -411,7 +411,7 @@ def config_leg(name, args, stream):
     import torch
     import workloads
     work = workloads.ALL[name]()
-    m, b = run_path(work, 0, args, stream)
+    m, b = run_path(work, 0, args, stream, json.loads(args.configs_schedule) if args.configs_schedule else None)
     out = {"workload": work.name, "replicas": len(work.replicas), "spins": work.spins,
            "value": m["value"], "unit": "flip attempts/s", "ms_per_step": m["ms_per_step"],
            "sweeps_per_step": args.sweeps_per_step, "steps": args.steps, "schedule": m["schedule"],
@@ -465,6 +465,8 @@ def main():
     ap.add_argument("--workload", default="uneven_512")
     ap.add_argument("--configs", default="batch_256x1024,paper_scale",
                     help="other plain configurations timed the same way (comma list, '' for none)")
+    ap.add_argument("--configs-schedule", default="",
+                    help="JSON dict of a fixed execution schedule for the configurations (no autotuning)")
     ap.add_argument("--rng", default="site", choices=list(RNG_NAMES),
                     help="random-number contract of the measured path (site: one Philox word per site; "
                          "bitsliced: transposed group words drawn lazily)")

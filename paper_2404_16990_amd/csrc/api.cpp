@@ -466,12 +466,8 @@ int ising_batch_run(ising_batch *b, uint64_t n_sweeps, uint32_t record_every, in
         rec.mag = dev_mag_trace;
         rec.every = record_every;
         rec.n_rec = (uint32_t)(n_sweeps / record_every);
-        const uint64_t slots = (uint64_t)b->n * rec.n_rec;
-        ISING_HIP(launch_fill_i64(rec.bond, slots, 0, hs));
-        ISING_HIP(launch_fill_i64(rec.mag, slots, 0, hs));
     }
-    ISING_HIP(launch_set_rec(b->d_rec, rec, hs));
-    ISING_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, hs));
+    ISING_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, b->d_rec, rec, hs));
     const uint64_t S = (uint64_t)b->sched.sweeps_per_launch;
     const uint64_t full = n_sweeps / S, rem = n_sweeps % S;
     if (full > 0) {

@@ -171,12 +171,8 @@ int run_cluster(ising_batch *b, int32_t algorithm, uint64_t n_steps, uint32_t re
         rec.mag = dev_mag_trace;
         rec.every = record_every;
         rec.n_rec = (uint32_t)(n_steps / record_every);
-        const uint64_t slots = (uint64_t)b->n * rec.n_rec;
-        CL_HIP(launch_fill_i64(rec.bond, slots, 0, hs));
-        CL_HIP(launch_fill_i64(rec.mag, slots, 0, hs));
     }
-    CL_HIP(launch_set_rec(b->d_rec, rec, hs));
-    CL_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, hs));
+    CL_HIP(launch_begin_run(b->d_rep, (uint32_t)b->n, b->d_rec, rec, hs));
     const bool recording = rec.every != 0;
     ClArgs a;
     a.reps = b->d_rep;

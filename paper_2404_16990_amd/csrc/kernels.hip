@@ -362,20 +362,22 @@ __global__ void k_fill_i64(int64_t *__restrict__ p, uint64_t n, int64_t v)
         p[i] = v;
 }
 
-// The recording arguments of the run about to be enqueued, written on the
-// stream in order, so a captured chunk reads the current run's traces on
-// every replay.
-__global__ void k_set_rec(RecArgs *__restrict__ dst, RecArgs v)
+// Start of a run, one launch: every replica's t0 = t, the recording
+// arguments of the run written to dst (on the stream in order, so a captured
+// chunk reads the current run's traces on every replay), and the run's trace
+// slots (if any) zeroed for the recording kernels' atomic sums.
+__global__ void k_begin_run(RepDev *__restrict__ reps, uint32_t n, RecArgs *__restrict__ dst, RecArgs v)
 {
-    if (threadIdx.x == 0)
+    const uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+    if (i0 < n)
+        reps[i0].t0 = reps[i0].t;
+    if (i0 == 0)
         *dst = v;
-}
-
-__global__ void k_begin_run(RepDev *__restrict__ reps, uint32_t n)
-{
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n)
-        reps[r].t0 = reps[r].t;
+    const uint64_t slots = v.bond ? (uint64_t)n * v.n_rec : 0;
+    for (uint64_t i = i0; i < slots; i += stride) {
+        v.bond[i] = 0;
+        v.mag[i] = 0;
+    }
 }
 
 __global__ void k_advance(RepDev *__restrict__ reps, uint32_t n, uint32_t delta)
@@ -421,15 +423,11 @@ hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_set_rec(RecArgs *dst, const RecArgs &v, hipStream_t st)
+hipError_t launch_begin_run(RepDev *reps, uint32_t n, RecArgs *dst, const RecArgs &v, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_set_rec, dim3(1), dim3(64), 0, st, dst, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_begin_run, dim3((n + 255) / 256), dim3(256), 0, st, reps, n);
+    const uint64_t slots = v.bond ? (uint64_t)n * v.n_rec : 0;
+    const uint64_t blocks = std::max<uint64_t>((n + 255) / 256, std::min<uint64_t>((slots + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_begin_run, dim3((uint32_t)blocks), dim3(256), 0, st, reps, n, dst, v);
     return hipGetLastError();
 }
 

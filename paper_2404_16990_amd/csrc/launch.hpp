@@ -37,14 +37,13 @@ hipError_t launch_observables(const RepDev *reps, uint32_t n, uint32_t max_words
 // Adds replica r's (B, M) after step t + step to its trace slot if the step
 // is a recorded one (slot from the device counters t, t0; see RecArgs).  The
 // recording arguments are read from device memory (rec), where
-// launch_set_rec put the current run's, so captured graphs stay valid.
+// launch_begin_run put the current run's, so captured graphs stay valid.
 hipError_t launch_observables_rec(const RepDev *reps, uint32_t n, uint32_t max_words, const RecArgs *rec,
                                   uint32_t step, hipStream_t st);
-// Write the recording arguments of the next run to device memory (a kernel,
-// ordered on the stream like the work that reads them).
-hipError_t launch_set_rec(RecArgs *dst, const RecArgs &v, hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t v, hipStream_t st);
-hipError_t launch_begin_run(RepDev *reps, uint32_t n, hipStream_t st);
+// Start of a run in one launch: t0 = t for every replica, the recording
+// arguments v to dst, and v's trace slots (n x v.n_rec each, if v.bond) zeroed.
+hipError_t launch_begin_run(RepDev *reps, uint32_t n, RecArgs *dst, const RecArgs &v, hipStream_t st);
 hipError_t launch_advance(RepDev *reps, uint32_t n, uint32_t delta, hipStream_t st);
 hipError_t launch_sweep_stream(const StreamList &L, int word_bits, int threads, uint32_t colour,
                                uint32_t sweep_off, const RecArgs *rec, hipStream_t st);

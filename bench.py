@@ -478,7 +478,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal comparison (64 x 256^2 near T_c)")
-    ap.add_argument("--learned-units", type=int, default=20000)
+    ap.add_argument("--learned-units", type=int, default=60000)
     ap.add_argument("--learned-train-steps", type=int, default=2000,
                     help="Adam steps of the learned leg's training (fewer only to profile it)")
     ap.add_argument("--plain-sweeps", type=int, default=1000000)

@@ -579,3 +579,30 @@ def test_block_round_follows_its_definition(Bs):
         assert np.array_equal(acc.cpu().numpy(), total), (acc.cpu().numpy(), total)
     n_blocks = 2 * len(descs) * (Lx // Bs) * (Ly // Bs)
     assert 0 < total.sum() < n_blocks, total
+
+
+def test_training_entry_points_reject_bad_arguments():
+    """Errors of the training entry points come back as ISING_E_INVALID with a
+    message, before any work is enqueued: a batch outside [1, max_batch], a
+    training set of no rows, a non-positive learning rate, a step count below
+    one."""
+    import torch
+    P = _P()
+    rng = np.random.default_rng(5)
+    Bs = 4
+    x, bnd, kc = _rand_blocks(rng, 40, Bs)
+    X, BN, K = _dev(x, torch.int8), _dev(bnd, torch.int8), _dev(kc, torch.float32)
+    net = P.Net(_params(1.0), block=Bs, max_batch=32, max_seq=64)
+    theta = net.params.copy()
+    bad = [lambda: net.train_step_sampled(X, BN, K, 33, 1e-3, 1),
+           lambda: net.train_step_sampled(X, BN, K, 0, 1e-3, 1),
+           lambda: net.train_step_sampled(X, BN, K, 16, 0.0, 1),
+           lambda: net.train_steps_sampled(X, BN, K, 16, 1e-3, 1, 0),
+           lambda: net.train_steps_sampled(X[:0], BN[:0], K[:0], 16, 1e-3, 1, 4),
+           lambda: net.train_step(X[:33], BN[:33], K[:33], 1e-3)]
+    for f in bad:
+        with pytest.raises(P.IsingError) as e:
+            f()
+        assert e.value.code == P.ISING_E_INVALID, e.value
+    torch.cuda.synchronize()
+    assert np.array_equal(net.params, theta)  # nothing was enqueued

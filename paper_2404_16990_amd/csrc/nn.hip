@@ -1,11 +1,14 @@
 // HIP kernels of the block-proposal network (definitions in nn.hpp):
-//  - training: masked-conv forward with an MFMA BF16 GEMM (FP32 accumulate),
-//    loss, backward (data and weight gradients as GEMMs), Adam;
-//  - the incremental autoregressive pass that scores a given block or samples
-//    a new one site by site with exactly the same arithmetic, accumulating
-//    log q in FP64 from uint32 thresholds;
-//  - gathering blocks from packed lattices, the Metropolis-Hastings decision
-//    and write-back, and training-block extraction.
+//  - training, three kernels a step: the forward and backward of each
+//    64-position tile (masked convolutions and their data gradients as
+//    implicit GEMMs on the BF16 matrix cores, FP32 accumulation), the weight
+//    gradients of all layers, and the reduction with Adam;
+//  - the incremental autoregressive passes that score a given block or
+//    sample a new one site by site with exactly the same arithmetic,
+//    accumulating log q in FP64 from uint32 thresholds; in a block round the
+//    scorer reads the current blocks from the packed lattice and the sampler
+//    ends with the Metropolis-Hastings decision and write-back;
+//  - training-block extraction from the packed lattices.
 #include <math.h>
 
 #include "device.hpp"

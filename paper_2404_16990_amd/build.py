@@ -16,8 +16,12 @@ SOURCES = ["kernels.hip", "api.cpp", "nn.hip", "nn_api.cpp", "cluster.hip", "clu
 PROBE_OUT = os.path.join(OUT_DIR, "libising_probe.so")
 PROBE_SOURCES = ["probe.hip"]
 # Packed FP32 instructions stay disabled in every HIP build of this project.
+# Matrix-core results go to ordinary vector registers (the VGPR form of the
+# MFMA instructions), so the activations read them without a copy out of the
+# accumulation registers.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _compile(sources, out, verbose):

@@ -19,7 +19,9 @@ namespace ising {
 namespace nn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 
 // float -> bfloat16 bits, round to nearest even (inputs are finite): one
 // v_cvt_pk_bf16_f32 on gfx950
@@ -28,17 +30,40 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
-// tanh from the hardware exp2 and reciprocal: tanh x = 1 - 2 / (1 + e^{2x}).
-// exp2 overflows to +inf (reciprocal 0) or underflows to 0 far from the
-// origin, so the ends are exactly +1 and -1; near 0 the error is absolute,
-// about one ulp of 1.  Three vector operations and two transcendentals: the
-// activations of every layer go through it, and it is the largest share of
-// the vector-unit work of the network kernels.  Every kernel of the network
-// uses this one definition, so training, scoring and sampling evaluate the
-// same function.
-__device__ __forceinline__ float net_tanh(float x)
+// two floats -> two bfloat16 (round to nearest even) in one v_cvt_pk_bf16_f32:
+// a in the low half, b in the high half
+__device__ __forceinline__ uint32_t f2bf2(float a, float b)
 {
-    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);  // e^{2x}; 2.885... = 2 log2(e)
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){a, b}, bf16x2));
+}
+
+// v[0..3] in BF16 to p[0], p[RS], p[2 RS], p[3 RS] (one column of four rows of
+// a row-major array): two conversions, the high halves stored straight from
+// the upper 16 bits
+template <int RS>
+__device__ __forceinline__ void store_col4(uint16_t *p, float v0, float v1, float v2, float v3)
+{
+    const uint32_t lo = f2bf2(v0, v1), hi = f2bf2(v2, v3);
+    p[0] = (uint16_t)lo;
+    p[RS] = (uint16_t)(lo >> 16);
+    p[2 * RS] = (uint16_t)hi;
+    p[3 * RS] = (uint16_t)(hi >> 16);
+}
+
+// tanh(x + b) from the hardware exp2 and reciprocal: tanh y = 1 - 2 / (1 + e^{2y}),
+// with 2 log2(e) (x + b) formed by one fused multiply-add from sb = tanh_bias(b)
+// (sb = 0: tanh x).  exp2 overflows to +inf (reciprocal 0) or underflows to 0
+// far from the origin, so the ends are exactly +1 and -1; near 0 the error is
+// absolute, about one ulp of 1.  Three vector operations and two
+// transcendentals: the activations of every layer go through it, and it is
+// the largest share of the vector-unit work of the network kernels.  Every
+// kernel of the network uses this one definition, so training, scoring and
+// sampling evaluate the same function.
+constexpr float TANH_K = 2.8853900817779268f;  // 2 log2(e)
+__device__ __forceinline__ float tanh_bias(float b) { return TANH_K * b; }
+__device__ __forceinline__ float net_tanh(float x, float sb = 0.f)
+{
+    const float e = __builtin_amdgcn_exp2f(fmaf(x, TANH_K, sb));  // e^{2(x + b)}
     return fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + e), 1.f);
 }
 
@@ -316,20 +341,21 @@ __global__ __launch_bounds__(256, 2) void k_train_tile(NetDev net, TrainWs ws, B
         tile_conv<false>(act[cur], net.wt + (size_t)(l - 2) * C * KB, bv, arow, ai, aj, alive, Bs, n0, r, kq, acc);
         // the next product's first B slices: layer l + 1, or the first data gradient (layer 4's)
         load_b<0, 5>(l < 4 ? net.wt + (size_t)(l - 1) * C * KB : net.wtd + (size_t)2 * C * KB, n0, r, kq, bv);
-        const float bias[2] = {P[off_b(l) + cb[0]], P[off_b(l) + cb[1]]};
+        const float sbias[2] = {tanh_bias(P[off_b(l) + cb[0]]), tanh_bias(P[off_b(l) + cb[1]])};
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < 2; ++b) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int p = m0 + a * 16 + 4 * g4 + i;
                     // rows past the batch read only zero rows: a finite tanh(bias), masked
-                    const float v = net_tanh(acc[a][b][i] + bias[b]) * (p0 + p < Pvalid ? 1.f : 0.f);
-                    h[l - 1][a][b][i] = v;
-                    if (l < 4)
-                        act[cur ^ 1][p][cb[b]] = f2bf(v);
+                    h[l - 1][a][b][i] = net_tanh(acc[a][b][i], sbias[b]) * (p0 + p < Pvalid ? 1.f : 0.f);
                 }
+                if (l < 4)
+                    store_col4<ACT_ROW>(&act[cur ^ 1][m0 + a * 16 + 4 * g4][cb[b]], h[l - 1][a][b][0],
+                                        h[l - 1][a][b][1], h[l - 1][a][b][2], h[l - 1][a][b][3]);
+            }
         if (l < 4) {
             __syncthreads();
             store_tile(act[cur ^ 1], ws.hb[l - 1] + (size_t)p0 * C, tid);
@@ -786,7 +812,7 @@ constexpr int RING_ROW = C + 8;  // padded row (bf16 elements) against LDS bank 
 
 // the FP32 parameters a lane of the incremental passes uses (output channel cw)
 struct ArScalars {
-    float bias[3], wo_c, bo;
+    float sbias[3], wo_c, bo;  // sbias: tanh_bias of the layer 2..4 biases
     float l1w[3];  // layer 1: this lane's B operands (channel cw, input k = lane >> 4 of each group)
 };
 
@@ -800,7 +826,7 @@ __device__ __forceinline__ void load_ar_scalars(const NetDev &net, int wave, int
     const int cw = 16 * wave + (lane & 15);
 #pragma unroll
     for (int l = 0; l < 3; ++l)
-        p.bias[l] = P[off_b(l + 2) + cw];
+        p.sbias[l] = tanh_bias(P[off_b(l + 2) + cw]);
     p.wo_c = P[OFF_WO + cw];
     p.bo = P[OFF_BO];
     const int k = lane >> 4;
@@ -892,7 +918,7 @@ __device__ __forceinline__ void head_rows(const floatx4 &acc, const ArScalars &p
 #pragma clang fp contract(off)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        float v = net_tanh(acc[r] + p.bias[2]) * p.wo_c;
+        float v = net_tanh(acc[r], p.sbias[2]) * p.wo_c;
         v = add_dpp<0xb1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
         v = add_dpp<0x4e>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
         v = add_dpp<0x104>(v);  // row_shl 4: lane + 4
@@ -929,6 +955,52 @@ __device__ __forceinline__ double logq_total(const double *part, int BB)
     for (int pt = 0; pt < 16; ++pt)
         sum += part[pt];
     return sum - (double)BB * 32.0 * 0.69314718055994530942;
+}
+
+// Layers 2..4 of the sampler at site k, for one class of sites: whether the
+// site is in the block's first row (TOP) or first or last column (LEFT,
+// RIGHT) fixes at compile time which of the five taps fall outside the block
+// (an all-zero A slice), so the ten A slices of a layer are all loaded from
+// the ring before its chain of products starts.  Every lane of the
+// workgroup is at the same site, so the class is the same for all of them.
+template <bool TOP, bool LEFT, bool RIGHT>
+__device__ constexpr bool tap_inside(int t)
+{
+    return t == 0 ? !TOP && !LEFT : t == 1 ? !TOP : t == 2 ? !TOP && !RIGHT : t == 3 ? !LEFT : true;
+}
+
+template <int BS, bool TOP, bool LEFT, bool RIGHT>
+__device__ __forceinline__ void sample_layers(uint16_t (*ring)[RING][SEQ_PER_WG][RING_ROW], const ArWeights &p, int k,
+                                              int lane, int cw, float *head_part)
+{
+    const int slot = k % RING;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        bf16x8 a[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const int t = q >> 1, half = q & 1;
+            if (tap_inside<TOP, LEFT, RIGHT>(t)) {
+                const int pslot = (k + tap_di(t) * BS + tap_dj(t) + RING) % RING;
+                a[q] = load_bf16x8(&ring[l][pslot][lane & 15][half * 32 + 8 * (lane >> 4)]);
+            } else {
+                a[q] = zero_bf16x8();
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the first product
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q], p.w[l][q], acc, 0, 0, 0);
+        if (l < 2) {
+            const float sb = p.sbias[l];
+            store_col4<RING_ROW>(&ring[l + 1][slot][4 * (lane >> 4)][cw], net_tanh(acc[0], sb), net_tanh(acc[1], sb),
+                                 net_tanh(acc[2], sb), net_tanh(acc[3], sb));
+        } else {
+            head_rows(acc, p, lane, head_part);
+        }
+        __syncthreads();
+    }
 }
 
 // ROUND: the sequences are a block round's proposals (sequence first + b for
@@ -1069,36 +1141,28 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
             layer1_inputs<BS>(&xs[srow][0], k - 1, xprev, &bs[srow][0], ks[srow], i, j, kin, &in_tap, &in_bnd,
                               &in_k);
             const floatx4 pre = layer1_tile(in_tap, in_bnd, in_k, p);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                ring[0][slot][4 * kin + r][cw] = f2bf(net_tanh(pre[r]));
+            store_col4<RING_ROW>(&ring[0][slot][4 * kin][cw], net_tanh(pre[0]), net_tanh(pre[1]),
+                                               net_tanh(pre[2]), net_tanh(pre[3]));
         }
         __syncthreads();
         if (k == BB)
             break;
         // layers 2..4 on the matrix cores; layer 4 feeds the logit head directly
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < 10; ++q) {
-                const int t = q >> 1, half = q & 1;
-                const int ii = i + tap_di(t), jj = j + tap_dj(t);
-                bf16x8 a = zero_bf16x8();
-                if (ii >= 0 && jj >= 0 && jj < BS) {  // the same for the whole workgroup
-                    const int pslot = (k + tap_di(t) * BS + tap_dj(t) + RING) % RING;
-                    a = load_bf16x8(&ring[l][pslot][lane & 15][half * 32 + 8 * (lane >> 4)]);
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, p.w[l][q], acc, 0, 0, 0);
-            }
-            if (l < 2) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    ring[l + 1][slot][4 * (lane >> 4) + r][cw] = f2bf(net_tanh(acc[r] + p.bias[l]));
-            } else {
-                head_rows(acc, p, lane, head_part[wave]);
-            }
-            __syncthreads();
+        float *hp = head_part[wave];
+        if (i == 0) {
+            if (j == 0)
+                sample_layers<BS, true, true, false>(ring, p, k, lane, cw, hp);
+            else if (j == BS - 1)
+                sample_layers<BS, true, false, true>(ring, p, k, lane, cw, hp);
+            else
+                sample_layers<BS, true, false, false>(ring, p, k, lane, cw, hp);
+        } else {
+            if (j == 0)
+                sample_layers<BS, false, true, false>(ring, p, k, lane, cw, hp);
+            else if (j == BS - 1)
+                sample_layers<BS, false, false, true>(ring, p, k, lane, cw, hp);
+            else
+                sample_layers<BS, false, false, false>(ring, p, k, lane, cw, hp);
         }
     }
     if (wave == 0 && kin == 0)
@@ -1289,9 +1353,8 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
         float in_tap, in_bnd, in_k;
         layer1_inputs<BS>(&xs[s][0], -1, 0.f, &bs[s][0], ks[s], i, j, lane >> 4, &in_tap, &in_bnd, &in_k);
         const floatx4 pre = layer1_tile(in_tap, in_bnd, in_k, p);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            hbuf[0][16 * m + 4 * (lane >> 4) + r][cw] = f2bf(net_tanh(pre[r]));
+        store_col4<RING_ROW>(&hbuf[0][16 * m + 4 * (lane >> 4)][cw], net_tanh(pre[0]), net_tanh(pre[1]),
+                             net_tanh(pre[2]), net_tanh(pre[3]));
     }
     __syncthreads();
 
@@ -1330,9 +1393,9 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
             for (int u = 0; u < SCORE_TILES; ++u) {
                 const int row0 = 16 * (m0 + u) + 4 * (lane >> 4);
                 if (l < 2) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        hout[row0 + r][cw] = f2bf(net_tanh(acc[u][r] + p.bias[l]));
+                    const float sb = p.sbias[l];
+                    store_col4<RING_ROW>(&hout[row0][cw], net_tanh(acc[u][0], sb), net_tanh(acc[u][1], sb),
+                                         net_tanh(acc[u][2], sb), net_tanh(acc[u][3], sb));
                 } else {
                     // hout is the other buffer, free now: head partials of this wave
                     head_rows(acc[u], p, lane, &head_part[wave][16 * (m0 + u)]);

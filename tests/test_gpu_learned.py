@@ -191,7 +191,7 @@ def test_extract_blocks_follow_their_definition():
         assert len(edges) > 2  # wrapped boundaries were among the draws
 
 
-@pytest.mark.parametrize("Bs", [8, 4])
+@pytest.mark.parametrize("Bs", [8, 4, 2])
 def test_sampler_and_scorer_match_the_float64_network(Bs):
     """The incremental kernels at the production block sizes against the float64
     network at the same bfloat16 rounding points.  log q is a sum of Bs^2 terms
@@ -551,7 +551,7 @@ def _host_block_round(net, spins, descs, Bs, round_):
     return out, acc, closest
 
 
-@pytest.mark.parametrize("Bs", [8, 4])
+@pytest.mark.parametrize("Bs", [8, 4, 2])
 def test_block_round_follows_its_definition(Bs):
     """Two block rounds of a batch (replicas at K = 0.02, 0.15 and 0.45, so
     proposals are both accepted and rejected) against the round computed on the

@@ -936,16 +936,21 @@ __device__ __forceinline__ float head_logit(const float *h0, const float *h1, co
 
 // log q = sum_k log(thr_k or 2^32 - thr_k) - BB * 32 ln 2 in FP64, summed in a
 // fixed order: 16 parts of 4 consecutive sites, then the parts in order.
+// log of the probability (times 2^32) that a site with threshold thr took spin x
+__device__ __forceinline__ double site_log(int8_t x, uint32_t thr)
+{
+    const double t = (double)thr;
+    return log(x > 0 ? t : 4294967296.0 - t);
+}
+
 template <int XS, int TS>
 __device__ __forceinline__ void logq_parts(const int8_t (*xs)[XS], const uint32_t (*thr)[TS], int BB, int tid,
                                            double (*part)[16])
 {
     const int s = tid >> 4, pt = tid & 15;
     double acc = 0.0;
-    for (int k = pt * 4; k < pt * 4 + 4 && k < BB; ++k) {
-        const double t = (double)thr[s][k];
-        acc += log(xs[s][k] > 0 ? t : 4294967296.0 - t);
-    }
+    for (int k = pt * 4; k < pt * 4 + 4 && k < BB; ++k)
+        acc += site_log(xs[s][k], thr[s][k]);
     part[s][pt] = acc;
 }
 
@@ -1250,16 +1255,19 @@ __global__ __launch_bounds__(256) void k_nn_sample(NetDev net, SeqDev seq, int f
 // workgroup holds all SCORE_POS positions of its blocks in LDS and runs the
 // network one layer at a time: layer 1 for every position, then for layers
 // 2..4 wave w (output channels 16w .. 16w+15) walks the position tiles of 16
-// rows, four independent MFMA chains at a time.  A row of a tile is one
+// rows, two independent MFMA chains at a time, the A slices of the next K
+// step loaded before the products of the current one.  A row of a tile is one
 // (block, site) pair; its A row is the previous layer at the site's five taps
 // (an all-zero LDS row outside the block, so the reads never branch), its B
 // operands and K order are the sampler's, and a matrix-core product row
 // depends only on its own A row, so every site gets the sampler's logit and
 // threshold bit for bit.  A wave holds one layer's weights at a time (the
 // next layer's load during the barrier), which with 128 positions per
-// workgroup leaves room for four workgroups per CU.
+// workgroup leaves room for four workgroups per CU.  The FP64 logarithms of
+// log q are taken one position per thread and then summed in the sampler's
+// order.
 constexpr int SCORE_POS = 128;  // positions per workgroup (a multiple of 64)
-constexpr int SCORE_TILES = 4;  // MFMA chains a wave runs together
+constexpr int SCORE_TILES = 2;  // MFMA chains a wave runs together
 
 // ROUND: the sequences are a block round's current blocks, read from the
 // packed lattice with their boundaries and K; the spins go to seq.x[b] and
@@ -1274,7 +1282,8 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     static_assert(P % 64 == 0 && MT % SCORE_TILES == 0, "whole tile groups");
     // activations of the layer being read and the layer being written
     // (ping-pong; row P of each is zero); after layer 4 the first holds the
-    // head partials, the thresholds and the log-q parts
+    // thresholds and the log-q parts, the second the head partials and the
+    // per-position logarithms
     __shared__ __attribute__((aligned(16))) uint16_t hbuf[2][P + 1][RING_ROW];
     __shared__ int8_t xs[G][64];
     __shared__ int8_t bs[G][32];
@@ -1282,6 +1291,7 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
     float(*head_part)[P] = reinterpret_cast<float(*)[P]>(&hbuf[1][0][0]);              // [4][P]
     uint32_t(*thr_s)[64] = reinterpret_cast<uint32_t(*)[64]>(&hbuf[0][0][0]);         // [G][64]
     double(*lq_part)[16] = reinterpret_cast<double(*)[16]>(&hbuf[0][0][0] + G * 64 * 2);  // [G][16]
+    double *lg = reinterpret_cast<double *>(&hbuf[1][0][0]) + 2 * P;  // [P], after the head partials
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int s0 = blockIdx.x * G;
@@ -1377,17 +1387,30 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
                 si[u] = k / BS;
                 sj[u] = k - si[u] * BS;
             }
-#pragma unroll
-            for (int q = 0; q < 10; ++q) {
+            // the A slices of K step q (tap q >> 1, channel half q & 1); those of
+            // step q + 1 are loaded before the products of step q
+            bf16x8 a_cur[SCORE_TILES], a_nxt[SCORE_TILES];
+            auto load_step = [&](int q, bf16x8 *a) {
                 const int t = q >> 1, half = q & 1;
 #pragma unroll
                 for (int u = 0; u < SCORE_TILES; ++u) {
                     const int ii = si[u] + tap_di(t), jj = sj[u] + tap_dj(t);
                     const bool ok = (ii >= 0) & (jj >= 0) & (jj < BS);
-                    const bf16x8 a =
-                        load_bf16x8(&hin[ok ? row[u] + tap_di(t) * BS + tap_dj(t) : P][half * 32 + kq]);
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[q], acc[u], 0, 0, 0);
+                    a[u] = load_bf16x8(&hin[ok ? row[u] + tap_di(t) * BS + tap_dj(t) : P][half * 32 + kq]);
                 }
+            };
+            load_step(0, a_cur);
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                if (q < 9)
+                    load_step(q + 1, a_nxt);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < SCORE_TILES; ++u)
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[u], w[q], acc[u], 0, 0, 0);
+#pragma unroll
+                for (int u = 0; u < SCORE_TILES; ++u)
+                    a_cur[u] = a_nxt[u];
             }
 #pragma unroll
             for (int u = 0; u < SCORE_TILES; ++u) {
@@ -1413,8 +1436,20 @@ __global__ __launch_bounds__(256) void k_nn_score(NetDev net, SeqDev seq, int n_
         thr_s[s][k] = site_threshold(head_logit(head_part[0], head_part[1], head_part[2], head_part[3], pos, p.bo));
     }
     __syncthreads();
-    for (int idx = tid; idx < G * 16; idx += 256)
-        logq_parts(xs, thr_s, BB, idx, lq_part);
+    // the FP64 logarithm of every position on a thread of its own, then the
+    // sampler's parts (four consecutive sites each, summed in order)
+    for (int pos = tid; pos < P; pos += 256) {
+        const int s = pos / BB, k = pos - s * BB;
+        lg[pos] = site_log(xs[s][k], thr_s[s][k]);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < G * 16; idx += 256) {
+        const int s = idx >> 4, pt = idx & 15;
+        double acc = 0.0;
+        for (int k = pt * 4; k < pt * 4 + 4 && k < BB; ++k)
+            acc += lg[s * BB + k];
+        lq_part[s][pt] = acc;
+    }
     __syncthreads();
     if (tid < G && s0 + tid < n_seq)
         seq.logq[s0 + tid] = logq_total(lq_part[tid], BB);

@@ -48,11 +48,16 @@ def alu_peak_flips():
     return lane_ops_peak() / OPS_PER_FLIP
 
 
-def kernel_source_digest():
+SWEEP_SOURCES = ("paper_2404_16990_amd/csrc/kernels.hip", "paper_2404_16990_amd/csrc/device.hpp",
+                 "paper_2404_16990_amd/csrc/launch.hpp")
+CLUSTER_SOURCES = ("paper_2404_16990_amd/csrc/cluster.hip", "paper_2404_16990_amd/csrc/cluster.hpp",
+                   "paper_2404_16990_amd/csrc/device.hpp")
+
+
+def kernel_source_digest(sources=SWEEP_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for rel in ("paper_2404_16990_amd/csrc/kernels.hip", "paper_2404_16990_amd/csrc/device.hpp",
-                "paper_2404_16990_amd/csrc/launch.hpp"):
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -82,6 +87,21 @@ def measured_traffic(kernel, workload_name, sweeps_per_launch):
     if e is None:
         return None, None
     return e["traffic_bytes_per_launch"], e.get("algorithmic_bytes_per_launch", d["algorithmic_bytes_per_launch"])
+
+
+def measured_cluster_traffic(workload_name):
+    """HBM bytes of one Swendsen-Wang step from the committed counter summary,
+    or None when it is for another workload or the cluster sources changed."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_cluster_sw_batch256x1024.json")) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("kernel_source_sha256") != kernel_source_digest(CLUSTER_SOURCES):
+        return None
+    if not d["workload"].startswith(workload_name):
+        return None
+    return d["traffic_bytes_per_step"]
 
 
 def host_threads():
@@ -320,7 +340,8 @@ def cluster_leg(work, stream, steps, warmup=2):
         "bound": "hbm" if peak_hbm <= peak_alu else "alu",
         "kernel": "k_cl_local + k_cl_cross<merge> + k_cl_cross<compress> + k_cl_flip (whole SW step)",
         "achieved": achieved / 1e9, "peak": min(peak_alu, peak_hbm) / 1e9, "unit": "Gsite/s",
-        "frac": achieved / min(peak_alu, peak_hbm), "traffic": None,
+        "frac": achieved / min(peak_alu, peak_hbm), "traffic": measured_cluster_traffic(work.name),
+        "traffic_per": "one SW step (bytes); the counted bytes are " + f"{SW_BYTES_PER_SITE * work.spins:.4g}",
         "per_unit": f"{SW_OPS_PER_SITE:.1f} VALU instructions (0.5 + 1/128 Philox calls) and "
                     f"{SW_BYTES_PER_SITE:.2f} HBM bytes per site",
         "alu_peak": peak_alu / 1e9, "hbm_peak": peak_hbm / 1e9}

@@ -147,10 +147,27 @@ __global__ __launch_bounds__(256) void k_clock(uint64_t *stamps, uint32_t *out, 
 // sweep kernels (256 threads as the streaming kernel; 1024 threads with at most
 // four waves per SIMD as the LDS-resident kernel).  Sites per second of the
 // faster shape is the measured ALU ceiling of the sweep's instruction mix
-// (thresholds of T_c; no data-dependent branches).
+// (thresholds of T_c).  With `bonds` 0 the neighbour words are unrelated to
+// the spin word, so half of the bonds are anti-aligned; with 1 each neighbour
+// word differs from the spin word in about 1/8 of its bits (the AND of three
+// hashed words), close to the 0.146 of the 2D model at T_c.  The site
+// contract's cost does not depend on the bonds; the bit-sliced contract's
+// lazy comparison runs until the wave's last undecided site is decided, and
+// far more sites are undecided (at most one anti-aligned neighbour) in an
+// ordered lattice than in random words.
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    // the finaliser of Steele, Lea and Flood's SplitMix64 (OOPSLA 2014)
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
 template <typename Word, bool BITSLICED, int THREADS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(1, THREADS >= 1024 ? 4 : 8)))
-void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8)
+void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8, int bonds)
 {
     using ising::SweepKey;
     const uint32_t tid = blockIdx.x * (uint32_t)THREADS + threadIdx.x;
@@ -168,21 +185,45 @@ void k_mix(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8
     const Word up = (Word)(tid * 0xC2B2AE3D27D4EB4Full), dn = (Word)(tid * 0x165667B19E3779F9ull);
     const Word same = (Word)(tid * 0x27D4EB2F165667C5ull);
     const Word side = same ^ up;
+    // anti-aligned bits of the four neighbours when bonds = 1
+    Word m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t h = 4u * (uint64_t)tid + (uint64_t)k;
+        m[k] = (Word)(mix64(3 * h + 1) & mix64(3 * h + 2) & mix64(3 * h + 3));
+    }
     constexpr uint32_t QW = ising::WordTraits<Word>::BITS / 4;
     Word acc = 0;
     for (int i = 0; i < iters; ++i) {
         K.t = (uint32_t)i;
         const Word v = (Word)(uint32_t)i * (Word)0x9E3779B9u;
         const uint32_t q = (2u * tid + (uint32_t)i * 0x200000u) * QW;
-        acc ^= ising::update_word<Word, BITSLICED>(s0 ^ v, up, dn, same, side, q, K);
-        acc ^= ising::update_word<Word, BITSLICED>(s1 ^ v, dn, up, side, same, q + QW, K);
+        const Word a = s0 ^ v, b = s1 ^ v;
+        if (bonds) {
+            Word na[4], nb[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                na[k] = a ^ m[k];
+                nb[k] = b ^ m[k ^ 1];
+            }
+            // opaque to the compiler (an empty statement, no instruction):
+            // otherwise it folds s ^ (s ^ m) to m and hoists the
+            // classification out of the loop, work the sweep cannot skip
+            asm volatile("" : "+v"(na[0]), "+v"(na[1]), "+v"(na[2]), "+v"(na[3]));
+            asm volatile("" : "+v"(nb[0]), "+v"(nb[1]), "+v"(nb[2]), "+v"(nb[3]));
+            acc ^= ising::update_word<Word, BITSLICED>(a, na[0], na[1], na[2], na[3], q, K);
+            acc ^= ising::update_word<Word, BITSLICED>(b, nb[0], nb[1], nb[2], nb[3], q + QW, K);
+        } else {
+            acc ^= ising::update_word<Word, BITSLICED>(a, up, dn, same, side, q, K);
+            acc ^= ising::update_word<Word, BITSLICED>(b, dn, up, side, same, q + QW, K);
+        }
     }
     out[tid] = (uint32_t)acc ^ (uint32_t)((uint64_t)acc >> 32);
 }
 
 // The 3D sweep's per-word arithmetic (six-input classification, Philox,
 // three-threshold acceptance) on register-resident words.
-template <bool BITSLICED>
+template <bool BITSLICED, bool BONDS>
 __global__ __launch_bounds__(256) void k_mix3(uint32_t *out, uint32_t seed, int iters, uint32_t thr4, uint32_t thr8,
                                               uint32_t thr12)
 {
@@ -200,10 +241,29 @@ __global__ __launch_bounds__(256) void k_mix3(uint32_t *out, uint32_t seed, int 
     uint32_t s = tid * 0x9E3779B9u;
     uint32_t n[6] = {tid * 0xC2B2AE3Du, tid * 0x165667B1u, tid * 0x27D4EB2Fu, tid * 0x85EBCA77u, tid * 0x7FEB352Du,
                      tid * 0x846CA68Bu};
+    // BONDS: neighbour k differs from the spin word where m[k] is set, in
+    // about 11/32 of the bits ((h1 & h2) | (h3 & h4 & h5)), close to the 0.33
+    // of the 3D model near its T_c
+    uint32_t m[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint64_t h = 8u * (uint64_t)(6u * tid + (uint32_t)k);
+        m[k] = (uint32_t)((mix64(h + 1) & mix64(h + 2)) | (mix64(h + 3) & mix64(h + 4) & mix64(h + 5)));
+    }
     for (int i = 0; i < iters; ++i) {
         K.t = (uint32_t)i;
         const uint32_t c = (tid + (uint32_t)i * 0x100000u) * 8u;
-        s ^= BITSLICED ? ising::flip_mask32_3d_bitsliced(s, n, c, K) : ising::flip_mask32_3d(s, n, c, K);
+        if constexpr (BONDS) {
+            uint32_t nn[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                nn[k] = s ^ m[k];
+            // opaque (no instruction): keeps s ^ (s ^ m) from folding to m
+            asm volatile("" : "+v"(nn[0]), "+v"(nn[1]), "+v"(nn[2]), "+v"(nn[3]), "+v"(nn[4]), "+v"(nn[5]));
+            s ^= BITSLICED ? ising::flip_mask32_3d_bitsliced(s, nn, c, K) : ising::flip_mask32_3d(s, nn, c, K);
+        } else {
+            s ^= BITSLICED ? ising::flip_mask32_3d_bitsliced(s, n, c, K) : ising::flip_mask32_3d(s, n, c, K);
+        }
     }
     out[tid] = s;
 }
@@ -257,8 +317,8 @@ hipError_t run_alu(uint32_t *out, int blocks, int iters, hipStream_t st)
 // Shortest of `reps` timed k_mix launches (after one warm-up launch) in each
 // of the two launch shapes.
 template <typename Word, bool BITSLICED>
-hipError_t mix_best(uint32_t *o, int blocks, int iters, unsigned thr4, unsigned thr8, int reps, hipEvent_t e0,
-                    hipEvent_t e1, float *best)
+hipError_t mix_best(uint32_t *o, int blocks, int iters, unsigned thr4, unsigned thr8, int bonds, int reps,
+                    hipEvent_t e0, hipEvent_t e1, float *best)
 {
     hipError_t err = hipSuccess;
     for (int shape = 0; shape < 2 && err == hipSuccess; ++shape) {
@@ -268,10 +328,10 @@ hipError_t mix_best(uint32_t *o, int blocks, int iters, unsigned thr4, unsigned 
                 break;
             if (shape == 0)
                 hipLaunchKernelGGL((k_mix<Word, BITSLICED, 256>), dim3(blocks), dim3(256), 0, nullptr, o, 12345u,
-                                   iters, thr4, thr8);
+                                   iters, thr4, thr8, bonds);
             else
                 hipLaunchKernelGGL((k_mix<Word, BITSLICED, 1024>), dim3(blocks / 4), dim3(1024), 0, nullptr, o,
-                                   12345u, iters, thr4, thr8);
+                                   12345u, iters, thr4, thr8, bonds);
             err = hipGetLastError();
             if (err == hipSuccess)
                 err = hipEventRecord(e1, nullptr);
@@ -293,21 +353,31 @@ extern "C" {
 
 /* Measured ALU ceiling of the 3D sweep's per-word arithmetic: k_mix3 over
  * blocks x 256 threads x iters words of 32 sites under contract rng (0 site,
- * 1 bit-sliced); *ms = kernel time. */
+ * 1 bit-sliced), with random neighbour words (bonds 0) or neighbours that
+ * differ from the spin word in about 11/32 of the bits (bonds 1); *ms =
+ * kernel time. */
 int ising_probe_mix3(void *out, int blocks, int iters, unsigned thr4, unsigned thr8, unsigned thr12, int rng,
-                     float *ms)
+                     int bonds, float *ms)
 {
-    if (!out || !ms || blocks <= 0 || iters <= 0 || (rng != 0 && rng != 1))
+    if (!out || !ms || blocks <= 0 || iters <= 0 || (rng != 0 && rng != 1) || (bonds != 0 && bonds != 1))
         return -1;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return -4;
     uint32_t *o = static_cast<uint32_t *>(out);
     auto launch = [&](uint32_t seed) {
-        if (rng)
-            hipLaunchKernelGGL(k_mix3<true>, dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8, thr12);
+        if (rng && bonds)
+            hipLaunchKernelGGL((k_mix3<true, true>), dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8,
+                               thr12);
+        else if (rng)
+            hipLaunchKernelGGL((k_mix3<true, false>), dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8,
+                               thr12);
+        else if (bonds)
+            hipLaunchKernelGGL((k_mix3<false, true>), dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8,
+                               thr12);
         else
-            hipLaunchKernelGGL(k_mix3<false>, dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4, thr8, thr12);
+            hipLaunchKernelGGL((k_mix3<false, false>), dim3(blocks), dim3(256), 0, nullptr, o, seed, iters, thr4,
+                               thr8, thr12);
     };
     launch(777u);
     hipError_t st = hipEventRecord(e0, nullptr);
@@ -328,13 +398,15 @@ int ising_probe_mix3(void *out, int blocks, int iters, unsigned thr4, unsigned t
  * contract, in two launch shapes with the same total thread count: blocks x
  * 256 threads, and blocks / 4 x 1024 threads (blocks must be a multiple of 4).
  * Each shape runs one warm-up launch, then `reps` timed launches; *ms receives
- * the shortest timed launch over both shapes.  Sites counted per launch:
+ * the shortest timed launch over both shapes.  bonds: 0 neighbour words
+ * unrelated to the spin word, 1 neighbour words that differ from it in about
+ * 1/8 of the bits (see k_mix).  Sites counted per launch:
  * blocks * 256 * iters * 2 * word_bits.  Returns 0, or <0 on error. */
 int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned thr4, unsigned thr8, int rng,
-                    int reps, float *ms)
+                    int bonds, int reps, float *ms)
 {
     if (!out || blocks <= 0 || blocks % 4 != 0 || iters <= 0 || reps <= 0 || !ms ||
-        (word_bits != 32 && word_bits != 64) || (rng != 0 && rng != 1))
+        (word_bits != 32 && word_bits != 64) || (rng != 0 && rng != 1) || (bonds != 0 && bonds != 1))
         return -1;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -343,13 +415,13 @@ int ising_probe_mix(int word_bits, void *out, int blocks, int iters, unsigned th
     *ms = 0.f;
     hipError_t err;
     if (word_bits == 32 && rng == 0)
-        err = mix_best<uint32_t, false>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+        err = mix_best<uint32_t, false>(o, blocks, iters, thr4, thr8, bonds, reps, e0, e1, ms);
     else if (word_bits == 32)
-        err = mix_best<uint32_t, true>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+        err = mix_best<uint32_t, true>(o, blocks, iters, thr4, thr8, bonds, reps, e0, e1, ms);
     else if (rng == 0)
-        err = mix_best<uint64_t, false>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+        err = mix_best<uint64_t, false>(o, blocks, iters, thr4, thr8, bonds, reps, e0, e1, ms);
     else
-        err = mix_best<uint64_t, true>(o, blocks, iters, thr4, thr8, reps, e0, e1, ms);
+        err = mix_best<uint64_t, true>(o, blocks, iters, thr4, thr8, bonds, reps, e0, e1, ms);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return err == hipSuccess ? 0 : -4;

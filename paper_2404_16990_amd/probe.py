@@ -48,40 +48,48 @@ def measure(blocks=256 * 16, iters=4096):
             "philox_lane_cycles_per_call": xor / res["philox4x32_10"]}
 
 
-def mix_rate(word_bits=64, blocks=256 * 16, iters=128, T=2.269185, rng=0, reps=5):
+def mix_rate(word_bits=64, blocks=256 * 16, iters=128, T=2.269185, rng=0, reps=5, bonds=0):
     """Measured ALU ceiling of the sweep's per-word arithmetic, in site updates
     (flip attempts) per second: k_mix runs ising::update_word on two
     register-resident words per thread (classification, Philox4x32-10,
     acceptance) with no memory traffic and no dependence between updates, in
     the streaming and the LDS-resident kernels' launch shapes; the best of
-    `reps` timed launches per shape after a warm-up launch."""
+    `reps` timed launches per shape after a warm-up launch.  bonds=0: random
+    neighbour words (half the bonds anti-aligned); bonds=1: about 1/8 of the
+    bonds anti-aligned, as in a 2D lattice near T_c (this matters for the
+    bit-sliced contract only, whose lazy comparison depends on how many sites
+    are undecided)."""
     import math
     import torch
     L = _lib()
     L.ising_probe_mix.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
-                                  ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+                                  ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_float)]
     thr = [min(int(math.floor(math.ldexp(math.exp(-4.0 * k / T), 32))), 2**32 - 1) for k in (1, 2)]
     out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     ms = ctypes.c_float()
-    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], int(rng), int(reps),
-                         ctypes.byref(ms)) != 0:
+    if L.ising_probe_mix(int(word_bits), out.data_ptr(), blocks, iters, thr[0], thr[1], int(rng), int(bonds),
+                         int(reps), ctypes.byref(ms)) != 0:
         raise RuntimeError("mix probe failed")
     return blocks * 256 * iters * 2 * word_bits / (ms.value * 1e-3)
 
 
-def mix3_rate(blocks=256 * 16, iters=64, T=4.5115, rng=0):
+def mix3_rate(blocks=256 * 16, iters=64, T=4.5115, rng=0, bonds=0):
     """Measured ALU ceiling of the 3D sweep's per-word arithmetic (flip
     attempts per second): k_mix3 runs ising::flip_mask32_3d on
-    register-resident words with no memory traffic."""
+    register-resident words with no memory traffic; bonds=1 gives the
+    neighbour words the bond statistics of the 3D model near T_c (about a
+    third of the bonds anti-aligned) instead of random words."""
     import math
     import torch
     L = _lib()
     L.ising_probe_mix3.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_uint,
-                                   ctypes.c_uint, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+                                   ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     thr = [min(int(math.floor(math.ldexp(math.exp(-4.0 * k / T), 32))), 2**32 - 1) for k in (1, 2, 3)]
     out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     ms = ctypes.c_float()
-    if L.ising_probe_mix3(out.data_ptr(), blocks, iters, thr[0], thr[1], thr[2], int(rng), ctypes.byref(ms)) != 0:
+    if L.ising_probe_mix3(out.data_ptr(), blocks, iters, thr[0], thr[1], thr[2], int(rng), int(bonds),
+                          ctypes.byref(ms)) != 0:
         raise RuntimeError("mix3 probe failed")
     return blocks * 256 * iters * 32 / (ms.value * 1e-3)
 
@@ -152,6 +160,12 @@ if __name__ == "__main__":
         r = measure()
         r["sweep_mix_flips_per_s"] = {str(w): mix_rate(w) for w in (32, 64)}
         r["sweep_mix_bitsliced_flips_per_s"] = {str(w): mix_rate(w, rng=1) for w in (32, 64)}
+        r["sweep_mix_ordered_bonds_flips_per_s"] = {str(w): mix_rate(w, bonds=1) for w in (32, 64)}
+        r["sweep_mix_bitsliced_ordered_bonds_flips_per_s"] = {str(w): mix_rate(w, rng=1, bonds=1)
+                                                              for w in (32, 64)}
+        r["mix3_flips_per_s"] = {"site": mix3_rate(), "bitsliced": mix3_rate(rng=1),
+                                 "site_ordered_bonds": mix3_rate(bonds=1),
+                                 "bitsliced_ordered_bonds": mix3_rate(rng=1, bonds=1)}
         r["clock"] = clock()
         r["copy_bytes_per_s"] = copy_bandwidth()
         print(json.dumps(r, indent=1))
